@@ -1,0 +1,537 @@
+"""CPU ORACLE -- test infrastructure only.
+
+A plain, slow, FP64 CPU implementation of what the GPU path computes: the
+paper's Green-operator FFT fixed point for a voxelized periodic polycrystal
+with the regularized Meric-Cailletaud law (Sections 3 and 4 of the paper).
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  It shares no code with the GPU
+library; the two are fed from the same seeded input generator only.
+
+The local law (``cp_law.c``) is plain C on Mandel 6-vectors; this module
+adds the per-label setup (rotations), the Green operator, the fixed-point
+iteration with mixed macroscopic conditions, and the per-step outputs.  The
+FFT is ``numpy.fft`` (a library primitive serving as one step).
+
+Readings of points the paper leaves open (each is listed with its reason in
+the design notes of the repository):
+
+* Green operator: the continuous isotropic Gamma0 of a reference medium
+  (lam0, mu0); frequencies xi_j = m_j / N_j with m_j in (-N_j/2, N_j/2];
+  Gamma0 = 0 at xi = 0 and at every frequency with a Nyquist component
+  (m_j = N_j/2, N_j even), which keeps the real field real.
+* Reference medium: k0 = (1/9) 1:C:1 (Voigt bulk), mu0 = mean of the
+  extreme deviatoric shear moduli of C, lam0 = k0 - 2 mu0 / 3.
+* Basic scheme: eps^{k+1} = eps^k - Gamma0 * sigma^k + dE^k, with the
+  stress-controlled mean strain corrected by the reference compliance.
+* Convergence: err_eq = sqrt(sum_xi |sigma_hat(xi) . xi_hat|^2) / |sigma_hat(0)|
+  over controlled frequencies, err_bc = |P_S(Sigma - Sigma*)| / |Sigma|.
+* Local integration: total strain linear in time within a load step;
+  RK4 with M = ceil(dt / h_max) equal substeps.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import math
+import os
+import time
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+SQ2 = math.sqrt(2.0)
+# tensor-component order of every 6-vector at the interfaces: 11,22,33,23,13,12
+VOIGT_PAIRS = [(0, 0), (1, 1), (2, 2), (1, 2), (0, 2), (0, 1)]
+MANDEL_W = np.array([1.0, 1.0, 1.0, SQ2, SQ2, SQ2])
+FROB_W = np.array([1.0, 1.0, 1.0, 2.0, 2.0, 2.0])   # |A|^2 in tensor comps
+
+
+# ---------------------------------------------------------------------------
+# C library
+# ---------------------------------------------------------------------------
+class _Material(ctypes.Structure):
+    _fields_ = [
+        ("n_sys", ctypes.c_int), ("n_labels", ctypes.c_int),
+        ("C_lab", ctypes.POINTER(ctypes.c_double)),
+        ("m_lab", ctypes.POINTER(ctypes.c_double)),
+        ("family", ctypes.POINTER(ctypes.c_int)),
+        ("tau0", ctypes.POINTER(ctypes.c_double)),
+        ("Q", ctypes.c_double * 2), ("b", ctypes.c_double * 2),
+        ("c", ctypes.c_double * 2), ("d", ctypes.c_double * 2),
+        ("K", ctypes.c_double * 2), ("n", ctypes.c_double * 2),
+        ("q_self", ctypes.c_double * 2), ("q_lat", ctypes.c_double * 2),
+        ("twin_mode", ctypes.c_int),
+        ("K_c", ctypes.c_double), ("f_m", ctypes.c_double),
+        ("gamma_T", ctypes.c_double), ("eta", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        path = os.path.join(_HERE, "_cp_law.so")
+        if not os.path.exists(path):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(path)
+        dp = ctypes.POINTER(ctypes.c_double)
+        L.orc_reg_rate.restype = ctypes.c_double
+        L.orc_reg_rate.argtypes = [ctypes.c_double] * 5
+        L.orc_rate.restype = None
+        L.orc_rate.argtypes = [ctypes.POINTER(_Material), ctypes.c_int, dp, dp, dp]
+        L.orc_cp_update.restype = ctypes.c_int
+        L.orc_cp_update.argtypes = [ctypes.POINTER(_Material), ctypes.c_long,
+                                    ctypes.POINTER(ctypes.c_int), dp, dp, dp, dp, dp,
+                                    ctypes.c_double, ctypes.c_int]
+        L.orc_max_threads.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _dp(a: np.ndarray):
+    assert a.dtype == np.float64 and a.flags.c_contiguous
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def threads() -> int:
+    return lib().orc_max_threads()
+
+
+# ---------------------------------------------------------------------------
+# Tensor bookkeeping
+# ---------------------------------------------------------------------------
+def to_mandel(t: np.ndarray) -> np.ndarray:
+    """tensor components (.., 6) -> Mandel (.., 6)"""
+    return np.asarray(t, dtype=np.float64) * MANDEL_W
+
+
+def from_mandel(m: np.ndarray) -> np.ndarray:
+    return np.asarray(m) / MANDEL_W
+
+
+def sym_to_mat(v: np.ndarray) -> np.ndarray:
+    """tensor components (..., 6) -> (..., 3, 3)"""
+    out = np.empty(v.shape[:-1] + (3, 3), dtype=v.dtype)
+    for I, (i, j) in enumerate(VOIGT_PAIRS):
+        out[..., i, j] = v[..., I]
+        out[..., j, i] = v[..., I]
+    return out
+
+
+def mat_to_sym(a: np.ndarray) -> np.ndarray:
+    return np.stack([a[..., i, j] for (i, j) in VOIGT_PAIRS], axis=-1)
+
+
+def von_mises(t: np.ndarray) -> np.ndarray:
+    """von Mises equivalent of tensor-component 6-vectors: sqrt(3/2 s:s)."""
+    t = np.asarray(t, dtype=np.float64)
+    p = (t[..., 0] + t[..., 1] + t[..., 2]) / 3.0
+    s = t.copy()
+    s[..., :3] -= p[..., None]
+    return np.sqrt(1.5 * np.sum(FROB_W * s * s, axis=-1))
+
+
+def frob(t: np.ndarray) -> float:
+    return float(np.sqrt(np.sum(FROB_W * np.asarray(t) ** 2)))
+
+
+# ---------------------------------------------------------------------------
+# Per-label setup (orientation, stiffness and Schmid tensors in the lab frame)
+# ---------------------------------------------------------------------------
+def euler_to_rotation(euler: np.ndarray) -> np.ndarray:
+    """Bunge angles (phi1, Phi, phi2) -> Q = Rz(phi1) Rx(Phi) Rz(phi2),
+    active, so that v_lab = Q v_crystal."""
+    e = np.atleast_2d(np.asarray(euler, dtype=np.float64))
+
+    def rz(a):
+        R = np.zeros(a.shape + (3, 3))
+        R[..., 0, 0] = np.cos(a); R[..., 0, 1] = -np.sin(a)
+        R[..., 1, 0] = np.sin(a); R[..., 1, 1] = np.cos(a)
+        R[..., 2, 2] = 1.0
+        return R
+
+    def rx(a):
+        R = np.zeros(a.shape + (3, 3))
+        R[..., 0, 0] = 1.0
+        R[..., 1, 1] = np.cos(a); R[..., 1, 2] = -np.sin(a)
+        R[..., 2, 1] = np.sin(a); R[..., 2, 2] = np.cos(a)
+        return R
+
+    return rz(e[:, 0]) @ rx(e[:, 1]) @ rz(e[:, 2])
+
+
+def stiffness_tensor(C_voigt: np.ndarray) -> np.ndarray:
+    """Voigt 6x6 (engineering shear) -> fourth-order C_ijkl."""
+    C4 = np.zeros((3, 3, 3, 3))
+    for I, (i, j) in enumerate(VOIGT_PAIRS):
+        for J, (k, l) in enumerate(VOIGT_PAIRS):
+            for (a, b) in {(i, j), (j, i)}:
+                for (c, d) in {(k, l), (l, k)}:
+                    C4[a, b, c, d] = C_voigt[I, J]
+    return C4
+
+
+def mandel_of_tensor4(C4: np.ndarray) -> np.ndarray:
+    M = np.empty(C4.shape[:-4] + (6, 6))
+    for I, (i, j) in enumerate(VOIGT_PAIRS):
+        for J, (k, l) in enumerate(VOIGT_PAIRS):
+            M[..., I, J] = MANDEL_W[I] * MANDEL_W[J] * C4[..., i, j, k, l]
+    return M
+
+
+def lab_stiffness(C_voigt: np.ndarray, Q: np.ndarray) -> np.ndarray:
+    """C'_ijkl = Q_ia Q_jb Q_kc Q_ld C_abcd for each rotation, in Mandel form."""
+    C4 = stiffness_tensor(np.asarray(C_voigt, dtype=np.float64))
+    C4r = np.einsum("nia,njb,nkc,nld,abcd->nijkl", Q, Q, Q, Q, C4)
+    return mandel_of_tensor4(C4r)
+
+
+def schmid_tensors(n_miller: np.ndarray, l_miller: np.ndarray) -> np.ndarray:
+    """Equation 2: m = (n (x) l + l (x) n) / 2 with unit n and l."""
+    n = np.asarray(n_miller, dtype=np.float64)
+    l = np.asarray(l_miller, dtype=np.float64)
+    n = n / np.linalg.norm(n, axis=1, keepdims=True)
+    l = l / np.linalg.norm(l, axis=1, keepdims=True)
+    return 0.5 * (n[:, :, None] * l[:, None, :] + l[:, :, None] * n[:, None, :])
+
+
+def lab_schmid(m_crys: np.ndarray, Q: np.ndarray) -> np.ndarray:
+    """m_lab = Q m Q^T for each label and system, as Mandel vectors [L,S,6]."""
+    mr = np.einsum("nia,sab,njb->nsij", Q, m_crys, Q)
+    return to_mandel(mat_to_sym(mr))
+
+
+def reference_medium(C_voigt: np.ndarray) -> tuple[float, float]:
+    """Isotropic reference medium (lam0, mu0) of a crystal stiffness.
+
+    k0 = (1/9) 1:C:1; mu0 = (mu_min + mu_max)/2 with 2*mu the extreme
+    eigenvalues of C restricted to deviatoric tensors; lam0 = k0 - 2 mu0/3.
+    """
+    CM = mandel_of_tensor4(stiffness_tensor(np.asarray(C_voigt, dtype=np.float64)))
+    one = np.array([1.0, 1, 1, 0, 0, 0])
+    k0 = float(one @ CM @ one) / 9.0
+    # orthonormal basis of the deviatoric subspace in Mandel space
+    P = np.eye(6) - np.outer(one, one) / 3.0
+    w, V = np.linalg.eigh(P)
+    B = V[:, w > 0.5]                       # 6 x 5
+    ev = np.linalg.eigvalsh(B.T @ CM @ B)
+    mu0 = 0.25 * (ev[0] + ev[-1])
+    return k0 - 2.0 * mu0 / 3.0, mu0
+
+
+def iso_stiffness(lam: float, mu: float) -> np.ndarray:
+    """Isotropic stiffness acting on tensor-component 6-vectors
+    (identical to its Mandel matrix)."""
+    K = np.zeros((6, 6))
+    K[:3, :3] = lam
+    for i in range(3):
+        K[i, i] = lam + 2 * mu
+    for i in range(3, 6):
+        K[i, i] = 2 * mu
+    return K
+
+
+def substeps(dt: float, h_max: float) -> int:
+    """Number of equal RK4 substeps in a load step of length dt."""
+    return max(1, int(math.ceil(dt / h_max * (1.0 - 1e-12))))
+
+
+# ---------------------------------------------------------------------------
+# Material-point law (wraps the C code)
+# ---------------------------------------------------------------------------
+class Material:
+    """Per-label lab-frame data plus law parameters for the C oracle."""
+
+    def __init__(self, euler, C_voigt, n_miller, l_miller, family, tau0, law):
+        self.Q = euler_to_rotation(euler)
+        self.C_lab = np.ascontiguousarray(lab_stiffness(C_voigt, self.Q))
+        self.m_crys = schmid_tensors(n_miller, l_miller)
+        self.m_lab = np.ascontiguousarray(lab_schmid(self.m_crys, self.Q))
+        self.family = np.ascontiguousarray(np.asarray(family, dtype=np.int32))
+        self.tau0 = np.ascontiguousarray(np.asarray(tau0, dtype=np.float64))
+        self.n_sys = int(self.family.shape[0])
+        self.n_labels = int(self.Q.shape[0])
+        self.law = law
+        s = _Material()
+        s.n_sys, s.n_labels = self.n_sys, self.n_labels
+        s.C_lab, s.m_lab = _dp(self.C_lab), _dp(self.m_lab)
+        s.family = self.family.ctypes.data_as(ctypes.POINTER(ctypes.c_int))
+        s.tau0 = _dp(self.tau0)
+        for k, fam in enumerate((law.slip, law.twin)):
+            for name in ("Q", "b", "c", "d", "K", "n"):
+                getattr(s, name)[k] = float(getattr(fam, name))
+            s.q_self[k] = float(fam.q_self)
+            s.q_lat[k] = float(fam.q_latent)
+        s.twin_mode = int(law.twin_mode)
+        s.K_c, s.f_m, s.gamma_T = float(law.K_c), float(law.f_m), float(law.gamma_T)
+        s.eta = float(law.eta)
+        self._s = s
+
+    @property
+    def state_dim(self) -> int:
+        return 6 + 2 * self.n_sys
+
+    def rate(self, label: int, eps_mandel, y) -> np.ndarray:
+        e = np.ascontiguousarray(eps_mandel, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        dy = np.zeros(self.state_dim)
+        lib().orc_rate(ctypes.byref(self._s), int(label), _dp(e), _dp(y), _dp(dy))
+        return dy
+
+    def update(self, labels, eps0, eps1, y0, dt, M):
+        """Integrate every point over one load increment (Mandel in/out)."""
+        labels = np.ascontiguousarray(np.asarray(labels, dtype=np.int32).ravel())
+        n = labels.shape[0]
+        eps0 = np.ascontiguousarray(np.broadcast_to(eps0, (n, 6)), dtype=np.float64)
+        eps1 = np.ascontiguousarray(np.broadcast_to(eps1, (n, 6)), dtype=np.float64)
+        y0 = np.ascontiguousarray(y0, dtype=np.float64)
+        y1 = np.empty_like(y0)
+        sig = np.empty((n, 6))
+        rc = lib().orc_cp_update(ctypes.byref(self._s), n,
+                                 labels.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                 _dp(eps0), _dp(eps1), _dp(y0), _dp(y1), _dp(sig),
+                                 float(dt), int(M))
+        if rc != 0:
+            raise ValueError("orc_cp_update rejected its input")
+        return y1, sig
+
+
+def reg_rate(o, A, K, n, eta) -> float:
+    return lib().orc_reg_rate(float(o), float(A), float(K), float(n), float(eta))
+
+
+# ---------------------------------------------------------------------------
+# Green operator (continuous, isotropic reference medium)
+# ---------------------------------------------------------------------------
+def frequency_directions(shape):
+    """Unit frequency directions xi_hat [3,nz,ny,nx] (x,y,z order) and the
+    mask of controlled frequencies (not zero, no Nyquist component)."""
+    nz, ny, nx = shape
+    ms, nyq = [], []
+    for N in (nx, ny, nz):
+        k = np.arange(N)
+        m = np.where(k <= N // 2, k, k - N).astype(np.float64)
+        ms.append(m / N)
+        nyq.append((N % 2 == 0) & (k == N // 2))
+    MZ, MY, MX = np.meshgrid(ms[2], ms[1], ms[0], indexing="ij")
+    NZ, NY, NX = np.meshgrid(nyq[2], nyq[1], nyq[0], indexing="ij")
+    xi = np.stack([MX, MY, MZ])
+    nrm = np.sqrt(np.sum(xi * xi, axis=0))
+    ctrl = (nrm > 0) & ~(NX | NY | NZ)
+    xi_hat = np.where(ctrl, xi / np.where(nrm > 0, nrm, 1.0), 0.0)
+    return xi_hat, ctrl
+
+
+def gamma0_apply(tau_hat: np.ndarray, lam0: float, mu0: float,
+                 xi_hat: Optional[np.ndarray] = None,
+                 ctrl: Optional[np.ndarray] = None) -> np.ndarray:
+    """eps_hat = Gamma0(xi) : tau_hat(xi) on a full spectrum.
+
+    tau_hat: [6,nz,ny,nx] tensor components.  With a = tau_hat . xi_hat and
+    b = xi_hat . tau_hat . xi_hat,
+      eps_hat_ij = (xi_i a_j + xi_j a_i) / (2 mu0)
+                   - (lam0 + mu0) / (mu0 (lam0 + 2 mu0)) * b * xi_i xi_j ,
+    and eps_hat = 0 at uncontrolled frequencies.
+    """
+    if xi_hat is None:
+        xi_hat, ctrl = frequency_directions(tau_hat.shape[1:])
+    T = sym_to_mat(np.moveaxis(tau_hat, 0, -1))          # [...,3,3]
+    x = np.moveaxis(xi_hat, 0, -1)                        # [...,3]
+    a = np.einsum("...ij,...j->...i", T, x)
+    b = np.einsum("...i,...i->...", x, a)
+    coef = (lam0 + mu0) / (mu0 * (lam0 + 2.0 * mu0))
+    E = (x[..., :, None] * a[..., None, :] + a[..., :, None] * x[..., None, :]) / (2.0 * mu0) \
+        - coef * b[..., None, None] * x[..., :, None] * x[..., None, :]
+    E = np.where(ctrl[..., None, None], E, 0.0)
+    return np.moveaxis(mat_to_sym(E), -1, 0)
+
+
+def fft3(field: np.ndarray) -> np.ndarray:
+    """Unnormalized forward DFT over the last three axes (z, y, x)."""
+    return np.fft.fftn(field, axes=(-3, -2, -1))
+
+
+def ifft3_real(spec: np.ndarray) -> np.ndarray:
+    """Inverse DFT (normalized by 1/N) over the last three axes, real part."""
+    return np.fft.ifftn(spec, axes=(-3, -2, -1)).real
+
+
+def equilibrium_sums(sig_hat: np.ndarray, xi_hat, ctrl) -> float:
+    """sum over controlled frequencies of |sigma_hat(xi) . xi_hat|^2."""
+    T = sym_to_mat(np.moveaxis(sig_hat, 0, -1))
+    x = np.moveaxis(xi_hat, 0, -1)
+    a = np.einsum("...ij,...j->...i", T, x)
+    return float(np.sum(np.where(ctrl, np.sum(np.abs(a) ** 2, axis=-1), 0.0)))
+
+
+# ---------------------------------------------------------------------------
+# The fixed-point solver
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class Options:
+    tol: float = 1e-8
+    max_iter: int = 1000
+    h_max: float = 0.05
+    M: Optional[int] = None           # fixed RK4 substeps, overrides h_max
+    lam0: Optional[float] = None      # reference medium override
+    mu0: Optional[float] = None
+
+
+class NotConverged(RuntimeError):
+    pass
+
+
+@dataclasses.dataclass
+class Result:
+    Sigma: np.ndarray          # [n_steps][6] tensor components, MPa
+    E: np.ndarray              # [n_steps][6]
+    sig_eq_of_mean: np.ndarray  # von Mises of Sigma
+    mean_sig_eq: np.ndarray    # mean of local von Mises
+    mean_v: np.ndarray         # mean accumulated slip over slip systems
+    mean_f: np.ndarray         # mean twin fraction over twin systems
+    iters: np.ndarray          # constitutive evaluations per step
+    err_eq: np.ndarray
+    err_bc: np.ndarray
+    wall: float = 0.0
+    fields: Optional[dict] = None
+
+
+class Solver:
+    """Plain FP64 Green-operator fixed point over mixed load steps."""
+
+    def __init__(self, labels, euler, C_voigt, n_miller, l_miller, family,
+                 tau0, law, options: Optional[Options] = None):
+        self.labels = np.ascontiguousarray(np.asarray(labels, dtype=np.int32))
+        self.shape = self.labels.shape
+        self.n_vox = int(self.labels.size)
+        self.mat = Material(euler, C_voigt, n_miller, l_miller, family, tau0, law)
+        self.opts = options or Options()
+        lam0, mu0 = reference_medium(C_voigt)
+        if self.opts.mu0 is not None:
+            lam0, mu0 = self.opts.lam0, self.opts.mu0
+        self.lam0, self.mu0 = lam0, mu0
+        self.K0 = iso_stiffness(lam0, mu0)
+        self.xi_hat, self.ctrl = frequency_directions(self.shape)
+        self.slip = self.mat.family == 0
+        self.twin = self.mat.family == 1
+        self.reset()
+
+    def reset(self):
+        n, D = self.n_vox, self.mat.state_dim
+        self.eps = np.zeros((n, 6))          # Mandel, committed total strain
+        self.y = np.zeros((n, D))            # committed internal variables
+        self.Sigma = np.zeros(6)             # committed mean stress (tensor)
+        self.E = np.zeros(6)                 # committed mean strain (tensor)
+        self.sig = np.zeros((n, 6))          # committed stress (Mandel)
+
+    # -- pieces ------------------------------------------------------------
+    def errors(self, sig_t: np.ndarray, Sigma: np.ndarray, sidx, target):
+        grid = np.moveaxis(sig_t.reshape(self.shape + (6,)), -1, 0)
+        sig_hat = fft3(grid)
+        num = math.sqrt(equilibrium_sums(sig_hat, self.xi_hat, self.ctrl))
+        den = self.n_vox * frob(Sigma)
+        err_eq = num / den if den > 0 else (0.0 if num == 0 else math.inf)
+        dS = np.where(sidx, Sigma - target, 0.0)
+        sn = frob(Sigma)
+        err_bc = frob(dS) / sn if sn > 0 else (0.0 if frob(dS) == 0 else math.inf)
+        return sig_hat, err_eq, err_bc
+
+    def correction(self, sig_hat: np.ndarray) -> np.ndarray:
+        """Gamma0 * sigma in real space, tensor components [n_vox][6]."""
+        eh = gamma0_apply(sig_hat, self.lam0, self.mu0, self.xi_hat, self.ctrl)
+        corr = ifft3_real(eh)
+        return np.moveaxis(corr, 0, -1).reshape(self.n_vox, 6)
+
+    def _stress_correction(self, sidx, rhs) -> np.ndarray:
+        dE = np.zeros(6)
+        S = np.nonzero(sidx)[0]
+        if S.size:
+            dE[S] = np.linalg.solve(self.K0[np.ix_(S, S)], rhs[S])
+        return dE
+
+    # -- one load step -----------------------------------------------------
+    def step(self, t0: float, t1: float, ctrl_row, target_row):
+        o = self.opts
+        dt = t1 - t0
+        M = o.M if o.M is not None else substeps(dt, o.h_max)
+        eidx = np.asarray(ctrl_row, dtype=bool)
+        sidx = ~eidx
+        target = np.asarray(target_row, dtype=np.float64)
+        # initial guess: homogeneous reference-medium prediction
+        dE = np.zeros(6)
+        dE[eidx] = target[eidx] - self.E[eidx]
+        rhs = (target - self.Sigma) - self.K0 @ dE
+        dE += self._stress_correction(sidx, rhs)
+        E = self.E + dE
+        eps = self.eps + to_mandel(dE)
+        for k in range(o.max_iter):
+            y1, sig = self.mat.update(self.labels, self.eps, eps, self.y, dt, M)
+            sig_t = from_mandel(sig)
+            Sigma = sig_t.mean(axis=0)
+            sig_hat, err_eq, err_bc = self.errors(sig_t, Sigma, sidx, target)
+            if not (np.isfinite(err_eq) and np.isfinite(err_bc)):
+                raise FloatingPointError("non-finite residual at iteration %d" % k)
+            if err_eq <= o.tol and err_bc <= o.tol:
+                break
+            corr = self.correction(sig_hat)
+            dE = self._stress_correction(sidx, target - Sigma)
+            E = E + dE
+            eps = eps - to_mandel(corr) + to_mandel(dE)
+        else:
+            raise NotConverged("no convergence in %d iterations" % o.max_iter)
+        self.eps, self.y, self.sig = eps, y1, sig
+        self.Sigma, self.E = Sigma, E
+        return k + 1, err_eq, err_bc
+
+    def outputs(self):
+        S = self.mat.n_sys
+        v = self.y[:, 6:6 + S]
+        sig_t = from_mandel(self.sig)
+        mv = float(v[:, self.slip].mean()) if self.slip.any() else 0.0
+        mf = float(v[:, self.twin].mean() / self.mat.law.gamma_T) if self.twin.any() else 0.0
+        return (float(von_mises(self.Sigma)), float(von_mises(sig_t).mean()), mv, mf)
+
+    def run(self, path, keep_fields: bool = False, n_steps: Optional[int] = None) -> Result:
+        ns = path.target.shape[0] if n_steps is None else n_steps
+        R = Result(*(np.zeros((ns, 6)) for _ in range(2)),
+                   *(np.zeros(ns) for _ in range(4)),
+                   np.zeros(ns, dtype=np.int64), np.zeros(ns), np.zeros(ns))
+        t_start = time.perf_counter()
+        for n in range(ns):
+            its, ee, eb = self.step(path.t[n], path.t[n + 1], path.strain_ctrl[n],
+                                    path.target[n])
+            R.Sigma[n], R.E[n] = self.Sigma, self.E
+            (R.sig_eq_of_mean[n], R.mean_sig_eq[n], R.mean_v[n],
+             R.mean_f[n]) = self.outputs()
+            R.iters[n], R.err_eq[n], R.err_bc[n] = its, ee, eb
+        R.wall = time.perf_counter() - t_start
+        if keep_fields:
+            R.fields = self.fields()
+        return R
+
+    def fields(self) -> dict:
+        """Committed local fields, tensor components, grid-shaped [6][nz][ny][nx]."""
+        S = self.mat.n_sys
+
+        def grid(a):
+            return np.moveaxis(a.reshape(self.shape + (a.shape[-1],)), -1, 0)
+
+        return {
+            "stress": grid(from_mandel(self.sig)),
+            "strain": grid(from_mandel(self.eps)),
+            "plastic_strain": grid(from_mandel(self.y[:, :6])),
+            "acc_slip": grid(self.y[:, 6:6 + S]),
+            "back_strain": grid(self.y[:, 6 + S:]),
+        }
+
+
+def solver_for(workload, options: Optional[Options] = None) -> Solver:
+    """Convenience: an oracle solver for an ``rvegen.Workload``-like object."""
+    w = workload
+    return Solver(w.rve.labels, w.rve.euler, w.C, w.systems.n_miller,
+                  w.systems.l_miller, w.systems.family, w.systems.tau0, w.law,
+                  options)
