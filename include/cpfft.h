@@ -1,0 +1,186 @@
+/*
+ * cpfft -- Green-operator FFT solver for voxelized periodic polycrystals
+ * with the regularized Meric-Cailletaud crystal-plasticity law, on one
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The problem follows the paper's statement (abstract; Section 5 opening):
+ * a grain-label voxel grid with one crystal orientation per label, an
+ * anisotropic crystal stiffness, a set of slip and twinning pseudo-slip
+ * systems (Table 1), the law parameters (Section 3, equations 1-6, with
+ * the viscous-hardening regularization of Section 4, equation "regu"),
+ * and a macroscopic loading path whose steps prescribe, per component,
+ * either the mean strain or the mean stress.  The solver returns effective
+ * (mean) stress-strain histories and the local fields.
+ *
+ * Units: MPa, seconds; strains dimensionless.  Symmetric tensors cross the
+ * ABI as 6 tensor components in the order 11, 22, 33, 23, 13, 12.
+ *
+ * Memory: the library never allocates device memory.  The caller obtains
+ * the size with cpf_solver_workspace_size(), allocates one device buffer
+ * (e.g. a torch uint8 tensor) and hands it over with cpf_solver_bind();
+ * it must stay alive and untouched until cpf_solver_destroy().  All device
+ * work is ordered on the bound HIP stream.  Host arrays passed in are
+ * copied; the caller keeps ownership.
+ *
+ * Errors: every call returns CPF_OK (0) or a negative CPF_E_* code and
+ * never throws or aborts across the ABI.  cpf_last_error_message() gives a
+ * thread-local description of the last failure on the calling thread.
+ */
+#ifndef CPFFT_H
+#define CPFFT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CPF_VERSION 10000
+
+#define CPF_OK 0
+#define CPF_E_INVALID_ARG (-1)
+#define CPF_E_WORKSPACE (-2)
+#define CPF_E_HIP (-3)
+#define CPF_E_NOT_CONVERGED (-4)
+#define CPF_E_NAN (-5)
+#define CPF_E_UNSUPPORTED_SIZE (-6)
+#define CPF_E_BAD_STATE (-7)
+
+#define CPF_FAMILY_SLIP 0
+#define CPF_FAMILY_TWIN 1
+
+/* Twin rate law (Section 3, equation 6).
+ * NORTON: same regularized Norton rate as slip, one-sided (>= 0).
+ * PAPER : rate prefactor gamma_T * K_c * (f_m - sum_beta f_beta). */
+#define CPF_TWIN_NORTON 0
+#define CPF_TWIN_PAPER 1
+
+#define CPF_PREC_FP64 0
+#define CPF_PREC_FP32 1 /* FP32 fields and law, FP64 reductions and means */
+
+#define CPF_FIELD_STRESS 0         /* 6 components                     */
+#define CPF_FIELD_STRAIN 1         /* 6 components                     */
+#define CPF_FIELD_PLASTIC_STRAIN 2 /* 6 components                     */
+#define CPF_FIELD_ACC_SLIP 3       /* n_sys components (v)             */
+#define CPF_FIELD_BACK_STRAIN 4    /* n_sys components (alpha)         */
+
+#define CPF_MAX_SYSTEMS 32
+
+/* Per-family hardening and viscosity parameters (Section 3, equations 4
+ * and 5): r = tau0 + Q sum_t q_st (1 - exp(-b v_t)) within the family,
+ * with q_st = q_self on the diagonal and q_latent elsewhere; Norton
+ * viscosity K (MPa s^(1/n)) and exponent n.  Kinematic hardening
+ * x = c*alpha, dalpha/dt = gdot - d |gdot| alpha (c = 0: the paper's law). */
+typedef struct cpf_law {
+    double Q, b, c, d, K, n, q_self, q_latent;
+} cpf_law;
+
+typedef struct cpf_problem_desc {
+    int nx, ny, nz;           /* grid; each 2^a 3^b, 2 <= n <= 256             */
+    const int32_t *labels;    /* host [nz][ny][nx], x fastest, in [0,n_labels) */
+    int n_labels;
+    const double *euler;      /* host [n_labels][3] Bunge (phi1, Phi, phi2),
+                                 radians: Q = Rz(phi1) Rx(Phi) Rz(phi2),
+                                 v_lab = Q v_crystal                           */
+    double C_crystal[36];     /* Voigt 6x6 (engineering shear), MPa            */
+    int n_sys;                /* 1 .. CPF_MAX_SYSTEMS                          */
+    const double *n_miller;   /* host [n_sys][3] plane normals (normalized
+                                 internally)                                  */
+    const double *l_miller;   /* host [n_sys][3] slip directions               */
+    const int32_t *family;    /* host [n_sys] CPF_FAMILY_*                     */
+    const double *tau0;       /* host [n_sys] initial resistance, MPa          */
+    cpf_law law[2];           /* [CPF_FAMILY_SLIP], [CPF_FAMILY_TWIN]          */
+    int twin_mode;            /* CPF_TWIN_*                                    */
+    double K_c, f_m, gamma_T; /* twin-fraction law (PAPER mode); f = v/gamma_T */
+    double eta;               /* regularization r' = r + eta |gdot|, MPa s     */
+} cpf_problem_desc;
+
+typedef struct cpf_options {
+    int precision;     /* CPF_PREC_*                                         */
+    double tol;        /* convergence: err_eq <= tol and err_bc <= tol       */
+    int max_iter;      /* iterations per load step before NOT_CONVERGED      */
+    double h_max;      /* RK4 substeps per step: ceil(dt/h_max)              */
+    int rk4_M;         /* > 0: fixed substep count (overrides h_max)         */
+    double lam0, mu0;  /* > 0: reference medium override (MPa)               */
+    double stag_tol;   /* FP32: accept a stalled residual below this (0: off)*/
+    int check_every;   /* iterations queued per host convergence poll (0: auto) */
+} cpf_options;
+
+/* Loading path: n_steps increments; t has n_steps+1 times (s).  For step
+ * n, strain_ctrl[n][i] = 1 prescribes the mean strain component i to
+ * target[n][i] at the end of the step; 0 prescribes the mean stress. */
+typedef struct cpf_path {
+    int n_steps;
+    const double *t;
+    const uint8_t *strain_ctrl;
+    const double *target;
+} cpf_path;
+
+/* Per-step results (Section 5 measures): mean stress and strain, von Mises
+ * of the mean stress, mean of the local von Mises stress, mean accumulated
+ * slip over slip systems, mean twin fraction over twin systems. */
+typedef struct cpf_step_out {
+    double Sigma[6], E[6];
+    double sig_eq_of_mean, mean_sig_eq, mean_v, mean_f;
+    double err_eq, err_bc;
+    int iters;        /* constitutive evaluations (fixed-point iterations) */
+    int status;       /* CPF_OK, CPF_E_NOT_CONVERGED or CPF_E_NAN          */
+} cpf_step_out;
+
+typedef struct cpf_problem cpf_problem;
+typedef struct cpf_solver cpf_solver;
+
+int cpf_version(void);
+const char *cpf_error_string(int code);
+const char *cpf_last_error_message(void);
+void cpf_options_default(cpf_options *opt);
+
+/* Validate and copy a problem (host only, no device work). */
+int cpf_problem_create(const cpf_problem_desc *desc, cpf_problem **out);
+void cpf_problem_destroy(cpf_problem *p);
+/* Isotropic reference medium chosen for the problem's crystal stiffness:
+ * k0 = (1/9) 1:C:1, mu0 = mean of the extreme deviatoric shear moduli,
+ * lam0 = k0 - 2 mu0/3. */
+int cpf_problem_reference_medium(const cpf_problem *p, double *lam0, double *mu0);
+
+/* Solver: creation is host only; bind uploads the problem to the caller's
+ * workspace on the caller's stream (hipStream_t, NULL = default). */
+int cpf_solver_create(const cpf_problem *p, const cpf_options *opt, cpf_solver **out);
+int cpf_solver_workspace_size(const cpf_solver *s, size_t *bytes);
+int cpf_solver_bind(cpf_solver *s, void *dev_workspace, size_t bytes, void *hip_stream);
+/* Return to the undeformed, stress-free state at t = 0. */
+int cpf_solver_reset(cpf_solver *s);
+/* Run load step n of the path from the committed state (the caller runs
+ * steps in order); fills *out.  Synchronous. */
+int cpf_solver_step(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *out);
+/* All steps of the path from the current state; out has n_steps entries. */
+int cpf_solver_run(cpf_solver *s, const cpf_path *path, cpf_step_out *out);
+/* Copy a committed local field into dev_out, [ncomp][nz][ny][nx] in the
+ * solver's precision (float or double). */
+int cpf_solver_field(cpf_solver *s, int field, void *dev_out);
+void cpf_solver_destroy(cpf_solver *s);
+
+/* Component operators on the bound solver, for parity checks of single
+ * steps of the iteration.  Device arrays in the solver's precision.
+ * fields [c][nz][ny][nx]; spectra complex [c][nz][ny][nx/2+1] (re, im). */
+/* Forward 3D DFT (unnormalized) of 6 real fields: spec = F[field]. */
+int cpf_op_forward_fft(cpf_solver *s, const void *dev_field, void *dev_spec);
+/* One Green-operator application: out = F^-1[Gamma0(xi) : spec](x), with
+ * Gamma0 = 0 at xi = 0 and at frequencies with a Nyquist component, plus
+ * *err2 = sum over controlled frequencies of |spec(xi).xi_hat|^2.  The
+ * input spectrum is consumed (overwritten). */
+int cpf_op_green(cpf_solver *s, void *dev_spec, void *dev_out, double *err2);
+/* Local law over one increment for every voxel: total strain linear in
+ * time from eps0 to eps1, internal variables state0 -> state1 by RK4 with
+ * M substeps.  state = [6 + 2 n_sys][nvox]: plastic strain (lab frame,
+ * tensor components), accumulated slip v[n_sys], back strain alpha[n_sys].
+ * sig1 = C_lab:(eps1 - eps_p). */
+int cpf_op_constitutive(cpf_solver *s, const void *dev_eps0, const void *dev_eps1,
+                        const void *dev_state0, void *dev_state1, void *dev_sig1,
+                        double dt, int M);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CPFFT_H */

@@ -1,0 +1,239 @@
+"""MI355X Green-operator FFT solver for voxelized polycrystals with the
+regularized Meric-Cailletaud crystal-plasticity law.
+
+Thin Python layer over the C-ABI library ``libcpfft.so`` (declared in
+``include/cpfft.h``): argument marshalling only.  Device memory and streams
+come from PyTorch; every step of the solve runs in the library's HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import numpy as np
+
+from . import _lib
+from ._lib import (CPF_FIELD_ACC_SLIP, CPF_FIELD_BACK_STRAIN, CPF_FIELD_PLASTIC_STRAIN,
+                   CPF_FIELD_STRAIN, CPF_FIELD_STRESS, CPF_PREC_FP32, CPF_PREC_FP64,
+                   CpfError, check)
+
+FIELDS = {
+    "stress": CPF_FIELD_STRESS,
+    "strain": CPF_FIELD_STRAIN,
+    "plastic_strain": CPF_FIELD_PLASTIC_STRAIN,
+    "acc_slip": CPF_FIELD_ACC_SLIP,
+    "back_strain": CPF_FIELD_BACK_STRAIN,
+}
+
+__all__ = ["Problem", "Solver", "CpfError", "FIELDS", "version"]
+
+
+def version() -> int:
+    return _lib.lib().cpf_version()
+
+
+def _f64(a, shape=None):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    if shape is not None:
+        a = a.reshape(shape)
+    return a
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+class Problem:
+    """Grain-label grid, orientations, stiffness, systems and law parameters.
+
+    labels: int [nz][ny][nx]; euler: [n_labels][3] Bunge radians;
+    C_voigt: 6x6 Voigt stiffness (MPa); n_miller, l_miller: [S][3];
+    family: [S] (0 slip, 1 twin); tau0: [S] (MPa); law: object with
+    ``slip``/``twin`` (Q, b, c, d, K, n, q_self, q_latent), ``twin_mode``,
+    ``K_c``, ``f_m``, ``gamma_T``, ``eta``.
+    """
+
+    def __init__(self, labels, euler, C_voigt, n_miller, l_miller, family, tau0, law):
+        L = _lib.lib()
+        self.labels = np.ascontiguousarray(np.asarray(labels, dtype=np.int32))
+        if self.labels.ndim != 3:
+            raise ValueError("labels must be a 3D [nz][ny][nx] array")
+        self.shape = self.labels.shape
+        self.euler = _f64(euler).reshape(-1, 3)
+        self.n_miller = _f64(n_miller).reshape(-1, 3)
+        self.l_miller = _f64(l_miller).reshape(-1, 3)
+        self.family = np.ascontiguousarray(np.asarray(family, dtype=np.int32))
+        self.tau0 = _f64(tau0)
+        self.n_sys = int(self.family.shape[0])
+        self.law = law
+        d = _lib.CpfProblemDesc()
+        d.nz, d.ny, d.nx = self.shape
+        d.labels = _ptr(self.labels, ctypes.c_int32)
+        d.n_labels = int(self.euler.shape[0])
+        d.euler = _ptr(self.euler, ctypes.c_double)
+        C = _f64(C_voigt).reshape(36)
+        for i in range(36):
+            d.C_crystal[i] = C[i]
+        d.n_sys = self.n_sys
+        d.n_miller = _ptr(self.n_miller, ctypes.c_double)
+        d.l_miller = _ptr(self.l_miller, ctypes.c_double)
+        d.family = _ptr(self.family, ctypes.c_int32)
+        d.tau0 = _ptr(self.tau0, ctypes.c_double)
+        for k, fam in enumerate((law.slip, law.twin)):
+            for name in ("Q", "b", "c", "d", "K", "n", "q_self", "q_latent"):
+                setattr(d.law[k], name, float(getattr(fam, name)))
+        d.twin_mode = int(law.twin_mode)
+        d.K_c, d.f_m, d.gamma_T, d.eta = (float(law.K_c), float(law.f_m),
+                                          float(law.gamma_T), float(law.eta))
+        h = ctypes.c_void_p()
+        check(L.cpf_problem_create(ctypes.byref(d), ctypes.byref(h)))
+        self._h = h
+        self.n_slip = int((self.family == 0).sum())
+        self.n_twin = int((self.family == 1).sum())
+
+    @classmethod
+    def from_workload(cls, w) -> "Problem":
+        return cls(w.rve.labels, w.rve.euler, w.C, w.systems.n_miller, w.systems.l_miller,
+                   w.systems.family, w.systems.tau0, w.law)
+
+    def reference_medium(self) -> tuple[float, float]:
+        lam, mu = ctypes.c_double(), ctypes.c_double()
+        check(_lib.lib().cpf_problem_reference_medium(self._h, ctypes.byref(lam), ctypes.byref(mu)))
+        return lam.value, mu.value
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.lib().cpf_problem_destroy(h)
+            self._h = None
+
+
+class _PathArgs:
+    """Keeps the numpy buffers of a cpf_path alive for one call."""
+
+    def __init__(self, path):
+        self.t = _f64(path.t)
+        self.ctrl = np.ascontiguousarray(np.asarray(path.strain_ctrl, dtype=np.uint8))
+        self.target = _f64(path.target)
+        n = int(self.target.shape[0])
+        if self.t.shape[0] != n + 1 or self.ctrl.shape != (n, 6) or self.target.shape != (n, 6):
+            raise ValueError("path arrays must be t[n+1], strain_ctrl[n][6], target[n][6]")
+        self.c = _lib.CpfPath(n, _ptr(self.t, ctypes.c_double), _ptr(self.ctrl, ctypes.c_uint8),
+                              _ptr(self.target, ctypes.c_double))
+        self.n = n
+
+
+def _outs_to_dict(outs, n):
+    keys = ("sig_eq_of_mean", "mean_sig_eq", "mean_v", "mean_f", "err_eq", "err_bc")
+    r = {"Sigma": np.array([list(outs[i].Sigma) for i in range(n)]).reshape(n, 6),
+         "E": np.array([list(outs[i].E) for i in range(n)]).reshape(n, 6),
+         "iters": np.array([outs[i].iters for i in range(n)], dtype=np.int64),
+         "status": np.array([outs[i].status for i in range(n)], dtype=np.int64)}
+    for k in keys:
+        r[k] = np.array([getattr(outs[i], k) for i in range(n)])
+    return r
+
+
+class Solver:
+    """A bound solver: device workspace from torch, work on a torch stream."""
+
+    def __init__(self, problem: Problem, precision: str = "fp64", tol: float = 1e-8,
+                 max_iter: int = 1000, h_max: float = 0.05, rk4_M: int = 0,
+                 lam0: Optional[float] = None, mu0: Optional[float] = None,
+                 stag_tol: float = 0.0, check_every: int = 0, device: str = "cuda:0",
+                 stream=None):
+        import torch
+        L = _lib.lib()
+        self.problem = problem
+        self.precision = precision
+        self.dtype = {"fp64": torch.float64, "fp32": torch.float32}[precision]
+        o = _lib.CpfOptions()
+        L.cpf_options_default(ctypes.byref(o))
+        o.precision = CPF_PREC_FP64 if precision == "fp64" else CPF_PREC_FP32
+        o.tol, o.max_iter, o.h_max, o.rk4_M = float(tol), int(max_iter), float(h_max), int(rk4_M)
+        if mu0 is not None:
+            o.lam0, o.mu0 = float(lam0), float(mu0)
+        o.stag_tol, o.check_every = float(stag_tol), int(check_every)
+        h = ctypes.c_void_p()
+        check(L.cpf_solver_create(problem._h, ctypes.byref(o), ctypes.byref(h)))
+        self._h = h
+        size = ctypes.c_size_t()
+        check(L.cpf_solver_workspace_size(h, ctypes.byref(size)))
+        self.device = torch.device(device)
+        self.workspace = torch.empty(int(size.value) + 256, dtype=torch.uint8, device=self.device)
+        base = self.workspace.data_ptr()
+        self._ws_ptr = (base + 255) & ~255
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        check(L.cpf_solver_bind(h, ctypes.c_void_p(self._ws_ptr), int(size.value),
+                                ctypes.c_void_p(self.stream.cuda_stream)))
+        self.nz, self.ny, self.nx = problem.shape
+        self.nvox = self.nx * self.ny * self.nz
+        self.nhx = self.nx // 2 + 1
+
+    # -- solve ---------------------------------------------------------------
+    def reset(self):
+        check(_lib.lib().cpf_solver_reset(self._h))
+
+    def run(self, path) -> dict:
+        pa = _PathArgs(path)
+        outs = (_lib.CpfStepOut * pa.n)()
+        check(_lib.lib().cpf_solver_run(self._h, ctypes.byref(pa.c), outs))
+        return _outs_to_dict(outs, pa.n)
+
+    def step(self, path, n: int) -> dict:
+        pa = _PathArgs(path)
+        out = (_lib.CpfStepOut * 1)()
+        check(_lib.lib().cpf_solver_step(self._h, ctypes.byref(pa.c), int(n), out))
+        return {k: v[0] for k, v in _outs_to_dict(out, 1).items()}
+
+    def field(self, name: str):
+        """Committed local field as a torch tensor [ncomp][nz][ny][nx]."""
+        import torch
+        k = FIELDS[name]
+        nc = 6 if k in (CPF_FIELD_STRESS, CPF_FIELD_STRAIN, CPF_FIELD_PLASTIC_STRAIN) \
+            else self.problem.n_sys
+        out = torch.empty((nc, self.nz, self.ny, self.nx), dtype=self.dtype, device=self.device)
+        check(_lib.lib().cpf_solver_field(self._h, k, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    # -- component operators ---------------------------------------------------
+    def forward_fft(self, f):
+        """Unnormalized 3D DFT of 6 real fields [6][nz][ny][nx] -> complex
+        half spectrum [6][nz][ny][nx/2+1] (torch complex tensor)."""
+        import torch
+        f = f.to(device=self.device, dtype=self.dtype).contiguous()
+        spec = torch.empty((6, self.nz, self.ny, self.nhx, 2), dtype=self.dtype, device=self.device)
+        check(_lib.lib().cpf_op_forward_fft(self._h, ctypes.c_void_p(f.data_ptr()),
+                                            ctypes.c_void_p(spec.data_ptr())))
+        return torch.view_as_complex(spec)
+
+    def green(self, spec):
+        """F^-1[Gamma0 : spec] on the grid and the residual sum.  `spec` is a
+        complex half spectrum; a copy is consumed."""
+        import torch
+        s = torch.view_as_real(spec.to(self.device)).to(self.dtype).contiguous().clone()
+        out = torch.empty((6, self.nz, self.ny, self.nx), dtype=self.dtype, device=self.device)
+        err2 = ctypes.c_double()
+        check(_lib.lib().cpf_op_green(self._h, ctypes.c_void_p(s.data_ptr()),
+                                      ctypes.c_void_p(out.data_ptr()), ctypes.byref(err2)))
+        return out, err2.value
+
+    def constitutive(self, eps0, eps1, state0, dt: float, M: int):
+        """Local law over one increment at every voxel (device arrays)."""
+        import torch
+        D = 6 + 2 * self.problem.n_sys
+        args = [t.to(device=self.device, dtype=self.dtype).contiguous()
+                for t in (eps0, eps1, state0)]
+        assert args[0].numel() == 6 * self.nvox and args[2].numel() == D * self.nvox
+        st1 = torch.empty((D, self.nz, self.ny, self.nx), dtype=self.dtype, device=self.device)
+        sig = torch.empty((6, self.nz, self.ny, self.nx), dtype=self.dtype, device=self.device)
+        check(_lib.lib().cpf_op_constitutive(
+            self._h, *[ctypes.c_void_p(a.data_ptr()) for a in args],
+            ctypes.c_void_p(st1.data_ptr()), ctypes.c_void_p(sig.data_ptr()), float(dt), int(M)))
+        return st1, sig
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.lib().cpf_solver_destroy(h)
+            self._h = None

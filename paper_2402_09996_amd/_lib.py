@@ -1,0 +1,127 @@
+"""ctypes binding of ``libcpfft.so`` (argument marshalling only).
+
+The library must have been built in-tree (``__graft_entry__.build()`` or
+``python paper_2402_09996_amd/build.py``); there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libcpfft.so")
+
+CPF_OK = 0
+CPF_E_INVALID_ARG = -1
+CPF_E_WORKSPACE = -2
+CPF_E_HIP = -3
+CPF_E_NOT_CONVERGED = -4
+CPF_E_NAN = -5
+CPF_E_UNSUPPORTED_SIZE = -6
+CPF_E_BAD_STATE = -7
+
+CPF_PREC_FP64 = 0
+CPF_PREC_FP32 = 1
+
+CPF_FIELD_STRESS = 0
+CPF_FIELD_STRAIN = 1
+CPF_FIELD_PLASTIC_STRAIN = 2
+CPF_FIELD_ACC_SLIP = 3
+CPF_FIELD_BACK_STRAIN = 4
+
+CPF_MAX_SYSTEMS = 32
+
+_d = ctypes.c_double
+_i = ctypes.c_int
+_p = ctypes.c_void_p
+_dp = ctypes.POINTER(ctypes.c_double)
+_ip = ctypes.POINTER(ctypes.c_int32)
+_u8p = ctypes.POINTER(ctypes.c_uint8)
+
+
+class CpfLaw(ctypes.Structure):
+    _fields_ = [(n, _d) for n in ("Q", "b", "c", "d", "K", "n", "q_self", "q_latent")]
+
+
+class CpfProblemDesc(ctypes.Structure):
+    _fields_ = [
+        ("nx", _i), ("ny", _i), ("nz", _i),
+        ("labels", _ip), ("n_labels", _i), ("euler", _dp),
+        ("C_crystal", _d * 36), ("n_sys", _i),
+        ("n_miller", _dp), ("l_miller", _dp), ("family", _ip), ("tau0", _dp),
+        ("law", CpfLaw * 2), ("twin_mode", _i),
+        ("K_c", _d), ("f_m", _d), ("gamma_T", _d), ("eta", _d),
+    ]
+
+
+class CpfOptions(ctypes.Structure):
+    _fields_ = [
+        ("precision", _i), ("tol", _d), ("max_iter", _i), ("h_max", _d),
+        ("rk4_M", _i), ("lam0", _d), ("mu0", _d), ("stag_tol", _d),
+        ("check_every", _i),
+    ]
+
+
+class CpfPath(ctypes.Structure):
+    _fields_ = [("n_steps", _i), ("t", _dp), ("strain_ctrl", _u8p), ("target", _dp)]
+
+
+class CpfStepOut(ctypes.Structure):
+    _fields_ = [
+        ("Sigma", _d * 6), ("E", _d * 6),
+        ("sig_eq_of_mean", _d), ("mean_sig_eq", _d), ("mean_v", _d), ("mean_f", _d),
+        ("err_eq", _d), ("err_bc", _d), ("iters", _i), ("status", _i),
+    ]
+
+
+# name -> (restype, argtypes); every symbol include/cpfft.h declares
+SIGNATURES = {
+    "cpf_version": (_i, []),
+    "cpf_error_string": (ctypes.c_char_p, [_i]),
+    "cpf_last_error_message": (ctypes.c_char_p, []),
+    "cpf_options_default": (None, [ctypes.POINTER(CpfOptions)]),
+    "cpf_problem_create": (_i, [ctypes.POINTER(CpfProblemDesc), ctypes.POINTER(_p)]),
+    "cpf_problem_destroy": (None, [_p]),
+    "cpf_problem_reference_medium": (_i, [_p, _dp, _dp]),
+    "cpf_solver_create": (_i, [_p, ctypes.POINTER(CpfOptions), ctypes.POINTER(_p)]),
+    "cpf_solver_workspace_size": (_i, [_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "cpf_solver_bind": (_i, [_p, _p, ctypes.c_size_t, _p]),
+    "cpf_solver_reset": (_i, [_p]),
+    "cpf_solver_step": (_i, [_p, ctypes.POINTER(CpfPath), _i, ctypes.POINTER(CpfStepOut)]),
+    "cpf_solver_run": (_i, [_p, ctypes.POINTER(CpfPath), ctypes.POINTER(CpfStepOut)]),
+    "cpf_solver_field": (_i, [_p, _i, _p]),
+    "cpf_solver_destroy": (None, [_p]),
+    "cpf_op_forward_fft": (_i, [_p, _p, _p]),
+    "cpf_op_green": (_i, [_p, _p, _p, _dp]),
+    "cpf_op_constitutive": (_i, [_p, _p, _p, _p, _p, _p, _d, _i]),
+}
+
+_lib = None
+
+
+class CpfError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("cpfft error %d: %s" % (code, msg))
+        self.code = code
+
+
+def lib():
+    """Load the in-tree HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libcpfft.so is not built: run __graft_entry__.build() "
+                              "or python paper_2402_09996_amd/build.py")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def check(code: int):
+    if code != CPF_OK:
+        raise CpfError(code, lib().cpf_last_error_message().decode())
+    return code

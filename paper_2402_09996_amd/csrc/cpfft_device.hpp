@@ -1,0 +1,461 @@
+// Device building blocks for the gfx950 solver: complex arithmetic, an
+// LDS-resident mixed-radix (2,3,4,8) Stockham FFT, the regularized
+// Meric-Cailletaud rate with RK4 substepping, and FP64 block reductions.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace cpf {
+
+constexpr int NSMAX = 32;    // systems per crystal
+constexpr int MAXPASS = 12;  // radix passes per 1D transform
+constexpr int NPX = 9;       // per-block FP64 sums of the x pass
+
+template <typename R>
+struct alignas(2 * sizeof(R)) C2 {
+    R x, y;
+};
+
+template <typename R>
+__device__ __forceinline__ C2<R> cadd(C2<R> a, C2<R> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename R>
+__device__ __forceinline__ C2<R> csub(C2<R> a, C2<R> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename R>
+__device__ __forceinline__ C2<R> cmul(C2<R> a, C2<R> b)
+{
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+// multiply by -i (forward sign) or +i (inverse sign)
+template <typename R, bool INV>
+__device__ __forceinline__ C2<R> rot90(C2<R> a)
+{
+    return INV ? C2<R>{-a.y, a.x} : C2<R>{a.y, -a.x};
+}
+
+struct FftPlan {
+    int n;
+    int npass;
+    int radix[MAXPASS];
+};
+
+// ---------------------------------------------------------------------------
+// Small DFTs.  Forward uses exp(-2 pi i pq / r), inverse exp(+2 pi i pq / r).
+// ---------------------------------------------------------------------------
+template <typename R, bool INV>
+__device__ __forceinline__ void dft2(C2<R> *v)
+{
+    C2<R> a = v[0], b = v[1];
+    v[0] = cadd(a, b);
+    v[1] = csub(a, b);
+}
+
+template <typename R, bool INV>
+__device__ __forceinline__ void dft3(C2<R> *v)
+{
+    const R h = R(0.5), s3 = R(0.866025403784438646763723170752936183);
+    C2<R> a = v[0], bc = cadd(v[1], v[2]), d = csub(v[1], v[2]);
+    C2<R> t = {a.x - h * bc.x, a.y - h * bc.y};
+    C2<R> s = {s3 * d.x, s3 * d.y};
+    v[0] = cadd(a, bc);
+    C2<R> ms = rot90<R, INV>(s);  // -i s (forward) / +i s (inverse)
+    v[1] = cadd(t, ms);
+    v[2] = csub(t, ms);
+}
+
+template <typename R, bool INV>
+__device__ __forceinline__ void dft4(C2<R> *v)
+{
+    C2<R> t0 = cadd(v[0], v[2]), t1 = csub(v[0], v[2]);
+    C2<R> t2 = cadd(v[1], v[3]), t3 = rot90<R, INV>(csub(v[1], v[3]));
+    v[0] = cadd(t0, t2);
+    v[2] = csub(t0, t2);
+    v[1] = cadd(t1, t3);
+    v[3] = csub(t1, t3);
+}
+
+template <typename R, bool INV>
+__device__ __forceinline__ void dft8(C2<R> *v)
+{
+    const R c = R(0.707106781186547524400844362104849039);
+    C2<R> e[4] = {v[0], v[2], v[4], v[6]};
+    C2<R> o[4] = {v[1], v[3], v[5], v[7]};
+    dft4<R, INV>(e);
+    dft4<R, INV>(o);
+    // o[p] *= w8^p (forward w8 = exp(-i pi/4); inverse: conjugate)
+    C2<R> o1 = INV ? C2<R>{c * (o[1].x - o[1].y), c * (o[1].x + o[1].y)}
+                   : C2<R>{c * (o[1].x + o[1].y), c * (o[1].y - o[1].x)};
+    C2<R> o2 = rot90<R, INV>(o[2]);
+    C2<R> o3 = INV ? C2<R>{-c * (o[3].x + o[3].y), c * (o[3].x - o[3].y)}
+                   : C2<R>{c * (o[3].y - o[3].x), -c * (o[3].x + o[3].y)};
+    v[0] = cadd(e[0], o[0]);
+    v[4] = csub(e[0], o[0]);
+    v[1] = cadd(e[1], o1);
+    v[5] = csub(e[1], o1);
+    v[2] = cadd(e[2], o2);
+    v[6] = csub(e[2], o2);
+    v[3] = cadd(e[3], o3);
+    v[7] = csub(e[3], o3);
+}
+
+template <typename R, bool INV, int RAD>
+__device__ __forceinline__ void dft(C2<R> *v)
+{
+    if constexpr (RAD == 2) dft2<R, INV>(v);
+    else if constexpr (RAD == 3) dft3<R, INV>(v);
+    else if constexpr (RAD == 4) dft4<R, INV>(v);
+    else dft8<R, INV>(v);
+}
+
+// ---------------------------------------------------------------------------
+// One Stockham pass over `nlines` transforms of length N held in LDS (line
+// stride ls).  Every thread first pulls all inputs of its butterflies into
+// registers, the block synchronizes, then the results are written back in
+// place at their autosorted positions.  MAXB bounds the butterflies per
+// thread: nlines*N/RAD <= MAXB*nthr must hold.
+// tw[k] = exp(-2 pi i k / N).
+// ---------------------------------------------------------------------------
+template <typename R, bool INV, int RAD, int MAXB>
+__device__ __forceinline__ void fft_pass(C2<R> *buf, int nlines, int ls, int N, int Ns,
+                                         const C2<R> *__restrict__ tw, int tid, int nthr)
+{
+    const int m = N / RAD;
+    const int nb = nlines * m;
+    const int tstride = N / (Ns * RAD);
+    C2<R> v[MAXB][RAD];
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+        const int i = tid + b * nthr;
+        if (i < nb) {
+            const int line = i / m, j = i - line * m;
+            const C2<R> *src = buf + line * ls + j;
+#pragma unroll
+            for (int q = 0; q < RAD; ++q) v[b][q] = src[q * m];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int b = 0; b < MAXB; ++b) {
+        const int i = tid + b * nthr;
+        if (i < nb) {
+            const int line = i / m, j = i - line * m;
+            const int k = j % Ns;
+            if (k) {
+#pragma unroll
+                for (int q = 1; q < RAD; ++q) {
+                    C2<R> w = tw[q * k * tstride];
+                    if (INV) w.y = -w.y;
+                    v[b][q] = cmul(v[b][q], w);
+                }
+            }
+            dft<R, INV, RAD>(v[b]);
+            C2<R> *dst = buf + line * ls + (j - k) * RAD + k;
+#pragma unroll
+            for (int q = 0; q < RAD; ++q) dst[q * Ns] = v[b][q];
+        }
+    }
+    __syncthreads();
+}
+
+// Full 1D transforms of nlines sequences in LDS.  EPT bounds the elements
+// per thread: nlines*N <= EPT*nthr.  Must be called by every thread of the
+// block (it synchronizes).
+template <typename R, bool INV, int EPT>
+__device__ void lds_fft(C2<R> *buf, int nlines, int ls, const FftPlan &P,
+                        const C2<R> *__restrict__ tw, int tid, int nthr)
+{
+    int Ns = 1;
+    for (int p = 0; p < P.npass; ++p) {
+        const int r = P.radix[p];
+        if (r == 8)
+            fft_pass<R, INV, 8, (EPT + 7) / 8>(buf, nlines, ls, P.n, Ns, tw, tid, nthr);
+        else if (r == 4)
+            fft_pass<R, INV, 4, (EPT + 3) / 4>(buf, nlines, ls, P.n, Ns, tw, tid, nthr);
+        else if (r == 3)
+            fft_pass<R, INV, 3, (EPT + 2) / 3>(buf, nlines, ls, P.n, Ns, tw, tid, nthr);
+        else
+            fft_pass<R, INV, 2, (EPT + 1) / 2>(buf, nlines, ls, P.n, Ns, tw, tid, nthr);
+        Ns *= r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// FP64 block reductions (deterministic: fixed shuffle tree, then fixed
+// order over waves).  Block size <= 1024, wave64.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+template <int NV>
+__device__ void block_sum(double (&v)[NV], double *out /* NV values, thread 0 */)
+{
+    __shared__ double red[16][NV];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nw = (blockDim.x + 63) >> 6;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < NV; ++i) red[wid][i] = v[i];
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0.0;
+        for (int w = 0; w < nw; ++w) s += red[w][threadIdx.x];
+        out[threadIdx.x] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric tensors as tensor components (11,22,33,23,13,12).
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void sym_full(const R a[6], R A[3][3])
+{
+    A[0][0] = a[0]; A[1][1] = a[1]; A[2][2] = a[2];
+    A[1][2] = A[2][1] = a[3];
+    A[0][2] = A[2][0] = a[4];
+    A[0][1] = A[1][0] = a[5];
+}
+
+// out = Q^T a Q  (lab -> crystal when v_lab = Q v_crystal)
+template <typename R>
+__device__ __forceinline__ void rot_to_crystal(const R Q[9], const R a[6], R out[6])
+{
+    R A[3][3], T[3][3];
+    sym_full(a, A);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            T[i][j] = A[i][0] * Q[0 * 3 + j] + A[i][1] * Q[1 * 3 + j] + A[i][2] * Q[2 * 3 + j];
+    // out_ij = sum_k Q_ki T_kj
+    const int I[6] = {0, 1, 2, 1, 0, 0}, J[6] = {0, 1, 2, 2, 2, 1};
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+        out[c] = Q[0 * 3 + I[c]] * T[0][J[c]] + Q[1 * 3 + I[c]] * T[1][J[c]] +
+                 Q[2 * 3 + I[c]] * T[2][J[c]];
+}
+
+// out = Q a Q^T  (crystal -> lab)
+template <typename R>
+__device__ __forceinline__ void rot_to_lab(const R Q[9], const R a[6], R out[6])
+{
+    R A[3][3], T[3][3];
+    sym_full(a, A);
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            T[i][j] = A[i][0] * Q[j * 3 + 0] + A[i][1] * Q[j * 3 + 1] + A[i][2] * Q[j * 3 + 2];
+    // out_ij = sum_k Q_ik T_kj
+    const int I[6] = {0, 1, 2, 1, 0, 0}, J[6] = {0, 1, 2, 2, 2, 1};
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+        out[c] = Q[I[c] * 3 + 0] * T[0][J[c]] + Q[I[c] * 3 + 1] * T[1][J[c]] +
+                 Q[I[c] * 3 + 2] * T[2][J[c]];
+}
+
+template <typename R>
+__device__ __forceinline__ R von_mises(const R s[6])
+{
+    const R p = (s[0] + s[1] + s[2]) * R(1.0 / 3.0);
+    const R a = s[0] - p, b = s[1] - p, c = s[2] - p;
+    return sqrt(R(1.5) * (a * a + b * b + c * c + R(2) * (s[3] * s[3] + s[4] * s[4] + s[5] * s[5])));
+}
+
+// ---------------------------------------------------------------------------
+// Law parameters, crystal frame (uniform over the grid: kernel arguments).
+// Per-family values are separate scalar fields so that the family of a
+// system (a uniform bit) selects them without indexing into the argument
+// block.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct FamP {
+    R QL;      // Q * q_latent
+    R QD;      // Q * (q_self - q_latent)
+    R bl2e;    // b * log2(e)
+    R c, d;    // kinematic hardening
+    R K, invK, n, inv_n, nm1;
+};
+
+template <typename R>
+struct LawP {
+    int nsys;
+    int twin_mode;        // 0 Norton, 1 paper twin-fraction law
+    uint32_t twin_mask;   // bit s set: system s is a twin system
+    R C[36];              // sigma_I = sum_J C[I][J] eps_J on tensor components
+    R m[NSMAX][6];        // Schmid tensors, tensor components
+    R tau0[NSMAX];
+    FamP<R> fs, ft;       // slip, twin
+    R Kc_gT, fm, inv_gT, eta, inv_eta;
+    R newton_rtol;
+};
+
+// Math in the working precision (FP32: hardware exp2/log2/rcp).
+__device__ __forceinline__ float lg2(float x) { return __log2f(x); }
+__device__ __forceinline__ double lg2(double x) { return log2(x); }
+__device__ __forceinline__ float ex2(float x) { return exp2f(x); }
+__device__ __forceinline__ double ex2(double x) { return exp2(x); }
+__device__ __forceinline__ float fdiv(float a, float b) { return __fdividef(a, b); }
+__device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
+
+// Regularized Norton rate: g = A y^n, y > 0 the root of K y + eta A y^n = o
+// (equations 5/6 with the yield stress raised by eta |g|).  Newton from the
+// smaller of the two upper bounds o/K and (o/(eta A))^(1/n) decreases
+// monotonically onto the root.
+template <typename R>
+__device__ __forceinline__ R reg_rate(R o, R A, R inv_etaA, R etaA, R K, R invK, R n, R inv_n, R nm1,
+                                      R rtol)
+{
+    if (!(o > R(0)) || !(A > R(0))) return R(0);
+    R y = ex2(lg2(o * inv_etaA) * inv_n);
+    const R yk = o * invK;
+    y = yk < y ? yk : y;
+    for (int it = 0; it < 40; ++it) {
+        const R yn1 = ex2(nm1 * lg2(y));
+        const R phi = K * y + etaA * yn1 * y - o;
+        const R dphi = K + etaA * n * yn1;
+        const R step = fdiv(phi, dphi);
+        y -= step;
+        if (fabs(step) <= rtol * y) break;
+    }
+    return A * ex2(n * lg2(y));
+}
+
+// One RK4 stage of the internal variables in the crystal frame.  Inputs:
+// total strain e at the stage time and the stage state t* (overwritten with
+// the next stage state y + cnext*k when has_next); the stage slope k is
+// accumulated into a* with weight wacc.
+template <typename R, int NS>
+__device__ __forceinline__ void rk_stage(const LawP<R> &P, const R e[6], R (&tep)[6], R (&tv)[NS],
+                                         R (&tal)[NS], const R (&yep)[6], const R (&yv)[NS],
+                                         const R (&yal)[NS], R (&aep)[6], R (&av)[NS],
+                                         R (&aal)[NS], R wacc, R cnext, bool has_next)
+{
+    R ee[6], sig[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) ee[i] = e[i] - tep[i];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        R s = R(0);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) s += P.C[i * 6 + j] * ee[j];
+        sig[i] = s;
+    }
+    // saturating hardening terms and family sums (equation 4)
+    R h[NS];
+    R Hs = R(0), Ht = R(0), sumf = R(0);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const bool tw = (P.twin_mask >> s) & 1u;
+        const R bl = tw ? P.ft.bl2e : P.fs.bl2e;
+        h[s] = R(1) - ex2(-bl * tv[s]);
+        if (tw) {
+            Ht += h[s];
+            sumf += tv[s] * P.inv_gT;
+        } else {
+            Hs += h[s];
+        }
+    }
+    const R wslip = R(1) - sumf;
+    // twin rate prefactor A (paper mode) and its regularization scale
+    const R Atw = P.twin_mode ? P.Kc_gT * (P.fm - sumf) : R(1);
+    const R etaAtw = P.eta * Atw;
+    const R inv_etaAtw = P.twin_mode ? fdiv(R(1), etaAtw) : P.inv_eta;
+    R dep[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const bool tw = (P.twin_mask >> s) & 1u;
+        const R QL = tw ? P.ft.QL : P.fs.QL, QD = tw ? P.ft.QD : P.fs.QD;
+        const R c = tw ? P.ft.c : P.fs.c, d = tw ? P.ft.d : P.fs.d;
+        const R K = tw ? P.ft.K : P.fs.K, invK = tw ? P.ft.invK : P.fs.invK;
+        const R n = tw ? P.ft.n : P.fs.n, inv_n = tw ? P.ft.inv_n : P.fs.inv_n;
+        const R nm1 = tw ? P.ft.nm1 : P.fs.nm1;
+        const R r = P.tau0[s] + QL * (tw ? Ht : Hs) + QD * h[s];
+        const R tau = sig[0] * P.m[s][0] + sig[1] * P.m[s][1] + sig[2] * P.m[s][2] +
+                      R(2) * (sig[3] * P.m[s][3] + sig[4] * P.m[s][4] + sig[5] * P.m[s][5]);
+        const R tx = tau - c * tal[s];
+        R gd;
+        if (tw) {
+            gd = reg_rate<R>(tx - r, Atw, inv_etaAtw, etaAtw, K, invK, n, inv_n, nm1, P.newton_rtol);
+        } else {
+            const R g = reg_rate<R>(fabs(tx) - r, R(1), P.inv_eta, P.eta, K, invK, n, inv_n, nm1,
+                                    P.newton_rtol);
+            gd = tx >= R(0) ? g : -g;
+        }
+        const R ag = fabs(gd);
+        const R dal = gd - d * ag * tal[s];
+        av[s] += wacc * ag;
+        aal[s] += wacc * dal;
+        if (has_next) {
+            tv[s] = yv[s] + cnext * ag;
+            tal[s] = yal[s] + cnext * dal;
+        }
+        const R wg = tw ? gd : wslip * gd;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) dep[i] += wg * P.m[s][i];
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        aep[i] += wacc * dep[i];
+        if (has_next) tep[i] = yep[i] + cnext * dep[i];
+    }
+}
+
+// Integrate the internal variables over one load increment (crystal frame):
+// total strain linear in time from e0 to e1, M classical RK4 substeps.
+template <typename R, int NS>
+__device__ void integrate(const LawP<R> &P, const R e0[6], const R e1[6], R (&ep)[6], R (&v)[NS],
+                          R (&al)[NS], R dt, int M)
+{
+    const R h = dt / R(M);
+    const R invM = R(1) / R(M);
+    R de[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) de[i] = e1[i] - e0[i];
+#pragma unroll 1
+    for (int j = 0; j < M; ++j) {
+        R tep[6], tv[NS], tal[NS], aep[6], av[NS], aal[NS];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) tep[i] = aep[i] = ep[i];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            tv[s] = av[s] = v[s];
+            tal[s] = aal[s] = al[s];
+        }
+#pragma unroll 1
+        for (int st = 0; st < 4; ++st) {
+            const R sfrac = (st == 0) ? R(j) * invM : (st == 3) ? R(j + 1) * invM : (R(j) + R(0.5)) * invM;
+            const R wacc = (st == 0 || st == 3) ? h * R(1.0 / 6.0) : h * R(1.0 / 3.0);
+            const R cnext = (st == 2) ? h : h * R(0.5);
+            R e[6];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) e[i] = e0[i] + sfrac * de[i];
+            rk_stage<R, NS>(P, e, tep, tv, tal, ep, v, al, aep, av, aal, wacc, cnext, st < 3);
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) ep[i] = aep[i];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            v[s] = av[s];
+            al[s] = aal[s];
+        }
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void hooke(const LawP<R> &P, const R e[6], const R ep[6], R sig[6])
+{
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        R s = R(0);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) s += P.C[i * 6 + j] * (e[j] - ep[j]);
+        sig[i] = s;
+    }
+}
+
+}  // namespace cpf

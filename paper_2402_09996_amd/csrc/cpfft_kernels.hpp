@@ -1,0 +1,581 @@
+// Kernels of one fixed-point iteration of the Green-operator scheme, for a
+// voxel grid stored [component][z][y][x] (x fastest):
+//
+//   xpass_iter : inverse x transform of the correction spectrum, strain
+//                update eps^{k+1} = eps^k - corr + dE, local law (RK4) at
+//                every voxel, FP64 block sums, forward x transform of sigma
+//   ypass      : C2C transform along y of the half spectrum (fwd or inv)
+//   zpass_green: forward z transform, Gamma0 apply + equilibrium residual
+//                (FP64), inverse z transform
+//   bc_update  : one block: reduce the block sums, residuals, convergence
+//                decision and mixed-boundary mean-strain correction
+//
+// Plus single-purpose kernels for the component operators and fields.
+#pragma once
+#include "cpfft_device.hpp"
+
+namespace cpf {
+
+// Device-resident scalars of the running load step (FP64).
+struct Scalars {
+    double dE[6];       // mean-strain increment applied by the next x pass
+    double E[6];        // mean strain of the current iterate
+    double target[6];   // step targets (strain or stress per component)
+    double K0inv[36];   // (C0_SS)^-1 embedded in 6x6 (zero outside S x S)
+    int sidx[6];        // 1: stress-controlled component
+    int iter;           // constitutive evaluations done in this step
+    int done;           // 1: the step has ended (converged or failed)
+    int status;         // 0 ok, negative CPF_E_* code
+    int stagnated;
+    double err_hist[8];
+    double Sigma[6];    // mean stress of the last evaluated iterate
+    double err_eq, err_bc, mean_sig_eq, mean_v, mean_f;
+};
+
+template <typename R>
+struct XArgs {
+    const int32_t *labels;
+    const R *Qtab;          // [n_labels][9]
+    const R *eps_n;         // committed strain [6][nvox]
+    R *eps_k;               // iterate [6][nvox]
+    const R *st_in;         // committed state [D][nvox]
+    R *st_out;              // trial state [D][nvox]
+    C2<R> *spec;            // [6][nz][ny][nhx]
+    const C2<R> *tw;        // [nx]
+    double *part;           // [nblocks][NPX]
+    Scalars *sc;
+    int nx, ny, nz, nhx, L, nlines;
+    long nvox;
+    R inv_nvox, dt;
+    int M;
+};
+
+// ---------------------------------------------------------------------------
+// x pass helpers (LDS layout: pair p, local line li -> (p*L + li)*nx)
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ void load_halfspec_pairs(const C2<R> *__restrict__ spec, C2<R> *buf,
+                                                    int nx, int ny, int nz, int nhx, int L,
+                                                    int li, int x, int y, int z, bool valid)
+{
+    // Z_k = A_k + i B_k over the full x spectrum from the stored halves,
+    // using A_{N-k} = conj(A_k); DC and Nyquist bins keep their real parts.
+    const long plane = (long)nz * ny * nhx;
+    const long row = ((long)z * ny + y) * nhx;
+    const bool mirror = x > nx / 2;
+    const int k = mirror ? nx - x : x;
+    const bool realbin = (k == 0) || ((nx & 1) == 0 && k == nx / 2);
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        C2<R> z2 = {R(0), R(0)};
+        if (valid) {
+            C2<R> A = spec[(2 * p) * plane + row + k];
+            C2<R> B = spec[(2 * p + 1) * plane + row + k];
+            if (realbin) { A.y = R(0); B.y = R(0); }
+            if (mirror) { A.y = -A.y; B.y = -B.y; }
+            z2 = {A.x - B.y, A.y + B.x};
+        }
+        buf[(p * L + li) * nx + x] = z2;
+    }
+}
+
+template <typename R>
+__device__ __forceinline__ void store_halfspec_pairs(C2<R> *__restrict__ spec, const C2<R> *buf,
+                                                     int nx, int ny, int nz, int nhx, int L,
+                                                     int li, int x, int y, int z, bool valid)
+{
+    // Split Z = FFT(a + i b) into A = FFT(a), B = FFT(b) on k in [0, nx/2].
+    if (!valid || x >= nhx) return;
+    const long plane = (long)nz * ny * nhx;
+    const long row = ((long)z * ny + y) * nhx;
+    const int xm = x == 0 ? 0 : nx - x;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        const C2<R> Zk = buf[(p * L + li) * nx + x];
+        const C2<R> Zm = buf[(p * L + li) * nx + xm];
+        const C2<R> A = {R(0.5) * (Zk.x + Zm.x), R(0.5) * (Zk.y - Zm.y)};
+        const C2<R> B = {R(0.5) * (Zk.y + Zm.y), R(0.5) * (Zm.x - Zk.x)};
+        spec[(2 * p) * plane + row + x] = A;
+        spec[(2 * p + 1) * plane + row + x] = B;
+    }
+}
+
+template <typename R, int NS>
+__device__ __forceinline__ void load_state(const R *__restrict__ st, long nvox, long vox, int nsys,
+                                           const R Q[9], R (&ep)[6], R (&v)[NS], R (&al)[NS])
+{
+    R epl[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) epl[i] = st[i * nvox + vox];
+    rot_to_crystal(Q, epl, ep);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        v[s] = s < nsys ? st[(6 + s) * nvox + vox] : R(0);
+        al[s] = s < nsys ? st[(6 + nsys + s) * nvox + vox] : R(0);
+    }
+}
+
+template <typename R, int NS>
+__device__ __forceinline__ void store_state(R *__restrict__ st, long nvox, long vox, int nsys,
+                                            const R Q[9], const R (&ep)[6], const R (&v)[NS],
+                                            const R (&al)[NS])
+{
+    R epl[6];
+    rot_to_lab(Q, ep, epl);
+#pragma unroll
+    for (int i = 0; i < 6; ++i) st[i * nvox + vox] = epl[i];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        if (s < nsys) {
+            st[(6 + s) * nvox + vox] = v[s];
+            st[(6 + nsys + s) * nvox + vox] = al[s];
+        }
+    }
+}
+
+// Local law at one voxel: lab strains in, lab stress out, state in place.
+template <typename R, int NS>
+__device__ __forceinline__ void voxel_law(const LawP<R> &P, const R Q[9], const R e0l[6],
+                                          const R e1l[6], R (&ep)[6], R (&v)[NS], R (&al)[NS],
+                                          R dt, int M, R sigl[6])
+{
+    R e0[6], e1[6], sc[6];
+    rot_to_crystal(Q, e0l, e0);
+    rot_to_crystal(Q, e1l, e1);
+    integrate<R, NS>(P, e0, e1, ep, v, al, dt, M);
+    hooke(P, e1, ep, sc);
+    rot_to_lab(Q, sc, sigl);
+}
+
+// ---------------------------------------------------------------------------
+// Fused x pass of one iteration.  Block = L x-lines of nx voxels.
+// ---------------------------------------------------------------------------
+template <typename R, int NS>
+__global__ __launch_bounds__(256) void k_xpass_iter(XArgs<R> a, LawP<R> P, FftPlan px, int first)
+{
+    if (a.sc->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    C2<R> *buf = reinterpret_cast<C2<R> *>(smem_raw);
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int li = tid / a.nx, x = tid - li * a.nx;
+    const int line = blockIdx.x * a.L + li;
+    const bool valid = line < a.nlines;
+    const int y = valid ? line % a.ny : 0, z = valid ? line / a.ny : 0;
+    const long vox = (long)line * a.nx + x;
+
+    R corr[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    if (!first) {
+        load_halfspec_pairs(a.spec, buf, a.nx, a.ny, a.nz, a.nhx, a.L, li, x, y, z, valid);
+        __syncthreads();
+        lds_fft<R, true, 8>(buf, 3 * a.L, a.nx, px, a.tw, tid, nthr);
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            const C2<R> zz = buf[(p * a.L + li) * a.nx + x];
+            corr[2 * p] = zz.x * a.inv_nvox;
+            corr[2 * p + 1] = zz.y * a.inv_nvox;
+        }
+        __syncthreads();
+    }
+
+    R sig[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    double part[NPX];
+#pragma unroll
+    for (int i = 0; i < NPX; ++i) part[i] = 0.0;
+    if (valid) {
+        const R *base = first ? a.eps_n : a.eps_k;
+        R e1[6], e0[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            e1[c] = base[c * a.nvox + vox] - corr[c] + R(a.sc->dE[c]);
+            e0[c] = a.eps_n[c * a.nvox + vox];
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) a.eps_k[c * a.nvox + vox] = e1[c];
+        const int lab = a.labels[vox];
+        R Q[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Q[i] = a.Qtab[lab * 9 + i];
+        R ep[6], v[NS], al[NS];
+        load_state<R, NS>(a.st_in, a.nvox, vox, P.nsys, Q, ep, v, al);
+        voxel_law<R, NS>(P, Q, e0, e1, ep, v, al, a.dt, a.M, sig);
+        store_state<R, NS>(a.st_out, a.nvox, vox, P.nsys, Q, ep, v, al);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) part[c] = (double)sig[c];
+        part[6] = (double)von_mises(sig);
+        double vs = 0.0, ft = 0.0;
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            if (s < P.nsys) {
+                if ((P.twin_mask >> s) & 1u) ft += (double)v[s] * (double)P.inv_gT;
+                else vs += (double)v[s];
+            }
+        }
+        part[7] = vs;
+        part[8] = ft;
+    }
+    block_sum<NPX>(part, a.part + (long)blockIdx.x * NPX);
+
+#pragma unroll
+    for (int p = 0; p < 3; ++p) buf[(p * a.L + li) * a.nx + x] = C2<R>{sig[2 * p], sig[2 * p + 1]};
+    __syncthreads();
+    lds_fft<R, false, 8>(buf, 3 * a.L, a.nx, px, a.tw, tid, nthr);
+    store_halfspec_pairs(a.spec, buf, a.nx, a.ny, a.nz, a.nhx, a.L, li, x, y, z, valid);
+}
+
+// Forward x transform of 6 real fields (component operator).
+template <typename R>
+__global__ __launch_bounds__(256) void k_xpass_fwd(const R *__restrict__ f, C2<R> *spec, const C2<R> *tw,
+                                                   FftPlan px, int nx, int ny, int nz, int nhx, int L,
+                                                   int nlines, long nvox)
+{
+    extern __shared__ unsigned char smem_raw[];
+    C2<R> *buf = reinterpret_cast<C2<R> *>(smem_raw);
+    const int tid = threadIdx.x;
+    const int li = tid / nx, x = tid - li * nx;
+    const int line = blockIdx.x * L + li;
+    const bool valid = line < nlines;
+    const int y = valid ? line % ny : 0, z = valid ? line / ny : 0;
+    const long vox = (long)line * nx + x;
+#pragma unroll
+    for (int p = 0; p < 3; ++p) {
+        C2<R> v = {R(0), R(0)};
+        if (valid) v = {f[(2 * p) * nvox + vox], f[(2 * p + 1) * nvox + vox]};
+        buf[(p * L + li) * nx + x] = v;
+    }
+    __syncthreads();
+    lds_fft<R, false, 8>(buf, 3 * L, nx, px, tw, tid, blockDim.x);
+    store_halfspec_pairs(spec, buf, nx, ny, nz, nhx, L, li, x, y, z, valid);
+}
+
+// Inverse x transform to 6 real fields, scaled by 1/nvox (component operator).
+template <typename R>
+__global__ __launch_bounds__(256) void k_xpass_inv(const C2<R> *__restrict__ spec, R *f, const C2<R> *tw,
+                                                   FftPlan px, int nx, int ny, int nz, int nhx, int L,
+                                                   int nlines, long nvox, R inv_nvox)
+{
+    extern __shared__ unsigned char smem_raw[];
+    C2<R> *buf = reinterpret_cast<C2<R> *>(smem_raw);
+    const int tid = threadIdx.x;
+    const int li = tid / nx, x = tid - li * nx;
+    const int line = blockIdx.x * L + li;
+    const bool valid = line < nlines;
+    const int y = valid ? line % ny : 0, z = valid ? line / ny : 0;
+    const long vox = (long)line * nx + x;
+    load_halfspec_pairs(spec, buf, nx, ny, nz, nhx, L, li, x, y, z, valid);
+    __syncthreads();
+    lds_fft<R, true, 8>(buf, 3 * L, nx, px, tw, tid, blockDim.x);
+    if (valid) {
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            const C2<R> zz = buf[(p * L + li) * nx + x];
+            f[(2 * p) * nvox + vox] = zz.x * inv_nvox;
+            f[(2 * p + 1) * nvox + vox] = zz.y * inv_nvox;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// y pass: C2C along y on the half spectrum.  Block = one component, one z,
+// a tile of ty consecutive kx columns; LDS holds ty lines of ny points.
+// ---------------------------------------------------------------------------
+template <typename R, bool INV, int EPT>
+__global__ __launch_bounds__(256) void k_ypass(C2<R> *spec, const C2<R> *tw, FftPlan py, int ny, int nz,
+                                               int nhx, int ty, const Scalars *sc)
+{
+    if (sc && sc->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    C2<R> *buf = reinterpret_cast<C2<R> *>(smem_raw);
+    const int kx0 = blockIdx.x * ty;
+    const int tw_ = min(ty, nhx - kx0);
+    const int z = blockIdx.y, c = blockIdx.z;
+    const int ls = ny + 1;
+    C2<R> *g = spec + ((long)c * nz + z) * ny * nhx + kx0;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    for (int i = tid; i < ny * tw_; i += nthr) {
+        const int y = i / tw_, col = i - y * tw_;
+        buf[col * ls + y] = g[(long)y * nhx + col];
+    }
+    __syncthreads();
+    lds_fft<R, INV, EPT>(buf, tw_, ls, py, tw, tid, nthr);
+    for (int i = tid; i < ny * tw_; i += nthr) {
+        const int y = i / tw_, col = i - y * tw_;
+        g[(long)y * nhx + col] = buf[col * ls + y];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// z pass fused with the Green operator.  Block = one ky, a tile of tz kx
+// columns, all kz, all 6 components.
+// ---------------------------------------------------------------------------
+template <typename R>
+struct GreenArgs {
+    int nx, ny, nz, nhx, tz;
+    R inv_mu0;      // 1 / mu0
+    R coef;         // (lam0 + mu0) / (mu0 (lam0 + 2 mu0))
+};
+
+template <typename R>
+__device__ __forceinline__ void green_point(C2<R> (&s)[6], int kx, int ky, int kz, const GreenArgs<R> &g,
+                                            double &err2)
+{
+    // frequency m_j in (-N_j/2, N_j/2]; direction of (m_x/N_x, m_y/N_y, m_z/N_z)
+    const int my = ky <= g.ny / 2 ? ky : ky - g.ny;
+    const int mz = kz <= g.nz / 2 ? kz : kz - g.nz;
+    const bool nyq = ((g.nx & 1) == 0 && 2 * kx == g.nx) || ((g.ny & 1) == 0 && 2 * ky == g.ny) ||
+                     ((g.nz & 1) == 0 && 2 * kz == g.nz);
+    if (nyq || (kx == 0 && my == 0 && mz == 0)) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) s[c] = C2<R>{R(0), R(0)};
+        return;
+    }
+    R x1 = R(kx) / R(g.nx), x2 = R(my) / R(g.ny), x3 = R(mz) / R(g.nz);
+    const R inr = R(1) / sqrt(x1 * x1 + x2 * x2 + x3 * x3);
+    x1 *= inr; x2 *= inr; x3 *= inr;
+    // a = tau . xi, b = xi . a
+    C2<R> a1, a2, a3;
+    a1.x = s[0].x * x1 + s[5].x * x2 + s[4].x * x3;
+    a1.y = s[0].y * x1 + s[5].y * x2 + s[4].y * x3;
+    a2.x = s[5].x * x1 + s[1].x * x2 + s[3].x * x3;
+    a2.y = s[5].y * x1 + s[1].y * x2 + s[3].y * x3;
+    a3.x = s[4].x * x1 + s[3].x * x2 + s[2].x * x3;
+    a3.y = s[4].y * x1 + s[3].y * x2 + s[2].y * x3;
+    const double w = kx == 0 ? 1.0 : 2.0;   // Hermitian partner in the half spectrum
+    err2 += w * ((double)a1.x * a1.x + (double)a1.y * a1.y + (double)a2.x * a2.x +
+                 (double)a2.y * a2.y + (double)a3.x * a3.x + (double)a3.y * a3.y);
+    const C2<R> b = {a1.x * x1 + a2.x * x2 + a3.x * x3, a1.y * x1 + a2.y * x2 + a3.y * x3};
+    const R hm = R(0.5) * g.inv_mu0;
+    const R xs[3] = {x1, x2, x3};
+    const C2<R> as[3] = {a1, a2, a3};
+    const int I[6] = {0, 1, 2, 1, 0, 0}, J[6] = {0, 1, 2, 2, 2, 1};
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        const R xi = xs[I[c]], xj = xs[J[c]];
+        const R q = g.coef * xi * xj;
+        s[c].x = hm * (xi * as[J[c]].x + xj * as[I[c]].x) - q * b.x;
+        s[c].y = hm * (xi * as[J[c]].y + xj * as[I[c]].y) - q * b.y;
+    }
+}
+
+// mode 1: forward z, Gamma0 and residual, inverse z; mode 0: forward z only.
+template <typename R, int EPT>
+__global__ __launch_bounds__(256) void k_zpass_green(C2<R> *spec, const C2<R> *tw, FftPlan pz,
+                                                     GreenArgs<R> g, double *part, const Scalars *sc,
+                                                     int mode)
+{
+    if (sc && sc->done) return;
+    extern __shared__ unsigned char smem_raw[];
+    C2<R> *buf = reinterpret_cast<C2<R> *>(smem_raw);
+    const int kx0 = blockIdx.x * g.tz;
+    const int tw_ = min(g.tz, g.nhx - kx0);
+    const int ky = blockIdx.y;
+    const int nz = g.nz, ls = nz + 1;
+    const long plane = (long)g.nz * g.ny * g.nhx;
+    const long colbase = (long)ky * g.nhx + kx0;
+    const long zstride = (long)g.ny * g.nhx;
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int nrow = 6 * nz;
+    for (int i = tid; i < nrow * tw_; i += nthr) {
+        const int r = i / tw_, col = i - r * tw_;
+        const int c = r / nz, kz = r - c * nz;
+        buf[(c * tw_ + col) * ls + kz] = spec[c * plane + kz * zstride + colbase + col];
+    }
+    __syncthreads();
+    lds_fft<R, false, EPT>(buf, 6 * tw_, ls, pz, tw, tid, nthr);
+    if (mode == 0) {
+        for (int i = tid; i < nrow * tw_; i += nthr) {
+            const int r = i / tw_, col = i - r * tw_;
+            const int c = r / nz, kz = r - c * nz;
+            spec[c * plane + kz * zstride + colbase + col] = buf[(c * tw_ + col) * ls + kz];
+        }
+        return;
+    }
+    double err2 = 0.0;
+    for (int i = tid; i < tw_ * nz; i += nthr) {
+        const int col = i / nz, kz = i - col * nz;
+        C2<R> s[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) s[c] = buf[(c * tw_ + col) * ls + kz];
+        green_point<R>(s, kx0 + col, ky, kz, g, err2);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) buf[(c * tw_ + col) * ls + kz] = s[c];
+    }
+    double e[1] = {err2};
+    block_sum<1>(e, part + (long)blockIdx.y * gridDim.x + blockIdx.x);
+    __syncthreads();
+    lds_fft<R, true, EPT>(buf, 6 * tw_, ls, pz, tw, tid, nthr);
+    for (int i = tid; i < nrow * tw_; i += nthr) {
+        const int r = i / tw_, col = i - r * tw_;
+        const int c = r / nz, kz = r - c * nz;
+        spec[c * plane + kz * zstride + colbase + col] = buf[(c * tw_ + col) * ls + kz];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Step bookkeeping
+// ---------------------------------------------------------------------------
+struct StepInit {
+    double dE0[6], E0[6], target[6], K0inv[36];
+    int sidx[6];
+};
+
+__global__ void k_begin_step(Scalars *sc, StepInit si)
+{
+    if (threadIdx.x != 0) return;
+    for (int i = 0; i < 6; ++i) {
+        sc->dE[i] = si.dE0[i];
+        sc->E[i] = si.E0[i];
+        sc->target[i] = si.target[i];
+        sc->sidx[i] = si.sidx[i];
+        sc->Sigma[i] = 0.0;
+    }
+    for (int i = 0; i < 36; ++i) sc->K0inv[i] = si.K0inv[i];
+    for (int i = 0; i < 8; ++i) sc->err_hist[i] = 0.0;
+    sc->iter = 0;
+    sc->done = 0;
+    sc->status = 0;
+    sc->stagnated = 0;
+    sc->err_eq = sc->err_bc = 0.0;
+    sc->mean_sig_eq = sc->mean_v = sc->mean_f = 0.0;
+}
+
+struct BcArgs {
+    int nbx, nbz;
+    double nvox, n_slip, n_twin;
+    double tol, stag_tol;
+    int max_iter;
+};
+
+__device__ __forceinline__ double frob2(const double a[6])
+{
+    return a[0] * a[0] + a[1] * a[1] + a[2] * a[2] + 2.0 * (a[3] * a[3] + a[4] * a[4] + a[5] * a[5]);
+}
+
+__global__ __launch_bounds__(256) void k_bc_update(const double *__restrict__ px, const double *__restrict__ pz,
+                                                   Scalars *sc, BcArgs b)
+{
+    if (sc->done) return;
+    double acc[NPX + 1];
+#pragma unroll
+    for (int i = 0; i < NPX + 1; ++i) acc[i] = 0.0;
+    for (int j = threadIdx.x; j < b.nbx; j += blockDim.x)
+#pragma unroll
+        for (int i = 0; i < NPX; ++i) acc[i] += px[(long)j * NPX + i];
+    for (int j = threadIdx.x; j < b.nbz; j += blockDim.x) acc[NPX] += pz[j];
+    __shared__ double tot[NPX + 1];
+    block_sum<NPX + 1>(acc, tot);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+
+    double S[6];
+    for (int i = 0; i < 6; ++i) S[i] = tot[i] / b.nvox;
+    const double nrm = sqrt(frob2(S));
+    const double num = sqrt(tot[NPX]);
+    double dS[6];
+    for (int i = 0; i < 6; ++i) dS[i] = sc->sidx[i] ? S[i] - sc->target[i] : 0.0;
+    const double nb = sqrt(frob2(dS));
+    const double err_eq = nrm > 0.0 ? num / (b.nvox * nrm) : (num == 0.0 ? 0.0 : INFINITY);
+    const double err_bc = nrm > 0.0 ? nb / nrm : (nb == 0.0 ? 0.0 : INFINITY);
+    const int it = sc->iter + 1;
+    sc->iter = it;
+    for (int i = 0; i < 6; ++i) sc->Sigma[i] = S[i];
+    sc->err_eq = err_eq;
+    sc->err_bc = err_bc;
+    sc->mean_sig_eq = tot[6] / b.nvox;
+    sc->mean_v = b.n_slip > 0 ? tot[7] / (b.nvox * b.n_slip) : 0.0;
+    sc->mean_f = b.n_twin > 0 ? tot[8] / (b.nvox * b.n_twin) : 0.0;
+
+    const double err = fmax(err_eq, err_bc);
+    if (!(err == err) || isinf(tot[0]) || !(tot[0] == tot[0])) {
+        sc->status = -5;  // CPF_E_NAN
+        sc->done = 1;
+        return;
+    }
+    if (err_eq <= b.tol && err_bc <= b.tol) {
+        sc->done = 1;
+        return;
+    }
+    // stalled residual below the acceptance level (reduced precision)
+    const double old = sc->err_hist[it & 7];
+    sc->err_hist[it & 7] = err;   // slot of iteration it; read back 8 iterations later
+    if (b.stag_tol > 0.0 && err < b.stag_tol && it > 8 && err > 0.99 * old) {
+        sc->stagnated = 1;
+        sc->done = 1;
+        return;
+    }
+    if (it >= b.max_iter) {
+        sc->status = -4;  // CPF_E_NOT_CONVERGED
+        sc->done = 1;
+        return;
+    }
+    // mixed conditions: dE_S = (C0_SS)^-1 (Sigma*_S - Sigma_S)
+    double r[6];
+    for (int i = 0; i < 6; ++i) r[i] = sc->sidx[i] ? sc->target[i] - S[i] : 0.0;
+    for (int i = 0; i < 6; ++i) {
+        double d = 0.0;
+        for (int j = 0; j < 6; ++j) d += sc->K0inv[i * 6 + j] * r[j];
+        sc->dE[i] = d;
+        sc->E[i] += d;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Component operators and field outputs
+// ---------------------------------------------------------------------------
+template <typename R, int NS>
+__global__ __launch_bounds__(256) void k_constitutive(const int32_t *labels, const R *Qtab, const R *eps0,
+                                                      const R *eps1, const R *st0, R *st1, R *sig,
+                                                      LawP<R> P, long nvox, R dt, int M)
+{
+    const long vox = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (vox >= nvox) return;
+    const int lab = labels[vox];
+    R Q[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Q[i] = Qtab[lab * 9 + i];
+    R e0[6], e1[6], s[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        e0[c] = eps0[c * nvox + vox];
+        e1[c] = eps1[c * nvox + vox];
+    }
+    R ep[6], v[NS], al[NS];
+    load_state<R, NS>(st0, nvox, vox, P.nsys, Q, ep, v, al);
+    voxel_law<R, NS>(P, Q, e0, e1, ep, v, al, dt, M, s);
+    store_state<R, NS>(st1, nvox, vox, P.nsys, Q, ep, v, al);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sig[c * nvox + vox] = s[c];
+}
+
+// sigma = C_lab : (eps - eps_p) from a committed strain and state
+template <typename R>
+__global__ __launch_bounds__(256) void k_stress_field(const int32_t *labels, const R *Qtab, const R *eps,
+                                                      const R *st, R *sig, LawP<R> P, long nvox)
+{
+    const long vox = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (vox >= nvox) return;
+    const int lab = labels[vox];
+    R Q[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Q[i] = Qtab[lab * 9 + i];
+    R el[6], epl[6], ec[6], epc[6], sc[6], sl[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        el[c] = eps[c * nvox + vox];
+        epl[c] = st[c * nvox + vox];
+    }
+    rot_to_crystal(Q, el, ec);
+    rot_to_crystal(Q, epl, epc);
+    hooke(P, ec, epc, sc);
+    rot_to_lab(Q, sc, sl);
+#pragma unroll
+    for (int c = 0; c < 6; ++c) sig[c * nvox + vox] = sl[c];
+}
+
+template <typename R>
+__global__ void k_fill(R *p, long n, R v)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+}  // namespace cpf

@@ -1,0 +1,121 @@
+"""The C-ABI library loads, exports every symbol the header declares, and
+rejects bad input on the host before any device call.  CPU only."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import rvegen
+from paper_2402_09996_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "cpfft.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(cpf_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported_and_bound():
+    L = _lib.lib()
+    names = _declared()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(L, n), n
+        assert n in _lib.SIGNATURES, n
+    assert L.cpf_version() == 10000
+    assert L.cpf_error_string(-4) == b"fixed point did not converge"
+
+
+def _desc(n=(8, 8, 8), **over):
+    w = rvegen.workload(0, n_override=8)
+    keep = {}
+    d = _lib.CpfProblemDesc()
+    d.nz, d.ny, d.nx = n
+    labels = np.zeros(n, np.int32) if "labels" not in over else over["labels"]
+    eul = np.ascontiguousarray(w.rve.euler)
+    S = w.systems
+    arrays = dict(labels=np.ascontiguousarray(labels, np.int32), euler=eul,
+                  n=np.ascontiguousarray(S.n_miller), l=np.ascontiguousarray(S.l_miller),
+                  fam=np.ascontiguousarray(S.family), tau0=np.ascontiguousarray(S.tau0))
+    keep.update(arrays)
+    d.labels = arrays["labels"].ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    d.n_labels = eul.shape[0]
+    d.euler = eul.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    for i, v in enumerate(w.C.ravel()):
+        d.C_crystal[i] = v
+    d.n_sys = S.family.shape[0]
+    d.n_miller = arrays["n"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.l_miller = arrays["l"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    d.family = arrays["fam"].ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+    d.tau0 = arrays["tau0"].ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    for k, fam in enumerate((w.law.slip, w.law.twin)):
+        for name in ("Q", "b", "c", "d", "K", "n", "q_self", "q_latent"):
+            setattr(d.law[k], name, getattr(fam, name))
+    d.twin_mode, d.K_c, d.f_m, d.gamma_T, d.eta = 0, 0.0, 1.0, 2 ** -0.5, 1e4
+    for k, v in over.items():
+        if k != "labels":
+            setattr(d, k, v)
+    return d, keep
+
+
+def _create(d):
+    h = ctypes.c_void_p()
+    rc = _lib.lib().cpf_problem_create(ctypes.byref(d), ctypes.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("n", [(8, 8, 10), (8, 7, 8), (512, 8, 8), (1, 8, 8)])
+def test_unsupported_grid_sizes_are_rejected(n):
+    d, keep = _desc(n=n, labels=np.zeros(n if max(n) < 64 else (1, 1, 1), np.int32))
+    rc, h = _create(d)
+    assert rc == _lib.CPF_E_UNSUPPORTED_SIZE
+    assert b"2^a 3^b" in _lib.lib().cpf_last_error_message()
+
+
+def test_bad_problem_inputs_are_rejected():
+    L = _lib.lib()
+    d, keep = _desc(labels=np.full((8, 8, 8), 99, np.int32))
+    assert _create(d)[0] == _lib.CPF_E_INVALID_ARG                 # label out of range
+    d, keep = _desc(n_sys=0)
+    assert _create(d)[0] == _lib.CPF_E_INVALID_ARG
+    d, keep = _desc(n_sys=33)
+    assert _create(d)[0] == _lib.CPF_E_INVALID_ARG
+    d, keep = _desc(twin_mode=7)
+    assert _create(d)[0] == _lib.CPF_E_INVALID_ARG
+    d, keep = _desc(eta=-1.0)
+    assert _create(d)[0] == _lib.CPF_E_INVALID_ARG
+    assert L.cpf_problem_create(None, None) == _lib.CPF_E_INVALID_ARG
+
+
+def test_solver_lifecycle_errors_before_binding():
+    L = _lib.lib()
+    d, keep = _desc()
+    rc, p = _create(d)
+    assert rc == 0
+    lam, mu = ctypes.c_double(), ctypes.c_double()
+    assert L.cpf_problem_reference_medium(p, ctypes.byref(lam), ctypes.byref(mu)) == 0
+    assert mu.value == pytest.approx(79625.0, rel=1e-12)
+    assert lam.value == pytest.approx(332000.0 / 3 - 2 * 79625.0 / 3, rel=1e-12)
+    o = _lib.CpfOptions()
+    L.cpf_options_default(ctypes.byref(o))
+    assert o.tol == 1e-8 and o.precision == 0
+    o.tol = -1.0
+    s = ctypes.c_void_p()
+    assert L.cpf_solver_create(p, ctypes.byref(o), ctypes.byref(s)) == _lib.CPF_E_INVALID_ARG
+    o.tol = 1e-8
+    assert L.cpf_solver_create(p, ctypes.byref(o), ctypes.byref(s)) == 0
+    size = ctypes.c_size_t()
+    assert L.cpf_solver_workspace_size(s, ctypes.byref(size)) == 0
+    # 512 voxels: at least eps x2, state x2 (30 comps), spectrum in FP64
+    assert size.value > 512 * 8 * (12 + 60)
+    out = _lib.CpfStepOut()
+    path = _lib.CpfPath()
+    assert L.cpf_solver_step(s, ctypes.byref(path), 0, ctypes.byref(out)) == _lib.CPF_E_BAD_STATE
+    assert L.cpf_solver_bind(s, None, 0, None) == _lib.CPF_E_WORKSPACE
+    assert L.cpf_solver_field(s, 0, None) == _lib.CPF_E_BAD_STATE
+    L.cpf_solver_destroy(s)
+    L.cpf_problem_destroy(p)
