@@ -1,0 +1,200 @@
+"""Benchmark: voxel-iterations/s of the Green-operator FFT solver on the
+128^3 twinned synthetic RVE (500 grains, half of them split into twin
+pairs, 750 labels, 12 slip + 4 twin systems, uniaxial tension at 1e-3/s to
+2% in 100 load steps).
+
+One bench "step" is one load step: the whole fixed-point iteration (local
+law, forward FFT, Green operator with residual, inverse FFT, mixed
+boundary update) repeated to convergence.  W warmup steps run from the
+undeformed state, the solver is reset, and K steps are timed from t = 0
+along the path (extended at the same rate if K > 100).
+
+Prints one JSON line.  FP32 bulk with FP64 reductions is the headline; the
+plain FP64 solve of the same steps is reported beside it.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxel-iterations/s @128^3 twinned RVE; batched-FP32 & adjoint speedup vs FP64"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+FP64_PEAK_TFLOPS = 78.6
+
+
+def law_flops(S: int, n_twin: int, M: int, nvox: int, n_active: float, n_newton: float) -> float:
+    """Algorithmic FLOPs of one local-law evaluation of the whole grid
+    (FMA = 2 flops, every other arithmetic op or transcendental = 1); the
+    breakdown is documented with the kernel."""
+    per_rate = 114 + 51 * S + 2 * n_twin
+    per_active = 10
+    per_newton = 16
+    per_voxel_fixed = 450 + 12 + 30          # frame rotations, strain update, sums
+    return nvox * (4 * M * per_rate + per_voxel_fixed) + n_active * per_active + n_newton * per_newton
+
+
+def fft_pass_bytes(nx: int, ny: int, nz: int, rbytes: int) -> float:
+    """Algorithmic HBM bytes of one y or z pass: read + write of the
+    6-component half spectrum."""
+    return 2.0 * 6 * nz * ny * (nx // 2 + 1) * 2 * rbytes
+
+
+def run_mode(cp, w, precision, K, W, tol, stag):
+    import torch
+    prob = cp.Problem.from_workload(w)
+    s = cp.Solver(prob, precision=precision, tol=tol, stag_tol=stag)
+    for n in range(W):
+        s.step(w.path, n)
+    s.reset()
+    s.set_timing(True)
+    torch.cuda.synchronize()
+    iters, act, newt, outs = 0, 0.0, 0.0, []
+    t0 = time.perf_counter()
+    for n in range(K):
+        o = s.step(w.path, n)
+        iters += int(o["iters"])
+        act += float(o["n_active"])
+        newt += float(o["n_newton"])
+        outs.append(o)
+        print("[bench] %s step %d iters %d Sigma_xx %.4f err %.2e" %
+              (precision, n, o["iters"], o["Sigma"][0], max(o["err_eq"], o["err_bc"])),
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    tm = s.timing()
+    return s, dict(iters=iters, wall=wall, n_active=act, n_newton=newt, kernels=tm, outs=outs)
+
+
+def cpu_baseline(w, s32, K, budget_s):
+    """The oracle timed on the host on a bounded sample of the same
+    workload: a few fixed-point iterations of the load step that follows the
+    timed run, starting from the GPU's committed state."""
+    import numpy as np
+    import oracle
+    nz, ny, nx = w.rve.labels.shape
+    o = oracle.solver_for(w, oracle.Options(tol=1e-8, max_iter=1))
+    f = {k: s32.field(k).double().cpu().numpy() for k in
+         ("strain", "plastic_strain", "acc_slip", "back_strain", "stress")}
+    pm = lambda a: a.reshape(a.shape[0], -1).T.copy()
+    o.eps = oracle.to_mandel(pm(f["strain"]))
+    o.y = np.hstack([oracle.to_mandel(pm(f["plastic_strain"])), pm(f["acc_slip"]),
+                     pm(f["back_strain"])])
+    o.sig = oracle.to_mandel(pm(f["stress"]))
+    o.Sigma = f["stress"].reshape(6, -1).mean(axis=1)
+    o.E = f["strain"].reshape(6, -1).mean(axis=1)
+    n = min(K, w.path.n_steps - 1)
+    its, t_used = 0, 0.0
+    while t_used < budget_s and its < 20:
+        t0 = time.perf_counter()
+        try:
+            o.step(w.path.t[n], w.path.t[n + 1], w.path.strain_ctrl[n], w.path.target[n])
+        except oracle.NotConverged:
+            pass
+        t_used += time.perf_counter() - t0
+        its += 1
+        print("[bench] oracle iteration %d: %.2f s" % (its, t_used), file=sys.stderr, flush=True)
+    return {"value": its * nx * ny * nz / t_used, "unit": "voxel-iterations/s",
+            "cores": oracle.threads(), "kind": "oracle",
+            "sample": "%d fixed-point iteration(s) of load step %d of the same 128^3 workload "
+                      "(FP64 oracle, from the GPU's committed state), %.1f s" % (its, n, t_used)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--fp64-steps", type=int, default=None)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the solver has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import rvegen
+    import paper_2402_09996_amd as cp
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+
+    K, W = args.steps, args.warmup
+    K64 = args.fp64_steps if args.fp64_steps is not None else K
+    nsteps = max(100, K, K64, W)
+    w = rvegen.workload(2, steps_override=nsteps)
+    nz, ny, nx = w.rve.labels.shape
+    nvox = nx * ny * nz
+    S = int(w.systems.family.shape[0])
+    n_twin = int((w.systems.family == 1).sum())
+    dt = w.path.t[1] - w.path.t[0]
+    M = max(1, math.ceil(dt / 0.05 * (1 - 1e-12)))
+
+    s32, r32 = run_mode(cp, w, "fp32", K, W, 1e-6, 1e-4)
+    value = r32["iters"] * nvox / r32["wall"]
+    s64, r64 = (None, None)
+    if K64 > 0:
+        s64, r64 = run_mode(cp, w, "fp64", K64, min(W, 1), 1e-8, 0.0)
+
+    # dominant kernel of the headline run
+    kern = r32["kernels"]
+    dom = max(kern, key=lambda k: kern[k][0])
+    it = max(1, r32["iters"])
+    if dom == "xpass_law":
+        flops = law_flops(S, n_twin, M, nvox, r32["n_active"] / it, r32["n_newton"] / it)
+        avg_s = kern[dom][0] / 1e3 / it
+        ach = flops / avg_s / 1e12
+        roof = {"bound": "alu", "kernel": "k_xpass_iter<float,16>", "achieved": ach,
+                "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP32_PEAK_TFLOPS,
+                "traffic": None, "avg_launch_ms": avg_s * 1e3}
+    else:
+        b = fft_pass_bytes(nx, ny, nz, 4)
+        avg_s = kern[dom][0] / 1e3 / it
+        ach = b / avg_s / 1e9
+        roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                "avg_launch_ms": avg_s * 1e3}
+    fft_gbs = {}
+    for k in ("ypass_fwd", "zpass_green", "ypass_inv"):
+        t = kern[k][0] / 1e3 / it
+        fft_gbs[k] = {"avg_ms": t * 1e3, "GB/s": fft_pass_bytes(nx, ny, nz, 4) / t / 1e9,
+                      "frac_hbm": fft_pass_bytes(nx, ny, nz, 4) / t / 1e9 / HBM_PEAK_GBS}
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "voxel-iterations/s", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": r32["wall"] / K * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name + " (FP32 bulk, FP64 reductions)", "grid": [nz, ny, nx],
+                   "labels": int(w.rve.n_labels), "systems": S, "load_steps_timed": K,
+                   "rk4_substeps": M, "tol": 1e-6, "global_batch": 1},
+        "iterations": r32["iters"],
+        "kernel_ms": {k: v[0] for k, v in kern.items()},
+        "fft_passes": fft_gbs,
+        "roofline": roof,
+    }
+    if r64 is not None:
+        v64 = r64["iters"] * nvox / r64["wall"]
+        line["fp64"] = {"value": v64, "unit": "voxel-iterations/s", "steps": K64,
+                        "iterations": r64["iters"], "ms_per_step": r64["wall"] / K64 * 1e3,
+                        "tol": 1e-8, "kernel_ms": {k: v[0] for k, v in r64["kernels"].items()},
+                        "fp32_over_fp64_wall": (r64["wall"] / K64) / (r32["wall"] / K)}
+        if K64 == K:
+            import numpy as np
+            a = np.array([o["Sigma"][0] for o in r32["outs"]])
+            b = np.array([o["Sigma"][0] for o in r64["outs"]])
+            line["fp64"]["fp32_max_rel_err_Sigma_xx"] = float(np.abs(a - b).max() / np.abs(b).max())
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w, s32, K, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

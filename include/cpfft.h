@@ -124,6 +124,8 @@ typedef struct cpf_step_out {
     double Sigma[6], E[6];
     double sig_eq_of_mean, mean_sig_eq, mean_v, mean_f;
     double err_eq, err_bc;
+    double n_active;  /* work counters over the step's iterations: system  */
+    double n_newton;  /* rate evaluations above yield, Newton iterations   */
     int iters;        /* constitutive evaluations (fixed-point iterations) */
     int status;       /* CPF_OK, CPF_E_NOT_CONVERGED or CPF_E_NAN          */
 } cpf_step_out;
@@ -160,6 +162,16 @@ int cpf_solver_run(cpf_solver *s, const cpf_path *path, cpf_step_out *out);
  * solver's precision (float or double). */
 int cpf_solver_field(cpf_solver *s, int field, void *dev_out);
 void cpf_solver_destroy(cpf_solver *s);
+
+/* Kernel timing (profiling aid).  While enabled, each kernel launch of the
+ * iteration is bracketed by HIP events on the bound stream and its device
+ * time is accumulated per kernel class: 0 x pass (local law and x
+ * transforms), 1 forward y pass, 2 z pass with the Green operator, 3
+ * inverse y pass, 4 boundary update.  Enabling clears the counters.
+ * Launches that return at once after the step has ended are included. */
+#define CPF_NKERNELS 5
+int cpf_solver_set_timing(cpf_solver *s, int enable);
+int cpf_solver_get_timing(const cpf_solver *s, double *ms /*[5]*/, long long *launches /*[5]*/);
 
 /* Component operators on the bound solver, for parity checks of single
  * steps of the iteration.  Device arrays in the solver's precision.

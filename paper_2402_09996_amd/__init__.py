@@ -124,7 +124,8 @@ class _PathArgs:
 
 
 def _outs_to_dict(outs, n):
-    keys = ("sig_eq_of_mean", "mean_sig_eq", "mean_v", "mean_f", "err_eq", "err_bc")
+    keys = ("sig_eq_of_mean", "mean_sig_eq", "mean_v", "mean_f", "err_eq", "err_bc",
+            "n_active", "n_newton")
     r = {"Sigma": np.array([list(outs[i].Sigma) for i in range(n)]).reshape(n, 6),
          "E": np.array([list(outs[i].E) for i in range(n)]).reshape(n, 6),
          "iters": np.array([outs[i].iters for i in range(n)], dtype=np.int64),
@@ -195,6 +196,18 @@ class Solver:
         out = torch.empty((nc, self.nz, self.ny, self.nx), dtype=self.dtype, device=self.device)
         check(_lib.lib().cpf_solver_field(self._h, k, ctypes.c_void_p(out.data_ptr())))
         return out
+
+    # -- kernel timing -------------------------------------------------------
+    KERNELS = ("xpass_law", "ypass_fwd", "zpass_green", "ypass_inv", "bc_update")
+
+    def set_timing(self, on: bool = True):
+        check(_lib.lib().cpf_solver_set_timing(self._h, int(bool(on))))
+
+    def timing(self) -> dict:
+        ms = (ctypes.c_double * 5)()
+        n = (ctypes.c_longlong * 5)()
+        check(_lib.lib().cpf_solver_get_timing(self._h, ms, n))
+        return {k: (ms[i], n[i]) for i, k in enumerate(self.KERNELS)}
 
     # -- component operators ---------------------------------------------------
     def forward_fft(self, f):

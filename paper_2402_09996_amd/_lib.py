@@ -9,7 +9,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libcpfft.so")
+# CPFFT_LIBRARY may point at another build of the same library (e.g. a
+# variant compiled with different launch bounds for a timing comparison).
+LIB_PATH = os.environ.get("CPFFT_LIBRARY", os.path.join(HERE, "libcpfft.so"))
 
 CPF_OK = 0
 CPF_E_INVALID_ARG = -1
@@ -70,7 +72,8 @@ class CpfStepOut(ctypes.Structure):
     _fields_ = [
         ("Sigma", _d * 6), ("E", _d * 6),
         ("sig_eq_of_mean", _d), ("mean_sig_eq", _d), ("mean_v", _d), ("mean_f", _d),
-        ("err_eq", _d), ("err_bc", _d), ("iters", _i), ("status", _i),
+        ("err_eq", _d), ("err_bc", _d), ("n_active", _d), ("n_newton", _d),
+        ("iters", _i), ("status", _i),
     ]
 
 
@@ -91,6 +94,8 @@ SIGNATURES = {
     "cpf_solver_run": (_i, [_p, ctypes.POINTER(CpfPath), ctypes.POINTER(CpfStepOut)]),
     "cpf_solver_field": (_i, [_p, _i, _p]),
     "cpf_solver_destroy": (None, [_p]),
+    "cpf_solver_set_timing": (_i, [_p, _i]),
+    "cpf_solver_get_timing": (_i, [_p, _dp, ctypes.POINTER(ctypes.c_longlong)]),
     "cpf_op_forward_fft": (_i, [_p, _p, _p]),
     "cpf_op_green": (_i, [_p, _p, _p, _dp]),
     "cpf_op_constitutive": (_i, [_p, _p, _p, _p, _p, _p, _d, _i]),

@@ -274,6 +274,7 @@ struct cpf_solver {
     size_t lds_x, lds_y, lds_z;
     double lam0, mu0, K0[36];
     int ns_inst;
+    int law_spec;     // LAW_GENERAL or LAW_TABLE1
     // workspace
     unsigned char *ws = nullptr;
     size_t ws_bytes = 0;
@@ -284,7 +285,61 @@ struct cpf_solver {
     double Sigma_n[6], E_n[6];
     int prev_iters = 8;
     Scalars *hsc = nullptr;   // pinned host mirror
+    // kernel timing
+    bool timing = false;
+    double t_ms[CPF_NKERNELS] = {0};
+    long long t_n[CPF_NKERNELS] = {0};
+    std::vector<hipEvent_t> ev_pool;
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
 };
+
+static int timed_begin(cpf_solver *s, hipEvent_t *a, hipEvent_t *b)
+{
+    if (!s->timing) return CPF_OK;
+    for (hipEvent_t *e : {a, b}) {
+        if (s->ev_pool.empty()) {
+            HIPCHK(hipEventCreate(e));
+        } else {
+            *e = s->ev_pool.back();
+            s->ev_pool.pop_back();
+        }
+    }
+    HIPCHK(hipEventRecord(*a, s->stream));
+    return CPF_OK;
+}
+
+static int timed_end(cpf_solver *s, int k, hipEvent_t a, hipEvent_t b)
+{
+    if (!s->timing) return CPF_OK;
+    HIPCHK(hipEventRecord(b, s->stream));
+    s->ev_pending.push_back({k, {a, b}});
+    return CPF_OK;
+}
+
+// After a stream synchronization: fold the pending event pairs into the counters.
+static int timed_collect(cpf_solver *s)
+{
+    for (auto &p : s->ev_pending) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, p.second.first, p.second.second));
+        s->t_ms[p.first] += ms;
+        s->t_n[p.first] += 1;
+        s->ev_pool.push_back(p.second.first);
+        s->ev_pool.push_back(p.second.second);
+    }
+    s->ev_pending.clear();
+    return CPF_OK;
+}
+
+#define TIMED(s, k, launch)                                   \
+    do {                                                      \
+        hipEvent_t ea_ = nullptr, eb_ = nullptr;              \
+        int rc_ = timed_begin(s, &ea_, &eb_);                 \
+        if (rc_) return rc_;                                  \
+        launch;                                               \
+        rc_ = timed_end(s, k, ea_, eb_);                      \
+        if (rc_) return rc_;                                  \
+    } while (0)
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -330,6 +385,25 @@ static void tiling(cpf_solver *s)
     s->lds_z = 6 * (size_t)s->tz * (s->nz + 1) * cb;
 }
 
+// The specialized law kernel applies when the systems are those of Table 1
+// in order (12 slip, or 12 slip + 4 twin) and the crystal stiffness has the
+// orthotropic zero pattern (no normal-shear or shear-shear coupling).
+static bool table1_specializable(const cpf_problem &p)
+{
+    if (p.nsys != 12 && p.nsys != 16) return false;
+    for (int s = 0; s < p.nsys; ++s) {
+        if (p.fam[s] != (s < 12 ? 0 : 1)) return false;
+        for (int i = 0; i < 6; ++i)
+            if (fabs(p.m[6 * s + i] - T1_M[s][i]) > 1e-12) return false;
+    }
+    for (int i = 0; i < 6; ++i)
+        for (int j = 0; j < 6; ++j) {
+            const bool nz = (i < 3 && j < 3) || i == j;
+            if (!nz && p.Cv[i * 6 + j] != 0.0) return false;
+        }
+    return true;
+}
+
 extern "C" int cpf_solver_create(const cpf_problem *p, const cpf_options *opt, cpf_solver **out)
 {
     if (!p || !out) return fail(CPF_E_INVALID_ARG, "null argument");
@@ -354,6 +428,7 @@ extern "C" int cpf_solver_create(const cpf_problem *p, const cpf_options *opt, c
     radix_plan(s->ny, s->py);
     radix_plan(s->nz, s->pz);
     s->ns_inst = p->nsys <= 4 ? 4 : p->nsys <= 12 ? 12 : p->nsys <= 16 ? 16 : 32;
+    s->law_spec = table1_specializable(*p) ? LAW_TABLE1 : LAW_GENERAL;
     if (s->prec == CPF_PREC_FP64) { tiling<double>(s); layout<double>(s); }
     else { tiling<float>(s); layout<float>(s); }
     if (o.mu0 > 0) {
@@ -387,7 +462,36 @@ extern "C" void cpf_solver_destroy(cpf_solver *s)
 {
     if (!s) return;
     if (s->hsc) (void)hipHostFree(s->hsc);
+    for (auto &p : s->ev_pending) {
+        (void)hipEventDestroy(p.second.first);
+        (void)hipEventDestroy(p.second.second);
+    }
+    for (hipEvent_t e : s->ev_pool) (void)hipEventDestroy(e);
     delete s;
+}
+
+extern "C" int cpf_solver_set_timing(cpf_solver *s, int enable)
+{
+    if (!s) return fail(CPF_E_INVALID_ARG, "null solver");
+    if (s->bound) HIPCHK(hipStreamSynchronize(s->stream));
+    int rc = timed_collect(s);
+    if (rc) return rc;
+    s->timing = enable != 0;
+    for (int k = 0; k < CPF_NKERNELS; ++k) {
+        s->t_ms[k] = 0.0;
+        s->t_n[k] = 0;
+    }
+    return CPF_OK;
+}
+
+extern "C" int cpf_solver_get_timing(const cpf_solver *s, double *ms, long long *n)
+{
+    if (!s || !ms || !n) return fail(CPF_E_INVALID_ARG, "null argument");
+    for (int k = 0; k < CPF_NKERNELS; ++k) {
+        ms[k] = s->t_ms[k];
+        n[k] = s->t_n[k];
+    }
+    return CPF_OK;
 }
 
 template <typename R>
@@ -423,6 +527,7 @@ static LawP<R> make_law(const cpf_solver *s)
         F.c = R(L.c); F.d = R(L.d);
         F.K = R(L.K); F.invK = R(1.0 / L.K);
         F.n = R(L.n); F.inv_n = R(1.0 / L.n); F.nm1 = R(L.n - 1.0);
+        F.nm1_int = (L.n == floor(L.n) && L.n >= 1.0 && L.n <= 64.0) ? (int)L.n - 1 : -1;
         (f ? P.ft : P.fs) = F;
     }
     P.Kc_gT = R(p.Kc * p.gT); P.fm = R(p.fm); P.inv_gT = R(1.0 / p.gT);
@@ -528,21 +633,26 @@ static void stress_block_inverse(const double K0[36], const int sidx[6], double 
         for (int b = 0; b < n; ++b) out[S[a] * 6 + S[b]] = A[a][n + b];
 }
 
-template <typename R, int NS>
+template <typename R, int NS, int SPEC>
 static void launch_xiter(cpf_solver *s, const XArgs<R> &a, const LawP<R> &P, int first)
 {
-    hipLaunchKernelGGL((k_xpass_iter<R, NS>), dim3(s->nbx), dim3(s->tpbx), s->lds_x, s->stream, a, P,
+    hipLaunchKernelGGL((k_xpass_iter<R, NS, SPEC>), dim3(s->nbx), dim3(s->tpbx), s->lds_x, s->stream, a, P,
                        s->px, first);
 }
 
 template <typename R>
 static void launch_xiter_any(cpf_solver *s, const XArgs<R> &a, const LawP<R> &P, int first)
 {
+    if (s->law_spec == LAW_TABLE1) {
+        if (s->ns_inst == 12) launch_xiter<R, 12, LAW_TABLE1>(s, a, P, first);
+        else launch_xiter<R, 16, LAW_TABLE1>(s, a, P, first);
+        return;
+    }
     switch (s->ns_inst) {
-    case 4: launch_xiter<R, 4>(s, a, P, first); break;
-    case 12: launch_xiter<R, 12>(s, a, P, first); break;
-    case 16: launch_xiter<R, 16>(s, a, P, first); break;
-    default: launch_xiter<R, 32>(s, a, P, first); break;
+    case 4: launch_xiter<R, 4, LAW_GENERAL>(s, a, P, first); break;
+    case 12: launch_xiter<R, 12, LAW_GENERAL>(s, a, P, first); break;
+    case 16: launch_xiter<R, 16, LAW_GENERAL>(s, a, P, first); break;
+    default: launch_xiter<R, 32, LAW_GENERAL>(s, a, P, first); break;
     }
 }
 
@@ -577,6 +687,11 @@ static void launch_z(cpf_solver *s, C2<R> *spec, int mode, const Scalars *sc)
     constexpr int EPT = sizeof(R) == 4 ? 24 : 12;
     hipLaunchKernelGGL((k_zpass_green<R, EPT>), grid, dim3(256), s->lds_z, s->stream, spec, tw, s->pz,
                        green_args<R>(s), dptr<double>(s, s->off_pz), sc, mode);
+}
+
+static void launch_bc(cpf_solver *s, const double *px, Scalars *sc, const BcArgs &b)
+{
+    hipLaunchKernelGGL(k_bc_update, dim3(1), dim3(256), 0, s->stream, px, dptr<double>(s, s->off_pz), sc, b);
 }
 
 template <typename R>
@@ -639,16 +754,19 @@ static int step_impl(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *o
     int chunk = s->opt.check_every > 0 ? s->opt.check_every : std::max(2, s->prev_iters);
     for (;;) {
         for (int c = 0; c < chunk; ++c, ++queued) {
-            launch_xiter_any<R>(s, a, P, queued == 0 ? 1 : 0);
-            launch_y<R>(s, a.spec, false, sc);
-            launch_z<R>(s, a.spec, 1, sc);
-            launch_y<R>(s, a.spec, true, sc);
-            hipLaunchKernelGGL(k_bc_update, dim3(1), dim3(256), 0, s->stream, a.part,
-                               dptr<double>(s, s->off_pz), sc, b);
+            TIMED(s, 0, (launch_xiter_any<R>(s, a, P, queued == 0 ? 1 : 0)));
+            TIMED(s, 1, (launch_y<R>(s, a.spec, false, sc)));
+            TIMED(s, 2, (launch_z<R>(s, a.spec, ZMODE_FWD | ZMODE_GREEN, sc)));
+            TIMED(s, 3, (launch_y<R>(s, a.spec, true, sc)));
+            TIMED(s, 4, launch_bc(s, a.part, sc, b));
         }
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(s->hsc, sc, sizeof(Scalars), hipMemcpyDeviceToHost, s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
+        {
+            int rc = timed_collect(s);
+            if (rc) return rc;
+        }
         if (s->hsc->done) break;
         if (queued > s->opt.max_iter + 8)
             return fail(CPF_E_BAD_STATE, "device did not end the step after %d iterations", queued);
@@ -667,6 +785,8 @@ static int step_impl(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *o
         out->mean_f = h.mean_f;
         out->err_eq = h.err_eq;
         out->err_bc = h.err_bc;
+        out->n_active = h.work_active;
+        out->n_newton = h.work_newton;
         out->iters = h.iter;
         out->status = h.status;
     }
@@ -766,7 +886,7 @@ static int op_fft_impl(cpf_solver *s, const void *field, void *spec)
                        sp, dptr<C2<R>>(s, s->off_tw[0]), s->px, s->nx, s->ny, s->nz, s->nhx, s->L,
                        s->ny * s->nz, s->nvox);
     launch_y<R>(s, sp, false, nullptr);
-    launch_z<R>(s, sp, 0, nullptr);
+    launch_z<R>(s, sp, ZMODE_FWD, nullptr);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s->stream));
     return CPF_OK;
@@ -784,7 +904,7 @@ template <typename R>
 static int op_green_impl(cpf_solver *s, void *spec, void *outp, double *err2)
 {
     C2<R> *sp = (C2<R> *)spec;
-    launch_z<R>(s, sp, 1, nullptr);
+    launch_z<R>(s, sp, ZMODE_GREEN, nullptr);
     launch_y<R>(s, sp, true, nullptr);
     hipLaunchKernelGGL(k_xpass_inv<R>, dim3(s->nbx), dim3(s->tpbx), s->lds_x, s->stream, sp, (R *)outp,
                        dptr<C2<R>>(s, s->off_tw[0]), s->px, s->nx, s->ny, s->nz, s->nhx, s->L,
@@ -811,11 +931,11 @@ extern "C" int cpf_op_green(cpf_solver *s, void *dev_spec, void *dev_out, double
                                     : op_green_impl<float>(s, dev_spec, dev_out, err2);
 }
 
-template <typename R, int NS>
+template <typename R, int NS, int SPEC = LAW_GENERAL>
 static void launch_cp(cpf_solver *s, const void *e0, const void *e1, const void *s0, void *s1, void *sig,
                       double dt, int M)
 {
-    hipLaunchKernelGGL((k_constitutive<R, NS>), dim3((s->nvox + 255) / 256), dim3(256), 0, s->stream,
+    hipLaunchKernelGGL((k_constitutive<R, NS, SPEC>), dim3((s->nvox + 255) / 256), dim3(256), 0, s->stream,
                        dptr<int32_t>(s, s->off_labels), dptr<R>(s, s->off_Q), (const R *)e0, (const R *)e1,
                        (const R *)s0, (R *)s1, (R *)sig, make_law<R>(s), s->nvox, R(dt), M);
 }
@@ -824,6 +944,13 @@ template <typename R>
 static int op_cp_impl(cpf_solver *s, const void *e0, const void *e1, const void *s0, void *s1, void *sig,
                       double dt, int M)
 {
+    if (s->law_spec == LAW_TABLE1) {
+        if (s->ns_inst == 12) launch_cp<R, 12, LAW_TABLE1>(s, e0, e1, s0, s1, sig, dt, M);
+        else launch_cp<R, 16, LAW_TABLE1>(s, e0, e1, s0, s1, sig, dt, M);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipStreamSynchronize(s->stream));
+        return CPF_OK;
+    }
     switch (s->ns_inst) {
     case 4: launch_cp<R, 4>(s, e0, e1, s0, s1, sig, dt, M); break;
     case 12: launch_cp<R, 12>(s, e0, e1, s0, s1, sig, dt, M); break;

@@ -9,7 +9,7 @@ namespace cpf {
 
 constexpr int NSMAX = 32;    // systems per crystal
 constexpr int MAXPASS = 12;  // radix passes per 1D transform
-constexpr int NPX = 9;       // per-block FP64 sums of the x pass
+constexpr int NPX = 11;      // per-block FP64 sums of the x pass
 
 template <typename R>
 struct alignas(2 * sizeof(R)) C2 {
@@ -279,6 +279,7 @@ struct FamP {
     R bl2e;    // b * log2(e)
     R c, d;    // kinematic hardening
     R K, invK, n, inv_n, nm1;
+    int nm1_int;   // n - 1 when n is an integer in [1, 64], else -1
 };
 
 template <typename R>
@@ -294,62 +295,179 @@ struct LawP {
     R newton_rtol;
 };
 
-// Math in the working precision (FP32: hardware exp2/log2/rcp).
-__device__ __forceinline__ float lg2(float x) { return __log2f(x); }
+// Math in the working precision.  FP32 uses the hardware transcendental
+// instructions directly (v_exp_f32, v_log_f32, v_rcp_f32: about 1 ulp;
+// results below the normal range flush to zero, which the law never needs).
+__device__ __forceinline__ float lg2(float x) { return __builtin_amdgcn_logf(x); }
 __device__ __forceinline__ double lg2(double x) { return log2(x); }
-__device__ __forceinline__ float ex2(float x) { return exp2f(x); }
+__device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ double ex2(double x) { return exp2(x); }
-__device__ __forceinline__ float fdiv(float a, float b) { return __fdividef(a, b); }
+__device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
 
-// Regularized Norton rate: g = A y^n, y > 0 the root of K y + eta A y^n = o
-// (equations 5/6 with the yield stress raised by eta |g|).  Newton from the
-// smaller of the two upper bounds o/K and (o/(eta A))^(1/n) decreases
-// monotonically onto the root.
+// y^p for an integer 0 <= p < 64 that is uniform across the wave: six
+// squarings with the multiplications selected by scalar branches.
 template <typename R>
-__device__ __forceinline__ R reg_rate(R o, R A, R inv_etaA, R etaA, R K, R invK, R n, R inv_n, R nm1,
-                                      R rtol)
+__device__ __forceinline__ R powi(R y, int p)
 {
-    if (!(o > R(0)) || !(A > R(0))) return R(0);
-    R y = ex2(lg2(o * inv_etaA) * inv_n);
-    const R yk = o * invK;
-    y = yk < y ? yk : y;
+    R r = R(1), b = y;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        if (p & (1 << k)) r *= b;
+        b *= b;
+    }
+    return r;
+}
+
+// y^(n-1) in the working precision: FP32 by the hardware exp2/log2, FP64 by
+// repeated squaring when n is an integer (software exp2/log2 otherwise).
+template <typename R>
+__device__ __forceinline__ R pow_nm1(R y, R nm1, int nm1_int)
+{
+    if constexpr (sizeof(R) == 4) return ex2(nm1 * lg2(y));
+    else return nm1_int >= 0 ? powi(y, nm1_int) : ex2(nm1 * lg2(y));
+}
+
+// Schmid tensors of the paper's system set (Table 1; system 9 read with
+// direction [110]): m = (n (x) l + l (x) n)/2 of the unit plane normal and
+// direction, tensor components (11,22,33,23,13,12).  Systems 1-12 are slip
+// (entries +-1/sqrt6, +-1/(2 sqrt6)), 13-16 twinning.
+constexpr double T1_M[16][6] = {
+    {0.0, 0.40824829046386302, -0.40824829046386302, 0.0, 0.20412414523193151, 0.20412414523193151},
+    {0.40824829046386302, 0.0, -0.40824829046386302, 0.20412414523193151, 0.0, 0.20412414523193151},
+    {0.40824829046386302, -0.40824829046386302, 0.0, 0.20412414523193151, -0.20412414523193151, 0.0},
+    {0.0, -0.40824829046386302, 0.40824829046386302, 0.0, -0.20412414523193151, 0.20412414523193151},
+    {0.40824829046386302, 0.0, -0.40824829046386302, -0.20412414523193151, 0.0, -0.20412414523193151},
+    {0.40824829046386302, -0.40824829046386302, 0.0, -0.20412414523193151, -0.20412414523193151, 0.0},
+    {0.0, -0.40824829046386302, 0.40824829046386302, 0.0, 0.20412414523193151, 0.20412414523193151},
+    {0.40824829046386302, 0.0, -0.40824829046386302, 0.20412414523193151, 0.0, -0.20412414523193151},
+    {0.40824829046386302, -0.40824829046386302, 0.0, 0.20412414523193151, 0.20412414523193151, 0.0},
+    {0.0, 0.40824829046386302, -0.40824829046386302, 0.0, -0.20412414523193151, 0.20412414523193151},
+    {0.40824829046386302, 0.0, -0.40824829046386302, -0.20412414523193151, 0.0, 0.20412414523193151},
+    {0.40824829046386302, -0.40824829046386302, 0.0, -0.20412414523193151, 0.20412414523193151, 0.0},
+    {0.23570226039551589, 0.23570226039551589, -0.47140452079103179, 0.11785113019775795,
+     0.11785113019775795, 0.23570226039551589},
+    {0.23570226039551589, 0.23570226039551589, -0.47140452079103179, -0.11785113019775795,
+     0.11785113019775795, -0.23570226039551589},
+    {0.23570226039551589, 0.23570226039551589, -0.47140452079103179, 0.11785113019775795,
+     -0.11785113019775795, -0.23570226039551589},
+    {0.23570226039551589, 0.23570226039551589, -0.47140452079103179, -0.11785113019775795,
+     -0.11785113019775795, 0.23570226039551589},
+};
+
+// Kernel specializations of the law:
+//   LAW_GENERAL : any systems (Schmid tensors and stiffness from the arguments)
+//   LAW_TABLE1  : the Table 1 systems in order (12 slip, optionally + 4 twin)
+//                 and a crystal stiffness with orthotropic zero pattern
+//                 (cubic, tetragonal): compile-time Schmid tensors, 12-term Hooke
+constexpr int LAW_GENERAL = 0;
+constexpr int LAW_TABLE1 = 1;
+
+template <typename R, int SPEC>
+__device__ __forceinline__ R schmid(const R (&m)[NSMAX][6], int s, int i)
+{
+    if constexpr (SPEC == LAW_TABLE1) return R(T1_M[s][i]);
+    else return m[s][i];
+}
+
+template <int SPEC>
+__device__ __forceinline__ bool schmid_nonzero(int s, int i)
+{
+    if constexpr (SPEC == LAW_TABLE1) return T1_M[s][i] != 0.0;
+    else return true;
+}
+
+template <typename R, int SPEC>
+__device__ __forceinline__ void hooke_c(const R (&C)[36], const R ee[6], R sig[6])
+{
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        R s = R(0);
+#pragma unroll
+        for (int j = 0; j < 6; ++j) {
+            const bool nz = SPEC == LAW_GENERAL || (i < 3 && j < 3) || i == j;
+            if (nz) s += C[i * 6 + j] * ee[j];
+        }
+        sig[i] = s;
+    }
+}
+
+// Regularized Norton rate (equations 5/6 with the yield stress raised by
+// eta |g|): g = A y^n, where y > 0 is the root of phi(y) = K y + eta A y^n - o.
+// phi is increasing and convex, so Newton converges from any y > 0 and
+// stays above the root after the first step.  The iteration starts from
+// ywarm (the root found for the same system at the previous RK stage) when
+// there is one, capped by the upper bound o/K; otherwise from the smaller
+// of the two upper bounds o/K and (o/(eta A))^(1/n).  At the root,
+// A y^n = (o - K y) / eta, which gives g without another power.
+// ywarm is updated (0 when the system is below its threshold).
+template <typename R>
+__device__ __forceinline__ R reg_rate(R o, R A, R inv_etaA, R etaA, R inv_eta, const FamP<R> &F,
+                                      R rtol, R &ywarm, int &nact, int &nnewt)
+{
+    if (!(o > R(0)) || !(A > R(0))) {
+        ywarm = R(0);
+        return R(0);
+    }
+    ++nact;
+    const R yk = o * F.invK;
+    R y;
+    if (ywarm > R(0)) {
+        y = ywarm < yk ? ywarm : yk;
+    } else {
+        y = ex2(lg2(o * inv_etaA) * F.inv_n);
+        y = yk < y ? yk : y;
+    }
+    R yn1 = R(0);
     for (int it = 0; it < 40; ++it) {
-        const R yn1 = ex2(nm1 * lg2(y));
-        const R phi = K * y + etaA * yn1 * y - o;
-        const R dphi = K + etaA * n * yn1;
+        yn1 = pow_nm1(y, F.nm1, F.nm1_int);
+        const R phi = F.K * y + etaA * yn1 * y - o;
+        const R dphi = F.K + etaA * F.n * yn1;
         const R step = fdiv(phi, dphi);
         y -= step;
+        ++nnewt;
         if (fabs(step) <= rtol * y) break;
     }
-    return A * ex2(n * lg2(y));
+    ywarm = y;
+    if (etaA > R(0)) return (o - F.K * y) * inv_eta;
+    return A * y * pow_nm1(y, F.nm1, F.nm1_int);
+}
+
+// Optional compiler fence between systems: keeps the per-system law
+// parameters from being hoisted (and held in registers) across the whole
+// system loop.
+#ifndef CPF_LAW_FENCE
+#define CPF_LAW_FENCE 1
+#endif
+__device__ __forceinline__ void law_fence()
+{
+#if CPF_LAW_FENCE
+    asm volatile("" ::: "memory");
+#endif
 }
 
 // One RK4 stage of the internal variables in the crystal frame.  Inputs:
 // total strain e at the stage time and the stage state t* (overwritten with
 // the next stage state y + cnext*k when has_next); the stage slope k is
-// accumulated into a* with weight wacc.
-template <typename R, int NS>
+// accumulated into a* with weight wacc.  yw holds the per-system Newton
+// warm starts.
+template <typename R, int NS, int SPEC>
 __device__ __forceinline__ void rk_stage(const LawP<R> &P, const R e[6], R (&tep)[6], R (&tv)[NS],
                                          R (&tal)[NS], const R (&yep)[6], const R (&yv)[NS],
                                          const R (&yal)[NS], R (&aep)[6], R (&av)[NS],
-                                         R (&aal)[NS], R wacc, R cnext, bool has_next)
+                                         R (&aal)[NS], R (&yw)[NS], R wacc, R cnext, bool has_next,
+                                         int &nact, int &nnewt)
 {
     R ee[6], sig[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) ee[i] = e[i] - tep[i];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        R s = R(0);
-#pragma unroll
-        for (int j = 0; j < 6; ++j) s += P.C[i * 6 + j] * ee[j];
-        sig[i] = s;
-    }
+    hooke_c<R, SPEC>(P.C, ee, sig);
     // saturating hardening terms and family sums (equation 4)
     R h[NS];
     R Hs = R(0), Ht = R(0), sumf = R(0);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
+        law_fence();
         const bool tw = (P.twin_mask >> s) & 1u;
         const R bl = tw ? P.ft.bl2e : P.fs.bl2e;
         h[s] = R(1) - ex2(-bl * tv[s]);
@@ -368,26 +486,27 @@ __device__ __forceinline__ void rk_stage(const LawP<R> &P, const R e[6], R (&tep
     R dep[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
+        law_fence();
         const bool tw = (P.twin_mask >> s) & 1u;
-        const R QL = tw ? P.ft.QL : P.fs.QL, QD = tw ? P.ft.QD : P.fs.QD;
-        const R c = tw ? P.ft.c : P.fs.c, d = tw ? P.ft.d : P.fs.d;
-        const R K = tw ? P.ft.K : P.fs.K, invK = tw ? P.ft.invK : P.fs.invK;
-        const R n = tw ? P.ft.n : P.fs.n, inv_n = tw ? P.ft.inv_n : P.fs.inv_n;
-        const R nm1 = tw ? P.ft.nm1 : P.fs.nm1;
-        const R r = P.tau0[s] + QL * (tw ? Ht : Hs) + QD * h[s];
-        const R tau = sig[0] * P.m[s][0] + sig[1] * P.m[s][1] + sig[2] * P.m[s][2] +
-                      R(2) * (sig[3] * P.m[s][3] + sig[4] * P.m[s][4] + sig[5] * P.m[s][5]);
-        const R tx = tau - c * tal[s];
+        const FamP<R> &F = tw ? P.ft : P.fs;
+        const R r = P.tau0[s] + F.QL * (tw ? Ht : Hs) + F.QD * h[s];
+        R tau = R(0);
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+            if (schmid_nonzero<SPEC>(s, i))
+                tau += (i < 3 ? sig[i] : R(2) * sig[i]) * schmid<R, SPEC>(P.m, s, i);
+        const R tx = tau - F.c * tal[s];
         R gd;
         if (tw) {
-            gd = reg_rate<R>(tx - r, Atw, inv_etaAtw, etaAtw, K, invK, n, inv_n, nm1, P.newton_rtol);
+            gd = reg_rate<R>(tx - r, Atw, inv_etaAtw, etaAtw, P.inv_eta, F, P.newton_rtol, yw[s], nact,
+                             nnewt);
         } else {
-            const R g = reg_rate<R>(fabs(tx) - r, R(1), P.inv_eta, P.eta, K, invK, n, inv_n, nm1,
-                                    P.newton_rtol);
+            const R g = reg_rate<R>(fabs(tx) - r, R(1), P.inv_eta, P.eta, P.inv_eta, F, P.newton_rtol,
+                                    yw[s], nact, nnewt);
             gd = tx >= R(0) ? g : -g;
         }
         const R ag = fabs(gd);
-        const R dal = gd - d * ag * tal[s];
+        const R dal = gd - F.d * ag * tal[s];
         av[s] += wacc * ag;
         aal[s] += wacc * dal;
         if (has_next) {
@@ -396,7 +515,8 @@ __device__ __forceinline__ void rk_stage(const LawP<R> &P, const R e[6], R (&tep
         }
         const R wg = tw ? gd : wslip * gd;
 #pragma unroll
-        for (int i = 0; i < 6; ++i) dep[i] += wg * P.m[s][i];
+        for (int i = 0; i < 6; ++i)
+            if (schmid_nonzero<SPEC>(s, i)) dep[i] += wg * schmid<R, SPEC>(P.m, s, i);
     }
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
@@ -407,15 +527,17 @@ __device__ __forceinline__ void rk_stage(const LawP<R> &P, const R e[6], R (&tep
 
 // Integrate the internal variables over one load increment (crystal frame):
 // total strain linear in time from e0 to e1, M classical RK4 substeps.
-template <typename R, int NS>
+template <typename R, int NS, int SPEC>
 __device__ void integrate(const LawP<R> &P, const R e0[6], const R e1[6], R (&ep)[6], R (&v)[NS],
-                          R (&al)[NS], R dt, int M)
+                          R (&al)[NS], R dt, int M, int &nact, int &nnewt)
 {
     const R h = dt / R(M);
     const R invM = R(1) / R(M);
-    R de[6];
+    R de[6], yw[NS];
 #pragma unroll
     for (int i = 0; i < 6; ++i) de[i] = e1[i] - e0[i];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) yw[s] = R(0);
 #pragma unroll 1
     for (int j = 0; j < M; ++j) {
         R tep[6], tv[NS], tal[NS], aep[6], av[NS], aal[NS];
@@ -434,7 +556,8 @@ __device__ void integrate(const LawP<R> &P, const R e0[6], const R e1[6], R (&ep
             R e[6];
 #pragma unroll
             for (int i = 0; i < 6; ++i) e[i] = e0[i] + sfrac * de[i];
-            rk_stage<R, NS>(P, e, tep, tv, tal, ep, v, al, aep, av, aal, wacc, cnext, st < 3);
+            rk_stage<R, NS, SPEC>(P, e, tep, tv, tal, ep, v, al, aep, av, aal, yw, wacc, cnext, st < 3,
+                                  nact, nnewt);
         }
 #pragma unroll
         for (int i = 0; i < 6; ++i) ep[i] = aep[i];
@@ -449,13 +572,10 @@ __device__ void integrate(const LawP<R> &P, const R e0[6], const R e1[6], R (&ep
 template <typename R>
 __device__ __forceinline__ void hooke(const LawP<R> &P, const R e[6], const R ep[6], R sig[6])
 {
+    R ee[6];
 #pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        R s = R(0);
-#pragma unroll
-        for (int j = 0; j < 6; ++j) s += P.C[i * 6 + j] * (e[j] - ep[j]);
-        sig[i] = s;
-    }
+    for (int i = 0; i < 6; ++i) ee[i] = e[i] - ep[i];
+    hooke_c<R, LAW_GENERAL>(P.C, ee, sig);
 }
 
 }  // namespace cpf

@@ -30,6 +30,7 @@ struct Scalars {
     double err_hist[8];
     double Sigma[6];    // mean stress of the last evaluated iterate
     double err_eq, err_bc, mean_sig_eq, mean_v, mean_f;
+    double work_active, work_newton;   // law work counters summed over the step
 };
 
 template <typename R>
@@ -134,15 +135,15 @@ __device__ __forceinline__ void store_state(R *__restrict__ st, long nvox, long 
 }
 
 // Local law at one voxel: lab strains in, lab stress out, state in place.
-template <typename R, int NS>
+template <typename R, int NS, int SPEC>
 __device__ __forceinline__ void voxel_law(const LawP<R> &P, const R Q[9], const R e0l[6],
                                           const R e1l[6], R (&ep)[6], R (&v)[NS], R (&al)[NS],
-                                          R dt, int M, R sigl[6])
+                                          R dt, int M, R sigl[6], int &nact, int &nnewt)
 {
     R e0[6], e1[6], sc[6];
     rot_to_crystal(Q, e0l, e0);
     rot_to_crystal(Q, e1l, e1);
-    integrate<R, NS>(P, e0, e1, ep, v, al, dt, M);
+    integrate<R, NS, SPEC>(P, e0, e1, ep, v, al, dt, M, nact, nnewt);
     hooke(P, e1, ep, sc);
     rot_to_lab(Q, sc, sigl);
 }
@@ -150,10 +151,41 @@ __device__ __forceinline__ void voxel_law(const LawP<R> &P, const R Q[9], const 
 // ---------------------------------------------------------------------------
 // Fused x pass of one iteration.  Block = L x-lines of nx voxels.
 // ---------------------------------------------------------------------------
-template <typename R, int NS>
-__global__ __launch_bounds__(256) void k_xpass_iter(XArgs<R> a, LawP<R> P, FftPlan px, int first)
+// Minimum resident blocks per CU for the law kernels (register budget):
+// two 256-thread blocks = 2 waves per SIMD.
+#ifndef CPF_XPASS_MINBLOCKS_F32
+#define CPF_XPASS_MINBLOCKS_F32 2
+#endif
+#ifndef CPF_XPASS_MINBLOCKS_F64
+#define CPF_XPASS_MINBLOCKS_F64 1
+#endif
+#define CPF_XPASS_MINBLOCKS(R) (sizeof(R) == 4 ? CPF_XPASS_MINBLOCKS_F32 : CPF_XPASS_MINBLOCKS_F64)
+#ifndef CPF_LAW_IN_LDS
+#define CPF_LAW_IN_LDS 0
+#endif
+// The law parameters as the kernel reads them: straight from the argument
+// block, or from a copy in LDS made once per block.
+template <typename R>
+__device__ __forceinline__ const LawP<R> &law_params(const LawP<R> &arg)
+{
+#if CPF_LAW_IN_LDS
+    __shared__ LawP<R> lp;
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(&arg);
+    uint32_t *dst = reinterpret_cast<uint32_t *>(&lp);
+    for (int i = threadIdx.x; i < (int)(sizeof(LawP<R>) / 4); i += blockDim.x) dst[i] = src[i];
+    __syncthreads();
+    return lp;
+#else
+    return arg;
+#endif
+}
+
+template <typename R, int NS, int SPEC>
+__global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R)) void k_xpass_iter(XArgs<R> a, LawP<R> Parg, FftPlan px,
+                                                                         int first)
 {
     if (a.sc->done) return;
+    const LawP<R> &P = law_params(Parg);
     extern __shared__ unsigned char smem_raw[];
     C2<R> *buf = reinterpret_cast<C2<R> *>(smem_raw);
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -197,8 +229,11 @@ __global__ __launch_bounds__(256) void k_xpass_iter(XArgs<R> a, LawP<R> P, FftPl
         for (int i = 0; i < 9; ++i) Q[i] = a.Qtab[lab * 9 + i];
         R ep[6], v[NS], al[NS];
         load_state<R, NS>(a.st_in, a.nvox, vox, P.nsys, Q, ep, v, al);
-        voxel_law<R, NS>(P, Q, e0, e1, ep, v, al, a.dt, a.M, sig);
+        int nact = 0, nnewt = 0;
+        voxel_law<R, NS, SPEC>(P, Q, e0, e1, ep, v, al, a.dt, a.M, sig, nact, nnewt);
         store_state<R, NS>(a.st_out, a.nvox, vox, P.nsys, Q, ep, v, al);
+        part[9] = (double)nact;
+        part[10] = (double)nnewt;
 #pragma unroll
         for (int c = 0; c < 6; ++c) part[c] = (double)sig[c];
         part[6] = (double)von_mises(sig);
@@ -356,7 +391,12 @@ __device__ __forceinline__ void green_point(C2<R> (&s)[6], int kx, int ky, int k
     }
 }
 
-// mode 1: forward z, Gamma0 and residual, inverse z; mode 0: forward z only.
+// mode bits: ZMODE_FWD forward z transform; ZMODE_GREEN Gamma0, residual and
+// inverse z transform.  The iteration uses both; the component operators
+// use one each.
+constexpr int ZMODE_FWD = 1;
+constexpr int ZMODE_GREEN = 2;
+
 template <typename R, int EPT>
 __global__ __launch_bounds__(256) void k_zpass_green(C2<R> *spec, const C2<R> *tw, FftPlan pz,
                                                      GreenArgs<R> g, double *part, const Scalars *sc,
@@ -380,8 +420,8 @@ __global__ __launch_bounds__(256) void k_zpass_green(C2<R> *spec, const C2<R> *t
         buf[(c * tw_ + col) * ls + kz] = spec[c * plane + kz * zstride + colbase + col];
     }
     __syncthreads();
-    lds_fft<R, false, EPT>(buf, 6 * tw_, ls, pz, tw, tid, nthr);
-    if (mode == 0) {
+    if (mode & ZMODE_FWD) lds_fft<R, false, EPT>(buf, 6 * tw_, ls, pz, tw, tid, nthr);
+    if (!(mode & ZMODE_GREEN)) {
         for (int i = tid; i < nrow * tw_; i += nthr) {
             const int r = i / tw_, col = i - r * tw_;
             const int c = r / nz, kz = r - c * nz;
@@ -436,6 +476,7 @@ __global__ void k_begin_step(Scalars *sc, StepInit si)
     sc->stagnated = 0;
     sc->err_eq = sc->err_bc = 0.0;
     sc->mean_sig_eq = sc->mean_v = sc->mean_f = 0.0;
+    sc->work_active = sc->work_newton = 0.0;
 }
 
 struct BcArgs {
@@ -483,6 +524,8 @@ __global__ __launch_bounds__(256) void k_bc_update(const double *__restrict__ px
     sc->mean_sig_eq = tot[6] / b.nvox;
     sc->mean_v = b.n_slip > 0 ? tot[7] / (b.nvox * b.n_slip) : 0.0;
     sc->mean_f = b.n_twin > 0 ? tot[8] / (b.nvox * b.n_twin) : 0.0;
+    sc->work_active += tot[9];
+    sc->work_newton += tot[10];
 
     const double err = fmax(err_eq, err_bc);
     if (!(err == err) || isinf(tot[0]) || !(tot[0] == tot[0])) {
@@ -521,11 +564,12 @@ __global__ __launch_bounds__(256) void k_bc_update(const double *__restrict__ px
 // ---------------------------------------------------------------------------
 // Component operators and field outputs
 // ---------------------------------------------------------------------------
-template <typename R, int NS>
-__global__ __launch_bounds__(256) void k_constitutive(const int32_t *labels, const R *Qtab, const R *eps0,
-                                                      const R *eps1, const R *st0, R *st1, R *sig,
-                                                      LawP<R> P, long nvox, R dt, int M)
+template <typename R, int NS, int SPEC>
+__global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R)) void k_constitutive(
+    const int32_t *labels, const R *Qtab, const R *eps0, const R *eps1, const R *st0, R *st1, R *sig,
+    LawP<R> Parg, long nvox, R dt, int M)
 {
+    const LawP<R> &P = law_params(Parg);
     const long vox = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (vox >= nvox) return;
     const int lab = labels[vox];
@@ -540,7 +584,8 @@ __global__ __launch_bounds__(256) void k_constitutive(const int32_t *labels, con
     }
     R ep[6], v[NS], al[NS];
     load_state<R, NS>(st0, nvox, vox, P.nsys, Q, ep, v, al);
-    voxel_law<R, NS>(P, Q, e0, e1, ep, v, al, dt, M, s);
+    int nact = 0, nnewt = 0;
+    voxel_law<R, NS, SPEC>(P, Q, e0, e1, ep, v, al, dt, M, s, nact, nnewt);
     store_state<R, NS>(st1, nvox, vox, P.nsys, Q, ep, v, al);
 #pragma unroll
     for (int c = 0; c < 6; ++c) sig[c * nvox + vox] = s[c];
