@@ -163,6 +163,29 @@ int cpf_solver_run(cpf_solver *s, const cpf_path *path, cpf_step_out *out);
 int cpf_solver_field(cpf_solver *s, int field, void *dev_out);
 void cpf_solver_destroy(cpf_solver *s);
 
+/* Batches (many RVEs in one solve).  All members share the crystal
+ * stiffness, the systems and the law; each has its own grid, labels and
+ * orientations (the paper's realizations, Section 2.3).  Every kernel of an
+ * iteration covers all members in one launch, each member keeps its own
+ * convergence flag on the device, and the load step ends when all members
+ * have converged.  cpf_solver_* calls act on member 0 where a single RVE is
+ * meant (fields, component operators); cpf_solver_step/run need n = 1. */
+int cpf_batch_create(int n, const cpf_problem *const *probs, const cpf_options *opt, cpf_solver **out);
+int cpf_batch_size(const cpf_solver *s, int *n);
+/* Load step n for every member; outs has one entry per member. */
+int cpf_batch_step(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *outs);
+int cpf_batch_field(cpf_solver *s, int rve, int field, void *dev_out);
+/* Launch iterations as one captured HIP graph of iters_per_launch
+ * iterations (all members, device-side early exit); 0 returns to direct
+ * launches.  Kernel timing does not see inside graphs. */
+int cpf_solver_set_graph(cpf_solver *s, int iters_per_launch);
+/* Pick the y and z pass tile widths (kx columns per block) of every
+ * member's grid size by timing the candidates on the bound workspace
+ * (results are cached per grid and precision for the process).  Resets the
+ * committed state.  *n_timed receives the number of timed configurations. */
+int cpf_solver_autotune(cpf_solver *s, int *n_timed);
+int cpf_solver_tiles(const cpf_solver *s, int rve, int *ty, int *tz);
+
 /* Kernel timing (profiling aid).  While enabled, each kernel launch of the
  * iteration is bracketed by HIP events on the bound stream and its device
  * time is accumulated per kernel class: 0 x pass (local law and x

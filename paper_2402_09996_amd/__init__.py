@@ -135,28 +135,40 @@ def _outs_to_dict(outs, n):
     return r
 
 
-class Solver:
-    """A bound solver: device workspace from torch, work on a torch stream."""
+def _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_every):
+    o = _lib.CpfOptions()
+    _lib.lib().cpf_options_default(ctypes.byref(o))
+    o.precision = CPF_PREC_FP64 if precision == "fp64" else CPF_PREC_FP32
+    o.tol, o.max_iter, o.h_max, o.rk4_M = float(tol), int(max_iter), float(h_max), int(rk4_M)
+    if mu0 is not None:
+        o.lam0, o.mu0 = float(lam0), float(mu0)
+    o.stag_tol, o.check_every = float(stag_tol), int(check_every)
+    return o
 
-    def __init__(self, problem: Problem, precision: str = "fp64", tol: float = 1e-8,
+
+class Solver:
+    """A bound solver: device workspace from torch, work on a torch stream.
+
+    ``problem`` is one :class:`Problem`, or a list of them for a batch
+    (members share the law; see :meth:`step_batch`)."""
+
+    def __init__(self, problem, precision: str = "fp64", tol: float = 1e-8,
                  max_iter: int = 1000, h_max: float = 0.05, rk4_M: int = 0,
                  lam0: Optional[float] = None, mu0: Optional[float] = None,
                  stag_tol: float = 0.0, check_every: int = 0, device: str = "cuda:0",
-                 stream=None):
+                 stream=None, graph_iters: int = 0, autotune: bool = False):
         import torch
         L = _lib.lib()
-        self.problem = problem
+        probs = list(problem) if isinstance(problem, (list, tuple)) else [problem]
+        self.problems = probs
+        self.problem = probs[0]
+        self.n_rve = len(probs)
         self.precision = precision
         self.dtype = {"fp64": torch.float64, "fp32": torch.float32}[precision]
-        o = _lib.CpfOptions()
-        L.cpf_options_default(ctypes.byref(o))
-        o.precision = CPF_PREC_FP64 if precision == "fp64" else CPF_PREC_FP32
-        o.tol, o.max_iter, o.h_max, o.rk4_M = float(tol), int(max_iter), float(h_max), int(rk4_M)
-        if mu0 is not None:
-            o.lam0, o.mu0 = float(lam0), float(mu0)
-        o.stag_tol, o.check_every = float(stag_tol), int(check_every)
+        o = _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_every)
         h = ctypes.c_void_p()
-        check(L.cpf_solver_create(problem._h, ctypes.byref(o), ctypes.byref(h)))
+        arr = (ctypes.c_void_p * self.n_rve)(*[p._h.value for p in probs])
+        check(L.cpf_batch_create(self.n_rve, arr, ctypes.byref(o), ctypes.byref(h)))
         self._h = h
         size = ctypes.c_size_t()
         check(L.cpf_solver_workspace_size(h, ctypes.byref(size)))
@@ -164,12 +176,54 @@ class Solver:
         self.workspace = torch.empty(int(size.value) + 256, dtype=torch.uint8, device=self.device)
         base = self.workspace.data_ptr()
         self._ws_ptr = (base + 255) & ~255
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        if stream is None:
+            # graph capture needs a stream of its own (the legacy default
+            # stream cannot be captured); default priority
+            stream = torch.cuda.Stream(self.device) if graph_iters else \
+                torch.cuda.current_stream(self.device)
+        self.stream = stream
         check(L.cpf_solver_bind(h, ctypes.c_void_p(self._ws_ptr), int(size.value),
                                 ctypes.c_void_p(self.stream.cuda_stream)))
-        self.nz, self.ny, self.nx = problem.shape
+        self.nz, self.ny, self.nx = self.problem.shape
         self.nvox = self.nx * self.ny * self.nz
         self.nhx = self.nx // 2 + 1
+        self.autotuned = 0
+        if autotune:
+            self.autotune()
+        if graph_iters:
+            self.set_graph(graph_iters)
+
+    def autotune(self) -> int:
+        n = ctypes.c_int()
+        check(_lib.lib().cpf_solver_autotune(self._h, ctypes.byref(n)))
+        self.autotuned = n.value
+        return n.value
+
+    def tiles(self, rve: int = 0) -> tuple[int, int]:
+        ty, tz = ctypes.c_int(), ctypes.c_int()
+        check(_lib.lib().cpf_solver_tiles(self._h, int(rve), ctypes.byref(ty), ctypes.byref(tz)))
+        return ty.value, tz.value
+
+    def set_graph(self, iters_per_launch: int):
+        check(_lib.lib().cpf_solver_set_graph(self._h, int(iters_per_launch)))
+
+    def step_batch(self, path, n: int) -> list[dict]:
+        """Load step n for every member of the batch."""
+        pa = _PathArgs(path)
+        outs = (_lib.CpfStepOut * self.n_rve)()
+        check(_lib.lib().cpf_batch_step(self._h, ctypes.byref(pa.c), int(n), outs))
+        d = _outs_to_dict(outs, self.n_rve)
+        return [{k: v[i] for k, v in d.items()} for i in range(self.n_rve)]
+
+    def field_of(self, rve: int, name: str):
+        import torch
+        k = FIELDS[name]
+        nz, ny, nx = self.problems[rve].shape
+        nc = 6 if k in (CPF_FIELD_STRESS, CPF_FIELD_STRAIN, CPF_FIELD_PLASTIC_STRAIN) \
+            else self.problem.n_sys
+        out = torch.empty((nc, nz, ny, nx), dtype=self.dtype, device=self.device)
+        check(_lib.lib().cpf_batch_field(self._h, int(rve), k, ctypes.c_void_p(out.data_ptr())))
+        return out
 
     # -- solve ---------------------------------------------------------------
     def reset(self):
@@ -209,6 +263,13 @@ class Solver:
         check(_lib.lib().cpf_solver_get_timing(self._h, ms, n))
         return {k: (ms[i], n[i]) for i, k in enumerate(self.KERNELS)}
 
+    def _order_after_torch(self):
+        # inputs made by torch on its current stream must be complete before
+        # the library reads them on the solver's stream
+        import torch
+        if self.stream != torch.cuda.current_stream(self.device):
+            torch.cuda.current_stream(self.device).synchronize()
+
     # -- component operators ---------------------------------------------------
     def forward_fft(self, f):
         """Unnormalized 3D DFT of 6 real fields [6][nz][ny][nx] -> complex
@@ -216,6 +277,7 @@ class Solver:
         import torch
         f = f.to(device=self.device, dtype=self.dtype).contiguous()
         spec = torch.empty((6, self.nz, self.ny, self.nhx, 2), dtype=self.dtype, device=self.device)
+        self._order_after_torch()
         check(_lib.lib().cpf_op_forward_fft(self._h, ctypes.c_void_p(f.data_ptr()),
                                             ctypes.c_void_p(spec.data_ptr())))
         return torch.view_as_complex(spec)
@@ -227,6 +289,7 @@ class Solver:
         s = torch.view_as_real(spec.to(self.device)).to(self.dtype).contiguous().clone()
         out = torch.empty((6, self.nz, self.ny, self.nx), dtype=self.dtype, device=self.device)
         err2 = ctypes.c_double()
+        self._order_after_torch()
         check(_lib.lib().cpf_op_green(self._h, ctypes.c_void_p(s.data_ptr()),
                                       ctypes.c_void_p(out.data_ptr()), ctypes.byref(err2)))
         return out, err2.value
@@ -240,6 +303,7 @@ class Solver:
         assert args[0].numel() == 6 * self.nvox and args[2].numel() == D * self.nvox
         st1 = torch.empty((D, self.nz, self.ny, self.nx), dtype=self.dtype, device=self.device)
         sig = torch.empty((6, self.nz, self.ny, self.nx), dtype=self.dtype, device=self.device)
+        self._order_after_torch()
         check(_lib.lib().cpf_op_constitutive(
             self._h, *[ctypes.c_void_p(a.data_ptr()) for a in args],
             ctypes.c_void_p(st1.data_ptr()), ctypes.c_void_p(sig.data_ptr()), float(dt), int(M)))

@@ -94,6 +94,13 @@ SIGNATURES = {
     "cpf_solver_run": (_i, [_p, ctypes.POINTER(CpfPath), ctypes.POINTER(CpfStepOut)]),
     "cpf_solver_field": (_i, [_p, _i, _p]),
     "cpf_solver_destroy": (None, [_p]),
+    "cpf_batch_create": (_i, [_i, ctypes.POINTER(_p), ctypes.POINTER(CpfOptions), ctypes.POINTER(_p)]),
+    "cpf_batch_size": (_i, [_p, ctypes.POINTER(_i)]),
+    "cpf_batch_step": (_i, [_p, ctypes.POINTER(CpfPath), _i, ctypes.POINTER(CpfStepOut)]),
+    "cpf_batch_field": (_i, [_p, _i, _i, _p]),
+    "cpf_solver_set_graph": (_i, [_p, _i]),
+    "cpf_solver_autotune": (_i, [_p, ctypes.POINTER(_i)]),
+    "cpf_solver_tiles": (_i, [_p, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
     "cpf_solver_set_timing": (_i, [_p, _i]),
     "cpf_solver_get_timing": (_i, [_p, _dp, ctypes.POINTER(ctypes.c_longlong)]),
     "cpf_op_forward_fft": (_i, [_p, _p, _p]),

@@ -12,6 +12,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <tuple>
 #include <new>
 #include <string>
 #include <vector>
@@ -260,31 +263,44 @@ extern "C" int cpf_problem_reference_medium(const cpf_problem *p, double *lam0, 
 }
 
 // ---------------------------------------------------------------------------
-// solver
+// solver: a batch of RVEs sharing one law (a single solve is a batch of one)
 // ---------------------------------------------------------------------------
-struct cpf_solver {
+struct RveHost {
     cpf_problem pb;
-    cpf_options opt;
-    int prec;
     int nx, ny, nz, nhx;
     long nvox;
-    int D;
     FftPlan px, py, pz;
     int L, tpbx, nbx, ty, nty, tz, ntz, nbz;
-    size_t lds_x, lds_y, lds_z;
-    double lam0, mu0, K0[36];
-    int ns_inst;
-    int law_spec;     // LAW_GENERAL or LAW_TABLE1
-    // workspace
-    unsigned char *ws = nullptr;
-    size_t ws_bytes = 0;
-    hipStream_t stream = nullptr;
-    bool bound = false;
-    size_t off_labels, off_Q, off_eps[2], off_st[2], off_spec, off_tw[3], off_px, off_pz, off_sc, total;
-    int eps_cur = 0, st_cur = 0;
+    bool tiles_fixed = false;   // set explicitly or by the autotuner
+    size_t off_labels, off_Q, off_eps[2], off_st[2], off_spec, off_tw[3], off_px, off_pz, off_sc;
+    int cur = 0;
     double Sigma_n[6], E_n[6];
     int prev_iters = 8;
-    Scalars *hsc = nullptr;   // pinned host mirror
+};
+
+struct cpf_solver {
+    std::vector<RveHost> rv;
+    cpf_options opt;
+    int prec;
+    int D;                      // state components 6 + 2S (shared law)
+    int ns_inst, law_spec;
+    double lam0, mu0, K0[36];
+    int n_slip, n_twin;
+    // pass grids over all RVEs
+    int nbx_tot = 0, nby_tot = 0, nbz_tot = 0;
+    size_t lds_x = 0, lds_y = 0, lds_z = 0;
+    // workspace
+    unsigned char *ws = nullptr;
+    size_t ws_bytes = 0, total = 0;
+    size_t off_dev, off_si, off_opdev;
+    hipStream_t stream = nullptr;
+    bool bound = false;
+    Scalars *hsc = nullptr;     // pinned host mirror of the per-RVE scalars
+    StepInit *hsi = nullptr;    // pinned per-RVE step records
+    // graph of G iterations (0: direct launches)
+    int graph_iters = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
     // kernel timing
     bool timing = false;
     double t_ms[CPF_NKERNELS] = {0};
@@ -343,46 +359,132 @@ static int timed_collect(cpf_solver *s)
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Elements per thread the y and z pass kernels are compiled for.
+constexpr int EPT_Y = 16;
+template <typename R> constexpr int ept_z() { return sizeof(R) == 4 ? 24 : 12; }
+constexpr size_t LDS_LIMIT = 64 * 1024;
+
+template <typename R>
+static bool tiles_valid(const RveHost &h, int ty, int tz)
+{
+    const size_t cb = sizeof(C2<R>);
+    return ty >= 1 && tz >= 1 && ty <= h.nhx && tz <= h.nhx && ty * h.ny <= EPT_Y * 256 &&
+           6 * tz * h.nz <= ept_z<R>() * 256 && (size_t)ty * (h.ny + 1) * cb <= LDS_LIMIT &&
+           6 * (size_t)tz * (h.nz + 1) * cb <= LDS_LIMIT;
+}
+
+template <typename R>
+static void set_tiles(RveHost &h, int ty, int tz)
+{
+    h.ty = ty;
+    h.nty = (h.nhx + ty - 1) / ty;
+    h.tz = tz;
+    h.ntz = (h.nhx + tz - 1) / tz;
+    h.nbz = h.ntz * h.ny;
+}
+
+template <typename R>
+static void default_tiles(RveHost &h)
+{
+    const bool f32 = sizeof(R) == 4;
+    int ty = std::min(std::min(f32 ? 16 : 8, std::max(1, EPT_Y * 256 / h.ny)), h.nhx);
+    int tz = std::min(std::min(16, std::max(1, ept_z<R>() * 256 / (6 * h.nz))), h.nhx);
+    while (!tiles_valid<R>(h, ty, tz) && tz > 1) --tz;
+    while (!tiles_valid<R>(h, ty, tz) && ty > 1) --ty;
+    set_tiles<R>(h, ty, tz);
+}
+
+// Grid offsets of every RVE in each pass and the LDS sizes of the launches.
+template <typename R>
+static void pass_grids(cpf_solver *s)
+{
+    const size_t cb = sizeof(C2<R>);
+    s->nbx_tot = s->nby_tot = s->nbz_tot = 0;
+    s->lds_x = 3 * 256 * cb;
+    s->lds_y = s->lds_z = 0;
+    for (auto &h : s->rv) {
+        s->nbx_tot += h.nbx;
+        s->nby_tot += h.nty * h.nz * 6;
+        s->nbz_tot += h.nbz;
+        s->lds_y = std::max(s->lds_y, (size_t)h.ty * (h.ny + 1) * cb);
+        s->lds_z = std::max(s->lds_z, 6 * (size_t)h.tz * (h.nz + 1) * cb);
+    }
+}
+
 template <typename R>
 static void layout(cpf_solver *s)
 {
     const size_t cb = sizeof(C2<R>);
     size_t o = 0;
     auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
-    s->off_labels = take(sizeof(int32_t) * s->nvox);
-    s->off_Q = take(sizeof(R) * 9 * s->pb.nlab);
-    s->off_eps[0] = take(sizeof(R) * 6 * s->nvox);
-    s->off_eps[1] = take(sizeof(R) * 6 * s->nvox);
-    s->off_st[0] = take(sizeof(R) * s->D * s->nvox);
-    s->off_st[1] = take(sizeof(R) * s->D * s->nvox);
-    s->off_spec = take(cb * 6 * (size_t)s->nz * s->ny * s->nhx);
-    s->off_tw[0] = take(cb * s->nx);
-    s->off_tw[1] = take(cb * s->ny);
-    s->off_tw[2] = take(cb * s->nz);
-    s->off_px = take(sizeof(double) * NPX * s->nbx);
-    s->off_pz = take(sizeof(double) * s->nbz);
-    s->off_sc = take(sizeof(Scalars));
+    for (auto &h : s->rv) {
+        h.off_labels = take(sizeof(int32_t) * h.nvox);
+        h.off_Q = take(sizeof(R) * 9 * h.pb.nlab);
+        h.off_eps[0] = take(sizeof(R) * 6 * h.nvox);
+        h.off_eps[1] = take(sizeof(R) * 6 * h.nvox);
+        h.off_st[0] = take(sizeof(R) * s->D * h.nvox);
+        h.off_st[1] = take(sizeof(R) * s->D * h.nvox);
+        h.off_spec = take(cb * 6 * (size_t)h.nz * h.ny * h.nhx);
+        h.off_tw[0] = take(cb * h.nx);
+        h.off_tw[1] = take(cb * h.ny);
+        h.off_tw[2] = take(cb * h.nz);
+        h.off_px = take(sizeof(double) * NPX * h.nbx);
+        h.off_pz = take(sizeof(double) * h.nhx * h.ny);   // room for the smallest z tile
+        h.off_sc = take(sizeof(Scalars));
+    }
+    const size_t n = s->rv.size();
+    s->off_dev = take(sizeof(RveDev<R>) * n);
+    s->off_si = take(sizeof(StepInit) * n);
+    s->off_opdev = take(sizeof(RveDev<R>));
     s->total = o;
 }
 
 template <typename R>
-static void tiling(cpf_solver *s)
+static R *dptr(cpf_solver *s, size_t off) { return reinterpret_cast<R *>(s->ws + off); }
+
+template <typename R>
+static RveDev<R> make_dev(cpf_solver *s, const RveHost &h, int bx0, int by0, int bz0)
 {
-    const size_t cb = sizeof(C2<R>);
-    const bool f32 = sizeof(R) == 4;
-    s->L = std::max(1, 256 / s->nx);
-    s->tpbx = s->L * s->nx;
-    s->nbx = (s->ny * s->nz + s->L - 1) / s->L;
-    s->lds_x = 3 * (size_t)s->tpbx * cb;
-    const int ty_max = f32 ? 16 : 8;
-    s->ty = std::min(std::min(ty_max, std::max(1, 16 * 256 / s->ny)), s->nhx);
-    s->nty = (s->nhx + s->ty - 1) / s->ty;
-    s->lds_y = (size_t)s->ty * (s->ny + 1) * cb;
-    const int ept_z = f32 ? 24 : 12;
-    s->tz = std::min(std::min(16, std::max(1, ept_z * 256 / (6 * s->nz))), s->nhx);
-    s->ntz = (s->nhx + s->tz - 1) / s->tz;
-    s->nbz = s->ntz * s->ny;
-    s->lds_z = 6 * (size_t)s->tz * (s->nz + 1) * cb;
+    RveDev<R> d;
+    memset(&d, 0, sizeof d);
+    d.nx = h.nx; d.ny = h.ny; d.nz = h.nz; d.nhx = h.nhx;
+    d.L = h.L; d.tpbx = h.tpbx; d.nlines = h.ny * h.nz;
+    d.ty = h.ty; d.nty = h.nty; d.tz = h.tz; d.ntz = h.ntz;
+    d.bx0 = bx0; d.by0 = by0; d.bz0 = bz0;
+    d.nvox = h.nvox;
+    d.inv_nvox = R(1.0 / (double)h.nvox);
+    d.px = h.px; d.py = h.py; d.pz = h.pz;
+    d.labels = dptr<int32_t>(s, h.off_labels);
+    d.Qtab = dptr<R>(s, h.off_Q);
+    d.eps[0] = dptr<R>(s, h.off_eps[0]);
+    d.eps[1] = dptr<R>(s, h.off_eps[1]);
+    d.st[0] = dptr<R>(s, h.off_st[0]);
+    d.st[1] = dptr<R>(s, h.off_st[1]);
+    d.spec = dptr<C2<R>>(s, h.off_spec);
+    for (int a = 0; a < 3; ++a) d.tw[a] = dptr<C2<R>>(s, h.off_tw[a]);
+    d.part_x = dptr<double>(s, h.off_px);
+    d.part_z = dptr<double>(s, h.off_pz);
+    d.sc = dptr<Scalars>(s, h.off_sc);
+    return d;
+}
+
+// Upload the descriptor table of all RVEs (after binding or a tile change).
+template <typename R>
+static int upload_devs(cpf_solver *s)
+{
+    pass_grids<R>(s);
+    std::vector<RveDev<R>> t;
+    int bx = 0, by = 0, bz = 0;
+    for (auto &h : s->rv) {
+        t.push_back(make_dev<R>(s, h, bx, by, bz));
+        bx += h.nbx;
+        by += h.nty * h.nz * 6;
+        bz += h.nbz;
+    }
+    HIPCHK(hipMemcpyAsync(s->ws + s->off_dev, t.data(), sizeof(RveDev<R>) * t.size(), hipMemcpyHostToDevice,
+                          s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return CPF_OK;
 }
 
 // The specialized law kernel applies when the systems are those of Table 1
@@ -404,10 +506,42 @@ static bool table1_specializable(const cpf_problem &p)
     return true;
 }
 
-extern "C" int cpf_solver_create(const cpf_problem *p, const cpf_options *opt, cpf_solver **out)
+// Members of a batch share the crystal stiffness, the systems and the law.
+static bool same_material(const cpf_problem &a, const cpf_problem &b)
 {
-    if (!p || !out) return fail(CPF_E_INVALID_ARG, "null argument");
+    if (a.nsys != b.nsys || a.twin_mode != b.twin_mode || a.Kc != b.Kc || a.fm != b.fm || a.gT != b.gT ||
+        a.eta != b.eta)
+        return false;
+    if (memcmp(a.Cv, b.Cv, sizeof a.Cv) != 0 || memcmp(a.law, b.law, sizeof a.law) != 0) return false;
+    return a.m == b.m && a.tau0 == b.tau0 && a.fam == b.fam;
+}
+
+template <typename R>
+static void init_rve(RveHost &h, const cpf_problem &p)
+{
+    h.pb = p;
+    h.nx = p.nx; h.ny = p.ny; h.nz = p.nz;
+    h.nhx = p.nx / 2 + 1;
+    h.nvox = (long)p.nx * p.ny * p.nz;
+    radix_plan(h.nx, h.px);
+    radix_plan(h.ny, h.py);
+    radix_plan(h.nz, h.pz);
+    h.L = std::max(1, 256 / h.nx);
+    h.tpbx = h.L * h.nx;
+    h.nbx = (h.ny * h.nz + h.L - 1) / h.L;
+    default_tiles<R>(h);
+}
+
+extern "C" int cpf_batch_create(int n, const cpf_problem *const *probs, const cpf_options *opt,
+                                cpf_solver **out)
+{
+    if (!probs || !out || n < 1) return fail(CPF_E_INVALID_ARG, "need n >= 1 problems and an output");
     *out = nullptr;
+    for (int i = 0; i < n; ++i) {
+        if (!probs[i]) return fail(CPF_E_INVALID_ARG, "problem %d is null", i);
+        if (!same_material(*probs[0], *probs[i]))
+            return fail(CPF_E_INVALID_ARG, "problem %d: batch members must share stiffness, systems and law", i);
+    }
     cpf_options o;
     cpf_options_default(&o);
     if (opt) o = *opt;
@@ -417,25 +551,26 @@ extern "C" int cpf_solver_create(const cpf_problem *p, const cpf_options *opt, c
         return fail(CPF_E_INVALID_ARG, "need tol > 0, max_iter >= 1 and rk4_M > 0 or h_max > 0");
     cpf_solver *s = new (std::nothrow) cpf_solver();
     if (!s) return fail(CPF_E_INVALID_ARG, "out of host memory");
-    s->pb = *p;
+    const cpf_problem &p0 = *probs[0];
     s->opt = o;
     s->prec = o.precision;
-    s->nx = p->nx; s->ny = p->ny; s->nz = p->nz;
-    s->nhx = p->nx / 2 + 1;
-    s->nvox = (long)p->nx * p->ny * p->nz;
-    s->D = 6 + 2 * p->nsys;
-    radix_plan(s->nx, s->px);
-    radix_plan(s->ny, s->py);
-    radix_plan(s->nz, s->pz);
-    s->ns_inst = p->nsys <= 4 ? 4 : p->nsys <= 12 ? 12 : p->nsys <= 16 ? 16 : 32;
-    s->law_spec = table1_specializable(*p) ? LAW_TABLE1 : LAW_GENERAL;
-    if (s->prec == CPF_PREC_FP64) { tiling<double>(s); layout<double>(s); }
-    else { tiling<float>(s); layout<float>(s); }
+    s->D = 6 + 2 * p0.nsys;
+    s->ns_inst = p0.nsys <= 4 ? 4 : p0.nsys <= 12 ? 12 : p0.nsys <= 16 ? 16 : 32;
+    s->law_spec = table1_specializable(p0) ? LAW_TABLE1 : LAW_GENERAL;
+    s->n_slip = p0.n_slip;
+    s->n_twin = p0.n_twin;
+    s->rv.resize(n);
+    for (int i = 0; i < n; ++i) {
+        if (s->prec == CPF_PREC_FP64) init_rve<double>(s->rv[i], *probs[i]);
+        else init_rve<float>(s->rv[i], *probs[i]);
+    }
+    if (s->prec == CPF_PREC_FP64) { layout<double>(s); pass_grids<double>(s); }
+    else { layout<float>(s); pass_grids<float>(s); }
     if (o.mu0 > 0) {
         s->lam0 = o.lam0;
         s->mu0 = o.mu0;
     } else {
-        cpf_problem_reference_medium(p, &s->lam0, &s->mu0);
+        cpf_problem_reference_medium(&p0, &s->lam0, &s->mu0);
     }
     if (!(s->mu0 > 0) || !(s->lam0 + 2 * s->mu0 / 3 > 0)) {
         delete s;
@@ -451,6 +586,19 @@ extern "C" int cpf_solver_create(const cpf_problem *p, const cpf_options *opt, c
     return CPF_OK;
 }
 
+extern "C" int cpf_solver_create(const cpf_problem *p, const cpf_options *opt, cpf_solver **out)
+{
+    if (!p || !out) return fail(CPF_E_INVALID_ARG, "null argument");
+    return cpf_batch_create(1, &p, opt, out);
+}
+
+extern "C" int cpf_batch_size(const cpf_solver *s, int *n)
+{
+    if (!s || !n) return fail(CPF_E_INVALID_ARG, "null argument");
+    *n = (int)s->rv.size();
+    return CPF_OK;
+}
+
 extern "C" int cpf_solver_workspace_size(const cpf_solver *s, size_t *bytes)
 {
     if (!s || !bytes) return fail(CPF_E_INVALID_ARG, "null argument");
@@ -458,10 +606,20 @@ extern "C" int cpf_solver_workspace_size(const cpf_solver *s, size_t *bytes)
     return CPF_OK;
 }
 
+static void drop_graph(cpf_solver *s)
+{
+    if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
+    if (s->graph) (void)hipGraphDestroy(s->graph);
+    s->graph_exec = nullptr;
+    s->graph = nullptr;
+}
+
 extern "C" void cpf_solver_destroy(cpf_solver *s)
 {
     if (!s) return;
+    drop_graph(s);
     if (s->hsc) (void)hipHostFree(s->hsc);
+    if (s->hsi) (void)hipHostFree(s->hsi);
     for (auto &p : s->ev_pending) {
         (void)hipEventDestroy(p.second.first);
         (void)hipEventDestroy(p.second.second);
@@ -494,13 +652,21 @@ extern "C" int cpf_solver_get_timing(const cpf_solver *s, double *ms, long long 
     return CPF_OK;
 }
 
-template <typename R>
-static R *dptr(cpf_solver *s, size_t off) { return reinterpret_cast<R *>(s->ws + off); }
+extern "C" int cpf_solver_set_graph(cpf_solver *s, int iters_per_launch)
+{
+    if (!s) return fail(CPF_E_INVALID_ARG, "null solver");
+    if (iters_per_launch < 0 || iters_per_launch > 1024)
+        return fail(CPF_E_INVALID_ARG, "iterations per graph launch must be in [0, 1024]");
+    if (s->bound) HIPCHK(hipStreamSynchronize(s->stream));
+    drop_graph(s);
+    s->graph_iters = iters_per_launch;
+    return CPF_OK;
+}
 
 template <typename R>
 static LawP<R> make_law(const cpf_solver *s)
 {
-    const cpf_problem &p = s->pb;
+    const cpf_problem &p = s->rv[0].pb;
     LawP<R> P;
     memset(&P, 0, sizeof P);
     P.nsys = p.nsys;
@@ -539,40 +705,53 @@ static LawP<R> make_law(const cpf_solver *s)
 template <typename R>
 static int zero_state(cpf_solver *s)
 {
-    const long n6 = 6 * s->nvox, nD = (long)s->D * s->nvox;
-    hipLaunchKernelGGL(k_fill<R>, dim3(1024), dim3(256), 0, s->stream, dptr<R>(s, s->off_eps[0]), n6, R(0));
-    hipLaunchKernelGGL(k_fill<R>, dim3(1024), dim3(256), 0, s->stream, dptr<R>(s, s->off_eps[1]), n6, R(0));
-    hipLaunchKernelGGL(k_fill<R>, dim3(1024), dim3(256), 0, s->stream, dptr<R>(s, s->off_st[0]), nD, R(0));
-    hipLaunchKernelGGL(k_fill<R>, dim3(1024), dim3(256), 0, s->stream, dptr<R>(s, s->off_st[1]), nD, R(0));
+    for (auto &h : s->rv) {
+        const long n6 = 6 * h.nvox, nD = (long)s->D * h.nvox;
+        for (int b = 0; b < 2; ++b) {
+            hipLaunchKernelGGL(k_fill<R>, dim3(512), dim3(256), 0, s->stream, dptr<R>(s, h.off_eps[b]), n6, R(0));
+            hipLaunchKernelGGL(k_fill<R>, dim3(512), dim3(256), 0, s->stream, dptr<R>(s, h.off_st[b]), nD, R(0));
+        }
+        h.cur = 0;
+        for (int i = 0; i < 6; ++i) h.Sigma_n[i] = h.E_n[i] = 0.0;
+        h.prev_iters = 8;
+    }
     HIPCHK(hipGetLastError());
-    s->eps_cur = s->st_cur = 0;
-    for (int i = 0; i < 6; ++i) s->Sigma_n[i] = s->E_n[i] = 0.0;
-    s->prev_iters = 8;
     return CPF_OK;
 }
 
 template <typename R>
 static int bind_impl(cpf_solver *s)
 {
-    const cpf_problem &p = s->pb;
-    std::vector<R> Qr(p.Q.size());
-    for (size_t i = 0; i < Qr.size(); ++i) Qr[i] = R(p.Q[i]);
-    HIPCHK(hipMemcpyAsync(s->ws + s->off_labels, p.labels.data(), sizeof(int32_t) * s->nvox,
-                          hipMemcpyHostToDevice, s->stream));
-    HIPCHK(hipMemcpyAsync(s->ws + s->off_Q, Qr.data(), sizeof(R) * Qr.size(), hipMemcpyHostToDevice,
-                          s->stream));
-    const int ns[3] = {s->nx, s->ny, s->nz};
-    std::vector<C2<R>> tw[3];
-    for (int a = 0; a < 3; ++a) {
-        tw[a].resize(ns[a]);
-        for (int k = 0; k < ns[a]; ++k) {
-            const long double ang = -2.0L * 3.141592653589793238462643383279502884L * k / ns[a];
-            tw[a][k] = C2<R>{R(cosl(ang)), R(sinl(ang))};
-        }
-        HIPCHK(hipMemcpyAsync(s->ws + s->off_tw[a], tw[a].data(), sizeof(C2<R>) * ns[a],
+    for (auto &h : s->rv) {
+        const cpf_problem &p = h.pb;
+        std::vector<R> Qr(p.Q.size());
+        for (size_t i = 0; i < Qr.size(); ++i) Qr[i] = R(p.Q[i]);
+        HIPCHK(hipMemcpyAsync(s->ws + h.off_labels, p.labels.data(), sizeof(int32_t) * h.nvox,
                               hipMemcpyHostToDevice, s->stream));
+        HIPCHK(hipMemcpyAsync(s->ws + h.off_Q, Qr.data(), sizeof(R) * Qr.size(), hipMemcpyHostToDevice,
+                              s->stream));
+        const int ns[3] = {h.nx, h.ny, h.nz};
+        for (int a = 0; a < 3; ++a) {
+            std::vector<C2<R>> tw(ns[a]);
+            for (int k = 0; k < ns[a]; ++k) {
+                const long double ang = -2.0L * 3.141592653589793238462643383279502884L * k / ns[a];
+                tw[k] = C2<R>{R(cosl(ang)), R(sinl(ang))};
+            }
+            HIPCHK(hipMemcpyAsync(s->ws + h.off_tw[a], tw.data(), sizeof(C2<R>) * ns[a], hipMemcpyHostToDevice,
+                                  s->stream));
+        }
+        // the host vectors above are pageable: make each copy complete before they go
+        HIPCHK(hipStreamSynchronize(s->stream));
+        // scalars start as an ended step so that nothing runs before a step begins
+        Scalars z;
+        memset(&z, 0, sizeof z);
+        z.done = 1;
+        HIPCHK(hipMemcpyAsync(s->ws + h.off_sc, &z, sizeof z, hipMemcpyHostToDevice, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
     }
     int rc = zero_state<R>(s);
+    if (rc) return rc;
+    rc = upload_devs<R>(s);
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(s->stream));
     return CPF_OK;
@@ -584,10 +763,13 @@ extern "C" int cpf_solver_bind(cpf_solver *s, void *ws, size_t bytes, void *stre
     if (!ws || bytes < s->total)
         return fail(CPF_E_WORKSPACE, "workspace of %zu bytes given, %zu needed", bytes, s->total);
     if (((uintptr_t)ws) & 255) return fail(CPF_E_WORKSPACE, "workspace must be 256-byte aligned");
+    drop_graph(s);
     s->ws = (unsigned char *)ws;
     s->ws_bytes = bytes;
     s->stream = (hipStream_t)stream;
-    if (!s->hsc) HIPCHK(hipHostMalloc((void **)&s->hsc, sizeof(Scalars), hipHostMallocDefault));
+    const size_t n = s->rv.size();
+    if (!s->hsc) HIPCHK(hipHostMalloc((void **)&s->hsc, sizeof(Scalars) * n, hipHostMallocDefault));
+    if (!s->hsi) HIPCHK(hipHostMalloc((void **)&s->hsi, sizeof(StepInit) * n, hipHostMallocDefault));
     int rc = s->prec == CPF_PREC_FP64 ? bind_impl<double>(s) : bind_impl<float>(s);
     s->bound = rc == CPF_OK;
     return rc;
@@ -633,172 +815,109 @@ static void stress_block_inverse(const double K0[36], const int sidx[6], double 
         for (int b = 0; b < n; ++b) out[S[a] * 6 + S[b]] = A[a][n + b];
 }
 
+// ---------------------------------------------------------------------------
+// launches (all RVEs per grid)
+// ---------------------------------------------------------------------------
 template <typename R, int NS, int SPEC>
-static void launch_xiter(cpf_solver *s, const XArgs<R> &a, const LawP<R> &P, int first)
+static void launch_xiter(cpf_solver *s, const LawP<R> &P)
 {
-    hipLaunchKernelGGL((k_xpass_iter<R, NS, SPEC>), dim3(s->nbx), dim3(s->tpbx), s->lds_x, s->stream, a, P,
-                       s->px, first);
+    hipLaunchKernelGGL((k_xpass_iter<R, NS, SPEC>), dim3(s->nbx_tot), dim3(256), s->lds_x, s->stream,
+                       dptr<RveDev<R>>(s, s->off_dev), (int)s->rv.size(), P);
 }
 
 template <typename R>
-static void launch_xiter_any(cpf_solver *s, const XArgs<R> &a, const LawP<R> &P, int first)
+static void launch_xiter_any(cpf_solver *s, const LawP<R> &P)
 {
     if (s->law_spec == LAW_TABLE1) {
-        if (s->ns_inst == 12) launch_xiter<R, 12, LAW_TABLE1>(s, a, P, first);
-        else launch_xiter<R, 16, LAW_TABLE1>(s, a, P, first);
+        if (s->ns_inst == 12) launch_xiter<R, 12, LAW_TABLE1>(s, P);
+        else launch_xiter<R, 16, LAW_TABLE1>(s, P);
         return;
     }
     switch (s->ns_inst) {
-    case 4: launch_xiter<R, 4, LAW_GENERAL>(s, a, P, first); break;
-    case 12: launch_xiter<R, 12, LAW_GENERAL>(s, a, P, first); break;
-    case 16: launch_xiter<R, 16, LAW_GENERAL>(s, a, P, first); break;
-    default: launch_xiter<R, 32, LAW_GENERAL>(s, a, P, first); break;
+    case 4: launch_xiter<R, 4, LAW_GENERAL>(s, P); break;
+    case 12: launch_xiter<R, 12, LAW_GENERAL>(s, P); break;
+    case 16: launch_xiter<R, 16, LAW_GENERAL>(s, P); break;
+    default: launch_xiter<R, 32, LAW_GENERAL>(s, P); break;
     }
 }
 
+// table/nrve/grid default to the whole batch; the component operators and
+// the autotuner pass a one-RVE table and an explicit spectrum
 template <typename R>
-static GreenArgs<R> green_args(const cpf_solver *s)
+static void launch_y(cpf_solver *s, bool inv, const RveDev<R> *table = nullptr, int nrve = 0, int grid = 0,
+                     size_t lds = 0, C2<R> *spec = nullptr)
 {
-    GreenArgs<R> g;
-    g.nx = s->nx; g.ny = s->ny; g.nz = s->nz; g.nhx = s->nhx; g.tz = s->tz;
-    g.inv_mu0 = R(1.0 / s->mu0);
-    g.coef = R((s->lam0 + s->mu0) / (s->mu0 * (s->lam0 + 2.0 * s->mu0)));
-    return g;
-}
-
-template <typename R>
-static void launch_y(cpf_solver *s, C2<R> *spec, bool inv, const Scalars *sc)
-{
-    const C2<R> *tw = dptr<C2<R>>(s, s->off_tw[1]);
-    dim3 grid(s->nty, s->nz, 6);
+    if (!table) {
+        table = dptr<RveDev<R>>(s, s->off_dev);
+        nrve = (int)s->rv.size();
+        grid = s->nby_tot;
+        lds = s->lds_y;
+    }
     if (inv)
-        hipLaunchKernelGGL((k_ypass<R, true, 16>), grid, dim3(256), s->lds_y, s->stream, spec, tw, s->py,
-                           s->ny, s->nz, s->nhx, s->ty, sc);
+        hipLaunchKernelGGL((k_ypass<R, true, EPT_Y>), dim3(grid), dim3(256), lds, s->stream, table, nrve, spec);
     else
-        hipLaunchKernelGGL((k_ypass<R, false, 16>), grid, dim3(256), s->lds_y, s->stream, spec, tw, s->py,
-                           s->ny, s->nz, s->nhx, s->ty, sc);
+        hipLaunchKernelGGL((k_ypass<R, false, EPT_Y>), dim3(grid), dim3(256), lds, s->stream, table, nrve, spec);
 }
 
 template <typename R>
-static void launch_z(cpf_solver *s, C2<R> *spec, int mode, const Scalars *sc)
+static void launch_z(cpf_solver *s, int mode, const RveDev<R> *table = nullptr, int nrve = 0, int grid = 0,
+                     size_t lds = 0, C2<R> *spec = nullptr)
 {
-    const C2<R> *tw = dptr<C2<R>>(s, s->off_tw[2]);
-    dim3 grid(s->ntz, s->ny);
-    constexpr int EPT = sizeof(R) == 4 ? 24 : 12;
-    hipLaunchKernelGGL((k_zpass_green<R, EPT>), grid, dim3(256), s->lds_z, s->stream, spec, tw, s->pz,
-                       green_args<R>(s), dptr<double>(s, s->off_pz), sc, mode);
-}
-
-static void launch_bc(cpf_solver *s, const double *px, Scalars *sc, const BcArgs &b)
-{
-    hipLaunchKernelGGL(k_bc_update, dim3(1), dim3(256), 0, s->stream, px, dptr<double>(s, s->off_pz), sc, b);
+    if (!table) {
+        table = dptr<RveDev<R>>(s, s->off_dev);
+        nrve = (int)s->rv.size();
+        grid = s->nbz_tot;
+        lds = s->lds_z;
+    }
+    const R inv_mu0 = R(1.0 / s->mu0);
+    const R coef = R((s->lam0 + s->mu0) / (s->mu0 * (s->lam0 + 2.0 * s->mu0)));
+    hipLaunchKernelGGL((k_zpass_green<R, ept_z<R>()>), dim3(grid), dim3(256), lds, s->stream, table, nrve,
+                       inv_mu0, coef, mode, spec);
 }
 
 template <typename R>
-static int step_impl(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *out)
+static void launch_bc(cpf_solver *s)
 {
-    const double dt = path->t[n + 1] - path->t[n];
-    const int M = s->opt.rk4_M > 0 ? s->opt.rk4_M : substeps(dt, s->opt.h_max);
-    StepInit si;
-    double dE0[6] = {0, 0, 0, 0, 0, 0};
-    for (int i = 0; i < 6; ++i) {
-        si.sidx[i] = path->strain_ctrl[6 * n + i] ? 0 : 1;
-        si.target[i] = path->target[6 * n + i];
-        if (!si.sidx[i]) dE0[i] = si.target[i] - s->E_n[i];
-    }
-    stress_block_inverse(s->K0, si.sidx, si.K0inv);
-    // homogeneous reference-medium prediction of the stress-controlled part
-    double rhs[6];
-    for (int i = 0; i < 6; ++i) {
-        double k = 0;
-        for (int j = 0; j < 6; ++j) k += s->K0[i * 6 + j] * dE0[j];
-        rhs[i] = si.sidx[i] ? (si.target[i] - s->Sigma_n[i]) - k : 0.0;
-    }
-    for (int i = 0; i < 6; ++i) {
-        double d = 0;
-        for (int j = 0; j < 6; ++j) d += si.K0inv[i * 6 + j] * rhs[j];
-        if (si.sidx[i]) dE0[i] = d;
-        si.dE0[i] = dE0[i];
-        si.E0[i] = s->E_n[i] + dE0[i];
-    }
-    Scalars *sc = dptr<Scalars>(s, s->off_sc);
-    hipLaunchKernelGGL(k_begin_step, dim3(1), dim3(64), 0, s->stream, sc, si);
-
-    XArgs<R> a;
-    a.labels = dptr<int32_t>(s, s->off_labels);
-    a.Qtab = dptr<R>(s, s->off_Q);
-    a.eps_n = dptr<R>(s, s->off_eps[s->eps_cur]);
-    a.eps_k = dptr<R>(s, s->off_eps[1 - s->eps_cur]);
-    a.st_in = dptr<R>(s, s->off_st[s->st_cur]);
-    a.st_out = dptr<R>(s, s->off_st[1 - s->st_cur]);
-    a.spec = dptr<C2<R>>(s, s->off_spec);
-    a.tw = dptr<C2<R>>(s, s->off_tw[0]);
-    a.part = dptr<double>(s, s->off_px);
-    a.sc = sc;
-    a.nx = s->nx; a.ny = s->ny; a.nz = s->nz; a.nhx = s->nhx; a.L = s->L;
-    a.nlines = s->ny * s->nz;
-    a.nvox = s->nvox;
-    a.inv_nvox = R(1.0 / (double)s->nvox);
-    a.dt = R(dt);
-    a.M = M;
-    const LawP<R> P = make_law<R>(s);
     BcArgs b;
-    b.nbx = s->nbx; b.nbz = s->nbz;
-    b.nvox = (double)s->nvox;
-    b.n_slip = s->pb.n_slip; b.n_twin = s->pb.n_twin;
+    b.n_slip = s->n_slip;
+    b.n_twin = s->n_twin;
     b.tol = s->opt.tol;
     b.stag_tol = s->opt.stag_tol;
     b.max_iter = s->opt.max_iter;
+    hipLaunchKernelGGL(k_bc_update<R>, dim3(s->rv.size()), dim3(256), 0, s->stream,
+                       dptr<RveDev<R>>(s, s->off_dev), b);
+}
 
-    int queued = 0;
-    int chunk = s->opt.check_every > 0 ? s->opt.check_every : std::max(2, s->prev_iters);
-    for (;;) {
-        for (int c = 0; c < chunk; ++c, ++queued) {
-            TIMED(s, 0, (launch_xiter_any<R>(s, a, P, queued == 0 ? 1 : 0)));
-            TIMED(s, 1, (launch_y<R>(s, a.spec, false, sc)));
-            TIMED(s, 2, (launch_z<R>(s, a.spec, ZMODE_FWD | ZMODE_GREEN, sc)));
-            TIMED(s, 3, (launch_y<R>(s, a.spec, true, sc)));
-            TIMED(s, 4, launch_bc(s, a.part, sc, b));
-        }
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipMemcpyAsync(s->hsc, sc, sizeof(Scalars), hipMemcpyDeviceToHost, s->stream));
-        HIPCHK(hipStreamSynchronize(s->stream));
-        {
-            int rc = timed_collect(s);
-            if (rc) return rc;
-        }
-        if (s->hsc->done) break;
-        if (queued > s->opt.max_iter + 8)
-            return fail(CPF_E_BAD_STATE, "device did not end the step after %d iterations", queued);
-        chunk = s->opt.check_every > 0 ? s->opt.check_every : 4;
-    }
-    const Scalars &h = *s->hsc;
-    if (out) {
-        for (int i = 0; i < 6; ++i) { out->Sigma[i] = h.Sigma[i]; out->E[i] = h.E[i]; }
-        const double p3 = (h.Sigma[0] + h.Sigma[1] + h.Sigma[2]) / 3.0;
-        const double a0 = h.Sigma[0] - p3, a1 = h.Sigma[1] - p3, a2 = h.Sigma[2] - p3;
-        out->sig_eq_of_mean = sqrt(1.5 * (a0 * a0 + a1 * a1 + a2 * a2 +
-                                          2.0 * (h.Sigma[3] * h.Sigma[3] + h.Sigma[4] * h.Sigma[4] +
-                                                 h.Sigma[5] * h.Sigma[5])));
-        out->mean_sig_eq = h.mean_sig_eq;
-        out->mean_v = h.mean_v;
-        out->mean_f = h.mean_f;
-        out->err_eq = h.err_eq;
-        out->err_bc = h.err_bc;
-        out->n_active = h.work_active;
-        out->n_newton = h.work_newton;
-        out->iters = h.iter;
-        out->status = h.status;
-    }
-    if (h.status == -5) return fail(CPF_E_NAN, "non-finite stress or residual in load step %d", n);
-    if (h.status == -4)
-        return fail(CPF_E_NOT_CONVERGED, "load step %d: no convergence in %d iterations (err %.3g)", n,
-                    h.iter, std::max(h.err_eq, h.err_bc));
-    // commit: the iterate and the trial state become the committed ones
-    s->eps_cur = 1 - s->eps_cur;
-    s->st_cur = 1 - s->st_cur;
-    for (int i = 0; i < 6; ++i) { s->Sigma_n[i] = h.Sigma[i]; s->E_n[i] = h.E[i]; }
-    s->prev_iters = h.iter;
+template <typename R>
+static int launch_iteration(cpf_solver *s, const LawP<R> &P)
+{
+    TIMED(s, 0, launch_xiter_any<R>(s, P));
+    TIMED(s, 1, launch_y<R>(s, false));
+    TIMED(s, 2, launch_z<R>(s, ZMODE_FWD | ZMODE_GREEN));
+    TIMED(s, 3, launch_y<R>(s, true));
+    TIMED(s, 4, launch_bc<R>(s));
+    return CPF_OK;
+}
+
+// Capture graph_iters iterations of the batch into one executable graph.
+template <typename R>
+static int build_graph(cpf_solver *s, const LawP<R> &P)
+{
+    drop_graph(s);
+    if (!s->stream)
+        return fail(CPF_E_INVALID_ARG, "graph launches need a solver bound to a non-default stream");
+    const bool was_timing = s->timing;
+    s->timing = false;   // events are not recorded inside the graph
+    HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
+    int rc = CPF_OK;
+    for (int i = 0; i < s->graph_iters && rc == CPF_OK; ++i) rc = launch_iteration<R>(s, P);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(s->stream, &g);
+    s->timing = was_timing;
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(CPF_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    s->graph = g;
+    HIPCHK(hipGraphInstantiate(&s->graph_exec, s->graph, nullptr, nullptr, 0));
     return CPF_OK;
 }
 
@@ -808,16 +927,138 @@ static int check_path(const cpf_path *p)
         return fail(CPF_E_INVALID_ARG, "path needs n_steps >= 1 and t, strain_ctrl, target");
     for (int n = 0; n < p->n_steps; ++n)
         if (!(p->t[n + 1] > p->t[n])) return fail(CPF_E_INVALID_ARG, "path times must increase");
+    for (int i = 0; i < 6 * p->n_steps; ++i)
+        if (!std::isfinite(p->target[i])) return fail(CPF_E_INVALID_ARG, "path targets must be finite");
     return CPF_OK;
 }
 
-extern "C" int cpf_solver_step(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *out)
+template <typename R>
+static int step_impl(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *outs)
+{
+    const double dt = path->t[n + 1] - path->t[n];
+    const int M = s->opt.rk4_M > 0 ? s->opt.rk4_M : substeps(dt, s->opt.h_max);
+    const size_t nr = s->rv.size();
+    for (size_t r = 0; r < nr; ++r) {
+        RveHost &h = s->rv[r];
+        StepInit &si = s->hsi[r];
+        double dE0[6] = {0, 0, 0, 0, 0, 0};
+        for (int i = 0; i < 6; ++i) {
+            si.sidx[i] = path->strain_ctrl[6 * n + i] ? 0 : 1;
+            si.target[i] = path->target[6 * n + i];
+            if (!si.sidx[i]) dE0[i] = si.target[i] - h.E_n[i];
+        }
+        stress_block_inverse(s->K0, si.sidx, si.K0inv);
+        // homogeneous reference-medium prediction of the stress-controlled part
+        double rhs[6];
+        for (int i = 0; i < 6; ++i) {
+            double k = 0;
+            for (int j = 0; j < 6; ++j) k += s->K0[i * 6 + j] * dE0[j];
+            rhs[i] = si.sidx[i] ? (si.target[i] - h.Sigma_n[i]) - k : 0.0;
+        }
+        for (int i = 0; i < 6; ++i) {
+            double d = 0;
+            for (int j = 0; j < 6; ++j) d += si.K0inv[i * 6 + j] * rhs[j];
+            if (si.sidx[i]) dE0[i] = d;
+            si.dE0[i] = dE0[i];
+            si.E0[i] = h.E_n[i] + dE0[i];
+        }
+        si.cur = h.cur;
+        si.M = M;
+        si.dt = dt;
+    }
+    HIPCHK(hipMemcpyAsync(s->ws + s->off_si, s->hsi, sizeof(StepInit) * nr, hipMemcpyHostToDevice, s->stream));
+    hipLaunchKernelGGL(k_begin_step<R>, dim3(nr), dim3(64), 0, s->stream, dptr<RveDev<R>>(s, s->off_dev),
+                       dptr<StepInit>(s, s->off_si));
+
+    const LawP<R> P = make_law<R>(s);
+    if (s->graph_iters > 0 && !s->graph_exec) {
+        int rc = build_graph<R>(s, P);
+        if (rc) return rc;
+    }
+    int queued = 0, prev = 0;
+    for (const auto &h : s->rv) prev = std::max(prev, h.prev_iters);
+    int chunk = s->opt.check_every > 0 ? s->opt.check_every : std::max(2, prev);
+    for (;;) {
+        if (s->graph_exec) {
+            HIPCHK(hipGraphLaunch(s->graph_exec, s->stream));
+            queued += s->graph_iters;
+        } else {
+            for (int c = 0; c < chunk; ++c, ++queued) {
+                int rc = launch_iteration<R>(s, P);
+                if (rc) return rc;
+            }
+        }
+        HIPCHK(hipGetLastError());
+        for (size_t r = 0; r < nr; ++r)
+            HIPCHK(hipMemcpyAsync(s->hsc + r, s->ws + s->rv[r].off_sc, sizeof(Scalars), hipMemcpyDeviceToHost,
+                                  s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        {
+            int rc = timed_collect(s);
+            if (rc) return rc;
+        }
+        bool all = true;
+        for (size_t r = 0; r < nr; ++r) all = all && s->hsc[r].done;
+        if (all) break;
+        if (queued > s->opt.max_iter + 8)
+            return fail(CPF_E_BAD_STATE, "device did not end the step after %d iterations", queued);
+        chunk = s->opt.check_every > 0 ? s->opt.check_every : 4;
+    }
+    int worst = CPF_OK, worst_r = -1;
+    for (size_t r = 0; r < nr; ++r) {
+        const Scalars &h = s->hsc[r];
+        if (outs) {
+            cpf_step_out *out = outs + r;
+            for (int i = 0; i < 6; ++i) { out->Sigma[i] = h.Sigma[i]; out->E[i] = h.E[i]; }
+            const double p3 = (h.Sigma[0] + h.Sigma[1] + h.Sigma[2]) / 3.0;
+            const double a0 = h.Sigma[0] - p3, a1 = h.Sigma[1] - p3, a2 = h.Sigma[2] - p3;
+            out->sig_eq_of_mean = sqrt(1.5 * (a0 * a0 + a1 * a1 + a2 * a2 +
+                                              2.0 * (h.Sigma[3] * h.Sigma[3] + h.Sigma[4] * h.Sigma[4] +
+                                                     h.Sigma[5] * h.Sigma[5])));
+            out->mean_sig_eq = h.mean_sig_eq;
+            out->mean_v = h.mean_v;
+            out->mean_f = h.mean_f;
+            out->err_eq = h.err_eq;
+            out->err_bc = h.err_bc;
+            out->n_active = h.work_active;
+            out->n_newton = h.work_newton;
+            out->iters = h.iter;
+            out->status = h.status;
+        }
+        if (h.status != 0 && worst == CPF_OK) {
+            worst = h.status;
+            worst_r = (int)r;
+        }
+    }
+    if (worst == CPF_E_NAN)
+        return fail(CPF_E_NAN, "non-finite stress or residual in load step %d (RVE %d)", n, worst_r);
+    if (worst == CPF_E_NOT_CONVERGED)
+        return fail(CPF_E_NOT_CONVERGED, "load step %d (RVE %d): no convergence in %d iterations (err %.3g)", n,
+                    worst_r, s->hsc[worst_r].iter,
+                    std::max(s->hsc[worst_r].err_eq, s->hsc[worst_r].err_bc));
+    // commit: the iterate and the trial state become the committed ones
+    for (size_t r = 0; r < nr; ++r) {
+        RveHost &h = s->rv[r];
+        h.cur = 1 - h.cur;
+        for (int i = 0; i < 6; ++i) { h.Sigma_n[i] = s->hsc[r].Sigma[i]; h.E_n[i] = s->hsc[r].E[i]; }
+        h.prev_iters = s->hsc[r].iter;
+    }
+    return CPF_OK;
+}
+
+extern "C" int cpf_batch_step(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *outs)
 {
     if (!s || !s->bound) return fail(CPF_E_BAD_STATE, "solver not bound");
     int rc = check_path(path);
     if (rc) return rc;
     if (n < 0 || n >= path->n_steps) return fail(CPF_E_INVALID_ARG, "step %d outside the path", n);
-    return s->prec == CPF_PREC_FP64 ? step_impl<double>(s, path, n, out) : step_impl<float>(s, path, n, out);
+    return s->prec == CPF_PREC_FP64 ? step_impl<double>(s, path, n, outs) : step_impl<float>(s, path, n, outs);
+}
+
+extern "C" int cpf_solver_step(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *out)
+{
+    if (s && s->rv.size() != 1) return fail(CPF_E_INVALID_ARG, "batch solver: use cpf_batch_step");
+    return cpf_batch_step(s, path, n, out);
 }
 
 extern "C" int cpf_solver_run(cpf_solver *s, const cpf_path *path, cpf_step_out *out)
@@ -825,25 +1066,27 @@ extern "C" int cpf_solver_run(cpf_solver *s, const cpf_path *path, cpf_step_out 
     if (!s || !s->bound) return fail(CPF_E_BAD_STATE, "solver not bound");
     int rc = check_path(path);
     if (rc) return rc;
+    const int nr = (int)s->rv.size();
     for (int n = 0; n < path->n_steps; ++n) {
-        rc = cpf_solver_step(s, path, n, out ? out + n : nullptr);
+        rc = cpf_batch_step(s, path, n, out ? out + (size_t)n * nr : nullptr);
         if (rc) return rc;
     }
     return CPF_OK;
 }
 
 template <typename R>
-static int field_impl(cpf_solver *s, int field, void *dev_out)
+static int field_impl(cpf_solver *s, int r, int field, void *dev_out)
 {
-    const long nv = s->nvox;
+    const RveHost &h = s->rv[r];
+    const long nv = h.nvox;
     R *o = (R *)dev_out;
-    const R *eps = dptr<R>(s, s->off_eps[s->eps_cur]);
-    const R *st = dptr<R>(s, s->off_st[s->st_cur]);
+    const R *eps = dptr<R>(s, h.off_eps[h.cur]);
+    const R *st = dptr<R>(s, h.off_st[h.cur]);
+    const int nsys = h.pb.nsys;
     switch (field) {
     case CPF_FIELD_STRESS:
         hipLaunchKernelGGL(k_stress_field<R>, dim3((nv + 255) / 256), dim3(256), 0, s->stream,
-                           dptr<int32_t>(s, s->off_labels), dptr<R>(s, s->off_Q), eps, st, o,
-                           make_law<R>(s), nv);
+                           dptr<int32_t>(s, h.off_labels), dptr<R>(s, h.off_Q), eps, st, o, make_law<R>(s), nv);
         HIPCHK(hipGetLastError());
         break;
     case CPF_FIELD_STRAIN:
@@ -853,12 +1096,11 @@ static int field_impl(cpf_solver *s, int field, void *dev_out)
         HIPCHK(hipMemcpyAsync(o, st, sizeof(R) * 6 * nv, hipMemcpyDeviceToDevice, s->stream));
         break;
     case CPF_FIELD_ACC_SLIP:
-        HIPCHK(hipMemcpyAsync(o, st + 6 * nv, sizeof(R) * s->pb.nsys * nv, hipMemcpyDeviceToDevice,
-                              s->stream));
+        HIPCHK(hipMemcpyAsync(o, st + 6 * nv, sizeof(R) * nsys * nv, hipMemcpyDeviceToDevice, s->stream));
         break;
     case CPF_FIELD_BACK_STRAIN:
-        HIPCHK(hipMemcpyAsync(o, st + (6 + s->pb.nsys) * nv, sizeof(R) * s->pb.nsys * nv,
-                              hipMemcpyDeviceToDevice, s->stream));
+        HIPCHK(hipMemcpyAsync(o, st + (6 + nsys) * nv, sizeof(R) * nsys * nv, hipMemcpyDeviceToDevice,
+                              s->stream));
         break;
     default:
         return fail(CPF_E_INVALID_ARG, "unknown field %d", field);
@@ -867,26 +1109,146 @@ static int field_impl(cpf_solver *s, int field, void *dev_out)
     return CPF_OK;
 }
 
-extern "C" int cpf_solver_field(cpf_solver *s, int field, void *dev_out)
+extern "C" int cpf_batch_field(cpf_solver *s, int rve, int field, void *dev_out)
 {
     if (!s || !s->bound) return fail(CPF_E_BAD_STATE, "solver not bound");
     if (!dev_out) return fail(CPF_E_INVALID_ARG, "null output");
-    return s->prec == CPF_PREC_FP64 ? field_impl<double>(s, field, dev_out)
-                                    : field_impl<float>(s, field, dev_out);
+    if (rve < 0 || rve >= (int)s->rv.size()) return fail(CPF_E_INVALID_ARG, "RVE %d outside the batch", rve);
+    return s->prec == CPF_PREC_FP64 ? field_impl<double>(s, rve, field, dev_out)
+                                    : field_impl<float>(s, rve, field, dev_out);
+}
+
+extern "C" int cpf_solver_field(cpf_solver *s, int field, void *dev_out)
+{
+    return cpf_batch_field(s, 0, field, dev_out);
 }
 
 // ---------------------------------------------------------------------------
-// component operators
+// tile autotuner
+// ---------------------------------------------------------------------------
+struct TuneKey {
+    int nx, ny, nz, prec;
+    bool operator<(const TuneKey &o) const
+    {
+        return std::tie(nx, ny, nz, prec) < std::tie(o.nx, o.ny, o.nz, o.prec);
+    }
+};
+static std::map<TuneKey, std::pair<int, int>> g_tune_cache;
+static std::mutex g_tune_mu;
+
+// Time `reps` launches of one pass of RVE r with a one-RVE table.
+template <typename R>
+static int time_pass(cpf_solver *s, int r, int ty, int tz, bool zpass, int reps, float *ms_out)
+{
+    RveHost h = s->rv[r];
+    set_tiles<R>(h, ty, tz);
+    RveDev<R> d = make_dev<R>(s, h, 0, 0, 0);
+    RveDev<R> *tab = dptr<RveDev<R>>(s, s->off_opdev);
+    HIPCHK(hipMemcpyAsync(tab, &d, sizeof d, hipMemcpyHostToDevice, s->stream));
+    const size_t cb = sizeof(C2<R>);
+    hipEvent_t a, b;
+    HIPCHK(hipEventCreate(&a));
+    HIPCHK(hipEventCreate(&b));
+    for (int it = 0; it < reps + 1; ++it) {
+        if (it == 1) HIPCHK(hipEventRecord(a, s->stream));
+        if (zpass)
+            launch_z<R>(s, ZMODE_FWD | ZMODE_GREEN, tab, 1, h.ntz * h.ny, 6 * (size_t)tz * (h.nz + 1) * cb,
+                        d.spec);
+        else
+            launch_y<R>(s, false, tab, 1, h.nty * h.nz * 6, (size_t)ty * (h.ny + 1) * cb, d.spec);
+    }
+    HIPCHK(hipEventRecord(b, s->stream));
+    HIPCHK(hipEventSynchronize(b));
+    HIPCHK(hipGetLastError());
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, a, b));
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    *ms_out = ms / reps;
+    return CPF_OK;
+}
+
+template <typename R>
+static int autotune_impl(cpf_solver *s, int *n_timed)
+{
+    *n_timed = 0;
+    for (size_t r = 0; r < s->rv.size(); ++r) {
+        RveHost &h = s->rv[r];
+        const TuneKey key{h.nx, h.ny, h.nz, (int)sizeof(R)};
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tune_cache.find(key);
+            if (it != g_tune_cache.end()) {
+                set_tiles<R>(h, it->second.first, it->second.second);
+                continue;
+            }
+        }
+        const int cand[] = {1, 2, 4, 6, 8, 12, 16, 24, 32};
+        int best_ty = h.ty, best_tz = h.tz;
+        float best = 1e30f;
+        for (int ty : cand) {
+            if (!tiles_valid<R>(h, ty, h.tz)) continue;
+            float ms;
+            int rc = time_pass<R>(s, (int)r, ty, h.tz, false, 3, &ms);
+            if (rc) return rc;
+            ++*n_timed;
+            if (ms < best) { best = ms; best_ty = ty; }
+        }
+        best = 1e30f;
+        for (int tz : cand) {
+            if (!tiles_valid<R>(h, best_ty, tz)) continue;
+            float ms;
+            int rc = time_pass<R>(s, (int)r, best_ty, tz, true, 3, &ms);
+            if (rc) return rc;
+            ++*n_timed;
+            if (ms < best) { best = ms; best_tz = tz; }
+        }
+        set_tiles<R>(h, best_ty, best_tz);
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tune_cache[key] = {best_ty, best_tz};
+    }
+    // the tuning passes ran on the spectra: restore a clean start
+    int rc = zero_state<R>(s);
+    if (rc) return rc;
+    return upload_devs<R>(s);
+}
+
+extern "C" int cpf_solver_autotune(cpf_solver *s, int *n_timed)
+{
+    if (!s || !s->bound) return fail(CPF_E_BAD_STATE, "solver not bound");
+    int dummy = 0;
+    drop_graph(s);
+    int rc = s->prec == CPF_PREC_FP64 ? autotune_impl<double>(s, n_timed ? n_timed : &dummy)
+                                      : autotune_impl<float>(s, n_timed ? n_timed : &dummy);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return CPF_OK;
+}
+
+extern "C" int cpf_solver_tiles(const cpf_solver *s, int rve, int *ty, int *tz)
+{
+    if (!s || !ty || !tz) return fail(CPF_E_INVALID_ARG, "null argument");
+    if (rve < 0 || rve >= (int)s->rv.size()) return fail(CPF_E_INVALID_ARG, "RVE %d outside the batch", rve);
+    *ty = s->rv[rve].ty;
+    *tz = s->rv[rve].tz;
+    return CPF_OK;
+}
+
+// ---------------------------------------------------------------------------
+// component operators (RVE 0)
 // ---------------------------------------------------------------------------
 template <typename R>
 static int op_fft_impl(cpf_solver *s, const void *field, void *spec)
 {
+    const RveHost &h = s->rv[0];
     C2<R> *sp = (C2<R> *)spec;
-    hipLaunchKernelGGL(k_xpass_fwd<R>, dim3(s->nbx), dim3(s->tpbx), s->lds_x, s->stream, (const R *)field,
-                       sp, dptr<C2<R>>(s, s->off_tw[0]), s->px, s->nx, s->ny, s->nz, s->nhx, s->L,
-                       s->ny * s->nz, s->nvox);
-    launch_y<R>(s, sp, false, nullptr);
-    launch_z<R>(s, sp, ZMODE_FWD, nullptr);
+    const RveDev<R> d = make_dev<R>(s, h, 0, 0, 0);
+    RveDev<R> *tab = dptr<RveDev<R>>(s, s->off_opdev);
+    HIPCHK(hipMemcpyAsync(tab, &d, sizeof d, hipMemcpyHostToDevice, s->stream));
+    const size_t cb = sizeof(C2<R>);
+    hipLaunchKernelGGL(k_xpass_fwd<R>, dim3(h.nbx), dim3(256), s->lds_x, s->stream, (const R *)field, sp, d);
+    launch_y<R>(s, false, tab, 1, h.nty * h.nz * 6, (size_t)h.ty * (h.ny + 1) * cb, sp);
+    launch_z<R>(s, ZMODE_FWD, tab, 1, h.nbz, 6 * (size_t)h.tz * (h.nz + 1) * cb, sp);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s->stream));
     return CPF_OK;
@@ -903,16 +1265,19 @@ extern "C" int cpf_op_forward_fft(cpf_solver *s, const void *dev_field, void *de
 template <typename R>
 static int op_green_impl(cpf_solver *s, void *spec, void *outp, double *err2)
 {
+    const RveHost &h = s->rv[0];
     C2<R> *sp = (C2<R> *)spec;
-    launch_z<R>(s, sp, ZMODE_GREEN, nullptr);
-    launch_y<R>(s, sp, true, nullptr);
-    hipLaunchKernelGGL(k_xpass_inv<R>, dim3(s->nbx), dim3(s->tpbx), s->lds_x, s->stream, sp, (R *)outp,
-                       dptr<C2<R>>(s, s->off_tw[0]), s->px, s->nx, s->ny, s->nz, s->nhx, s->L,
-                       s->ny * s->nz, s->nvox, R(1.0 / (double)s->nvox));
+    const RveDev<R> d = make_dev<R>(s, h, 0, 0, 0);
+    RveDev<R> *tab = dptr<RveDev<R>>(s, s->off_opdev);
+    HIPCHK(hipMemcpyAsync(tab, &d, sizeof d, hipMemcpyHostToDevice, s->stream));
+    const size_t cb = sizeof(C2<R>);
+    launch_z<R>(s, ZMODE_GREEN, tab, 1, h.nbz, 6 * (size_t)h.tz * (h.nz + 1) * cb, sp);
+    launch_y<R>(s, true, tab, 1, h.nty * h.nz * 6, (size_t)h.ty * (h.ny + 1) * cb, sp);
+    hipLaunchKernelGGL(k_xpass_inv<R>, dim3(h.nbx), dim3(256), s->lds_x, s->stream, sp, (R *)outp, d);
     HIPCHK(hipGetLastError());
     if (err2) {
-        std::vector<double> pz(s->nbz);
-        HIPCHK(hipMemcpyAsync(pz.data(), s->ws + s->off_pz, sizeof(double) * s->nbz, hipMemcpyDeviceToHost,
+        std::vector<double> pz(h.nbz);
+        HIPCHK(hipMemcpyAsync(pz.data(), s->ws + h.off_pz, sizeof(double) * h.nbz, hipMemcpyDeviceToHost,
                               s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
         double t = 0;
@@ -935,9 +1300,10 @@ template <typename R, int NS, int SPEC = LAW_GENERAL>
 static void launch_cp(cpf_solver *s, const void *e0, const void *e1, const void *s0, void *s1, void *sig,
                       double dt, int M)
 {
-    hipLaunchKernelGGL((k_constitutive<R, NS, SPEC>), dim3((s->nvox + 255) / 256), dim3(256), 0, s->stream,
-                       dptr<int32_t>(s, s->off_labels), dptr<R>(s, s->off_Q), (const R *)e0, (const R *)e1,
-                       (const R *)s0, (R *)s1, (R *)sig, make_law<R>(s), s->nvox, R(dt), M);
+    const RveHost &h = s->rv[0];
+    hipLaunchKernelGGL((k_constitutive<R, NS, SPEC>), dim3((h.nvox + 255) / 256), dim3(256), 0, s->stream,
+                       dptr<int32_t>(s, h.off_labels), dptr<R>(s, h.off_Q), (const R *)e0, (const R *)e1,
+                       (const R *)s0, (R *)s1, (R *)sig, make_law<R>(s), h.nvox, R(dt), M);
 }
 
 template <typename R>
@@ -947,15 +1313,13 @@ static int op_cp_impl(cpf_solver *s, const void *e0, const void *e1, const void 
     if (s->law_spec == LAW_TABLE1) {
         if (s->ns_inst == 12) launch_cp<R, 12, LAW_TABLE1>(s, e0, e1, s0, s1, sig, dt, M);
         else launch_cp<R, 16, LAW_TABLE1>(s, e0, e1, s0, s1, sig, dt, M);
-        HIPCHK(hipGetLastError());
-        HIPCHK(hipStreamSynchronize(s->stream));
-        return CPF_OK;
-    }
-    switch (s->ns_inst) {
-    case 4: launch_cp<R, 4>(s, e0, e1, s0, s1, sig, dt, M); break;
-    case 12: launch_cp<R, 12>(s, e0, e1, s0, s1, sig, dt, M); break;
-    case 16: launch_cp<R, 16>(s, e0, e1, s0, s1, sig, dt, M); break;
-    default: launch_cp<R, 32>(s, e0, e1, s0, s1, sig, dt, M); break;
+    } else {
+        switch (s->ns_inst) {
+        case 4: launch_cp<R, 4>(s, e0, e1, s0, s1, sig, dt, M); break;
+        case 12: launch_cp<R, 12>(s, e0, e1, s0, s1, sig, dt, M); break;
+        case 16: launch_cp<R, 16>(s, e0, e1, s0, s1, sig, dt, M); break;
+        default: launch_cp<R, 32>(s, e0, e1, s0, s1, sig, dt, M); break;
+        }
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s->stream));

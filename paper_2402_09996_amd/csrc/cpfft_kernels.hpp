@@ -7,16 +7,18 @@
 //   ypass      : C2C transform along y of the half spectrum (fwd or inv)
 //   zpass_green: forward z transform, Gamma0 apply + equilibrium residual
 //                (FP64), inverse z transform
-//   bc_update  : one block: reduce the block sums, residuals, convergence
-//                decision and mixed-boundary mean-strain correction
+//   bc_update  : one block per RVE: reduce the block sums, residuals,
+//                convergence decision and mixed-boundary mean-strain correction
 //
+// Every pass covers all RVEs of a batch in one grid (a single solve is a
+// batch of one); blocks of RVEs whose step has ended return at once.
 // Plus single-purpose kernels for the component operators and fields.
 #pragma once
 #include "cpfft_device.hpp"
 
 namespace cpf {
 
-// Device-resident scalars of the running load step (FP64).
+// Device-resident scalars of the running load step of one RVE (FP64).
 struct Scalars {
     double dE[6];       // mean-strain increment applied by the next x pass
     double E[6];        // mean strain of the current iterate
@@ -27,29 +29,48 @@ struct Scalars {
     int done;           // 1: the step has ended (converged or failed)
     int status;         // 0 ok, negative CPF_E_* code
     int stagnated;
+    int cur;            // index of the committed strain/state buffers
+    int M;              // RK4 substeps of this load step
+    double dt;          // load step duration
     double err_hist[8];
     double Sigma[6];    // mean stress of the last evaluated iterate
     double err_eq, err_bc, mean_sig_eq, mean_v, mean_f;
     double work_active, work_newton;   // law work counters summed over the step
 };
 
+// One RVE of a (possibly one-element) batch as the kernels see it.  Every
+// pass launches one grid over all RVEs; block b belongs to the RVE whose
+// first block of that pass (bx0/by0/bz0) is the largest one <= b.
 template <typename R>
-struct XArgs {
-    const int32_t *labels;
-    const R *Qtab;          // [n_labels][9]
-    const R *eps_n;         // committed strain [6][nvox]
-    R *eps_k;               // iterate [6][nvox]
-    const R *st_in;         // committed state [D][nvox]
-    R *st_out;              // trial state [D][nvox]
-    C2<R> *spec;            // [6][nz][ny][nhx]
-    const C2<R> *tw;        // [nx]
-    double *part;           // [nblocks][NPX]
-    Scalars *sc;
-    int nx, ny, nz, nhx, L, nlines;
+struct RveDev {
+    int nx, ny, nz, nhx;
+    int L, tpbx, nlines;       // x pass: lines per block, threads used
+    int ty, nty, tz, ntz;      // y / z pass tiles (kx columns) and tile counts
+    int bx0, by0, bz0;         // first block in the x, y and z pass grids
     long nvox;
-    R inv_nvox, dt;
-    int M;
+    R inv_nvox;
+    FftPlan px, py, pz;
+    const int32_t *labels;     // [nvox]
+    const R *Qtab;             // [n_labels][9]
+    R *eps[2];                 // strain [6][nvox]: committed = eps[cur]
+    R *st[2];                  // state [6+2S][nvox]: committed = st[cur]
+    C2<R> *spec;               // [6][nz][ny][nhx]
+    const C2<R> *tw[3];        // twiddles exp(-2 pi i k / n) along x, y, z
+    double *part_x;            // [x blocks][NPX]
+    double *part_z;            // [z blocks]
+    Scalars *sc;
 };
+
+template <typename R>
+__device__ __forceinline__ int find_rve(const RveDev<R> *__restrict__ rv, int nrve, int b, int pass)
+{
+    int r = 0;
+    for (int i = 1; i < nrve; ++i) {
+        const int f = pass == 0 ? rv[i].bx0 : pass == 1 ? rv[i].by0 : rv[i].bz0;
+        if (f <= b) r = i;
+    }
+    return r;
+}
 
 // ---------------------------------------------------------------------------
 // x pass helpers (LDS layout: pair p, local line li -> (p*L + li)*nx)
@@ -181,30 +202,40 @@ __device__ __forceinline__ const LawP<R> &law_params(const LawP<R> &arg)
 }
 
 template <typename R, int NS, int SPEC>
-__global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R)) void k_xpass_iter(XArgs<R> a, LawP<R> Parg, FftPlan px,
-                                                                         int first)
+__global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R)) void k_xpass_iter(const RveDev<R> *__restrict__ rv,
+                                                                            int nrve, LawP<R> Parg)
 {
-    if (a.sc->done) return;
+    const int r = find_rve(rv, nrve, (int)blockIdx.x, 0);
+    const RveDev<R> &d = rv[r];
+    Scalars *sc = d.sc;
+    if (sc->done) return;
     const LawP<R> &P = law_params(Parg);
     extern __shared__ unsigned char smem_raw[];
     C2<R> *buf = reinterpret_cast<C2<R> *>(smem_raw);
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int li = tid / a.nx, x = tid - li * a.nx;
-    const int line = blockIdx.x * a.L + li;
-    const bool valid = line < a.nlines;
-    const int y = valid ? line % a.ny : 0, z = valid ? line / a.ny : 0;
-    const long vox = (long)line * a.nx + x;
+    const int first = sc->iter == 0;
+    const int cur = sc->cur;
+    const int li = tid / d.nx, x = tid - li * d.nx;
+    const int line = (blockIdx.x - d.bx0) * d.L + li;
+    const bool valid = tid < d.tpbx && line < d.nlines;
+    const int y = valid ? line % d.ny : 0, z = valid ? line / d.ny : 0;
+    const long vox = (long)line * d.nx + x;
+    const R *eps_n = d.eps[cur];
+    R *eps_k = d.eps[1 - cur];
 
     R corr[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
     if (!first) {
-        load_halfspec_pairs(a.spec, buf, a.nx, a.ny, a.nz, a.nhx, a.L, li, x, y, z, valid);
+        if (tid < d.tpbx)
+            load_halfspec_pairs(d.spec, buf, d.nx, d.ny, d.nz, d.nhx, d.L, li, x, y, z, valid);
         __syncthreads();
-        lds_fft<R, true, 8>(buf, 3 * a.L, a.nx, px, a.tw, tid, nthr);
+        lds_fft<R, true, 8>(buf, 3 * d.L, d.nx, d.px, d.tw[0], tid, nthr);
+        if (tid < d.tpbx) {
 #pragma unroll
-        for (int p = 0; p < 3; ++p) {
-            const C2<R> zz = buf[(p * a.L + li) * a.nx + x];
-            corr[2 * p] = zz.x * a.inv_nvox;
-            corr[2 * p + 1] = zz.y * a.inv_nvox;
+            for (int p = 0; p < 3; ++p) {
+                const C2<R> zz = buf[(p * d.L + li) * d.nx + x];
+                corr[2 * p] = zz.x * d.inv_nvox;
+                corr[2 * p + 1] = zz.y * d.inv_nvox;
+            }
         }
         __syncthreads();
     }
@@ -214,24 +245,24 @@ __global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R)) void k_xpass_iter(XArg
 #pragma unroll
     for (int i = 0; i < NPX; ++i) part[i] = 0.0;
     if (valid) {
-        const R *base = first ? a.eps_n : a.eps_k;
+        const R *base = first ? eps_n : eps_k;
         R e1[6], e0[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) {
-            e1[c] = base[c * a.nvox + vox] - corr[c] + R(a.sc->dE[c]);
-            e0[c] = a.eps_n[c * a.nvox + vox];
+            e1[c] = base[c * d.nvox + vox] - corr[c] + R(sc->dE[c]);
+            e0[c] = eps_n[c * d.nvox + vox];
         }
 #pragma unroll
-        for (int c = 0; c < 6; ++c) a.eps_k[c * a.nvox + vox] = e1[c];
-        const int lab = a.labels[vox];
+        for (int c = 0; c < 6; ++c) eps_k[c * d.nvox + vox] = e1[c];
+        const int lab = d.labels[vox];
         R Q[9];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) Q[i] = a.Qtab[lab * 9 + i];
+        for (int i = 0; i < 9; ++i) Q[i] = d.Qtab[lab * 9 + i];
         R ep[6], v[NS], al[NS];
-        load_state<R, NS>(a.st_in, a.nvox, vox, P.nsys, Q, ep, v, al);
+        load_state<R, NS>(d.st[cur], d.nvox, vox, P.nsys, Q, ep, v, al);
         int nact = 0, nnewt = 0;
-        voxel_law<R, NS, SPEC>(P, Q, e0, e1, ep, v, al, a.dt, a.M, sig, nact, nnewt);
-        store_state<R, NS>(a.st_out, a.nvox, vox, P.nsys, Q, ep, v, al);
+        voxel_law<R, NS, SPEC>(P, Q, e0, e1, ep, v, al, R(sc->dt), sc->M, sig, nact, nnewt);
+        store_state<R, NS>(d.st[1 - cur], d.nvox, vox, P.nsys, Q, ep, v, al);
         part[9] = (double)nact;
         part[10] = (double)nnewt;
 #pragma unroll
@@ -248,63 +279,64 @@ __global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R)) void k_xpass_iter(XArg
         part[7] = vs;
         part[8] = ft;
     }
-    block_sum<NPX>(part, a.part + (long)blockIdx.x * NPX);
+    block_sum<NPX>(part, d.part_x + (long)(blockIdx.x - d.bx0) * NPX);
 
+    if (tid < d.tpbx) {
 #pragma unroll
-    for (int p = 0; p < 3; ++p) buf[(p * a.L + li) * a.nx + x] = C2<R>{sig[2 * p], sig[2 * p + 1]};
+        for (int p = 0; p < 3; ++p) buf[(p * d.L + li) * d.nx + x] = C2<R>{sig[2 * p], sig[2 * p + 1]};
+    }
     __syncthreads();
-    lds_fft<R, false, 8>(buf, 3 * a.L, a.nx, px, a.tw, tid, nthr);
-    store_halfspec_pairs(a.spec, buf, a.nx, a.ny, a.nz, a.nhx, a.L, li, x, y, z, valid);
+    lds_fft<R, false, 8>(buf, 3 * d.L, d.nx, d.px, d.tw[0], tid, nthr);
+    if (tid < d.tpbx)
+        store_halfspec_pairs(d.spec, buf, d.nx, d.ny, d.nz, d.nhx, d.L, li, x, y, z, valid);
 }
 
-// Forward x transform of 6 real fields (component operator).
+// Forward x transform of 6 real fields (component operator, one RVE).
 template <typename R>
-__global__ __launch_bounds__(256) void k_xpass_fwd(const R *__restrict__ f, C2<R> *spec, const C2<R> *tw,
-                                                   FftPlan px, int nx, int ny, int nz, int nhx, int L,
-                                                   int nlines, long nvox)
+__global__ __launch_bounds__(256) void k_xpass_fwd(const R *__restrict__ f, C2<R> *spec, RveDev<R> d)
 {
     extern __shared__ unsigned char smem_raw[];
     C2<R> *buf = reinterpret_cast<C2<R> *>(smem_raw);
     const int tid = threadIdx.x;
-    const int li = tid / nx, x = tid - li * nx;
-    const int line = blockIdx.x * L + li;
-    const bool valid = line < nlines;
-    const int y = valid ? line % ny : 0, z = valid ? line / ny : 0;
-    const long vox = (long)line * nx + x;
+    const int li = tid / d.nx, x = tid - li * d.nx;
+    const int line = blockIdx.x * d.L + li;
+    const bool valid = tid < d.tpbx && line < d.nlines;
+    const int y = valid ? line % d.ny : 0, z = valid ? line / d.ny : 0;
+    const long vox = (long)line * d.nx + x;
+    if (tid < d.tpbx) {
 #pragma unroll
-    for (int p = 0; p < 3; ++p) {
-        C2<R> v = {R(0), R(0)};
-        if (valid) v = {f[(2 * p) * nvox + vox], f[(2 * p + 1) * nvox + vox]};
-        buf[(p * L + li) * nx + x] = v;
+        for (int p = 0; p < 3; ++p) {
+            C2<R> v = {R(0), R(0)};
+            if (valid) v = {f[(2 * p) * d.nvox + vox], f[(2 * p + 1) * d.nvox + vox]};
+            buf[(p * d.L + li) * d.nx + x] = v;
+        }
     }
     __syncthreads();
-    lds_fft<R, false, 8>(buf, 3 * L, nx, px, tw, tid, blockDim.x);
-    store_halfspec_pairs(spec, buf, nx, ny, nz, nhx, L, li, x, y, z, valid);
+    lds_fft<R, false, 8>(buf, 3 * d.L, d.nx, d.px, d.tw[0], tid, blockDim.x);
+    if (tid < d.tpbx) store_halfspec_pairs(spec, buf, d.nx, d.ny, d.nz, d.nhx, d.L, li, x, y, z, valid);
 }
 
 // Inverse x transform to 6 real fields, scaled by 1/nvox (component operator).
 template <typename R>
-__global__ __launch_bounds__(256) void k_xpass_inv(const C2<R> *__restrict__ spec, R *f, const C2<R> *tw,
-                                                   FftPlan px, int nx, int ny, int nz, int nhx, int L,
-                                                   int nlines, long nvox, R inv_nvox)
+__global__ __launch_bounds__(256) void k_xpass_inv(const C2<R> *__restrict__ spec, R *f, RveDev<R> d)
 {
     extern __shared__ unsigned char smem_raw[];
     C2<R> *buf = reinterpret_cast<C2<R> *>(smem_raw);
     const int tid = threadIdx.x;
-    const int li = tid / nx, x = tid - li * nx;
-    const int line = blockIdx.x * L + li;
-    const bool valid = line < nlines;
-    const int y = valid ? line % ny : 0, z = valid ? line / ny : 0;
-    const long vox = (long)line * nx + x;
-    load_halfspec_pairs(spec, buf, nx, ny, nz, nhx, L, li, x, y, z, valid);
+    const int li = tid / d.nx, x = tid - li * d.nx;
+    const int line = blockIdx.x * d.L + li;
+    const bool valid = tid < d.tpbx && line < d.nlines;
+    const int y = valid ? line % d.ny : 0, z = valid ? line / d.ny : 0;
+    const long vox = (long)line * d.nx + x;
+    if (tid < d.tpbx) load_halfspec_pairs(spec, buf, d.nx, d.ny, d.nz, d.nhx, d.L, li, x, y, z, valid);
     __syncthreads();
-    lds_fft<R, true, 8>(buf, 3 * L, nx, px, tw, tid, blockDim.x);
+    lds_fft<R, true, 8>(buf, 3 * d.L, d.nx, d.px, d.tw[0], tid, blockDim.x);
     if (valid) {
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
-            const C2<R> zz = buf[(p * L + li) * nx + x];
-            f[(2 * p) * nvox + vox] = zz.x * inv_nvox;
-            f[(2 * p + 1) * nvox + vox] = zz.y * inv_nvox;
+            const C2<R> zz = buf[(p * d.L + li) * d.nx + x];
+            f[(2 * p) * d.nvox + vox] = zz.x * d.inv_nvox;
+            f[(2 * p + 1) * d.nvox + vox] = zz.y * d.inv_nvox;
         }
     }
 }
@@ -313,25 +345,32 @@ __global__ __launch_bounds__(256) void k_xpass_inv(const C2<R> *__restrict__ spe
 // y pass: C2C along y on the half spectrum.  Block = one component, one z,
 // a tile of ty consecutive kx columns; LDS holds ty lines of ny points.
 // ---------------------------------------------------------------------------
+// spec_override (component operators): transform this array instead of the
+// RVE's own spectrum, and ignore the step flag.
 template <typename R, bool INV, int EPT>
-__global__ __launch_bounds__(256) void k_ypass(C2<R> *spec, const C2<R> *tw, FftPlan py, int ny, int nz,
-                                               int nhx, int ty, const Scalars *sc)
+__global__ __launch_bounds__(256) void k_ypass(const RveDev<R> *__restrict__ rv, int nrve,
+                                               C2<R> *spec_override)
 {
-    if (sc && sc->done) return;
+    const int r = find_rve(rv, nrve, (int)blockIdx.x, 1);
+    const RveDev<R> &d = rv[r];
+    if (!spec_override && d.sc->done) return;
     extern __shared__ unsigned char smem_raw[];
     C2<R> *buf = reinterpret_cast<C2<R> *>(smem_raw);
-    const int kx0 = blockIdx.x * ty;
-    const int tw_ = min(ty, nhx - kx0);
-    const int z = blockIdx.y, c = blockIdx.z;
+    const int local = blockIdx.x - d.by0;
+    const int tile = local % d.nty, zc = local / d.nty;
+    const int z = zc % d.nz, c = zc / d.nz;
+    const int ny = d.ny, nhx = d.nhx;
+    const int kx0 = tile * d.ty;
+    const int tw_ = min(d.ty, nhx - kx0);
     const int ls = ny + 1;
-    C2<R> *g = spec + ((long)c * nz + z) * ny * nhx + kx0;
+    C2<R> *g = (spec_override ? spec_override : d.spec) + ((long)c * d.nz + z) * ny * nhx + kx0;
     const int tid = threadIdx.x, nthr = blockDim.x;
     for (int i = tid; i < ny * tw_; i += nthr) {
         const int y = i / tw_, col = i - y * tw_;
         buf[col * ls + y] = g[(long)y * nhx + col];
     }
     __syncthreads();
-    lds_fft<R, INV, EPT>(buf, tw_, ls, py, tw, tid, nthr);
+    lds_fft<R, INV, EPT>(buf, tw_, ls, d.py, d.tw[1], tid, nthr);
     for (int i = tid; i < ny * tw_; i += nthr) {
         const int y = i / tw_, col = i - y * tw_;
         g[(long)y * nhx + col] = buf[col * ls + y];
@@ -344,7 +383,7 @@ __global__ __launch_bounds__(256) void k_ypass(C2<R> *spec, const C2<R> *tw, Fft
 // ---------------------------------------------------------------------------
 template <typename R>
 struct GreenArgs {
-    int nx, ny, nz, nhx, tz;
+    int nx, ny, nz;
     R inv_mu0;      // 1 / mu0
     R coef;         // (lam0 + mu0) / (mu0 (lam0 + 2 mu0))
 };
@@ -393,42 +432,46 @@ __device__ __forceinline__ void green_point(C2<R> (&s)[6], int kx, int ky, int k
 
 // mode bits: ZMODE_FWD forward z transform; ZMODE_GREEN Gamma0, residual and
 // inverse z transform.  The iteration uses both; the component operators
-// use one each.
+// use one each (with spec_override).
 constexpr int ZMODE_FWD = 1;
 constexpr int ZMODE_GREEN = 2;
 
 template <typename R, int EPT>
-__global__ __launch_bounds__(256) void k_zpass_green(C2<R> *spec, const C2<R> *tw, FftPlan pz,
-                                                     GreenArgs<R> g, double *part, const Scalars *sc,
-                                                     int mode)
+__global__ __launch_bounds__(256) void k_zpass_green(const RveDev<R> *__restrict__ rv, int nrve, R inv_mu0,
+                                                     R coef, int mode, C2<R> *spec_override)
 {
-    if (sc && sc->done) return;
+    const int r = find_rve(rv, nrve, (int)blockIdx.x, 2);
+    const RveDev<R> &d = rv[r];
+    if (!spec_override && d.sc->done) return;
     extern __shared__ unsigned char smem_raw[];
     C2<R> *buf = reinterpret_cast<C2<R> *>(smem_raw);
-    const int kx0 = blockIdx.x * g.tz;
-    const int tw_ = min(g.tz, g.nhx - kx0);
-    const int ky = blockIdx.y;
-    const int nz = g.nz, ls = nz + 1;
-    const long plane = (long)g.nz * g.ny * g.nhx;
-    const long colbase = (long)ky * g.nhx + kx0;
-    const long zstride = (long)g.ny * g.nhx;
+    const int local = blockIdx.x - d.bz0;
+    const int tile = local % d.ntz, ky = local / d.ntz;
+    const int kx0 = tile * d.tz;
+    const int tw_ = min(d.tz, d.nhx - kx0);
+    const int nz = d.nz, ls = nz + 1;
+    C2<R> *spec = spec_override ? spec_override : d.spec;
+    const long plane = (long)d.nz * d.ny * d.nhx;
+    const long colbase = (long)ky * d.nhx + kx0;
+    const long zstride = (long)d.ny * d.nhx;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int nrow = 6 * nz;
     for (int i = tid; i < nrow * tw_; i += nthr) {
-        const int r = i / tw_, col = i - r * tw_;
-        const int c = r / nz, kz = r - c * nz;
+        const int rr = i / tw_, col = i - rr * tw_;
+        const int c = rr / nz, kz = rr - c * nz;
         buf[(c * tw_ + col) * ls + kz] = spec[c * plane + kz * zstride + colbase + col];
     }
     __syncthreads();
-    if (mode & ZMODE_FWD) lds_fft<R, false, EPT>(buf, 6 * tw_, ls, pz, tw, tid, nthr);
+    if (mode & ZMODE_FWD) lds_fft<R, false, EPT>(buf, 6 * tw_, ls, d.pz, d.tw[2], tid, nthr);
     if (!(mode & ZMODE_GREEN)) {
         for (int i = tid; i < nrow * tw_; i += nthr) {
-            const int r = i / tw_, col = i - r * tw_;
-            const int c = r / nz, kz = r - c * nz;
+            const int rr = i / tw_, col = i - rr * tw_;
+            const int c = rr / nz, kz = rr - c * nz;
             spec[c * plane + kz * zstride + colbase + col] = buf[(c * tw_ + col) * ls + kz];
         }
         return;
     }
+    const GreenArgs<R> g = {d.nx, d.ny, d.nz, inv_mu0, coef};
     double err2 = 0.0;
     for (int i = tid; i < tw_ * nz; i += nthr) {
         const int col = i / nz, kz = i - col * nz;
@@ -440,12 +483,12 @@ __global__ __launch_bounds__(256) void k_zpass_green(C2<R> *spec, const C2<R> *t
         for (int c = 0; c < 6; ++c) buf[(c * tw_ + col) * ls + kz] = s[c];
     }
     double e[1] = {err2};
-    block_sum<1>(e, part + (long)blockIdx.y * gridDim.x + blockIdx.x);
+    block_sum<1>(e, d.part_z + local);
     __syncthreads();
-    lds_fft<R, true, EPT>(buf, 6 * tw_, ls, pz, tw, tid, nthr);
+    lds_fft<R, true, EPT>(buf, 6 * tw_, ls, d.pz, d.tw[2], tid, nthr);
     for (int i = tid; i < nrow * tw_; i += nthr) {
-        const int r = i / tw_, col = i - r * tw_;
-        const int c = r / nz, kz = r - c * nz;
+        const int rr = i / tw_, col = i - rr * tw_;
+        const int c = rr / nz, kz = rr - c * nz;
         spec[c * plane + kz * zstride + colbase + col] = buf[(c * tw_ + col) * ls + kz];
     }
 }
@@ -456,32 +499,40 @@ __global__ __launch_bounds__(256) void k_zpass_green(C2<R> *spec, const C2<R> *t
 struct StepInit {
     double dE0[6], E0[6], target[6], K0inv[36];
     int sidx[6];
+    int cur, M;
+    double dt;
 };
 
-__global__ void k_begin_step(Scalars *sc, StepInit si)
+// One block per RVE: reset the step scalars from the host-prepared record.
+template <typename R>
+__global__ void k_begin_step(const RveDev<R> *__restrict__ rv, const StepInit *__restrict__ si)
 {
     if (threadIdx.x != 0) return;
+    Scalars *sc = rv[blockIdx.x].sc;
+    const StepInit &q = si[blockIdx.x];
     for (int i = 0; i < 6; ++i) {
-        sc->dE[i] = si.dE0[i];
-        sc->E[i] = si.E0[i];
-        sc->target[i] = si.target[i];
-        sc->sidx[i] = si.sidx[i];
+        sc->dE[i] = q.dE0[i];
+        sc->E[i] = q.E0[i];
+        sc->target[i] = q.target[i];
+        sc->sidx[i] = q.sidx[i];
         sc->Sigma[i] = 0.0;
     }
-    for (int i = 0; i < 36; ++i) sc->K0inv[i] = si.K0inv[i];
+    for (int i = 0; i < 36; ++i) sc->K0inv[i] = q.K0inv[i];
     for (int i = 0; i < 8; ++i) sc->err_hist[i] = 0.0;
     sc->iter = 0;
     sc->done = 0;
     sc->status = 0;
     sc->stagnated = 0;
+    sc->cur = q.cur;
+    sc->M = q.M;
+    sc->dt = q.dt;
     sc->err_eq = sc->err_bc = 0.0;
     sc->mean_sig_eq = sc->mean_v = sc->mean_f = 0.0;
     sc->work_active = sc->work_newton = 0.0;
 }
 
 struct BcArgs {
-    int nbx, nbz;
-    double nvox, n_slip, n_twin;
+    double n_slip, n_twin;
     double tol, stag_tol;
     int max_iter;
 };
@@ -491,39 +542,46 @@ __device__ __forceinline__ double frob2(const double a[6])
     return a[0] * a[0] + a[1] * a[1] + a[2] * a[2] + 2.0 * (a[3] * a[3] + a[4] * a[4] + a[5] * a[5]);
 }
 
-__global__ __launch_bounds__(256) void k_bc_update(const double *__restrict__ px, const double *__restrict__ pz,
-                                                   Scalars *sc, BcArgs b)
+// One block per RVE: reduce the block sums of the x and z passes (fixed
+// order), evaluate the residuals, decide convergence and correct the
+// stress-controlled mean strain.
+template <typename R>
+__global__ __launch_bounds__(256) void k_bc_update(const RveDev<R> *__restrict__ rv, BcArgs b)
 {
+    const RveDev<R> &d = rv[blockIdx.x];
+    Scalars *sc = d.sc;
     if (sc->done) return;
+    const int nbx = (d.nlines + d.L - 1) / d.L, nbz = d.ntz * d.ny;
+    const double nvox = (double)d.nvox;
     double acc[NPX + 1];
 #pragma unroll
     for (int i = 0; i < NPX + 1; ++i) acc[i] = 0.0;
-    for (int j = threadIdx.x; j < b.nbx; j += blockDim.x)
+    for (int j = threadIdx.x; j < nbx; j += blockDim.x)
 #pragma unroll
-        for (int i = 0; i < NPX; ++i) acc[i] += px[(long)j * NPX + i];
-    for (int j = threadIdx.x; j < b.nbz; j += blockDim.x) acc[NPX] += pz[j];
+        for (int i = 0; i < NPX; ++i) acc[i] += d.part_x[(long)j * NPX + i];
+    for (int j = threadIdx.x; j < nbz; j += blockDim.x) acc[NPX] += d.part_z[j];
     __shared__ double tot[NPX + 1];
     block_sum<NPX + 1>(acc, tot);
     __syncthreads();
     if (threadIdx.x != 0) return;
 
     double S[6];
-    for (int i = 0; i < 6; ++i) S[i] = tot[i] / b.nvox;
+    for (int i = 0; i < 6; ++i) S[i] = tot[i] / nvox;
     const double nrm = sqrt(frob2(S));
     const double num = sqrt(tot[NPX]);
     double dS[6];
     for (int i = 0; i < 6; ++i) dS[i] = sc->sidx[i] ? S[i] - sc->target[i] : 0.0;
     const double nb = sqrt(frob2(dS));
-    const double err_eq = nrm > 0.0 ? num / (b.nvox * nrm) : (num == 0.0 ? 0.0 : INFINITY);
+    const double err_eq = nrm > 0.0 ? num / (nvox * nrm) : (num == 0.0 ? 0.0 : INFINITY);
     const double err_bc = nrm > 0.0 ? nb / nrm : (nb == 0.0 ? 0.0 : INFINITY);
     const int it = sc->iter + 1;
     sc->iter = it;
     for (int i = 0; i < 6; ++i) sc->Sigma[i] = S[i];
     sc->err_eq = err_eq;
     sc->err_bc = err_bc;
-    sc->mean_sig_eq = tot[6] / b.nvox;
-    sc->mean_v = b.n_slip > 0 ? tot[7] / (b.nvox * b.n_slip) : 0.0;
-    sc->mean_f = b.n_twin > 0 ? tot[8] / (b.nvox * b.n_twin) : 0.0;
+    sc->mean_sig_eq = tot[6] / nvox;
+    sc->mean_v = b.n_slip > 0 ? tot[7] / (nvox * b.n_slip) : 0.0;
+    sc->mean_f = b.n_twin > 0 ? tot[8] / (nvox * b.n_twin) : 0.0;
     sc->work_active += tot[9];
     sc->work_newton += tot[10];
 
@@ -551,13 +609,13 @@ __global__ __launch_bounds__(256) void k_bc_update(const double *__restrict__ px
         return;
     }
     // mixed conditions: dE_S = (C0_SS)^-1 (Sigma*_S - Sigma_S)
-    double r[6];
-    for (int i = 0; i < 6; ++i) r[i] = sc->sidx[i] ? sc->target[i] - S[i] : 0.0;
+    double rr[6];
+    for (int i = 0; i < 6; ++i) rr[i] = sc->sidx[i] ? sc->target[i] - S[i] : 0.0;
     for (int i = 0; i < 6; ++i) {
-        double d = 0.0;
-        for (int j = 0; j < 6; ++j) d += sc->K0inv[i * 6 + j] * r[j];
-        sc->dE[i] = d;
-        sc->E[i] += d;
+        double dd = 0.0;
+        for (int j = 0; j < 6; ++j) dd += sc->K0inv[i * 6 + j] * rr[j];
+        sc->dE[i] = dd;
+        sc->E[i] += dd;
     }
 }
 
