@@ -107,6 +107,66 @@ def cpu_baseline(w, s32, K, budget_s):
                       "(FP64 oracle, from the GPU's committed state), %.1f s" % (its, n, t_used)}
 
 
+def batch_leg(cp, steps, graph_iters=16):
+    """Workload 3: 32 RVEs of uneven sizes (32^3..96^3), half twinned, the
+    same law, 2% tension in 50 steps (the first `steps` steps are run).
+    FP32 batched solve (one launch per pass for all members, graph replays,
+    autotuned tiles) against the sum of 32 plain FP64 single-RVE solves."""
+    import numpy as np
+    import torch
+    import rvegen
+    C, law = rvegen.config_law()
+    S = rvegen.config_systems(with_twins=True)
+    members = rvegen.batch_members(32)
+    path = rvegen.uniaxial_path(0.02 / 50 * steps, steps)
+    probs = [cp.Problem(m.labels, m.euler, C, S.n_miller, S.l_miller, S.family, S.tau0, law)
+             for m in members]
+    nvox = sum(int(m.labels.size) for m in members)
+    b = cp.Solver(probs, precision="fp32", tol=1e-6, stag_tol=1e-4, graph_iters=graph_iters,
+                  autotune=True)
+    b.step_batch(path, 0)          # warm-up: graph capture, first launches
+    b.reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs, it32 = [], 0
+    for n in range(steps):
+        o = b.step_batch(path, n)
+        outs.append(o)
+        it32 += sum(int(x["iters"]) * int(m.labels.size) for x, m in zip(o, members))
+        print("[bench] batch fp32 step %d: max iters %d" % (n, max(x["iters"] for x in o)),
+              file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t32 = time.perf_counter() - t0
+    t64, it64, err = 0.0, 0, 0.0
+    for j, p in enumerate(probs):
+        s = cp.Solver(p, precision="fp64", tol=1e-8)
+        s.step(path, 0)
+        s.reset()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for n in range(steps):
+            o = s.step(path, n)
+            it64 += int(o["iters"]) * int(members[j].labels.size)
+            ref = o["Sigma"][0]
+            err = max(err, abs(outs[n][j]["Sigma"][0] - ref) / max(abs(ref), 1e-30))
+        torch.cuda.synchronize()
+        t64 += time.perf_counter() - t0
+        del s
+        print("[bench] fp64 single RVE %d (%d^3) done, %.2f s so far" %
+              (j, members[j].labels.shape[0], t64), file=sys.stderr, flush=True)
+    sizes = sorted(set(int(m.labels.shape[0]) for m in members))
+    return {"workload": "32 RVEs, N in {32,48,64,96}^3, 50-300 grains, even members twinned, "
+                        "2%/50-step tension (first %d steps)" % steps,
+            "rves": len(members), "voxels": nvox, "grid_sizes": sizes, "steps": steps,
+            "graph_iters_per_launch": graph_iters,
+            "tiles": {str(n): b.tiles(next(i for i, m in enumerate(members)
+                                            if m.labels.shape[0] == n)) for n in sizes},
+            "fp32_batched_s": t32, "fp64_single_sum_s": t64, "speedup": t64 / t32,
+            "fp32_batched_voxel_iterations_per_s": it32 / t32,
+            "fp64_single_voxel_iterations_per_s": it64 / t64,
+            "fp32_vs_fp64_max_rel_err_Sigma_xx": err}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -115,6 +175,7 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--batch-steps", type=int, default=10)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path "
@@ -191,6 +252,8 @@ def main():
             a = np.array([o["Sigma"][0] for o in r32["outs"]])
             b = np.array([o["Sigma"][0] for o in r64["outs"]])
             line["fp64"]["fp32_max_rel_err_Sigma_xx"] = float(np.abs(a - b).max() / np.abs(b).max())
+    if args.batch_steps > 0:
+        line["batched"] = batch_leg(cp, args.batch_steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, s32, K, args.cpu_seconds)
     print(json.dumps(line), flush=True)

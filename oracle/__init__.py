@@ -88,6 +88,11 @@ def lib():
                                     ctypes.POINTER(ctypes.c_int), dp, dp, dp, dp, dp,
                                     ctypes.c_double, ctypes.c_int]
         L.orc_max_threads.restype = ctypes.c_int
+        L.orc_rate_vjp_point.restype = None
+        L.orc_rate_vjp_point.argtypes = [ctypes.POINTER(_Material), ctypes.c_int, dp, dp, dp, dp, dp, dp]
+        L.orc_vjp_grid.restype = ctypes.c_int
+        L.orc_vjp_grid.argtypes = [ctypes.POINTER(_Material), ctypes.c_long, ctypes.POINTER(ctypes.c_int),
+                                   dp, dp, dp, ctypes.c_double, ctypes.c_int, dp, dp, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -298,6 +303,43 @@ class Material:
         if rc != 0:
             raise ValueError("orc_cp_update rejected its input")
         return y1, sig
+
+
+    # -- reverse mode -------------------------------------------------------
+    def rate_vjp(self, label: int, eps_mandel, y, kbar):
+        """Cotangents (y_bar, eps_bar, theta_bar[2][7]) of dy/dt = F(eps, y)
+        for the cotangent kbar of its output; theta = (r0, Q, b, c, d, K, n)
+        per family (slip, twin)."""
+        e = np.ascontiguousarray(eps_mandel, dtype=np.float64)
+        y = np.ascontiguousarray(y, dtype=np.float64)
+        kb = np.ascontiguousarray(kbar, dtype=np.float64)
+        yb = np.zeros(self.state_dim)
+        eb = np.zeros(6)
+        th = np.zeros(14)
+        lib().orc_rate_vjp_point(ctypes.byref(self._s), int(label), _dp(e), _dp(y), _dp(kb),
+                                 _dp(yb), _dp(eb), _dp(th))
+        return yb, eb, th.reshape(2, 7)
+
+    def update_vjp(self, labels, eps0, eps1, y0, dt, M, sig_bar, y_bar):
+        """Reverse of :meth:`update`: cotangents of eps0, eps1, y0 (per
+        point, Mandel) and of theta (summed) for cotangents of the end stress
+        and end state."""
+        labels = np.ascontiguousarray(np.asarray(labels, dtype=np.int32).ravel())
+        n = labels.shape[0]
+        D = self.state_dim
+        a = [np.ascontiguousarray(np.broadcast_to(x, (n, k)), dtype=np.float64)
+             for x, k in ((eps0, 6), (eps1, 6), (y0, D), (sig_bar, 6), (y_bar, D))]
+        e0b, e1b, y0b, th = np.empty((n, 6)), np.empty((n, 6)), np.empty((n, D)), np.empty(14)
+        rc = lib().orc_vjp_grid(ctypes.byref(self._s), n,
+                                labels.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                _dp(a[0]), _dp(a[1]), _dp(a[2]), float(dt), int(M), _dp(a[3]),
+                                _dp(a[4]), _dp(e0b), _dp(e1b), _dp(y0b), _dp(th))
+        if rc != 0:
+            raise ValueError("orc_vjp_grid rejected its input")
+        return e0b, e1b, y0b, th.reshape(2, 7)
+
+
+THETA_NAMES = ("r0", "Q", "b", "c", "d", "K", "n")
 
 
 def reg_rate(o, A, K, n, eta) -> float:
@@ -512,6 +554,90 @@ class Solver:
         if keep_fields:
             R.fields = self.fields()
         return R
+
+    # -- discrete adjoint -------------------------------------------------------
+    def gradient(self, path, target_xx, adj_tol: float = 1e-12, n_steps: Optional[int] = None):
+        """Loss L = sum_n (Sigma_xx,n - target_xx[n])^2 over the load steps and
+        its gradient with respect to theta[f] = (r0, Q, b, c, d, K, n) of the
+        slip (f = 0) and twin (f = 1) families.
+
+        Forward: the converged steps, recording (eps_n, y_n, eps_n+1).
+        Reverse, per step n (last to first), with the cotangents S_bar,
+        eps_bar carried from step n+1:
+          g  = d/d eps_{n+1} of [sigma_bar_L . sigma + S_bar . S] + eps_bar,
+               sigma_bar_L = dL/dSigma_n+1 / N at every voxel;
+          A  = d sigma_{n+1} / d eps_{n+1} per voxel (six reverse sweeps);
+          mu in the admissible strain space (compatible, zero mean, free
+               mean on stress-controlled components) with A^T mu - g weakly
+               equilibrated -- the same Green-operator fixed point as the
+               forward problem, tangent transposed, target mean stress 0;
+          then one reverse sweep of the local law with cotangents
+          (sigma_bar_L - mu, S_bar) gives S_bar_n, eps_bar_n and theta_bar.
+        """
+        ns = path.target.shape[0] if n_steps is None else n_steps
+        self.reset()
+        rec = []
+        Sig = np.zeros(ns)
+        for n in range(ns):
+            e0, y0 = self.eps.copy(), self.y.copy()
+            self.step(path.t[n], path.t[n + 1], path.strain_ctrl[n], path.target[n])
+            dt = path.t[n + 1] - path.t[n]
+            M = self.opts.M if self.opts.M is not None else substeps(dt, self.opts.h_max)
+            rec.append((e0, y0, self.eps.copy(), dt, M, np.asarray(path.strain_ctrl[n], bool)))
+            Sig[n] = self.Sigma[0]
+        tgt = np.asarray(target_xx, dtype=np.float64)[:ns]
+        L = float(np.sum((Sig - tgt) ** 2))
+        N = self.n_vox
+        D = self.mat.state_dim
+        Sb = np.zeros((N, D))
+        eb = np.zeros((N, 6))
+        grad = np.zeros((2, 7))
+        lab = self.labels.ravel()
+        eye = np.eye(6)
+        self.adj_iters = []
+        for n in range(ns - 1, -1, -1):
+            e0, y0, e1, dt, M, ectrl = rec[n]
+            sigL = np.zeros((N, 6))
+            sigL[:, 0] = 2.0 * (Sig[n] - tgt[n]) / N
+            _, g, _, _ = self.mat.update_vjp(lab, e0, e1, y0, dt, M, sigL, Sb)
+            g = g + eb
+            Arows = np.empty((N, 6, 6))
+            zero = np.zeros((N, D))
+            for i in range(6):
+                _, Arows[:, i, :], _, _ = self.mat.update_vjp(lab, e0, e1, y0, dt, M,
+                                                              np.broadcast_to(eye[i], (N, 6)), zero)
+            mu = self._adjoint_equilibrium(Arows, g, ~ectrl, adj_tol)
+            e0b, _, y0b, th = self.mat.update_vjp(lab, e0, e1, y0, dt, M, sigL - mu, Sb)
+            grad += th
+            Sb, eb = y0b, e0b
+        self.reset()
+        return L, grad, Sig
+
+    def _adjoint_equilibrium(self, Arows, g, sidx, tol):
+        """mu (Mandel, per voxel) with A^T mu - g weakly equilibrated, by the
+        basic scheme with Gamma0."""
+        N = self.n_vox
+        gn = math.sqrt(float(np.sum(g * g)))
+        mu = np.zeros((N, 6))
+        if gn == 0.0:
+            self.adj_iters.append(0)
+            return mu
+        grms = gn / math.sqrt(N)
+        for k in range(self.opts.max_iter):
+            tau = np.einsum("ni,nij->nj", mu, Arows) - g
+            tau_t = from_mandel(tau)
+            T = tau_t.mean(axis=0)
+            grid = np.moveaxis(tau_t.reshape(self.shape + (6,)), -1, 0)
+            th = fft3(grid)
+            err_eq = math.sqrt(equilibrium_sums(th, self.xi_hat, self.ctrl)) / (math.sqrt(N) * gn)
+            err_bc = frob(np.where(sidx, T, 0.0)) / grms
+            if err_eq <= tol and err_bc <= tol:
+                self.adj_iters.append(k + 1)
+                return mu
+            corr = self.correction(th)
+            dM = self._stress_correction(sidx, -T)
+            mu = mu - to_mandel(corr) + to_mandel(dM)
+        raise NotConverged("adjoint equilibrium: no convergence in %d iterations" % self.opts.max_iter)
 
     def fields(self) -> dict:
         """Committed local fields, tensor components, grid-shaped [6][nz][ny][nx]."""

@@ -21,6 +21,7 @@
  */
 #include <float.h>
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #define ORC_MAXS 64
@@ -217,4 +218,299 @@ int orc_max_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------------
+ * Reverse mode (adjoint) of the local law, for gradients with respect to
+ * the per-family parameters theta[f] = (r0, Q, b, c, d, K, n), f = slip,
+ * twin.  Everything is the plain chain rule of the forward definitions
+ * above; the regularized rate g(o, A) enters through the implicit-function
+ * derivatives of its defining equation K y + eta A y^n = o, g = A y^n:
+ *   D = K + eta A n y^(n-1)
+ *   dg/do = A n y^(n-1) / D        dg/dA = y^n K / D
+ *   dg/dK = -A n y^n / D           dg/dn = A y^n ln(y) K / D
+ * ------------------------------------------------------------------------ */
+enum { TH_R0 = 0, TH_Q, TH_B, TH_C, TH_D, TH_K, TH_N, TH_NUM };
+
+/* root y of the regularized rate (0 when inactive) */
+static double reg_root(double o, double A, double K, double n, double eta)
+{
+    if (!(o > 0.0) || !(A > 0.0))
+        return 0.0;
+    if (eta == 0.0)
+        return o / K;
+    double y = pow(o / (eta * A), 1.0 / n);
+    if (K > 0.0 && o / K < y)
+        y = o / K;
+    for (int it = 0; it < 50; ++it) {
+        double yn1 = pow(y, n - 1.0);
+        double step = (K * y + eta * A * yn1 * y - o) / (K + eta * A * n * yn1);
+        y -= step;
+        if (fabs(step) <= 4.0 * DBL_EPSILON * y)
+            break;
+    }
+    return y;
+}
+
+static double sgn(double x) { return (x > 0.0) - (x < 0.0); }
+
+/* kb: cotangent of dy/dt = F(eps, y).  Accumulates yb (+=), eb (+=), th (+=). */
+void orc_rate_vjp(const orc_material *mt, int lab, const double eps[6], const double *y,
+                  const double *kb, double *yb, double *eb, double th[2][TH_NUM])
+{
+    const int S = mt->n_sys;
+    const double *C = mt->C_lab + 36 * (long)lab;
+    const double *m = mt->m_lab + 6 * (long)S * lab;
+    const double *ep = y, *v = y + 6, *al = y + 6 + S;
+    const double *kep = kb, *kv = kb + 6, *kal = kb + 6 + S;
+    double sig[6], hs[ORC_MAXS], ex[ORC_MAXS], r[ORC_MAXS], tx[ORC_MAXS], o[ORC_MAXS];
+    double A[ORC_MAXS], yr[ORC_MAXS], gd[ORC_MAXS];
+
+    /* forward recomputation */
+    for (int i = 0; i < 6; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < 6; ++j)
+            s += C[6 * i + j] * (eps[j] - ep[j]);
+        sig[i] = s;
+    }
+    double sum_f = 0.0;
+    for (int s = 0; s < S; ++s)
+        if (mt->family[s] == ORC_FAM_TWIN)
+            sum_f += v[s] / mt->gamma_T;
+    for (int t = 0; t < S; ++t) {
+        ex[t] = exp(-mt->b[mt->family[t]] * v[t]);
+        hs[t] = 1.0 - ex[t];
+    }
+    for (int s = 0; s < S; ++s) {
+        const int f = mt->family[s];
+        double rr = mt->tau0[s];
+        for (int t = 0; t < S; ++t)
+            if (mt->family[t] == f)
+                rr += mt->Q[f] * ((t == s) ? mt->q_self[f] : mt->q_lat[f]) * hs[t];
+        r[s] = rr;
+        double tau = 0.0;
+        for (int i = 0; i < 6; ++i)
+            tau += sig[i] * m[6 * s + i];
+        tx[s] = tau - mt->c[f] * al[s];
+        if (f == ORC_FAM_SLIP) {
+            A[s] = 1.0;
+            o[s] = fabs(tx[s]) - r[s];
+        } else {
+            A[s] = (mt->twin_mode == ORC_TWIN_PAPER) ? mt->gamma_T * mt->K_c * (mt->f_m - sum_f) : 1.0;
+            o[s] = tx[s] - r[s];
+        }
+        yr[s] = reg_root(o[s], A[s], mt->K[f], mt->n[f], mt->eta);
+        double g = (yr[s] > 0.0) ? A[s] * pow(yr[s], mt->n[f]) : 0.0;
+        gd[s] = (f == ORC_FAM_SLIP && tx[s] < 0.0) ? -g : g;
+    }
+
+    /* reverse */
+    double gdb[ORC_MAXS], sigb[6] = {0, 0, 0, 0, 0, 0}, hb[ORC_MAXS], sumfb = 0.0;
+    for (int s = 0; s < S; ++s) {
+        const int f = mt->family[s];
+        double mk = 0.0;
+        for (int i = 0; i < 6; ++i)
+            mk += m[6 * s + i] * kep[i];
+        if (f == ORC_FAM_SLIP) {
+            gdb[s] = (1.0 - sum_f) * mk;
+            sumfb -= gd[s] * mk;
+        } else {
+            gdb[s] = mk;
+        }
+        gdb[s] += sgn(gd[s]) * kv[s];
+        gdb[s] += kal[s] * (1.0 - mt->d[f] * sgn(gd[s]) * al[s]);
+        yb[6 + S + s] -= mt->d[f] * fabs(gd[s]) * kal[s];
+        th[f][TH_D] -= fabs(gd[s]) * al[s] * kal[s];
+        hb[s] = 0.0;
+    }
+    for (int s = 0; s < S; ++s) {
+        const int f = mt->family[s];
+        double txb = 0.0, rb = 0.0;
+        if (yr[s] > 0.0) {
+            const double n = mt->n[f], K = mt->K[f], eta = mt->eta, y1 = yr[s];
+            const double yn1 = pow(y1, n - 1.0), yn = yn1 * y1;
+            const double D = K + eta * A[s] * n * yn1;
+            const double Go = A[s] * n * yn1 / D;
+            const double GA = yn * K / D;
+            const double GK = -A[s] * n * yn / D;
+            const double Gn = A[s] * yn * log(y1) * K / D;
+            double gb;
+            if (f == ORC_FAM_SLIP) {
+                gb = sgn(tx[s]) * gdb[s];            /* g = |gd| */
+                const double ob = Go * gb;
+                txb = sgn(tx[s]) * ob;
+                rb = -ob;
+            } else {
+                gb = gdb[s];
+                const double ob = Go * gb;
+                txb = ob;
+                rb = -ob;
+                if (mt->twin_mode == ORC_TWIN_PAPER)
+                    sumfb -= mt->gamma_T * mt->K_c * GA * gb;
+            }
+            th[f][TH_K] += GK * gb;
+            th[f][TH_N] += Gn * gb;
+        }
+        /* tx = tau - c alpha */
+        yb[6 + S + s] -= mt->c[f] * txb;
+        th[f][TH_C] -= al[s] * txb;
+        for (int i = 0; i < 6; ++i)
+            sigb[i] += txb * m[6 * s + i];
+        /* r = tau0 + Q sum_t q_st h_t */
+        th[f][TH_R0] += rb;
+        double qh = 0.0;
+        for (int t = 0; t < S; ++t) {
+            if (mt->family[t] != f)
+                continue;
+            const double q = (t == s) ? mt->q_self[f] : mt->q_lat[f];
+            qh += q * hs[t];
+            hb[t] += mt->Q[f] * q * rb;
+        }
+        th[f][TH_Q] += qh * rb;
+    }
+    for (int t = 0; t < S; ++t) {
+        const int f = mt->family[t];
+        yb[6 + t] += hb[t] * mt->b[f] * ex[t];
+        th[f][TH_B] += hb[t] * v[t] * ex[t];
+        if (f == ORC_FAM_TWIN)
+            yb[6 + t] += sumfb / mt->gamma_T;
+    }
+    /* sigma = C (eps - eps_p) */
+    for (int j = 0; j < 6; ++j) {
+        double cs = 0.0;
+        for (int i = 0; i < 6; ++i)
+            cs += C[6 * i + j] * sigb[i];
+        eb[j] += cs;
+        yb[j] -= cs;
+    }
+}
+
+/*
+ * Reverse of orc_integrate_point: given cotangents of the end stress (sigb)
+ * and end state (ybM), accumulate those of eps0, eps1, y0 and theta.
+ * The substep states are recomputed forward and kept; the stage states of
+ * each substep are recomputed during its reverse.
+ */
+void orc_point_vjp(const orc_material *mt, int lab, const double eps0[6], const double eps1[6],
+                   const double *y0, double dt, int M, const double sigb[6], const double *ybM,
+                   double *e0b, double *e1b, double *y0b, double th[2][TH_NUM])
+{
+    const int S = mt->n_sys, D = 6 + 2 * S;
+    const double h = dt / M;
+    double *ys = (double *)malloc(sizeof(double) * (size_t)(M + 1) * D);
+    double k1[6 + 2 * ORC_MAXS], k2[6 + 2 * ORC_MAXS], k3[6 + 2 * ORC_MAXS], k4[6 + 2 * ORC_MAXS];
+    double z2[6 + 2 * ORC_MAXS], z3[6 + 2 * ORC_MAXS], z4[6 + 2 * ORC_MAXS];
+    double yb[6 + 2 * ORC_MAXS], yjb[6 + 2 * ORC_MAXS], kb1[6 + 2 * ORC_MAXS], kb2[6 + 2 * ORC_MAXS];
+    double kb3[6 + 2 * ORC_MAXS], kb4[6 + 2 * ORC_MAXS], zb[6 + 2 * ORC_MAXS];
+    double e[6], eb[6];
+    memcpy(ys, y0, sizeof(double) * D);
+    for (int j = 0; j < M; ++j) {
+        double *yj = ys + (size_t)j * D, *yn = ys + (size_t)(j + 1) * D;
+        const double s0 = (double)j / M, sh = (j + 0.5) / M, s1 = (double)(j + 1) / M;
+        for (int i = 0; i < 6; ++i) e[i] = eps0[i] + s0 * (eps1[i] - eps0[i]);
+        orc_rate(mt, lab, e, yj, k1);
+        for (int i = 0; i < 6; ++i) e[i] = eps0[i] + sh * (eps1[i] - eps0[i]);
+        for (int q = 0; q < D; ++q) z2[q] = yj[q] + 0.5 * h * k1[q];
+        orc_rate(mt, lab, e, z2, k2);
+        for (int q = 0; q < D; ++q) z3[q] = yj[q] + 0.5 * h * k2[q];
+        orc_rate(mt, lab, e, z3, k3);
+        for (int i = 0; i < 6; ++i) e[i] = eps0[i] + s1 * (eps1[i] - eps0[i]);
+        for (int q = 0; q < D; ++q) z4[q] = yj[q] + h * k3[q];
+        orc_rate(mt, lab, e, z4, k4);
+        for (int q = 0; q < D; ++q)
+            yn[q] = yj[q] + h / 6.0 * (k1[q] + 2.0 * k2[q] + 2.0 * k3[q] + k4[q]);
+    }
+    /* end stress sig = C (eps1 - eps_p(M)) */
+    const double *C = mt->C_lab + 36 * (long)lab;
+    memcpy(yb, ybM, sizeof(double) * D);
+    for (int j = 0; j < 6; ++j) {
+        double cs = 0.0;
+        for (int i = 0; i < 6; ++i)
+            cs += C[6 * i + j] * sigb[i];
+        e1b[j] += cs;
+        yb[j] -= cs;
+    }
+    for (int j = M - 1; j >= 0; --j) {
+        const double *yj = ys + (size_t)j * D;
+        const double sv[4] = {(double)j / M, (j + 0.5) / M, (j + 0.5) / M, (double)(j + 1) / M};
+        /* recompute the stage states */
+        for (int i = 0; i < 6; ++i) e[i] = eps0[i] + sv[0] * (eps1[i] - eps0[i]);
+        orc_rate(mt, lab, e, yj, k1);
+        for (int i = 0; i < 6; ++i) e[i] = eps0[i] + sv[1] * (eps1[i] - eps0[i]);
+        for (int q = 0; q < D; ++q) z2[q] = yj[q] + 0.5 * h * k1[q];
+        orc_rate(mt, lab, e, z2, k2);
+        for (int q = 0; q < D; ++q) z3[q] = yj[q] + 0.5 * h * k2[q];
+        orc_rate(mt, lab, e, z3, k3);
+        for (int q = 0; q < D; ++q) z4[q] = yj[q] + h * k3[q];
+        /* y_{j+1} = y_j + h/6 (k1 + 2 k2 + 2 k3 + k4) */
+        for (int q = 0; q < D; ++q) {
+            yjb[q] = yb[q];
+            kb1[q] = h / 6.0 * yb[q];
+            kb2[q] = h / 3.0 * yb[q];
+            kb3[q] = h / 3.0 * yb[q];
+            kb4[q] = h / 6.0 * yb[q];
+        }
+        const double *zs[4] = {yj, z2, z3, z4};
+        double *kbs[4] = {kb1, kb2, kb3, kb4};
+        const double cprev[4] = {0.0, 0.5 * h, 0.5 * h, h};
+        for (int st = 3; st >= 0; --st) {
+            for (int i = 0; i < 6; ++i) e[i] = eps0[i] + sv[st] * (eps1[i] - eps0[i]);
+            for (int q = 0; q < D; ++q) zb[q] = 0.0;
+            for (int i = 0; i < 6; ++i) eb[i] = 0.0;
+            orc_rate_vjp(mt, lab, e, zs[st], kbs[st], zb, eb, th);
+            for (int i = 0; i < 6; ++i) {
+                e0b[i] += (1.0 - sv[st]) * eb[i];
+                e1b[i] += sv[st] * eb[i];
+            }
+            /* z_st = y_j + cprev * k_{st-1} */
+            for (int q = 0; q < D; ++q) {
+                yjb[q] += zb[q];
+                if (st > 0) kbs[st - 1][q] += cprev[st] * zb[q];
+            }
+        }
+        memcpy(yb, yjb, sizeof(double) * D);
+    }
+    for (int q = 0; q < D; ++q) y0b[q] += yb[q];
+    free(ys);
+}
+
+/* Grid version: per point sigb[n][6], ybM[n][D] -> e0b, e1b [n][6], y0b [n][D]
+ * (overwritten) and theta[2][7] (summed, overwritten). */
+int orc_vjp_grid(const orc_material *mt, long n_pts, const int *labels, const double *eps0,
+                 const double *eps1, const double *y0, double dt, int M, const double *sigb,
+                 const double *ybM, double *e0b, double *e1b, double *y0b, double *theta)
+{
+    if (mt->n_sys < 0 || mt->n_sys > ORC_MAXS || M < 1)
+        return -1;
+    const int D = 6 + 2 * mt->n_sys;
+    double tot[2][TH_NUM];
+    memset(tot, 0, sizeof tot);
+#pragma omp parallel
+    {
+        double th[2][TH_NUM];
+        memset(th, 0, sizeof th);
+#pragma omp for schedule(dynamic, 64)
+        for (long p = 0; p < n_pts; ++p) {
+            memset(e0b + 6 * p, 0, 6 * sizeof(double));
+            memset(e1b + 6 * p, 0, 6 * sizeof(double));
+            memset(y0b + D * p, 0, D * sizeof(double));
+            orc_point_vjp(mt, labels[p], eps0 + 6 * p, eps1 + 6 * p, y0 + D * p, dt, M, sigb + 6 * p,
+                          ybM + D * p, e0b + 6 * p, e1b + 6 * p, y0b + D * p, th);
+        }
+#pragma omp critical
+        for (int f = 0; f < 2; ++f)
+            for (int k = 0; k < TH_NUM; ++k) tot[f][k] += th[f][k];
+    }
+    memcpy(theta, tot, sizeof tot);
+    return 0;
+}
+
+/* Per-point rate VJP for tests. */
+void orc_rate_vjp_point(const orc_material *mt, int lab, const double eps[6], const double *y,
+                        const double *kb, double *yb, double *eb, double *theta)
+{
+    double th[2][TH_NUM];
+    memset(th, 0, sizeof th);
+    orc_rate_vjp(mt, lab, eps, y, kb, yb, eb, th);
+    memcpy(theta, th, sizeof th);
 }
