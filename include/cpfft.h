@@ -215,6 +215,45 @@ int cpf_op_constitutive(cpf_solver *s, const void *dev_eps0, const void *dev_eps
                         const void *dev_state0, void *dev_state1, void *dev_sig1,
                         double dt, int M);
 
+/* Discrete adjoint of the load-stepped solve (gradient-based parameter
+ * identification, Sec. 5 of the paper, which fits the law parameters of
+ * Sec. 2 to effective stress curves).  Loss
+ *   L = sum_n (Sigma_11(t_n+1) - target_xx[n])^2
+ * over the path's steps, and its exact gradient with respect to the 14
+ * parameters theta[f][k], f = 0 slip / 1 twin family, k = r0 (initial
+ * critical resolved shear stress of every system of the family), Q, b, c, d,
+ * K, n.  Single-RVE solvers only; the solver must be bound.
+ *
+ * Forward: the whole path is solved on the device, and the committed
+ * (strain, state) pair is copied to the adjoint workspace every
+ * checkpoint_every steps.  Reverse: segment by segment, from the last, the
+ * segment is recomputed from its checkpoint keeping every step's start
+ * state, then for each step (last to first) one launch per voxel recomputes
+ * the RK4 stage states (kept in the workspace) and sweeps them backwards for
+ * the tangent d sigma / d eps and the load vector; the transposed-tangent
+ * equilibrium is solved with the forward FFT and Green-operator passes to
+ * adj_tol (residuals normalized by the load vector's norm); a last sweep
+ * gives the cotangents carried to the previous step and the step's
+ * parameter gradient (FP64 block partials, summed on the host in a fixed
+ * order).
+ *
+ * dev_ws: device buffer of at least cpf_adjoint_workspace_size() bytes,
+ *   256-byte aligned, owned by the caller, used only during the call.
+ * target_xx[n_steps], grad[14] (row-major [2][7]), *loss: host, written by
+ *   the call.  sigma_xx[n_steps] (host, may be NULL) receives the forward
+ *   Sigma_11 per step.
+ * The solver is reset to the undeformed state on return (also on errors
+ * raised after the forward solve started).  Errors: CPF_E_WORKSPACE for a
+ * short or misaligned buffer, CPF_E_NOT_CONVERGED / CPF_E_NAN from the
+ * forward steps or an adjoint equilibrium, CPF_E_INVALID_ARG for batches,
+ * checkpoint_every < 1, adj_tol <= 0 or a bad path.  The graph mode is not
+ * used inside the call. */
+int cpf_adjoint_workspace_size(const cpf_solver *s, const cpf_path *path, int checkpoint_every,
+                               size_t *bytes);
+int cpf_adjoint_gradient(cpf_solver *s, const cpf_path *path, const double *target_xx,
+                         int checkpoint_every, double adj_tol, void *dev_ws, size_t bytes,
+                         double *loss, double *grad /*[2][7]*/, double *sigma_xx);
+
 #ifdef __cplusplus
 }
 #endif

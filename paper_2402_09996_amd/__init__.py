@@ -25,7 +25,7 @@ FIELDS = {
     "back_strain": CPF_FIELD_BACK_STRAIN,
 }
 
-__all__ = ["Problem", "Solver", "CpfError", "FIELDS", "version"]
+__all__ = ["Problem", "Solver", "CpfError", "FIELDS", "version", "StressCurveLoss", "with_theta"]
 
 
 def version() -> int:
@@ -66,6 +66,7 @@ class Problem:
         self.tau0 = _f64(tau0)
         self.n_sys = int(self.family.shape[0])
         self.law = law
+        self.C_voigt = _f64(C_voigt).reshape(6, 6)
         d = _lib.CpfProblemDesc()
         d.nz, d.ny, d.nx = self.shape
         d.labels = _ptr(self.labels, ctypes.c_int32)
@@ -251,6 +252,40 @@ class Solver:
         check(_lib.lib().cpf_solver_field(self._h, k, ctypes.c_void_p(out.data_ptr())))
         return out
 
+    # -- gradients -------------------------------------------------------------
+    THETA_NAMES = ("r0", "Q", "b", "c", "d", "K", "n")
+
+    def adjoint_workspace_size(self, path, checkpoint_every: int = 10) -> int:
+        pa = _PathArgs(path)
+        size = ctypes.c_size_t()
+        check(_lib.lib().cpf_adjoint_workspace_size(self._h, ctypes.byref(pa.c), int(checkpoint_every),
+                                                    ctypes.byref(size)))
+        return int(size.value)
+
+    def gradient(self, path, target_xx, checkpoint_every: int = 10, adj_tol: float = 1e-10):
+        """Loss sum_n (Sigma_11,n - target_xx[n])^2 over the path and its
+        gradient [2][7] with respect to (r0, Q, b, c, d, K, n) of the slip
+        and twin families, by the discrete adjoint on the device.  Returns
+        (loss, grad, sigma_xx).  The solver is left at the undeformed state."""
+        import torch
+        pa = _PathArgs(path)
+        tgt = _f64(target_xx)
+        if tgt.shape != (pa.n,):
+            raise ValueError("target_xx must have one value per load step")
+        need = self.adjoint_workspace_size(path, checkpoint_every)
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        ptr = (ws.data_ptr() + 255) & ~255
+        self._order_after_torch()
+        loss = ctypes.c_double()
+        grad = np.zeros(14)
+        sxx = np.zeros(pa.n)
+        check(_lib.lib().cpf_adjoint_gradient(self._h, ctypes.byref(pa.c), _ptr(tgt, ctypes.c_double),
+                                              int(checkpoint_every), float(adj_tol), ctypes.c_void_p(ptr),
+                                              need, ctypes.byref(loss), _ptr(grad, ctypes.c_double),
+                                              _ptr(sxx, ctypes.c_double)))
+        del ws
+        return loss.value, grad.reshape(2, 7), sxx
+
     # -- kernel timing -------------------------------------------------------
     KERNELS = ("xpass_law", "ypass_fwd", "zpass_green", "ypass_inv", "bc_update")
 
@@ -314,3 +349,56 @@ class Solver:
         if h is not None and h.value:
             _lib.lib().cpf_solver_destroy(h)
             self._h = None
+
+
+def with_theta(problem: Problem, theta) -> Problem:
+    """A copy of ``problem`` whose law parameters are theta[2][7]: per family
+    (slip, twin) r0 (initial critical resolved shear stress of all its
+    systems), Q, b, c, d, K, n."""
+    import copy
+    th = np.asarray(theta, dtype=np.float64).reshape(2, 7)
+    law = copy.deepcopy(problem.law)
+    tau0 = problem.tau0.copy()
+    for f, fam in enumerate((law.slip, law.twin)):
+        tau0[problem.family == f] = th[f, 0]
+        for k, name in enumerate(Solver.THETA_NAMES[1:], start=1):
+            setattr(fam, name, float(th[f, k]))
+    return Problem(problem.labels, problem.euler, problem.C_voigt, problem.n_miller,
+                   problem.l_miller, problem.family, tau0, law)
+
+
+class StressCurveLoss:
+    """torch.autograd binding of :meth:`Solver.gradient`.
+
+    ``StressCurveLoss.apply(theta, problem, path, target_xx, options)`` with
+    theta a float64 tensor [2][7] returns the scalar loss; its backward
+    multiplies the adjoint gradient by the incoming cotangent.  options: a
+    dict of :class:`Solver` keyword arguments plus ``checkpoint_every`` and
+    ``adj_tol``."""
+
+    @staticmethod
+    def _function():
+        import torch
+
+        class _Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, theta, problem, path, target_xx, options):
+                opts = dict(options or {})
+                ck = opts.pop("checkpoint_every", 10)
+                at = opts.pop("adj_tol", 1e-10)
+                p = with_theta(problem, theta.detach().cpu().numpy())
+                s = Solver(p, **opts)
+                L, g, _ = s.gradient(path, target_xx, checkpoint_every=ck, adj_tol=at)
+                ctx.save_for_backward(torch.as_tensor(g, dtype=theta.dtype, device=theta.device))
+                return torch.tensor(L, dtype=theta.dtype, device=theta.device)
+
+            @staticmethod
+            def backward(ctx, gout):
+                (g,) = ctx.saved_tensors
+                return gout * g, None, None, None, None
+
+        return _Fn
+
+    @classmethod
+    def apply(cls, theta, problem, path, target_xx, options=None):
+        return cls._function().apply(theta, problem, path, target_xx, options)

@@ -106,6 +106,8 @@ SIGNATURES = {
     "cpf_op_forward_fft": (_i, [_p, _p, _p]),
     "cpf_op_green": (_i, [_p, _p, _p, _dp]),
     "cpf_op_constitutive": (_i, [_p, _p, _p, _p, _p, _p, _d, _i]),
+    "cpf_adjoint_workspace_size": (_i, [_p, ctypes.POINTER(CpfPath), _i, ctypes.POINTER(ctypes.c_size_t)]),
+    "cpf_adjoint_gradient": (_i, [_p, ctypes.POINTER(CpfPath), _dp, _i, _d, _p, ctypes.c_size_t, _dp, _dp, _dp]),
 }
 
 _lib = None

@@ -20,7 +20,7 @@
 #include <vector>
 
 #include "../../include/cpfft.h"
-#include "cpfft_kernels.hpp"
+#include "cpfft_adjoint.hpp"
 
 using namespace cpf;
 
@@ -694,6 +694,7 @@ static LawP<R> make_law(const cpf_solver *s)
         F.K = R(L.K); F.invK = R(1.0 / L.K);
         F.n = R(L.n); F.inv_n = R(1.0 / L.n); F.nm1 = R(L.n - 1.0);
         F.nm1_int = (L.n == floor(L.n) && L.n >= 1.0 && L.n <= 64.0) ? (int)L.n - 1 : -1;
+        F.Q = R(L.Q); F.b = R(L.b); F.qs = R(L.q_self); F.ql = R(L.q_latent);
         (f ? P.ft : P.fs) = F;
     }
     P.Kc_gT = R(p.Kc * p.gT); P.fm = R(p.fm); P.inv_gT = R(1.0 / p.gT);
@@ -1334,4 +1335,253 @@ extern "C" int cpf_op_constitutive(cpf_solver *s, const void *e0, const void *e1
     if (!(dt > 0) || M < 1) return fail(CPF_E_INVALID_ARG, "need dt > 0 and M >= 1");
     return s->prec == CPF_PREC_FP64 ? op_cp_impl<double>(s, e0, e1, s0, s1, sig, dt, M)
                                     : op_cp_impl<float>(s, e0, e1, s0, s1, sig, dt, M);
+}
+
+// ---------------------------------------------------------------------------
+// discrete adjoint of the load-stepped solve (single RVE)
+// ---------------------------------------------------------------------------
+struct AdjLayout {
+    size_t mu, g, A, Sb, eb, scratch, seg, ckpt, th, total;
+    int M_max, n_ckpt, C, nblk;
+};
+
+template <typename R>
+static AdjLayout adj_layout(const cpf_solver *s, const cpf_path *path, int C)
+{
+    const RveHost &h = s->rv[0];
+    const size_t N = h.nvox, D = s->D;
+    AdjLayout a;
+    a.C = C;
+    a.n_ckpt = (path->n_steps + C - 1) / C;
+    a.M_max = 1;
+    for (int n = 0; n < path->n_steps; ++n) {
+        const double dt = path->t[n + 1] - path->t[n];
+        a.M_max = std::max(a.M_max, s->opt.rk4_M > 0 ? s->opt.rk4_M : substeps(dt, s->opt.h_max));
+    }
+    a.nblk = (int)((N + 255) / 256);
+    size_t o = 0;
+    auto take = [&](size_t bytes) { size_t r = o; o = align256(o + bytes); return r; };
+    a.mu = take(sizeof(R) * 6 * N);
+    a.g = take(sizeof(R) * 6 * N);
+    a.A = take(sizeof(R) * 36 * N);
+    a.Sb = take(sizeof(R) * D * N);
+    a.eb = take(sizeof(R) * 6 * N);
+    a.scratch = take(sizeof(R) * (size_t)a.M_max * 4 * D * N);
+    a.seg = take(sizeof(R) * (size_t)(C + 1) * (6 + D) * N);
+    a.ckpt = take(sizeof(R) * (size_t)a.n_ckpt * (6 + D) * N);
+    a.th = take(sizeof(double) * NTH * a.nblk);
+    a.total = o;
+    return a;
+}
+
+extern "C" int cpf_adjoint_workspace_size(const cpf_solver *s, const cpf_path *path, int checkpoint_every,
+                                          size_t *bytes)
+{
+    if (!s || !bytes) return fail(CPF_E_INVALID_ARG, "null argument");
+    if (s->rv.size() != 1) return fail(CPF_E_INVALID_ARG, "the adjoint needs a single-RVE solver");
+    int rc = check_path(path);
+    if (rc) return rc;
+    if (checkpoint_every < 1) return fail(CPF_E_INVALID_ARG, "checkpoint_every must be >= 1");
+    *bytes = s->prec == CPF_PREC_FP64 ? adj_layout<double>(s, path, checkpoint_every).total
+                                      : adj_layout<float>(s, path, checkpoint_every).total;
+    return CPF_OK;
+}
+
+template <typename R, int NS>
+static void launch_vjp(cpf_solver *s, const AdjArgs<R> &a, int mode)
+{
+    const RveHost &h = s->rv[0];
+    hipLaunchKernelGGL((k_law_vjp<R, NS>), dim3((h.nvox + 255) / 256), dim3(256), 0, s->stream, a, make_law<R>(s),
+                       mode);
+}
+
+template <typename R>
+static int launch_vjp_any(cpf_solver *s, const AdjArgs<R> &a, int mode)
+{
+    switch (s->ns_inst) {
+    case 4: launch_vjp<R, 4>(s, a, mode); break;
+    case 12: launch_vjp<R, 12>(s, a, mode); break;
+    case 16: launch_vjp<R, 16>(s, a, mode); break;
+    default: launch_vjp<R, 32>(s, a, mode); break;
+    }
+    HIPCHK(hipGetLastError());
+    return CPF_OK;
+}
+
+template <typename R>
+static int copy_fields(cpf_solver *s, void *dst, const void *src, size_t bytes)
+{
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s->stream));
+    return CPF_OK;
+}
+
+// Solve the transposed-tangent equilibrium of step n for mu (on the device).
+template <typename R>
+static int adjoint_equilibrium(cpf_solver *s, const cpf_path *path, int n, const AdjArgs<R> &a, double tol,
+                               int *iters)
+{
+    const RveHost &h = s->rv[0];
+    StepInit &si = s->hsi[0];
+    memset(&si, 0, sizeof si);
+    for (int i = 0; i < 6; ++i) si.sidx[i] = path->strain_ctrl[6 * n + i] ? 0 : 1;
+    stress_block_inverse(s->K0, si.sidx, si.K0inv);
+    si.cur = h.cur;
+    si.M = 1;
+    si.dt = 1.0;
+    HIPCHK(hipMemcpyAsync(s->ws + s->off_si, s->hsi, sizeof(StepInit), hipMemcpyHostToDevice, s->stream));
+    hipLaunchKernelGGL(k_begin_step<R>, dim3(1), dim3(64), 0, s->stream, dptr<RveDev<R>>(s, s->off_dev),
+                       dptr<StepInit>(s, s->off_si));
+    int queued = 0, chunk = 8;
+    for (;;) {
+        for (int c = 0; c < chunk; ++c, ++queued) {
+            hipLaunchKernelGGL(k_adj_xpass<R>, dim3(h.nbx), dim3(256), s->lds_x, s->stream, a);
+            launch_y<R>(s, false);
+            launch_z<R>(s, ZMODE_FWD | ZMODE_GREEN);
+            launch_y<R>(s, true);
+            hipLaunchKernelGGL(k_adj_bc<R>, dim3(1), dim3(256), 0, s->stream, dptr<RveDev<R>>(s, s->off_dev), tol,
+                               s->opt.max_iter);
+        }
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(s->hsc, s->ws + h.off_sc, sizeof(Scalars), hipMemcpyDeviceToHost, s->stream));
+        HIPCHK(hipStreamSynchronize(s->stream));
+        if (s->hsc->done) break;
+        if (queued > s->opt.max_iter + 16)
+            return fail(CPF_E_BAD_STATE, "adjoint equilibrium of step %d did not end", n);
+        chunk = 8;
+    }
+    if (s->hsc->status == CPF_E_NAN) return fail(CPF_E_NAN, "adjoint equilibrium of step %d: non-finite", n);
+    if (s->hsc->status == CPF_E_NOT_CONVERGED)
+        return fail(CPF_E_NOT_CONVERGED, "adjoint equilibrium of step %d: no convergence in %d iterations", n,
+                    s->hsc->iter);
+    *iters = s->hsc->iter;
+    return CPF_OK;
+}
+
+template <typename R>
+static int adjoint_impl(cpf_solver *s, const cpf_path *path, const double *target, int C, double adj_tol,
+                        unsigned char *aws, double *loss, double *grad, double *sigxx)
+{
+    const AdjLayout L = adj_layout<R>(s, path, C);
+    RveHost &h = s->rv[0];
+    const long N = h.nvox;
+    const int D = s->D, ns = path->n_steps;
+    const size_t fe = sizeof(R) * 6 * N, fs = sizeof(R) * D * N, slot = fe + fs;
+    auto P = [&](size_t off) { return aws + off; };
+    std::vector<double> Sxx(ns);
+    struct Ck { double Sigma[6], E[6]; int prev; };
+    std::vector<Ck> ck(L.n_ckpt);
+    cpf_step_out out;
+
+    // forward with checkpoints
+    int rc = zero_state<R>(s);
+    if (rc) return rc;
+    for (int n = 0; n < ns; ++n) {
+        if (n % C == 0) {
+            unsigned char *c = P(L.ckpt) + (size_t)(n / C) * slot;
+            rc = copy_fields<R>(s, c, s->ws + h.off_eps[h.cur], fe);
+            if (!rc) rc = copy_fields<R>(s, c + fe, s->ws + h.off_st[h.cur], fs);
+            if (rc) return rc;
+            Ck &k = ck[n / C];
+            memcpy(k.Sigma, h.Sigma_n, sizeof k.Sigma);
+            memcpy(k.E, h.E_n, sizeof k.E);
+            k.prev = h.prev_iters;
+        }
+        rc = step_impl<R>(s, path, n, &out);
+        if (rc) return rc;
+        Sxx[n] = out.Sigma[0];
+    }
+    double Lsum = 0;
+    for (int n = 0; n < ns; ++n) Lsum += (Sxx[n] - target[n]) * (Sxx[n] - target[n]);
+
+    // reverse
+    AdjArgs<R> a;
+    a.rv = dptr<RveDev<R>>(s, s->off_dev);
+    a.scratch = (R *)P(L.scratch);
+    a.g = (R *)P(L.g);
+    a.A = (R *)P(L.A);
+    a.mu = (R *)P(L.mu);
+    a.Sb = (R *)P(L.Sb);
+    a.eb = (R *)P(L.eb);
+    a.th_part = (double *)P(L.th);
+    hipLaunchKernelGGL(k_fill<R>, dim3(512), dim3(256), 0, s->stream, a.Sb, (long)D * N, R(0));
+    hipLaunchKernelGGL(k_fill<R>, dim3(512), dim3(256), 0, s->stream, a.eb, 6L * N, R(0));
+    double G[NTH] = {0};
+    std::vector<double> thp((size_t)NTH * L.nblk);
+    for (int sg = L.n_ckpt - 1; sg >= 0; --sg) {
+        const int n0 = sg * C, n1 = std::min(ns, n0 + C);
+        // restore the checkpoint and recompute the segment, keeping every state
+        const unsigned char *c = P(L.ckpt) + (size_t)sg * slot;
+        rc = copy_fields<R>(s, s->ws + h.off_eps[h.cur], c, fe);
+        if (!rc) rc = copy_fields<R>(s, s->ws + h.off_st[h.cur], c + fe, fs);
+        if (rc) return rc;
+        memcpy(h.Sigma_n, ck[sg].Sigma, sizeof h.Sigma_n);
+        memcpy(h.E_n, ck[sg].E, sizeof h.E_n);
+        h.prev_iters = ck[sg].prev;
+        for (int n = n0; n < n1; ++n) {
+            unsigned char *sl = P(L.seg) + (size_t)(n - n0) * slot;
+            rc = copy_fields<R>(s, sl, s->ws + h.off_eps[h.cur], fe);
+            if (!rc) rc = copy_fields<R>(s, sl + fe, s->ws + h.off_st[h.cur], fs);
+            if (rc) return rc;
+            rc = step_impl<R>(s, path, n, &out);
+            if (rc) return rc;
+        }
+        rc = copy_fields<R>(s, P(L.seg) + (size_t)(n1 - n0) * slot, s->ws + h.off_eps[h.cur], fe);
+        if (rc) return rc;
+        for (int n = n1 - 1; n >= n0; --n) {
+            const unsigned char *sl = P(L.seg) + (size_t)(n - n0) * slot;
+            a.e0 = (const R *)sl;
+            a.st0 = (const R *)(sl + fe);
+            a.e1 = (const R *)(sl + slot);
+            a.sigL_xx = R(2.0 * (Sxx[n] - target[n]) / (double)N);
+            a.dt = R(path->t[n + 1] - path->t[n]);
+            a.M = s->opt.rk4_M > 0 ? s->opt.rk4_M : substeps(path->t[n + 1] - path->t[n], s->opt.h_max);
+            rc = launch_vjp_any<R>(s, a, VJP_GA);
+            if (rc) return rc;
+            int its = 0;
+            rc = adjoint_equilibrium<R>(s, path, n, a, adj_tol, &its);
+            if (rc) return rc;
+            rc = launch_vjp_any<R>(s, a, VJP_F);
+            if (rc) return rc;
+            HIPCHK(hipMemcpyAsync(thp.data(), a.th_part, sizeof(double) * thp.size(), hipMemcpyDeviceToHost,
+                                  s->stream));
+            HIPCHK(hipStreamSynchronize(s->stream));
+            for (int b = 0; b < L.nblk; ++b)
+                for (int k = 0; k < NTH; ++k) G[k] += thp[(size_t)b * NTH + k];
+        }
+    }
+    // leave the solver at the undeformed state
+    rc = zero_state<R>(s);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    *loss = Lsum;
+    for (int k = 0; k < NTH; ++k) grad[k] = G[k];
+    if (sigxx)
+        for (int n = 0; n < ns; ++n) sigxx[n] = Sxx[n];
+    return CPF_OK;
+}
+
+extern "C" int cpf_adjoint_gradient(cpf_solver *s, const cpf_path *path, const double *target_xx,
+                                    int checkpoint_every, double adj_tol, void *dev_ws, size_t bytes, double *loss,
+                                    double *grad, double *sigma_xx)
+{
+    if (!s || !s->bound) return fail(CPF_E_BAD_STATE, "solver not bound");
+    if (s->rv.size() != 1) return fail(CPF_E_INVALID_ARG, "the adjoint needs a single-RVE solver");
+    if (!target_xx || !loss || !grad) return fail(CPF_E_INVALID_ARG, "null argument");
+    if (!(adj_tol > 0)) return fail(CPF_E_INVALID_ARG, "adj_tol must be > 0");
+    size_t need = 0;
+    int rc = cpf_adjoint_workspace_size(s, path, checkpoint_every, &need);
+    if (rc) return rc;
+    if (!dev_ws || bytes < need)
+        return fail(CPF_E_WORKSPACE, "adjoint workspace of %zu bytes given, %zu needed", bytes, need);
+    if (((uintptr_t)dev_ws) & 255) return fail(CPF_E_WORKSPACE, "adjoint workspace must be 256-byte aligned");
+    drop_graph(s);
+    const int g = s->graph_iters;
+    s->graph_iters = 0;
+    rc = s->prec == CPF_PREC_FP64
+             ? adjoint_impl<double>(s, path, target_xx, checkpoint_every, adj_tol, (unsigned char *)dev_ws, loss,
+                                    grad, sigma_xx)
+             : adjoint_impl<float>(s, path, target_xx, checkpoint_every, adj_tol, (unsigned char *)dev_ws, loss,
+                                   grad, sigma_xx);
+    s->graph_iters = g;
+    return rc;
 }

@@ -280,6 +280,7 @@ struct FamP {
     R c, d;    // kinematic hardening
     R K, invK, n, inv_n, nm1;
     int nm1_int;   // n - 1 when n is an integer in [1, 64], else -1
+    R Q, b, qs, ql;   // raw values for the reverse mode
 };
 
 template <typename R>

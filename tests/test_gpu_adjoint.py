@@ -1,0 +1,139 @@
+"""Discrete adjoint on the device: the gradient of the effective stress
+loss with respect to the 14 law parameters matches the FP64 oracle's
+adjoint (itself pinned to finite differences on the CPU), central
+differences of the device's own forward solves, and does not depend on
+the checkpoint interval; the torch.autograd binding returns the same
+gradient."""
+import numpy as np
+import pytest
+
+import oracle
+import rvegen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+cp = pytest.importorskip("paper_2402_09996_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    cp._lib.lib()
+    yield
+
+
+def _case(shape=(4, 4, 6), grains=3, seed=77, steps=3, total=0.006, twin_mode=rvegen.TWIN_NORTON):
+    C, law = rvegen.config_law()
+    law.twin_mode = twin_mode
+    if twin_mode == rvegen.TWIN_PAPER:
+        law.K_c, law.f_m = 1.45, 0.8
+    S = rvegen.config_systems(True)
+    rve = rvegen.make_rve(shape, grains, seed, twin_share=0.5)
+    path = rvegen.uniaxial_path(total, steps, rate=1e-2)
+    return rvegen.Workload("adj", rve, S, C, law, path)
+
+
+def _theta(w):
+    return np.array([[80.0] + [getattr(w.law.slip, k) for k in ("Q", "b", "c", "d", "K", "n")],
+                     [120.0] + [getattr(w.law.twin, k) for k in ("Q", "b", "c", "d", "K", "n")]])
+
+
+def _target(w):
+    sv = cp.Solver(cp.Problem.from_workload(w), precision="fp64", tol=1e-12)
+    return sv.run(w.path)["Sigma"][:, 0] * 1.03
+
+
+@pytest.mark.parametrize("twin_mode", [rvegen.TWIN_NORTON, rvegen.TWIN_PAPER])
+def test_adjoint_matches_oracle_fp64(twin_mode):
+    w = _case(twin_mode=twin_mode)
+    tgt = _target(w)
+    print("adjoint vs oracle, twin_mode", twin_mode, flush=True)
+    s = cp.Solver(cp.Problem.from_workload(w), precision="fp64", tol=1e-12)
+    L, g, sxx = s.gradient(w.path, tgt, checkpoint_every=2, adj_tol=1e-12)
+    Lo, go, so = oracle.solver_for(w, oracle.Options(tol=1e-12)).gradient(w.path, tgt, adj_tol=1e-12)
+    assert np.abs(sxx - so).max() <= 1e-10 * np.abs(so).max()
+    assert L == pytest.approx(Lo, rel=1e-7)
+    for f in (0, 1):
+        scale = np.abs(go[f]).max()
+        assert scale > 0
+        assert np.abs(g[f] - go[f]).max() <= 1e-7 * scale, (f, g[f], go[f])
+
+
+def test_adjoint_independent_of_checkpoint_interval():
+    """Recomputation from checkpoints replays the same deterministic
+    forward steps, so every interval (1, a ragged 2 of 5, all) gives the
+    same numbers bit for bit."""
+    w = _case(shape=(8, 8, 8), grains=5, seed=5, steps=5, total=0.008)
+    tgt = _target(w)
+    s = cp.Solver(cp.Problem.from_workload(w), precision="fp64", tol=1e-10)
+    res = [s.gradient(w.path, tgt, checkpoint_every=c, adj_tol=1e-10) for c in (1, 2, 5)]
+    for L, g, sxx in res[1:]:
+        assert L == res[0][0]
+        assert np.array_equal(g, res[0][1])
+        assert np.array_equal(sxx, res[0][2])
+    # the solver is back at the undeformed state
+    assert float(s.field("strain").abs().max()) == 0.0
+
+
+def test_adjoint_matches_device_finite_differences():
+    w = _case(shape=(8, 8, 8), grains=5, seed=5, steps=4, total=0.008)
+    tgt = _target(w)
+    base = cp.Problem.from_workload(w)
+    s = cp.Solver(base, precision="fp64", tol=1e-12)
+    L, g, _ = s.gradient(w.path, tgt, checkpoint_every=2, adj_tol=1e-12)
+    theta = _theta(w)
+
+    def loss(th):
+        sv = cp.Solver(cp.with_theta(base, th), precision="fp64", tol=1e-12)
+        return float(np.sum((sv.run(w.path)["Sigma"][:, 0] - tgt) ** 2))
+
+    for f, k in [(0, 0), (0, 1), (0, 3), (0, 5), (0, 6), (1, 0), (1, 5)]:
+        h = 1e-5 * max(abs(theta[f, k]), 1.0)
+        tp, tm = theta.copy(), theta.copy()
+        tp[f, k] += h
+        tm[f, k] -= h
+        fd = (loss(tp) - loss(tm)) / (2 * h)
+        print("fd", f, k, fd, g[f, k], flush=True)
+        assert abs(g[f, k] - fd) <= 1e-5 * abs(fd) + 1e-7 * np.abs(g).max(), (f, k, g[f, k], fd)
+
+
+def test_adjoint_fp32_close_to_fp64():
+    w = _case(shape=(8, 8, 8), grains=5, seed=5, steps=4, total=0.008)
+    tgt = _target(w)
+    p = cp.Problem.from_workload(w)
+    L64, g64, _ = cp.Solver(p, precision="fp64", tol=1e-10).gradient(w.path, tgt, adj_tol=1e-10)
+    L32, g32, _ = cp.Solver(p, precision="fp32", tol=1e-6, stag_tol=1e-4).gradient(
+        w.path, tgt, adj_tol=1e-6)
+    print("fp32 vs fp64", L32, L64, np.abs(g32 - g64).max() / np.abs(g64).max(), flush=True)
+    assert L32 == pytest.approx(L64, rel=1e-4)
+    assert np.abs(g32 - g64).max() <= 1e-4 * np.abs(g64).max()
+
+
+def test_autograd_binding():
+    w = _case()
+    tgt = _target(w)
+    p = cp.Problem.from_workload(w)
+    theta = torch.tensor(_theta(w), dtype=torch.float64, requires_grad=True)
+    opts = dict(precision="fp64", tol=1e-12, adj_tol=1e-12, checkpoint_every=10)
+    L = cp.StressCurveLoss.apply(theta, p, w.path, tgt, opts)
+    (3.0 * L).backward()
+    L2, g2, _ = cp.Solver(p, precision="fp64", tol=1e-12).gradient(w.path, tgt, adj_tol=1e-12)
+    assert float(L.detach()) == L2
+    assert np.array_equal(theta.grad.numpy(), 3.0 * g2)
+
+
+def test_adjoint_argument_errors():
+    w = _case()
+    tgt = _target(w)
+    p = cp.Problem.from_workload(w)
+    s = cp.Solver(p, precision="fp64")
+    with pytest.raises(ValueError):
+        s.gradient(w.path, tgt[:-1])
+    with pytest.raises(cp.CpfError):
+        s.gradient(w.path, tgt, checkpoint_every=0)
+    with pytest.raises(cp.CpfError):
+        s.gradient(w.path, tgt, adj_tol=0.0)
+    b = cp.Solver([p, p], precision="fp64")
+    with pytest.raises(cp.CpfError):
+        b.gradient(w.path, tgt)
