@@ -167,6 +167,70 @@ def batch_leg(cp, steps, graph_iters=16):
             "fp32_vs_fp64_max_rel_err_Sigma_xx": err}
 
 
+def adjoint_leg(cp, steps, checkpoint_every=10):
+    """Workload 4: gradient of L = sum_n (Sigma_xx,n - target_n)^2 over 50
+    load steps of the 64^3 fully twinned RVE with respect to the 14 law
+    parameters.  The target curve comes from a forward solve with every
+    parameter scaled by (1 + 0.05 u), u ~ U[-1, 1] (seeded).  Times the
+    device adjoint (checkpoints every 10 steps) against one FP64 forward
+    solve; central differences need 28 such solves."""
+    import numpy as np
+    import torch
+    import rvegen
+    w = rvegen.workload(4, steps_override=steps)
+    base = cp.Problem.from_workload(w)
+    theta = np.array([[80.0] + [getattr(w.law.slip, k) for k in ("Q", "b", "c", "d", "K", "n")],
+                      [120.0] + [getattr(w.law.twin, k) for k in ("Q", "b", "c", "d", "K", "n")]])
+    u = np.random.default_rng(20240219).uniform(-1.0, 1.0, theta.shape)
+    tgt = cp.Solver(cp.with_theta(base, theta * (1 + 0.05 * u)), precision="fp64",
+                    tol=1e-8).run(w.path)["Sigma"][:, 0]
+
+    def forward(prob):
+        s = cp.Solver(prob, precision="fp64", tol=1e-8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = s.run(w.path)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0, r
+
+    t_fwd, r = forward(base)
+    nvox = int(w.rve.labels.size)
+    print("[bench] adjoint leg: FP64 forward %.2f s, %d iterations" % (t_fwd, int(r["iters"].sum())),
+          file=sys.stderr, flush=True)
+    out = {"workload": "64^3 fully twinned RVE (100 grains, 12+4 systems), 2%% tension in %d steps; "
+                       "14 law parameters; target from parameters x (1 + 0.05 u)" % steps,
+           "checkpoint_every": checkpoint_every, "fp64_forward_s": t_fwd,
+           "fp64_forward_iterations": int(r["iters"].sum())}
+    for key, prec, tol, ck in (("fp64", "fp64", 1e-8, checkpoint_every), ("fp32", "fp32", 1e-6, checkpoint_every),
+                               ("fp64_every_step_checkpoint", "fp64", 1e-8, 1)):
+        s = cp.Solver(base, precision=prec, tol=tol, stag_tol=0.0 if prec == "fp64" else 1e-4)
+        need = s.adjoint_workspace_size(w.path, ck)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L, g, _ = s.gradient(w.path, tgt, checkpoint_every=ck, adj_tol=tol)
+        torch.cuda.synchronize()
+        t_adj = time.perf_counter() - t0
+        print("[bench] adjoint %s: %.2f s, L %.6g" % (key, t_adj, L), file=sys.stderr, flush=True)
+        out[key] = {"adjoint_s": t_adj, "loss": L, "grad": g.tolist(), "tol": tol, "checkpoint_every": ck,
+                    "workspace_MB": need / 1e6, **s.adjoint_stats(),
+                    "fd_over_adjoint": 28 * t_fwd / t_adj, "adjoint_over_forward": t_adj / t_fwd}
+        del s
+    g64 = np.array(out["fp64"]["grad"])
+    out["fp32_vs_fp64_grad_max_rel"] = float(np.abs(np.array(out["fp32"]["grad"]) - g64).max()
+                                             / np.abs(g64).max())
+    # one central difference at full size (slip K) as a check of the gradient
+    h = 1e-5 * theta[0, 5]
+    tp, tm = theta.copy(), theta.copy()
+    tp[0, 5] += h
+    tm[0, 5] -= h
+    Lp = float(np.sum((forward(cp.with_theta(base, tp))[1]["Sigma"][:, 0] - tgt) ** 2))
+    Lm = float(np.sum((forward(cp.with_theta(base, tm))[1]["Sigma"][:, 0] - tgt) ** 2))
+    out["fd_check_slip_K"] = {"fd": (Lp - Lm) / (2 * h), "adjoint": float(g64[0, 5])}
+    out["fd_estimate_s"] = 28 * t_fwd
+    out["voxels"] = nvox
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,6 +240,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--batch-steps", type=int, default=10)
+    ap.add_argument("--adjoint-steps", type=int, default=50)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path "
@@ -254,6 +319,8 @@ def main():
             line["fp64"]["fp32_max_rel_err_Sigma_xx"] = float(np.abs(a - b).max() / np.abs(b).max())
     if args.batch_steps > 0:
         line["batched"] = batch_leg(cp, args.batch_steps)
+    if args.adjoint_steps > 0:
+        line["adjoint"] = adjoint_leg(cp, args.adjoint_steps)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, s32, K, args.cpu_seconds)
     print(json.dumps(line), flush=True)

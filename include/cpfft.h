@@ -226,9 +226,10 @@ int cpf_op_constitutive(cpf_solver *s, const void *dev_eps0, const void *dev_eps
  *
  * Forward: the whole path is solved on the device, and the committed
  * (strain, state) pair is copied to the adjoint workspace every
- * checkpoint_every steps.  Reverse: segment by segment, from the last, the
- * segment is recomputed from its checkpoint keeping every step's start
- * state, then for each step (last to first) one launch per voxel recomputes
+ * checkpoint_every steps and at the end.  Reverse: segment by segment, from
+ * the last, the segment's steps but its last are recomputed from its
+ * checkpoint keeping every step's start state (checkpoint_every = 1
+ * recomputes nothing), then for each step (last to first) one launch per voxel recomputes
  * the RK4 stage states (kept in the workspace) and sweeps them backwards for
  * the tangent d sigma / d eps and the load vector; the transposed-tangent
  * equilibrium is solved with the forward FFT and Green-operator passes to
@@ -253,6 +254,12 @@ int cpf_adjoint_workspace_size(const cpf_solver *s, const cpf_path *path, int ch
 int cpf_adjoint_gradient(cpf_solver *s, const cpf_path *path, const double *target_xx,
                          int checkpoint_every, double adj_tol, void *dev_ws, size_t bytes,
                          double *loss, double *grad /*[2][7]*/, double *sigma_xx);
+/* Work of the last cpf_adjoint_gradient call on this solver: fixed-point
+ * iterations of the forward steps (the first pass and the recomputed
+ * steps), iterations of the adjoint equilibria, and the number of
+ * recomputed steps (n_steps - ceil(n_steps / checkpoint_every) per call). */
+int cpf_adjoint_last_stats(const cpf_solver *s, long long *fwd_iters, long long *adj_iters,
+                           int *recomputed_steps);
 
 #ifdef __cplusplus
 }

@@ -89,6 +89,7 @@ class Problem:
         h = ctypes.c_void_p()
         check(L.cpf_problem_create(ctypes.byref(d), ctypes.byref(h)))
         self._h = h
+        self._destroy = L.cpf_problem_destroy   # usable during interpreter shutdown
         self.n_slip = int((self.family == 0).sum())
         self.n_twin = int((self.family == 1).sum())
 
@@ -105,7 +106,7 @@ class Problem:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            _lib.lib().cpf_problem_destroy(h)
+            self._destroy(h)
             self._h = None
 
 
@@ -171,6 +172,7 @@ class Solver:
         arr = (ctypes.c_void_p * self.n_rve)(*[p._h.value for p in probs])
         check(L.cpf_batch_create(self.n_rve, arr, ctypes.byref(o), ctypes.byref(h)))
         self._h = h
+        self._destroy = L.cpf_solver_destroy
         size = ctypes.c_size_t()
         check(L.cpf_solver_workspace_size(h, ctypes.byref(size)))
         self.device = torch.device(device)
@@ -286,6 +288,12 @@ class Solver:
         del ws
         return loss.value, grad.reshape(2, 7), sxx
 
+    def adjoint_stats(self) -> dict:
+        """Work of the last :meth:`gradient` call."""
+        f, a, r = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_int()
+        check(_lib.lib().cpf_adjoint_last_stats(self._h, ctypes.byref(f), ctypes.byref(a), ctypes.byref(r)))
+        return {"forward_iterations": f.value, "adjoint_iterations": a.value, "recomputed_steps": r.value}
+
     # -- kernel timing -------------------------------------------------------
     KERNELS = ("xpass_law", "ypass_fwd", "zpass_green", "ypass_inv", "bc_update")
 
@@ -347,7 +355,7 @@ class Solver:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h is not None and h.value:
-            _lib.lib().cpf_solver_destroy(h)
+            self._destroy(h)
             self._h = None
 
 

@@ -14,6 +14,12 @@
 //   then the reverse sweep with sigma_bar = sigma_bar_L - W mu gives
 //   S_bar_n, eps_bar_n and the parameter gradient.
 // Parameter order per family (slip, twin): r0, Q, b, c, d, K, n.
+//
+// The forward integration of the step is replayed once per step by
+// k_law_record with the solver's own stage code (same specialization, same
+// Newton warm starts), so the recorded stage states and Newton roots are
+// those of the converged forward step; the reverse sweeps read them and
+// never solve for a root.
 #pragma once
 #include "cpfft_kernels.hpp"
 
@@ -37,128 +43,157 @@ __device__ __forceinline__ void cot_to_lab(const R Q[9], const R cc[6], R cl[6])
     cl[3] *= R(2); cl[4] *= R(2); cl[5] *= R(2);
 }
 
-__device__ __forceinline__ double sgnd(double x) { return (x > 0.0) - (x < 0.0); }
-
-// Root y of the regularized rate (0 below threshold), cold start.
-template <typename R>
-__device__ __forceinline__ R reg_root(R o, R A, R eta, const FamP<R> &F, R rtol)
+// Family of system s: compile-time for the Table 1 set (systems 13-16 are
+// the twins), from the mask otherwise.
+template <int SPEC, typename R>
+__device__ __forceinline__ bool is_twin(const LawP<R> &P, int s)
 {
-    if (!(o > R(0)) || !(A > R(0))) return R(0);
-    R yw = R(0);
-    int na = 0, nn = 0;
-    const R etaA = eta * A;
-    const R inv_etaA = etaA > R(0) ? R(1) / etaA : R(0);
-    reg_rate<R>(o, A, inv_etaA, etaA, eta > R(0) ? R(1) / eta : R(0), F, rtol, yw, na, nn);
-    return yw;
+    if constexpr (SPEC == LAW_TABLE1) return s >= 12;
+    else return (P.twin_mask >> s) & 1u;
 }
 
-// Reverse of one rate evaluation dy/dt = F(e, z) in the crystal frame.
-// kb: cotangent of the output; accumulates zb, eb and th (FP64).
-template <typename R, int NS>
-__device__ void rate_vjp(const LawP<R> &P, const R e[6], const R (&zep)[6], const R (&zv)[NS],
-                         const R (&zal)[NS], const R (&kep)[6], const R (&kv)[NS], const R (&kal)[NS],
-                         R (&zbep)[6], R (&zbv)[NS], R (&zbal)[NS], R eb[6], double (&th)[NTH])
+// th[k] (slip) or th[7 + k] (twin) += x with a constant index k, so the
+// accumulators stay in registers whether or not the family is known at
+// compile time.
+__device__ __forceinline__ void th_add(double (&th)[NTH], bool tw, int k, double x)
 {
-    // forward recomputation
+    th[k] += tw ? 0.0 : x;
+    th[7 + k] += tw ? x : 0.0;
+}
+
+// Transposed elastic product out += C^T v (tensor components, same zero
+// pattern as hooke_c).
+template <typename R, int SPEC>
+__device__ __forceinline__ void hooke_ct(const R (&C)[36], const R v[6], R out[6])
+{
+#pragma unroll
+    for (int j = 0; j < 6; ++j) {
+        R s = R(0);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            const bool nz = SPEC == LAW_GENERAL || (i < 3 && j < 3) || i == j;
+            if (nz) s += C[i * 6 + j] * v[i];
+        }
+        out[j] = s;
+    }
+}
+
+// Reverse of one rate evaluation dy/dt = F(e, z) in the crystal frame, at
+// the recorded stage state z and Newton roots ys (0 where inactive).
+// k*: cotangent of the rate; adds to z_bar (zb*), e_bar (eb) and, if TH,
+// the parameter gradient th.
+template <typename R, int NS, int SPEC, bool TH>
+__device__ __forceinline__ void rate_vjp(const LawP<R> &P, const R e[6], const R (&zep)[6], const R (&zv)[NS],
+                                         const R (&zal)[NS], const R (&ys)[NS], const R (&kep)[6],
+                                         const R (&kv)[NS], const R (&kal)[NS], R (&zbep)[6], R (&zbv)[NS],
+                                         R (&zbal)[NS], R (&eb)[6], double (&th)[NTH])
+{
     R ee[6], sig[6];
 #pragma unroll
     for (int i = 0; i < 6; ++i) ee[i] = e[i] - zep[i];
-    hooke_c<R, LAW_GENERAL>(P.C, ee, sig);
+    hooke_c<R, SPEC>(P.C, ee, sig);
     R h[NS];
     R Hs = R(0), Ht = R(0), sumf = R(0);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        const bool tw = (P.twin_mask >> s) & 1u;
-        const FamP<R> &F = tw ? P.ft : P.fs;
-        h[s] = R(1) - exp(-F.b * zv[s]);
+        const bool tw = is_twin<SPEC>(P, s);
+        const R bl = tw ? P.ft.bl2e : P.fs.bl2e;
+        h[s] = R(1) - ex2(-bl * zv[s]);
         if (tw) { Ht += h[s]; sumf += zv[s] * P.inv_gT; }
         else Hs += h[s];
     }
     const R Atw = P.twin_mode ? P.Kc_gT * (P.fm - sumf) : R(1);
-    // reverse: dep, dv, dalpha -> gd; accumulate sigma_bar, h_bar, sumf_bar
     R sigb[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
     R hb[NS];
     R Hsb = R(0), Htb = R(0), sumfb = R(0);
 #pragma unroll
-    for (int s = 0; s < NS; ++s) hb[s] = R(0);
-#pragma unroll
     for (int s = 0; s < NS; ++s) {
-        const bool tw = (P.twin_mask >> s) & 1u;
+        law_fence();
+        const bool tw = is_twin<SPEC>(P, s);
         const FamP<R> &F = tw ? P.ft : P.fs;
-        const int fo = tw ? 7 : 0;
         const R r = P.tau0[s] + F.QL * (tw ? Ht : Hs) + F.QD * h[s];
-        R tau = R(0);
+        R tau = R(0), mk = R(0);
 #pragma unroll
-        for (int i = 0; i < 6; ++i) tau += (i < 3 ? sig[i] : R(2) * sig[i]) * P.m[s][i];
+        for (int i = 0; i < 6; ++i)
+            if (schmid_nonzero<SPEC>(s, i)) {
+                const R m = schmid<R, SPEC>(P.m, s, i);
+                tau += (i < 3 ? sig[i] : R(2) * sig[i]) * m;
+                mk += m * kep[i];
+            }
         const R tx = tau - F.c * zal[s];
         const R A = tw ? Atw : R(1);
-        const R o = tw ? tx - r : fabs(tx) - r;
-        const R y = reg_root<R>(o, A, P.eta, F, P.newton_rtol);
+        const R y = ys[s];
+        // g = A y^n with K y + eta A y^n = o: partials of g in o, A, K, n
         R g = R(0), Go = R(0), GA = R(0), GK = R(0), Gn = R(0);
         if (y > R(0)) {
-            const R yn1 = pow(y, F.nm1), yn = yn1 * y;
-            const R Dn = F.K + P.eta * A * F.n * yn1;
+            const R yn1 = pow_nm1(y, F.nm1, F.nm1_int), yn = yn1 * y;
+            const R inv_D = R(1) / (F.K + P.eta * A * F.n * yn1);
             g = A * yn;
-            Go = A * F.n * yn1 / Dn;
-            GA = yn * F.K / Dn;
-            GK = -A * F.n * yn / Dn;
-            Gn = A * yn * log(y) * F.K / Dn;
+            Go = A * F.n * yn1 * inv_D;
+            GA = yn * F.K * inv_D;
+            if constexpr (TH) {
+                GK = -A * F.n * yn * inv_D;
+                Gn = A * yn * log(y) * F.K * inv_D;
+            }
         }
-        const R gd = (!tw && tx < R(0)) ? -g : g;
+        const bool neg = !tw && tx < R(0);
+        const R gd = neg ? -g : g;
         const R sg = gd > R(0) ? R(1) : (gd < R(0) ? R(-1) : R(0));
-        // dep = sum_s w_s gd_s m_s (w = 1 - sumf for slip), dv = |gd|,
-        // dalpha = gd - d |gd| alpha
-        R mk = R(0);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) mk += P.m[s][i] * kep[i];
+        // ep' = sum w_s gd_s m_s (w = 1 - sum f for slip), v' = |gd|,
+        // alpha' = gd - d |gd| alpha
         R gdb = tw ? mk : (R(1) - sumf) * mk;
         if (!tw) sumfb -= gd * mk;
         gdb += sg * kv[s];
         gdb += kal[s] * (R(1) - F.d * sg * zal[s]);
         zbal[s] -= F.d * fabs(gd) * kal[s];
-        th[fo + 4] -= (double)(fabs(gd) * zal[s] * kal[s]);
-        // gd through the regularized rate
+        if constexpr (TH) th_add(th, tw, 4, -(double)(fabs(gd) * zal[s] * kal[s]));
         R txb = R(0), rb = R(0);
         if (y > R(0)) {
-            const R gb = tw ? gdb : (tx < R(0) ? -gdb : gdb);
+            const R gb = neg ? -gdb : gdb;
             const R ob = Go * gb;
-            txb = tw ? ob : (tx < R(0) ? -ob : ob);
+            txb = neg ? -ob : ob;
             rb = -ob;
             if (tw && P.twin_mode) sumfb -= P.Kc_gT * GA * gb;
-            th[fo + 5] += (double)(GK * gb);
-            th[fo + 6] += (double)(Gn * gb);
+            if constexpr (TH) {
+                th_add(th, tw, 5, (double)(GK * gb));
+                th_add(th, tw, 6, (double)(Gn * gb));
+            }
         }
         // tx = tau - c alpha, tau = sigma : m
         zbal[s] -= F.c * txb;
-        th[fo + 3] -= (double)(zal[s] * txb);
+        if constexpr (TH) th_add(th, tw, 3, -(double)(zal[s] * txb));
 #pragma unroll
-        for (int i = 0; i < 6; ++i) sigb[i] += txb * (i < 3 ? P.m[s][i] : R(2) * P.m[s][i]);
-        // r = tau0 + Q (q_lat H_f + (q_self - q_lat) h_s)
-        th[fo + 0] += (double)rb;
-        th[fo + 1] += (double)(rb * (F.ql * (tw ? Ht : Hs) + (F.qs - F.ql) * h[s]));
-        hb[s] += F.QD * rb;
+        for (int i = 0; i < 6; ++i)
+            if (schmid_nonzero<SPEC>(s, i)) {
+                const R m = schmid<R, SPEC>(P.m, s, i);
+                sigb[i] += txb * (i < 3 ? m : R(2) * m);
+            }
+        // r = r0 + Q (q_lat H_family + (q_self - q_lat) h_s)
+        if constexpr (TH) {
+            th_add(th, tw, 0, (double)rb);
+            th_add(th, tw, 1, (double)(rb * (F.ql * (tw ? Ht : Hs) + (F.qs - F.ql) * h[s])));
+        }
+        hb[s] = F.QD * rb;
         if (tw) Htb += F.QL * rb;
         else Hsb += F.QL * rb;
     }
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
-        const bool tw = (P.twin_mask >> s) & 1u;
+        const bool tw = is_twin<SPEC>(P, s);
         const FamP<R> &F = tw ? P.ft : P.fs;
-        const int fo = tw ? 7 : 0;
         const R hbt = hb[s] + (tw ? Htb : Hsb);
         const R ex = R(1) - h[s];   // exp(-b v)
         zbv[s] += hbt * F.b * ex;
-        th[fo + 2] += (double)(hbt * zv[s] * ex);
+        if constexpr (TH) th_add(th, tw, 2, (double)(hbt * zv[s] * ex));
         if (tw) zbv[s] += sumfb * P.inv_gT;
     }
     // sigma = C (e - ep)
+    R cs[6];
+    hooke_ct<R, SPEC>(P.C, sigb, cs);
 #pragma unroll
     for (int j = 0; j < 6; ++j) {
-        R cs = R(0);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) cs += P.C[i * 6 + j] * sigb[i];
-        eb[j] += cs;
-        zbep[j] -= cs;
+        eb[j] += cs[j];
+        zbep[j] -= cs[j];
     }
 }
 
@@ -171,7 +206,7 @@ struct AdjArgs {
     const R *e0;             // eps_n   [6][N] lab
     const R *e1;             // eps_n+1 [6][N] lab
     const R *st0;            // S_n     [D][N] lab plastic strain, v, alpha
-    R *scratch;              // [M][4][D][N] crystal-frame stage states
+    R *scratch;              // [M][4][D + S][N] crystal-frame stage states and Newton roots
     R *g;                    // [6][N]
     R *A;                    // [36][N], row i = d sigma_i / d eps_n+1
     R *mu;                   // [6][N]
@@ -183,33 +218,110 @@ struct AdjArgs {
     int M;
 };
 
-constexpr int VJP_GA = 0;   // forward recompute, g and A
-constexpr int VJP_F = 1;    // final sweep with sigma_bar_L - W mu (scratch reused)
+constexpr int VJP_GA = 0;   // g and A (seven sweeps)
+constexpr int VJP_F = 1;    // final sweep with sigma_bar_L - W mu, parameter gradient
 
-template <typename R, int NS>
-__device__ void sweep(const LawP<R> &P, const AdjArgs<R> &a, long N, long vox, int nsys, const R e0c[6],
-                      const R e1c[6], const R sbc[6], const R (&Sbep)[6], const R (&Sbv)[NS],
-                      const R (&Sbal)[NS], R e0bc[6], R e1bc[6], R (&ybep)[6], R (&ybv)[NS],
-                      R (&ybal)[NS], double (&th)[NTH])
+// Replay of the forward integration of the step (the solver's integrate()
+// with every stage input and Newton root written to the scratch).
+template <typename R, int NS, int SPEC>
+__global__ __launch_bounds__(256) void k_law_record(AdjArgs<R> a, LawP<R> P)
 {
-    const int D = 6 + 2 * nsys;
+    const RveDev<R> &d = a.rv[0];
+    const long N = d.nvox;
+    const long vox = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (vox >= N) return;
+    const int nsys = P.nsys, D = 6 + 2 * nsys, DY = D + nsys;
+    const int lab = d.labels[vox];
+    R Q[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Q[i] = d.Qtab[lab * 9 + i];
+    R e0l[6], e1l[6], e0[6], e1[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        e0l[c] = a.e0[c * N + vox];
+        e1l[c] = a.e1[c * N + vox];
+    }
+    rot_to_crystal(Q, e0l, e0);
+    rot_to_crystal(Q, e1l, e1);
+    R ep[6], v[NS], al[NS];
+    load_state<R, NS>(a.st0, N, vox, nsys, Q, ep, v, al);
+    const int M = a.M;
+    const R h = a.dt / R(M), invM = R(1) / R(M);
+    R de[6], yw[NS];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) de[i] = e1[i] - e0[i];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) yw[s] = R(0);
+    int nact = 0, nnewt = 0;
+#pragma unroll 1
+    for (int j = 0; j < M; ++j) {
+        R tep[6], tv[NS], tal[NS], aep[6], av[NS], aal[NS];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) tep[i] = aep[i] = ep[i];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            tv[s] = av[s] = v[s];
+            tal[s] = aal[s] = al[s];
+        }
+#pragma unroll 1
+        for (int st = 0; st < 4; ++st) {
+            R *zs = a.scratch + (((long)j * 4 + st) * DY) * N + vox;
+#pragma unroll
+            for (int i = 0; i < 6; ++i) zs[i * N] = tep[i];
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+                if (s < nsys) {
+                    zs[(6 + s) * N] = tv[s];
+                    zs[(6 + nsys + s) * N] = tal[s];
+                }
+            const R sfrac = (st == 0) ? R(j) * invM : (st == 3) ? R(j + 1) * invM : (R(j) + R(0.5)) * invM;
+            const R wacc = (st == 0 || st == 3) ? h * R(1.0 / 6.0) : h * R(1.0 / 3.0);
+            const R cnext = (st == 2) ? h : h * R(0.5);
+            R e[6];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) e[i] = e0[i] + sfrac * de[i];
+            rk_stage<R, NS, SPEC>(P, e, tep, tv, tal, ep, v, al, aep, av, aal, yw, wacc, cnext, st < 3, nact,
+                                  nnewt);
+#pragma unroll
+            for (int s = 0; s < NS; ++s)
+                if (s < nsys) zs[(D + s) * N] = yw[s];
+        }
+#pragma unroll
+        for (int i = 0; i < 6; ++i) ep[i] = aep[i];
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            v[s] = av[s];
+            al[s] = aal[s];
+        }
+    }
+}
+
+// Reverse RK4 over the recorded stages.  In: cotangents of the end stress
+// (sbc) and of the end state (yb*, overwritten with the cotangent of the
+// start state).  Adds the strain cotangents to e0bc / e1bc.
+template <typename R, int NS, int SPEC, bool TH>
+__device__ __forceinline__ void sweep(const LawP<R> &P, const AdjArgs<R> &a, long N, long vox, int nsys,
+                                      const R (&e0c)[6], const R (&e1c)[6], const R (&sbc)[6], R (&e0bc)[6],
+                                      R (&e1bc)[6], R (&ybep)[6], R (&ybv)[NS], R (&ybal)[NS],
+                                      double (&th)[NTH])
+{
+    const int D = 6 + 2 * nsys, DY = D + nsys;
     const R h = a.dt / R(a.M);
     const R invM = R(1) / R(a.M);
     // end stress sigma = C (e1 - ep_M)
+    {
+        R cs[6];
+        hooke_ct<R, SPEC>(P.C, sbc, cs);
 #pragma unroll
-    for (int i = 0; i < 6; ++i) ybep[i] = Sbep[i];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) { ybv[s] = Sbv[s]; ybal[s] = Sbal[s]; }
-#pragma unroll
-    for (int j = 0; j < 6; ++j) {
-        R cs = R(0);
-#pragma unroll
-        for (int i = 0; i < 6; ++i) cs += P.C[i * 6 + j] * sbc[i];
-        e1bc[j] += cs;
-        ybep[j] -= cs;
+        for (int j = 0; j < 6; ++j) {
+            e1bc[j] += cs[j];
+            ybep[j] -= cs[j];
+        }
     }
+#pragma unroll 1
     for (int j = a.M - 1; j >= 0; --j) {
-        R aep[6], av[NS], aal[NS];        // y_j bar accumulator
+        // y_{j+1} = y_j + sum_st w_st k_st, z_0 = y_j, z_{st+1} = y_j + c_st k_st
+        R aep[6], av[NS], aal[NS];
 #pragma unroll
         for (int i = 0; i < 6; ++i) aep[i] = ybep[i];
 #pragma unroll
@@ -217,37 +329,41 @@ __device__ void sweep(const LawP<R> &P, const AdjArgs<R> &a, long N, long vox, i
         R zbep[6] = {R(0), R(0), R(0), R(0), R(0), R(0)}, zbv[NS], zbal[NS];
 #pragma unroll
         for (int s = 0; s < NS; ++s) { zbv[s] = R(0); zbal[s] = R(0); }
+#pragma unroll 1
         for (int st = 3; st >= 0; --st) {
             const R wst = (st == 0 || st == 3) ? h * R(1.0 / 6.0) : h * R(1.0 / 3.0);
-            const R cn = (st == 2) ? h : h * R(0.5);   // z_{st+1} = y + cn k_st
-            // k_bar_st = w_st y_bar + cn z_bar_{st+1}
+            const R cn = (st == 2) ? h : h * R(0.5);
+            const R cz = st < 3 ? cn : R(0);
+            // k_bar_st = w_st y_bar + c_st z_bar_{st+1}
             R kep[6], kv[NS], kal[NS];
 #pragma unroll
-            for (int i = 0; i < 6; ++i) kep[i] = wst * ybep[i] + (st < 3 ? cn * zbep[i] : R(0));
+            for (int i = 0; i < 6; ++i) kep[i] = wst * ybep[i] + cz * zbep[i];
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                kv[s] = wst * ybv[s] + (st < 3 ? cn * zbv[s] : R(0));
-                kal[s] = wst * ybal[s] + (st < 3 ? cn * zbal[s] : R(0));
+                kv[s] = wst * ybv[s] + cz * zbv[s];
+                kal[s] = wst * ybal[s] + cz * zbal[s];
             }
-            // stage input z_st from the scratch
-            const R *zs = a.scratch + (((long)j * 4 + st) * D) * N + vox;
-            R zep[6], zv[NS], zal[NS];
+            const R *zs = a.scratch + (((long)j * 4 + st) * DY) * N + vox;
+            R zep[6], zv[NS], zal[NS], ys[NS];
 #pragma unroll
             for (int i = 0; i < 6; ++i) zep[i] = zs[i * N];
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
                 zv[s] = s < nsys ? zs[(6 + s) * N] : R(0);
                 zal[s] = s < nsys ? zs[(6 + nsys + s) * N] : R(0);
+                ys[s] = s < nsys ? zs[(D + s) * N] : R(0);
             }
             const R sf = (st == 0) ? R(j) * invM : (st == 3) ? R(j + 1) * invM : (R(j) + R(0.5)) * invM;
-            R e[6], ebs[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+            R e[6], ebs[6];
 #pragma unroll
-            for (int i = 0; i < 6; ++i) e[i] = e0c[i] + sf * (e1c[i] - e0c[i]);
-#pragma unroll
-            for (int i = 0; i < 6; ++i) zbep[i] = R(0);
+            for (int i = 0; i < 6; ++i) {
+                e[i] = e0c[i] + sf * (e1c[i] - e0c[i]);
+                ebs[i] = R(0);
+                zbep[i] = R(0);
+            }
 #pragma unroll
             for (int s = 0; s < NS; ++s) { zbv[s] = R(0); zbal[s] = R(0); }
-            rate_vjp<R, NS>(P, e, zep, zv, zal, kep, kv, kal, zbep, zbv, zbal, ebs, th);
+            rate_vjp<R, NS, SPEC, TH>(P, e, zep, zv, zal, ys, kep, kv, kal, zbep, zbv, zbal, ebs, th);
 #pragma unroll
             for (int i = 0; i < 6; ++i) {
                 e0bc[i] += (R(1) - sf) * ebs[i];
@@ -264,8 +380,14 @@ __device__ void sweep(const LawP<R> &P, const AdjArgs<R> &a, long N, long vox, i
     }
 }
 
-template <typename R, int NS>
-__global__ __launch_bounds__(256) void k_law_vjp(AdjArgs<R> a, LawP<R> P, int mode)
+// MODE VJP_GA: seven sweeps of the recorded step, r = 0 with the loss
+// cotangent and the carried S_bar (-> g, plus the carried eps_bar), r = 1..6
+// with sigma_bar = unit vector r-1 and S_bar = 0 (-> row r-1 of A).
+// MODE VJP_F: one sweep with sigma_bar = sigma_bar_L - W mu and the carried
+// S_bar; writes S_bar_n, eps_bar_n and the FP64 block partials of the
+// parameter gradient.
+template <typename R, int NS, int SPEC, int MODE>
+__global__ __launch_bounds__(256) void k_law_vjp(AdjArgs<R> a, LawP<R> P)
 {
     const RveDev<R> &d = a.rv[0];
     const long N = d.nvox;
@@ -275,105 +397,65 @@ __global__ __launch_bounds__(256) void k_law_vjp(AdjArgs<R> a, LawP<R> P, int mo
     for (int k = 0; k < NTH; ++k) th[k] = 0.0;
     const int nsys = P.nsys;
     if (vox < N) {
-        const int D = 6 + 2 * nsys;
         const int lab = d.labels[vox];
         R Q[9];
 #pragma unroll
         for (int i = 0; i < 9; ++i) Q[i] = d.Qtab[lab * 9 + i];
-        R e0l[6], e1l[6], e0c[6], e1c[6];
-#pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            e0l[c] = a.e0[c * N + vox];
-            e1l[c] = a.e1[c * N + vox];
-        }
-        rot_to_crystal(Q, e0l, e0c);
-        rot_to_crystal(Q, e1l, e1c);
-        if (mode == VJP_GA) {
-            // forward recompute of the stage inputs into the scratch
-            R ep[6], v[NS], al[NS];
-            load_state<R, NS>(a.st0, N, vox, nsys, Q, ep, v, al);
-            const R h = a.dt / R(a.M), invM = R(1) / R(a.M);
-            for (int j = 0; j < a.M; ++j) {
-                R tep[6], tv[NS], tal[NS], aep[6], av[NS], aal[NS], yw[NS];
-#pragma unroll
-                for (int i = 0; i < 6; ++i) tep[i] = aep[i] = ep[i];
-#pragma unroll
-                for (int s = 0; s < NS; ++s) {
-                    tv[s] = av[s] = v[s];
-                    tal[s] = aal[s] = al[s];
-                    yw[s] = R(0);
-                }
-                for (int st = 0; st < 4; ++st) {
-                    R *zs = a.scratch + (((long)j * 4 + st) * D) * N + vox;
-#pragma unroll
-                    for (int i = 0; i < 6; ++i) zs[i * N] = tep[i];
-#pragma unroll
-                    for (int s = 0; s < NS; ++s)
-                        if (s < nsys) {
-                            zs[(6 + s) * N] = tv[s];
-                            zs[(6 + nsys + s) * N] = tal[s];
-                        }
-                    const R sf = (st == 0) ? R(j) * invM : (st == 3) ? R(j + 1) * invM : (R(j) + R(0.5)) * invM;
-                    const R wacc = (st == 0 || st == 3) ? h * R(1.0 / 6.0) : h * R(1.0 / 3.0);
-                    const R cnext = (st == 2) ? h : h * R(0.5);
-                    R e[6];
-#pragma unroll
-                    for (int i = 0; i < 6; ++i) e[i] = e0c[i] + sf * (e1c[i] - e0c[i]);
-                    int na = 0, nn = 0;
-                    rk_stage<R, NS, LAW_GENERAL>(P, e, tep, tv, tal, ep, v, al, aep, av, aal, yw, wacc, cnext,
-                                                 st < 3, na, nn);
-                }
-#pragma unroll
-                for (int i = 0; i < 6; ++i) ep[i] = aep[i];
-#pragma unroll
-                for (int s = 0; s < NS; ++s) { v[s] = av[s]; al[s] = aal[s]; }
-            }
-        }
-        R Sbep[6], Sbv[NS], Sbal[NS];
+        R e0c[6], e1c[6];
         {
-            R tl[6], tc[6];
+            R e0l[6], e1l[6];
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                e0l[c] = a.e0[c * N + vox];
+                e1l[c] = a.e1[c * N + vox];
+            }
+            rot_to_crystal(Q, e0l, e0c);
+            rot_to_crystal(Q, e1l, e1c);
+        }
+        // carried cotangent of S_n+1 (crystal frame)
+        R Sep[6], Sv[NS], Sal[NS];
+        {
+            R tl[6];
 #pragma unroll
             for (int i = 0; i < 6; ++i) tl[i] = a.Sb[i * N + vox];
-            cot_to_crystal(Q, tl, tc);
-#pragma unroll
-            for (int i = 0; i < 6; ++i) Sbep[i] = tc[i];
+            cot_to_crystal(Q, tl, Sep);
 #pragma unroll
             for (int s = 0; s < NS; ++s) {
-                Sbv[s] = s < nsys ? a.Sb[(6 + s) * N + vox] : R(0);
-                Sbal[s] = s < nsys ? a.Sb[(6 + nsys + s) * N + vox] : R(0);
+                Sv[s] = s < nsys ? a.Sb[(6 + s) * N + vox] : R(0);
+                Sal[s] = s < nsys ? a.Sb[(6 + nsys + s) * N + vox] : R(0);
             }
         }
-        R ybep[6], ybv[NS], ybal[NS];
-        if (mode == VJP_GA) {
-            // g: cotangents (sigma_bar_L, S_bar) plus the carried eps_bar
-            R sbl[6] = {a.sigL_xx, R(0), R(0), R(0), R(0), R(0)}, sbc[6];
-            cot_to_crystal(Q, sbl, sbc);
-            R e0b[6] = {R(0), R(0), R(0), R(0), R(0), R(0)}, e1b[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-            double thd[NTH];
+        if constexpr (MODE == VJP_GA) {
+#pragma unroll 1
+            for (int r = 0; r < 7; ++r) {
+                R sbl[6], sbc[6];
 #pragma unroll
-            for (int k = 0; k < NTH; ++k) thd[k] = 0.0;
-            sweep<R, NS>(P, a, N, vox, nsys, e0c, e1c, sbc, Sbep, Sbv, Sbal, e0b, e1b, ybep, ybv, ybal, thd);
-            R gl[6];
-            cot_to_lab(Q, e1b, gl);
+                for (int c = 0; c < 6; ++c)
+                    sbl[c] = r == 0 ? (c == 0 ? a.sigL_xx : R(0)) : (c == r - 1 ? R(1) : R(0));
+                cot_to_crystal(Q, sbl, sbc);
+                R ybep[6], ybv[NS], ybal[NS], e0b[6], e1b[6];
 #pragma unroll
-            for (int c = 0; c < 6; ++c) a.g[c * N + vox] = gl[c] + a.eb[c * N + vox];
-            // A: rows d sigma_i / d eps_n+1 (sigma_bar = e_i, S_bar = 0)
-            R zep6[6] = {R(0), R(0), R(0), R(0), R(0), R(0)}, zv[NS], zal[NS];
+                for (int i = 0; i < 6; ++i) {
+                    ybep[i] = r == 0 ? Sep[i] : R(0);
+                    e0b[i] = e1b[i] = R(0);
+                }
 #pragma unroll
-            for (int s = 0; s < NS; ++s) { zv[s] = R(0); zal[s] = R(0); }
-            for (int i = 0; i < 6; ++i) {
-                R el[6] = {R(0), R(0), R(0), R(0), R(0), R(0)}, ec[6];
-                el[i] = R(1);
-                cot_to_crystal(Q, el, ec);
-                R a0[6] = {R(0), R(0), R(0), R(0), R(0), R(0)}, a1[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-                sweep<R, NS>(P, a, N, vox, nsys, e0c, e1c, ec, zep6, zv, zal, a0, a1, ybep, ybv, ybal, thd);
-                R rl[6];
-                cot_to_lab(Q, a1, rl);
+                for (int s = 0; s < NS; ++s) {
+                    ybv[s] = r == 0 ? Sv[s] : R(0);
+                    ybal[s] = r == 0 ? Sal[s] : R(0);
+                }
+                sweep<R, NS, SPEC, false>(P, a, N, vox, nsys, e0c, e1c, sbc, e0b, e1b, ybep, ybv, ybal, th);
+                R out[6];
+                cot_to_lab(Q, e1b, out);
+                if (r == 0) {
 #pragma unroll
-                for (int c = 0; c < 6; ++c) a.A[(i * 6 + c) * N + vox] = rl[c];
+                    for (int c = 0; c < 6; ++c) a.g[c * N + vox] = out[c] + a.eb[c * N + vox];
+                } else {
+#pragma unroll
+                    for (int c = 0; c < 6; ++c) a.A[((r - 1) * 6 + c) * N + vox] = out[c];
+                }
             }
         } else {
-            // final sweep: sigma_bar = sigma_bar_L - W mu
             R sbl[6], sbc[6];
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
@@ -382,10 +464,10 @@ __global__ __launch_bounds__(256) void k_law_vjp(AdjArgs<R> a, LawP<R> P, int mo
             }
             cot_to_crystal(Q, sbl, sbc);
             R e0b[6] = {R(0), R(0), R(0), R(0), R(0), R(0)}, e1b[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-            sweep<R, NS>(P, a, N, vox, nsys, e0c, e1c, sbc, Sbep, Sbv, Sbal, e0b, e1b, ybep, ybv, ybal, th);
+            sweep<R, NS, SPEC, true>(P, a, N, vox, nsys, e0c, e1c, sbc, e0b, e1b, Sep, Sv, Sal, th);
             R el[6], epl[6];
             cot_to_lab(Q, e0b, el);
-            cot_to_lab(Q, ybep, epl);
+            cot_to_lab(Q, Sep, epl);
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
                 a.eb[c * N + vox] = el[c];
@@ -394,12 +476,12 @@ __global__ __launch_bounds__(256) void k_law_vjp(AdjArgs<R> a, LawP<R> P, int mo
 #pragma unroll
             for (int s = 0; s < NS; ++s)
                 if (s < nsys) {
-                    a.Sb[(6 + s) * N + vox] = ybv[s];
-                    a.Sb[(6 + nsys + s) * N + vox] = ybal[s];
+                    a.Sb[(6 + s) * N + vox] = Sv[s];
+                    a.Sb[(6 + nsys + s) * N + vox] = Sal[s];
                 }
         }
     }
-    if (mode == VJP_F) block_sum<NTH>(th, a.th_part + (long)blockIdx.x * NTH);
+    if constexpr (MODE == VJP_F) block_sum<NTH>(th, a.th_part + (long)blockIdx.x * NTH);
 }
 
 // ---------------------------------------------------------------------------

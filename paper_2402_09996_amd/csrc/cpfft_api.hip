@@ -286,6 +286,10 @@ struct cpf_solver {
     int ns_inst, law_spec;
     double lam0, mu0, K0[36];
     int n_slip, n_twin;
+    // last adjoint call: forward iterations (with recomputation), adjoint
+    // equilibrium iterations, recomputed steps
+    long long adj_fwd_iters = 0, adj_eq_iters = 0;
+    int adj_recomputed = 0;
     // pass grids over all RVEs
     int nbx_tot = 0, nby_tot = 0, nbz_tot = 0;
     size_t lds_x = 0, lds_y = 0, lds_z = 0;
@@ -1366,9 +1370,11 @@ static AdjLayout adj_layout(const cpf_solver *s, const cpf_path *path, int C)
     a.A = take(sizeof(R) * 36 * N);
     a.Sb = take(sizeof(R) * D * N);
     a.eb = take(sizeof(R) * 6 * N);
-    a.scratch = take(sizeof(R) * (size_t)a.M_max * 4 * D * N);
-    a.seg = take(sizeof(R) * (size_t)(C + 1) * (6 + D) * N);
-    a.ckpt = take(sizeof(R) * (size_t)a.n_ckpt * (6 + D) * N);
+    a.scratch = take(sizeof(R) * (size_t)a.M_max * 4 * (D + s->n_slip + s->n_twin) * N);
+    // checkpoints at steps 0, C, 2C, ... and the end state; a segment's
+    // other start states are recomputed into C - 1 slots
+    a.seg = take(sizeof(R) * (size_t)(C - 1) * (6 + D) * N);
+    a.ckpt = take(sizeof(R) * (size_t)(a.n_ckpt + 1) * (6 + D) * N);
     a.th = take(sizeof(double) * NTH * a.nblk);
     a.total = o;
     return a;
@@ -1387,22 +1393,31 @@ extern "C" int cpf_adjoint_workspace_size(const cpf_solver *s, const cpf_path *p
     return CPF_OK;
 }
 
-template <typename R, int NS>
-static void launch_vjp(cpf_solver *s, const AdjArgs<R> &a, int mode)
+template <typename R, int NS, int SPEC>
+static void launch_law_adj(cpf_solver *s, const AdjArgs<R> &a, int what)
 {
     const RveHost &h = s->rv[0];
-    hipLaunchKernelGGL((k_law_vjp<R, NS>), dim3((h.nvox + 255) / 256), dim3(256), 0, s->stream, a, make_law<R>(s),
-                       mode);
+    const dim3 grid((h.nvox + 255) / 256), block(256);
+    const LawP<R> P = make_law<R>(s);
+    if (what == 0) hipLaunchKernelGGL((k_law_record<R, NS, SPEC>), grid, block, 0, s->stream, a, P);
+    else if (what == 1) hipLaunchKernelGGL((k_law_vjp<R, NS, SPEC, VJP_GA>), grid, block, 0, s->stream, a, P);
+    else hipLaunchKernelGGL((k_law_vjp<R, NS, SPEC, VJP_F>), grid, block, 0, s->stream, a, P);
 }
 
+// what: 0 record the forward stages, 1 g and A sweeps, 2 final sweep
 template <typename R>
-static int launch_vjp_any(cpf_solver *s, const AdjArgs<R> &a, int mode)
+static int launch_law_adj_any(cpf_solver *s, const AdjArgs<R> &a, int what)
 {
-    switch (s->ns_inst) {
-    case 4: launch_vjp<R, 4>(s, a, mode); break;
-    case 12: launch_vjp<R, 12>(s, a, mode); break;
-    case 16: launch_vjp<R, 16>(s, a, mode); break;
-    default: launch_vjp<R, 32>(s, a, mode); break;
+    if (s->law_spec == LAW_TABLE1) {
+        if (s->ns_inst == 12) launch_law_adj<R, 12, LAW_TABLE1>(s, a, what);
+        else launch_law_adj<R, 16, LAW_TABLE1>(s, a, what);
+    } else {
+        switch (s->ns_inst) {
+        case 4: launch_law_adj<R, 4, LAW_GENERAL>(s, a, what); break;
+        case 12: launch_law_adj<R, 12, LAW_GENERAL>(s, a, what); break;
+        case 16: launch_law_adj<R, 16, LAW_GENERAL>(s, a, what); break;
+        default: launch_law_adj<R, 32, LAW_GENERAL>(s, a, what); break;
+        }
     }
     HIPCHK(hipGetLastError());
     return CPF_OK;
@@ -1472,6 +1487,8 @@ static int adjoint_impl(cpf_solver *s, const cpf_path *path, const double *targe
     std::vector<Ck> ck(L.n_ckpt);
     cpf_step_out out;
 
+    s->adj_fwd_iters = s->adj_eq_iters = 0;
+    s->adj_recomputed = 0;
     // forward with checkpoints
     int rc = zero_state<R>(s);
     if (rc) return rc;
@@ -1489,6 +1506,13 @@ static int adjoint_impl(cpf_solver *s, const cpf_path *path, const double *targe
         rc = step_impl<R>(s, path, n, &out);
         if (rc) return rc;
         Sxx[n] = out.Sigma[0];
+        s->adj_fwd_iters += out.iters;
+    }
+    {
+        unsigned char *c = P(L.ckpt) + (size_t)L.n_ckpt * slot;
+        rc = copy_fields<R>(s, c, s->ws + h.off_eps[h.cur], fe);
+        if (!rc) rc = copy_fields<R>(s, c + fe, s->ws + h.off_st[h.cur], fs);
+        if (rc) return rc;
     }
     double Lsum = 0;
     for (int n = 0; n < ns; ++n) Lsum += (Sxx[n] - target[n]) * (Sxx[n] - target[n]);
@@ -1509,38 +1533,46 @@ static int adjoint_impl(cpf_solver *s, const cpf_path *path, const double *targe
     std::vector<double> thp((size_t)NTH * L.nblk);
     for (int sg = L.n_ckpt - 1; sg >= 0; --sg) {
         const int n0 = sg * C, n1 = std::min(ns, n0 + C);
-        // restore the checkpoint and recompute the segment, keeping every state
+        // start states of the segment: the checkpoint, then recomputed steps
         const unsigned char *c = P(L.ckpt) + (size_t)sg * slot;
-        rc = copy_fields<R>(s, s->ws + h.off_eps[h.cur], c, fe);
-        if (!rc) rc = copy_fields<R>(s, s->ws + h.off_st[h.cur], c + fe, fs);
-        if (rc) return rc;
-        memcpy(h.Sigma_n, ck[sg].Sigma, sizeof h.Sigma_n);
-        memcpy(h.E_n, ck[sg].E, sizeof h.E_n);
-        h.prev_iters = ck[sg].prev;
-        for (int n = n0; n < n1; ++n) {
-            unsigned char *sl = P(L.seg) + (size_t)(n - n0) * slot;
-            rc = copy_fields<R>(s, sl, s->ws + h.off_eps[h.cur], fe);
-            if (!rc) rc = copy_fields<R>(s, sl + fe, s->ws + h.off_st[h.cur], fs);
+        if (n1 - n0 > 1) {
+            rc = copy_fields<R>(s, s->ws + h.off_eps[h.cur], c, fe);
+            if (!rc) rc = copy_fields<R>(s, s->ws + h.off_st[h.cur], c + fe, fs);
             if (rc) return rc;
-            rc = step_impl<R>(s, path, n, &out);
-            if (rc) return rc;
+            memcpy(h.Sigma_n, ck[sg].Sigma, sizeof h.Sigma_n);
+            memcpy(h.E_n, ck[sg].E, sizeof h.E_n);
+            h.prev_iters = ck[sg].prev;
+            for (int n = n0; n < n1 - 1; ++n) {
+                rc = step_impl<R>(s, path, n, &out);
+                if (rc) return rc;
+                s->adj_fwd_iters += out.iters;
+                s->adj_recomputed += 1;
+                unsigned char *sl = P(L.seg) + (size_t)(n - n0) * slot;
+                rc = copy_fields<R>(s, sl, s->ws + h.off_eps[h.cur], fe);
+                if (!rc) rc = copy_fields<R>(s, sl + fe, s->ws + h.off_st[h.cur], fs);
+                if (rc) return rc;
+            }
         }
-        rc = copy_fields<R>(s, P(L.seg) + (size_t)(n1 - n0) * slot, s->ws + h.off_eps[h.cur], fe);
-        if (rc) return rc;
+        auto start_of = [&](int n) -> const unsigned char * {
+            return n == n0 ? c : n == n1 ? P(L.ckpt) + (size_t)(sg + 1) * slot
+                                         : P(L.seg) + (size_t)(n - n0 - 1) * slot;
+        };
         for (int n = n1 - 1; n >= n0; --n) {
-            const unsigned char *sl = P(L.seg) + (size_t)(n - n0) * slot;
+            const unsigned char *sl = start_of(n);
             a.e0 = (const R *)sl;
             a.st0 = (const R *)(sl + fe);
-            a.e1 = (const R *)(sl + slot);
+            a.e1 = (const R *)start_of(n + 1);
             a.sigL_xx = R(2.0 * (Sxx[n] - target[n]) / (double)N);
             a.dt = R(path->t[n + 1] - path->t[n]);
             a.M = s->opt.rk4_M > 0 ? s->opt.rk4_M : substeps(path->t[n + 1] - path->t[n], s->opt.h_max);
-            rc = launch_vjp_any<R>(s, a, VJP_GA);
+            rc = launch_law_adj_any<R>(s, a, 0);
+            if (!rc) rc = launch_law_adj_any<R>(s, a, 1);
             if (rc) return rc;
             int its = 0;
             rc = adjoint_equilibrium<R>(s, path, n, a, adj_tol, &its);
             if (rc) return rc;
-            rc = launch_vjp_any<R>(s, a, VJP_F);
+            s->adj_eq_iters += its;
+            rc = launch_law_adj_any<R>(s, a, 2);
             if (rc) return rc;
             HIPCHK(hipMemcpyAsync(thp.data(), a.th_part, sizeof(double) * thp.size(), hipMemcpyDeviceToHost,
                                   s->stream));
@@ -1583,5 +1615,21 @@ extern "C" int cpf_adjoint_gradient(cpf_solver *s, const cpf_path *path, const d
              : adjoint_impl<float>(s, path, target_xx, checkpoint_every, adj_tol, (unsigned char *)dev_ws, loss,
                                    grad, sigma_xx);
     s->graph_iters = g;
+    if (rc) {
+        // back to the undeformed state; the first error stays reported
+        if (s->prec == CPF_PREC_FP64) zero_state<double>(s);
+        else zero_state<float>(s);
+        (void)hipStreamSynchronize(s->stream);
+    }
     return rc;
+}
+
+extern "C" int cpf_adjoint_last_stats(const cpf_solver *s, long long *fwd_iters, long long *adj_iters,
+                                      int *recomputed_steps)
+{
+    if (!s || !fwd_iters || !adj_iters || !recomputed_steps) return fail(CPF_E_INVALID_ARG, "null argument");
+    *fwd_iters = s->adj_fwd_iters;
+    *adj_iters = s->adj_eq_iters;
+    *recomputed_steps = s->adj_recomputed;
+    return CPF_OK;
 }

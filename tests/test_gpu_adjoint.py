@@ -67,7 +67,12 @@ def test_adjoint_independent_of_checkpoint_interval():
     w = _case(shape=(8, 8, 8), grains=5, seed=5, steps=5, total=0.008)
     tgt = _target(w)
     s = cp.Solver(cp.Problem.from_workload(w), precision="fp64", tol=1e-10)
-    res = [s.gradient(w.path, tgt, checkpoint_every=c, adj_tol=1e-10) for c in (1, 2, 5)]
+    res = []
+    for c in (1, 2, 5):
+        res.append(s.gradient(w.path, tgt, checkpoint_every=c, adj_tol=1e-10))
+        st = s.adjoint_stats()
+        assert st["recomputed_steps"] == 5 - (5 + c - 1) // c
+        assert st["adjoint_iterations"] > 0 and st["forward_iterations"] > 0
     for L, g, sxx in res[1:]:
         assert L == res[0][0]
         assert np.array_equal(g, res[0][1])
