@@ -156,7 +156,7 @@ def batch_leg(cp, steps, graph_iters=16):
               (j, members[j].labels.shape[0], t64), file=sys.stderr, flush=True)
     sizes = sorted(set(int(m.labels.shape[0]) for m in members))
     return {"workload": "32 RVEs, N in {32,48,64,96}^3, 50-300 grains, even members twinned, "
-                        "2%/50-step tension (first %d steps)" % steps,
+                        "2%%/50-step tension (first %d steps)" % steps,
             "rves": len(members), "voxels": nvox, "grid_sizes": sizes, "steps": steps,
             "graph_iters_per_launch": graph_iters,
             "tiles": {str(n): b.tiles(next(i for i, m in enumerate(members)
@@ -231,6 +231,19 @@ def adjoint_leg(cp, steps, checkpoint_every=10):
     return out
 
 
+def copy_probe(nbytes=1 << 30, reps=5):
+    """Plain device-to-device copies of a known size: the reference for
+    the FETCH_SIZE / WRITE_SIZE counters (bytes read and written per copy
+    are both nbytes)."""
+    import torch
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_probe_bytes": nbytes, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -241,7 +254,12 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--adjoint-steps", type=int, default=50)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run plain 1 GiB device copies (calibrates the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        copy_probe()
+        return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)

@@ -43,15 +43,6 @@ __device__ __forceinline__ void cot_to_lab(const R Q[9], const R cc[6], R cl[6])
     cl[3] *= R(2); cl[4] *= R(2); cl[5] *= R(2);
 }
 
-// Family of system s: compile-time for the Table 1 set (systems 13-16 are
-// the twins), from the mask otherwise.
-template <int SPEC, typename R>
-__device__ __forceinline__ bool is_twin(const LawP<R> &P, int s)
-{
-    if constexpr (SPEC == LAW_TABLE1) return s >= 12;
-    else return (P.twin_mask >> s) & 1u;
-}
-
 // th[k] (slip) or th[7 + k] (twin) += x with a constant index k, so the
 // accumulators stay in registers whether or not the family is known at
 // compile time.
@@ -111,7 +102,6 @@ __device__ __forceinline__ void rate_vjp(const LawP<R> &P, const R e[6], const R
         law_fence();
         const bool tw = is_twin<SPEC>(P, s);
         const FamP<R> &F = tw ? P.ft : P.fs;
-        const R r = P.tau0[s] + F.QL * (tw ? Ht : Hs) + F.QD * h[s];
         R tau = R(0), mk = R(0);
 #pragma unroll
         for (int i = 0; i < 6; ++i)
@@ -222,7 +212,8 @@ constexpr int VJP_GA = 0;   // g and A (seven sweeps)
 constexpr int VJP_F = 1;    // final sweep with sigma_bar_L - W mu, parameter gradient
 
 // Replay of the forward integration of the step (the solver's integrate()
-// with every stage input and Newton root written to the scratch).
+// with every stage input and Newton root written to the scratch).  Dynamic
+// LDS: law_lds_bytes<R, NS>().
 template <typename R, int NS, int SPEC>
 __global__ __launch_bounds__(256) void k_law_record(AdjArgs<R> a, LawP<R> P)
 {
@@ -231,6 +222,8 @@ __global__ __launch_bounds__(256) void k_law_record(AdjArgs<R> a, LawP<R> P)
     const long vox = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (vox >= N) return;
     const int nsys = P.nsys, D = 6 + 2 * nsys, DY = D + nsys;
+    extern __shared__ unsigned char smem_raw[];
+    const LawLds<R> W = law_lds<R, NS>(smem_raw, 0);
     const int lab = d.labels[vox];
     R Q[9];
 #pragma unroll
@@ -248,6 +241,7 @@ __global__ __launch_bounds__(256) void k_law_record(AdjArgs<R> a, LawP<R> P)
     const int M = a.M;
     const R h = a.dt / R(M), invM = R(1) / R(M);
     R de[6], yw[NS];
+    uint32_t warm = 0;
 #pragma unroll
     for (int i = 0; i < 6; ++i) de[i] = e1[i] - e0[i];
 #pragma unroll
@@ -280,11 +274,19 @@ __global__ __launch_bounds__(256) void k_law_record(AdjArgs<R> a, LawP<R> P)
             R e[6];
 #pragma unroll
             for (int i = 0; i < 6; ++i) e[i] = e0[i] + sfrac * de[i];
-            rk_stage<R, NS, SPEC>(P, e, tep, tv, tal, ep, v, al, aep, av, aal, yw, wacc, cnext, st < 3, nact,
-                                  nnewt);
+            if constexpr (law_compact<R>()) {
+                rk_stage_cmp<R, NS, SPEC>(P, e, tep, tv, tal, ep, v, al, aep, av, aal, warm, W, wacc, cnext,
+                                          st < 3, nact, nnewt);
 #pragma unroll
-            for (int s = 0; s < NS; ++s)
-                if (s < nsys) zs[(D + s) * N] = yw[s];
+                for (int s = 0; s < NS; ++s)
+                    if (s < nsys) zs[(D + s) * N] = ((warm >> s) & 1u) ? W.y[s * W.ls] : R(0);
+            } else {
+                rk_stage<R, NS, SPEC>(P, e, tep, tv, tal, ep, v, al, aep, av, aal, yw, wacc, cnext, st < 3,
+                                      nact, nnewt);
+#pragma unroll
+                for (int s = 0; s < NS; ++s)
+                    if (s < nsys) zs[(D + s) * N] = yw[s];
+            }
         }
 #pragma unroll
         for (int i = 0; i < 6; ++i) ep[i] = aep[i];

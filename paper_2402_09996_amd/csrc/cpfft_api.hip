@@ -404,7 +404,8 @@ static void pass_grids(cpf_solver *s)
 {
     const size_t cb = sizeof(C2<R>);
     s->nbx_tot = s->nby_tot = s->nbz_tot = 0;
-    s->lds_x = 3 * 256 * cb;
+    // x pass: FFT buffer, then the law's per-thread work area
+    s->lds_x = xfft_lds_bytes<R>() + (law_compact<R>() ? 2 * (size_t)s->ns_inst * 256 * sizeof(R) : 0);
     s->lds_y = s->lds_z = 0;
     for (auto &h : s->rv) {
         s->nbx_tot += h.nbx;
@@ -1306,7 +1307,8 @@ static void launch_cp(cpf_solver *s, const void *e0, const void *e1, const void 
                       double dt, int M)
 {
     const RveHost &h = s->rv[0];
-    hipLaunchKernelGGL((k_constitutive<R, NS, SPEC>), dim3((h.nvox + 255) / 256), dim3(256), 0, s->stream,
+    const size_t lds = law_lds_bytes<R, NS>();
+    hipLaunchKernelGGL((k_constitutive<R, NS, SPEC>), dim3((h.nvox + 255) / 256), dim3(256), lds, s->stream,
                        dptr<int32_t>(s, h.off_labels), dptr<R>(s, h.off_Q), (const R *)e0, (const R *)e1,
                        (const R *)s0, (R *)s1, (R *)sig, make_law<R>(s), h.nvox, R(dt), M);
 }
@@ -1399,7 +1401,8 @@ static void launch_law_adj(cpf_solver *s, const AdjArgs<R> &a, int what)
     const RveHost &h = s->rv[0];
     const dim3 grid((h.nvox + 255) / 256), block(256);
     const LawP<R> P = make_law<R>(s);
-    if (what == 0) hipLaunchKernelGGL((k_law_record<R, NS, SPEC>), grid, block, 0, s->stream, a, P);
+    const size_t lds = law_lds_bytes<R, NS>();
+    if (what == 0) hipLaunchKernelGGL((k_law_record<R, NS, SPEC>), grid, block, lds, s->stream, a, P);
     else if (what == 1) hipLaunchKernelGGL((k_law_vjp<R, NS, SPEC, VJP_GA>), grid, block, 0, s->stream, a, P);
     else hipLaunchKernelGGL((k_law_vjp<R, NS, SPEC, VJP_F>), grid, block, 0, s->stream, a, P);
 }

@@ -378,6 +378,15 @@ __device__ __forceinline__ bool schmid_nonzero(int s, int i)
     else return true;
 }
 
+// Family of system s: known at compile time for the Table 1 set (systems
+// 13-16 are the twins), from the mask otherwise.
+template <int SPEC, typename R>
+__device__ __forceinline__ bool is_twin(const LawP<R> &P, int s)
+{
+    if constexpr (SPEC == LAW_TABLE1) return s >= 12;
+    else return (P.twin_mask >> s) & 1u;
+}
+
 template <typename R, int SPEC>
 __device__ __forceinline__ void hooke_c(const R (&C)[36], const R ee[6], R sig[6])
 {
@@ -403,6 +412,36 @@ __device__ __forceinline__ void hooke_c(const R (&C)[36], const R ee[6], R sig[6
 // A y^n = (o - K y) / eta, which gives g without another power.
 // ywarm is updated (0 when the system is below its threshold).
 template <typename R>
+__device__ __forceinline__ R newton_root(R o, R A, R inv_etaA, R etaA, R inv_eta, R K, R invK, R n, R inv_n,
+                                         R nm1, int nm1_int, R rtol, R &ywarm, int &nnewt)
+{
+    const R yk = o * invK;
+    R y;
+    if (ywarm > R(0)) {
+        y = ywarm < yk ? ywarm : yk;
+    } else {
+        y = ex2(lg2(o * inv_etaA) * inv_n);
+        y = yk < y ? yk : y;
+    }
+    R yn1 = R(0);
+    // not unrolled: an unrolled loop leaves a long chain of exec-mask
+    // restores at every exit, paid once per solve
+#pragma unroll 1
+    for (int it = 0; it < 40; ++it) {
+        yn1 = pow_nm1(y, nm1, nm1_int);
+        const R phi = K * y + etaA * yn1 * y - o;
+        const R dphi = K + etaA * n * yn1;
+        const R step = fdiv(phi, dphi);
+        y -= step;
+        ++nnewt;
+        if (fabs(step) <= rtol * y) break;
+    }
+    ywarm = y;
+    if (etaA > R(0)) return (o - K * y) * inv_eta;
+    return A * y * pow_nm1(y, nm1, nm1_int);
+}
+
+template <typename R>
 __device__ __forceinline__ R reg_rate(R o, R A, R inv_etaA, R etaA, R inv_eta, const FamP<R> &F,
                                       R rtol, R &ywarm, int &nact, int &nnewt)
 {
@@ -411,27 +450,8 @@ __device__ __forceinline__ R reg_rate(R o, R A, R inv_etaA, R etaA, R inv_eta, c
         return R(0);
     }
     ++nact;
-    const R yk = o * F.invK;
-    R y;
-    if (ywarm > R(0)) {
-        y = ywarm < yk ? ywarm : yk;
-    } else {
-        y = ex2(lg2(o * inv_etaA) * F.inv_n);
-        y = yk < y ? yk : y;
-    }
-    R yn1 = R(0);
-    for (int it = 0; it < 40; ++it) {
-        yn1 = pow_nm1(y, F.nm1, F.nm1_int);
-        const R phi = F.K * y + etaA * yn1 * y - o;
-        const R dphi = F.K + etaA * F.n * yn1;
-        const R step = fdiv(phi, dphi);
-        y -= step;
-        ++nnewt;
-        if (fabs(step) <= rtol * y) break;
-    }
-    ywarm = y;
-    if (etaA > R(0)) return (o - F.K * y) * inv_eta;
-    return A * y * pow_nm1(y, F.nm1, F.nm1_int);
+    return newton_root<R>(o, A, inv_etaA, etaA, inv_eta, F.K, F.invK, F.n, F.inv_n, F.nm1, F.nm1_int, rtol,
+                          ywarm, nnewt);
 }
 
 // Optional compiler fence between systems: keeps the per-system law
@@ -469,7 +489,7 @@ __device__ __forceinline__ void rk_stage(const LawP<R> &P, const R e[6], R (&tep
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         law_fence();
-        const bool tw = (P.twin_mask >> s) & 1u;
+        const bool tw = is_twin<SPEC>(P, s);
         const R bl = tw ? P.ft.bl2e : P.fs.bl2e;
         h[s] = R(1) - ex2(-bl * tv[s]);
         if (tw) {
@@ -488,7 +508,7 @@ __device__ __forceinline__ void rk_stage(const LawP<R> &P, const R e[6], R (&tep
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         law_fence();
-        const bool tw = (P.twin_mask >> s) & 1u;
+        const bool tw = is_twin<SPEC>(P, s);
         const FamP<R> &F = tw ? P.ft : P.fs;
         const R r = P.tau0[s] + F.QL * (tw ? Ht : Hs) + F.QD * h[s];
         R tau = R(0);
@@ -526,15 +546,152 @@ __device__ __forceinline__ void rk_stage(const LawP<R> &P, const R e[6], R (&tep
     }
 }
 
+// Per-thread LDS work area of the compacted stage: overstress / rate and
+// Newton root per system, column of the thread with stride ls.
+template <typename R>
+struct LawLds {
+    R *o;
+    R *y;
+    int ls;
+};
+
+// Whether the law kernels solve the active systems of a stage compacted per
+// lane (needs 2 NS words of LDS per thread).
+template <typename R>
+constexpr bool law_compact()
+{
+#ifdef CPF_LAW_COMPACT
+    return CPF_LAW_COMPACT != 0 && sizeof(R) == 4;
+#else
+    return sizeof(R) == 4;
+#endif
+}
+
+template <typename R, int NS>
+constexpr size_t law_lds_bytes()
+{
+    return law_compact<R>() ? 2 * NS * 256 * sizeof(R) : 0;
+}
+
+// The same RK4 stage as rk_stage, with the Newton solves compacted: the
+// lanes of a wave rarely share their active systems (only a third of the
+// systems that some lane needs are active in a given lane), so instead of
+// one divergent solve per system, every lane takes its own next active
+// system in each pass of the solve loop.  Overstresses go to the thread's
+// LDS column, rates and roots come back through it; warm holds the systems
+// whose root from the previous stage is a valid warm start.
+template <typename R, int NS, int SPEC>
+__device__ __forceinline__ void rk_stage_cmp(const LawP<R> &P, const R e[6], R (&tep)[6], R (&tv)[NS],
+                                             R (&tal)[NS], const R (&yep)[6], const R (&yv)[NS],
+                                             const R (&yal)[NS], R (&aep)[6], R (&av)[NS], R (&aal)[NS],
+                                             uint32_t &warm, const LawLds<R> &W, R wacc, R cnext,
+                                             bool has_next, int &nact, int &nnewt)
+{
+    R ee[6], sig[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) ee[i] = e[i] - tep[i];
+    hooke_c<R, SPEC>(P.C, ee, sig);
+    R h[NS];
+    R Hs = R(0), Ht = R(0), sumf = R(0);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        law_fence();
+        const bool tw = is_twin<SPEC>(P, s);
+        const R bl = tw ? P.ft.bl2e : P.fs.bl2e;
+        h[s] = R(1) - ex2(-bl * tv[s]);
+        if (tw) {
+            Ht += h[s];
+            sumf += tv[s] * P.inv_gT;
+        } else {
+            Hs += h[s];
+        }
+    }
+    const R wslip = R(1) - sumf;
+    const R Atw = P.twin_mode ? P.Kc_gT * (P.fm - sumf) : R(1);
+    const R etaAtw = P.eta * Atw;
+    const R inv_etaAtw = P.twin_mode ? fdiv(R(1), etaAtw) : P.inv_eta;
+    // overstress of every system
+    uint32_t act = 0, neg = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        law_fence();
+        const bool tw = is_twin<SPEC>(P, s);
+        const FamP<R> &F = tw ? P.ft : P.fs;
+        const R r = P.tau0[s] + F.QL * (tw ? Ht : Hs) + F.QD * h[s];
+        R tau = R(0);
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+            if (schmid_nonzero<SPEC>(s, i))
+                tau += (i < 3 ? sig[i] : R(2) * sig[i]) * schmid<R, SPEC>(P.m, s, i);
+        const R tx = tau - F.c * tal[s];
+        const R o = tw ? tx - r : fabs(tx) - r;
+        const R A = tw ? Atw : R(1);
+        if (o > R(0) && A > R(0)) act |= 1u << s;
+        if (!tw && tx < R(0)) neg |= 1u << s;
+        W.o[s * W.ls] = o;
+    }
+    nact += __popc(act);
+    // Newton solves of the active systems, one system per lane per pass
+    uint32_t rem = act;
+    while (__any(rem != 0u)) {
+        if (rem) {
+            const int s = __builtin_ctz(rem);
+            rem &= rem - 1u;
+            const bool tw = SPEC == LAW_TABLE1 ? s >= 12 : ((P.twin_mask >> s) & 1u) != 0u;
+            const FamP<R> &Fs = P.fs;
+            const FamP<R> &Ft = P.ft;
+            const R o = W.o[s * W.ls];
+            R yw = ((warm >> s) & 1u) ? W.y[s * W.ls] : R(0);
+            const R g = newton_root<R>(o, tw ? Atw : R(1), tw ? inv_etaAtw : P.inv_eta, tw ? etaAtw : P.eta,
+                                       P.inv_eta, tw ? Ft.K : Fs.K, tw ? Ft.invK : Fs.invK, tw ? Ft.n : Fs.n,
+                                       tw ? Ft.inv_n : Fs.inv_n, tw ? Ft.nm1 : Fs.nm1,
+                                       tw ? Ft.nm1_int : Fs.nm1_int, P.newton_rtol, yw, nnewt);
+            W.y[s * W.ls] = yw;
+            W.o[s * W.ls] = g;
+        }
+    }
+    warm = act;
+    // rates of the internal variables
+    R dep[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        law_fence();
+        const bool tw = is_twin<SPEC>(P, s);
+        const FamP<R> &F = tw ? P.ft : P.fs;
+        const R gl = W.o[s * W.ls];
+        const R g = ((act >> s) & 1u) ? gl : R(0);
+        const R gd = ((neg >> s) & 1u) ? -g : g;
+        const R ag = fabs(gd);
+        const R dal = gd - F.d * ag * tal[s];
+        av[s] += wacc * ag;
+        aal[s] += wacc * dal;
+        if (has_next) {
+            tv[s] = yv[s] + cnext * ag;
+            tal[s] = yal[s] + cnext * dal;
+        }
+        const R wg = tw ? gd : wslip * gd;
+#pragma unroll
+        for (int i = 0; i < 6; ++i)
+            if (schmid_nonzero<SPEC>(s, i)) dep[i] += wg * schmid<R, SPEC>(P.m, s, i);
+    }
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+        aep[i] += wacc * dep[i];
+        if (has_next) tep[i] = yep[i] + cnext * dep[i];
+    }
+}
+
 // Integrate the internal variables over one load increment (crystal frame):
 // total strain linear in time from e0 to e1, M classical RK4 substeps.
+// W: LDS work area, used when law_compact<R>().
 template <typename R, int NS, int SPEC>
 __device__ void integrate(const LawP<R> &P, const R e0[6], const R e1[6], R (&ep)[6], R (&v)[NS],
-                          R (&al)[NS], R dt, int M, int &nact, int &nnewt)
+                          R (&al)[NS], R dt, int M, int &nact, int &nnewt, const LawLds<R> &W)
 {
     const R h = dt / R(M);
     const R invM = R(1) / R(M);
     R de[6], yw[NS];
+    uint32_t warm = 0;
 #pragma unroll
     for (int i = 0; i < 6; ++i) de[i] = e1[i] - e0[i];
 #pragma unroll
@@ -557,8 +714,12 @@ __device__ void integrate(const LawP<R> &P, const R e0[6], const R e1[6], R (&ep
             R e[6];
 #pragma unroll
             for (int i = 0; i < 6; ++i) e[i] = e0[i] + sfrac * de[i];
-            rk_stage<R, NS, SPEC>(P, e, tep, tv, tal, ep, v, al, aep, av, aal, yw, wacc, cnext, st < 3,
-                                  nact, nnewt);
+            if constexpr (law_compact<R>())
+                rk_stage_cmp<R, NS, SPEC>(P, e, tep, tv, tal, ep, v, al, aep, av, aal, warm, W, wacc, cnext,
+                                          st < 3, nact, nnewt);
+            else
+                rk_stage<R, NS, SPEC>(P, e, tep, tv, tal, ep, v, al, aep, av, aal, yw, wacc, cnext, st < 3,
+                                      nact, nnewt);
         }
 #pragma unroll
         for (int i = 0; i < 6; ++i) ep[i] = aep[i];

@@ -159,12 +159,12 @@ __device__ __forceinline__ void store_state(R *__restrict__ st, long nvox, long 
 template <typename R, int NS, int SPEC>
 __device__ __forceinline__ void voxel_law(const LawP<R> &P, const R Q[9], const R e0l[6],
                                           const R e1l[6], R (&ep)[6], R (&v)[NS], R (&al)[NS],
-                                          R dt, int M, R sigl[6], int &nact, int &nnewt)
+                                          R dt, int M, R sigl[6], int &nact, int &nnewt, const LawLds<R> &W)
 {
     R e0[6], e1[6], sc[6];
     rot_to_crystal(Q, e0l, e0);
     rot_to_crystal(Q, e1l, e1);
-    integrate<R, NS, SPEC>(P, e0, e1, ep, v, al, dt, M, nact, nnewt);
+    integrate<R, NS, SPEC>(P, e0, e1, ep, v, al, dt, M, nact, nnewt, W);
     hooke(P, e1, ep, sc);
     rot_to_lab(Q, sc, sigl);
 }
@@ -199,6 +199,23 @@ __device__ __forceinline__ const LawP<R> &law_params(const LawP<R> &arg)
 #else
     return arg;
 #endif
+}
+
+// The law's LDS work area of this thread inside a 256-thread block's
+// dynamic LDS, after `offset` bytes used by the kernel itself.
+template <typename R, int NS>
+__device__ __forceinline__ LawLds<R> law_lds(unsigned char *smem, size_t offset)
+{
+    R *base = reinterpret_cast<R *>(smem + offset);
+    return LawLds<R>{base + threadIdx.x, base + NS * 256 + threadIdx.x, 256};
+}
+
+// Bytes of the x pass FFT buffer in dynamic LDS (3 complex lines of up to
+// 256 points).
+template <typename R>
+constexpr size_t xfft_lds_bytes()
+{
+    return 3 * 256 * sizeof(C2<R>);
 }
 
 template <typename R, int NS, int SPEC>
@@ -261,7 +278,8 @@ __global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R)) void k_xpass_iter(cons
         R ep[6], v[NS], al[NS];
         load_state<R, NS>(d.st[cur], d.nvox, vox, P.nsys, Q, ep, v, al);
         int nact = 0, nnewt = 0;
-        voxel_law<R, NS, SPEC>(P, Q, e0, e1, ep, v, al, R(sc->dt), sc->M, sig, nact, nnewt);
+        voxel_law<R, NS, SPEC>(P, Q, e0, e1, ep, v, al, R(sc->dt), sc->M, sig, nact, nnewt,
+                               law_lds<R, NS>(smem_raw, xfft_lds_bytes<R>()));
         store_state<R, NS>(d.st[1 - cur], d.nvox, vox, P.nsys, Q, ep, v, al);
         part[9] = (double)nact;
         part[10] = (double)nnewt;
@@ -628,6 +646,7 @@ __global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R)) void k_constitutive(
     LawP<R> Parg, long nvox, R dt, int M)
 {
     const LawP<R> &P = law_params(Parg);
+    extern __shared__ unsigned char smem_raw[];
     const long vox = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (vox >= nvox) return;
     const int lab = labels[vox];
@@ -643,7 +662,7 @@ __global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R)) void k_constitutive(
     R ep[6], v[NS], al[NS];
     load_state<R, NS>(st0, nvox, vox, P.nsys, Q, ep, v, al);
     int nact = 0, nnewt = 0;
-    voxel_law<R, NS, SPEC>(P, Q, e0, e1, ep, v, al, dt, M, s, nact, nnewt);
+    voxel_law<R, NS, SPEC>(P, Q, e0, e1, ep, v, al, dt, M, s, nact, nnewt, law_lds<R, NS>(smem_raw, 0));
     store_state<R, NS>(st1, nvox, vox, P.nsys, Q, ep, v, al);
 #pragma unroll
     for (int c = 0; c < 6; ++c) sig[c * nvox + vox] = s[c];
