@@ -556,15 +556,15 @@ struct LawLds {
 };
 
 // Whether the law kernels solve the active systems of a stage compacted per
-// lane (needs 2 NS words of LDS per thread).
+// lane (2 NS words of LDS per thread: 32 KB per 256-thread block in FP32 and
+// 64 KB in FP64 at NS = 16, within the 160 KB a block may use).
+#ifndef CPF_LAW_COMPACT
+#define CPF_LAW_COMPACT 1
+#endif
 template <typename R>
 constexpr bool law_compact()
 {
-#ifdef CPF_LAW_COMPACT
-    return CPF_LAW_COMPACT != 0 && sizeof(R) == 4;
-#else
-    return sizeof(R) == 4;
-#endif
+    return CPF_LAW_COMPACT != 0;
 }
 
 template <typename R, int NS>
