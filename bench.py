@@ -30,6 +30,23 @@ FP32_PEAK_TFLOPS = 157.3
 FP64_PEAK_TFLOPS = 78.6
 
 
+# HBM bytes per launch of the x pass (the dominant kernel) at 128^3 FP32,
+# from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy (factors
+# 0.5 and 1.0); valid only for the library sources they were taken on.
+XPASS_TRAFFIC = {"src": "67a07e6613101cd8", "read_bytes": 485.8e6, "write_bytes": 421.9e6}
+
+
+def library_source_hash() -> str:
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2402_09996_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def law_flops(S: int, n_twin: int, M: int, nvox: int, n_active: float, n_newton: float) -> float:
     """Algorithmic FLOPs of one local-law evaluation of the whole grid
     (FMA = 2 flops, every other arithmetic op or transcendental = 1); the
@@ -295,9 +312,13 @@ def main():
         flops = law_flops(S, n_twin, M, nvox, r32["n_active"] / it, r32["n_newton"] / it)
         avg_s = kern[dom][0] / 1e3 / it
         ach = flops / avg_s / 1e12
+        same = library_source_hash() == XPASS_TRAFFIC["src"] and (nz, ny, nx) == (128, 128, 128)
+        traffic = XPASS_TRAFFIC["read_bytes"] + XPASS_TRAFFIC["write_bytes"] if same else None
         roof = {"bound": "alu", "kernel": "k_xpass_iter<float,16>", "achieved": ach,
                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP32_PEAK_TFLOPS,
-                "traffic": None, "avg_launch_ms": avg_s * 1e3}
+                "traffic": traffic, "traffic_unit": "bytes per launch",
+                "algorithmic_bytes": 428.75 * nvox, "avg_launch_ms": avg_s * 1e3,
+                "flops_per_launch": flops}
     else:
         b = fft_pass_bytes(nx, ny, nz, 4)
         avg_s = kern[dom][0] / 1e3 / it
