@@ -508,7 +508,7 @@ __global__ __launch_bounds__(256) void k_adj_xpass(AdjArgs<R> a)
     const long vox = (long)line * d.nx + x;
     R corr[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
     if (!first) {
-        if (tid < d.tpbx) load_halfspec_pairs(d.spec, buf, d.nx, d.ny, d.nz, d.nhx, d.L, li, x, y, z, valid);
+        if (tid < d.tpbx) load_halfspec_pairs(d.spec, buf, d.nx, d.ny, d.nz, d.nkx, d.nhp, d.L, li, x, y, z, valid);
         __syncthreads();
         lds_fft<R, true, 8>(buf, 3 * d.L, d.nx, d.px, d.tw[0], tid, nthr);
         if (tid < d.tpbx) {
@@ -554,7 +554,7 @@ __global__ __launch_bounds__(256) void k_adj_xpass(AdjArgs<R> a)
     }
     __syncthreads();
     lds_fft<R, false, 8>(buf, 3 * d.L, d.nx, d.px, d.tw[0], tid, nthr);
-    if (tid < d.tpbx) store_halfspec_pairs(d.spec, buf, d.nx, d.ny, d.nz, d.nhx, d.L, li, x, y, z, valid);
+    if (tid < d.tpbx) store_halfspec_pairs(d.spec, buf, d.nx, d.ny, d.nz, d.nkx, d.nhp, d.L, li, x, y, z, valid);
 }
 
 template <typename R>

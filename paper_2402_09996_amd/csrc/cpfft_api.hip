@@ -268,6 +268,7 @@ extern "C" int cpf_problem_reference_medium(const cpf_problem *p, double *lam0, 
 struct RveHost {
     cpf_problem pb;
     int nx, ny, nz, nhx;
+    int nkx, nhp;               // kx columns of the stored spectrum, row pitch
     long nvox;
     FftPlan px, py, pz;
     int L, tpbx, nbx, ty, nty, tz, ntz, nbz;
@@ -372,7 +373,7 @@ template <typename R>
 static bool tiles_valid(const RveHost &h, int ty, int tz)
 {
     const size_t cb = sizeof(C2<R>);
-    return ty >= 1 && tz >= 1 && ty <= h.nhx && tz <= h.nhx && ty * h.ny <= EPT_Y * 256 &&
+    return ty >= 1 && tz >= 1 && ty <= h.nkx && tz <= h.nkx && ty * h.ny <= EPT_Y * 256 &&
            6 * tz * h.nz <= ept_z<R>() * 256 && (size_t)ty * (h.ny + 1) * cb <= LDS_LIMIT &&
            6 * (size_t)tz * (h.nz + 1) * cb <= LDS_LIMIT;
 }
@@ -381,9 +382,9 @@ template <typename R>
 static void set_tiles(RveHost &h, int ty, int tz)
 {
     h.ty = ty;
-    h.nty = (h.nhx + ty - 1) / ty;
+    h.nty = (h.nkx + ty - 1) / ty;
     h.tz = tz;
-    h.ntz = (h.nhx + tz - 1) / tz;
+    h.ntz = (h.nkx + tz - 1) / tz;
     h.nbz = h.ntz * h.ny;
 }
 
@@ -391,8 +392,8 @@ template <typename R>
 static void default_tiles(RveHost &h)
 {
     const bool f32 = sizeof(R) == 4;
-    int ty = std::min(std::min(f32 ? 16 : 8, std::max(1, EPT_Y * 256 / h.ny)), h.nhx);
-    int tz = std::min(std::min(16, std::max(1, ept_z<R>() * 256 / (6 * h.nz))), h.nhx);
+    int ty = std::min(std::min(f32 ? 16 : 8, std::max(1, EPT_Y * 256 / h.ny)), h.nkx);
+    int tz = std::min(std::min(16, std::max(1, ept_z<R>() * 256 / (6 * h.nz))), h.nkx);
     while (!tiles_valid<R>(h, ty, tz) && tz > 1) --tz;
     while (!tiles_valid<R>(h, ty, tz) && ty > 1) --ty;
     set_tiles<R>(h, ty, tz);
@@ -429,7 +430,7 @@ static void layout(cpf_solver *s)
         h.off_eps[1] = take(sizeof(R) * 6 * h.nvox);
         h.off_st[0] = take(sizeof(R) * s->D * h.nvox);
         h.off_st[1] = take(sizeof(R) * s->D * h.nvox);
-        h.off_spec = take(cb * 6 * (size_t)h.nz * h.ny * h.nhx);
+        h.off_spec = take(cb * 6 * (size_t)h.nz * h.ny * h.nhp);
         h.off_tw[0] = take(cb * h.nx);
         h.off_tw[1] = take(cb * h.ny);
         h.off_tw[2] = take(cb * h.nz);
@@ -453,6 +454,7 @@ static RveDev<R> make_dev(cpf_solver *s, const RveHost &h, int bx0, int by0, int
     RveDev<R> d;
     memset(&d, 0, sizeof d);
     d.nx = h.nx; d.ny = h.ny; d.nz = h.nz; d.nhx = h.nhx;
+    d.nkx = h.nkx; d.nhp = h.nhp;
     d.L = h.L; d.tpbx = h.tpbx; d.nlines = h.ny * h.nz;
     d.ty = h.ty; d.nty = h.nty; d.tz = h.tz; d.ntz = h.ntz;
     d.bx0 = bx0; d.by0 = by0; d.bz0 = bz0;
@@ -527,6 +529,12 @@ static void init_rve(RveHost &h, const cpf_problem &p)
     h.pb = p;
     h.nx = p.nx; h.ny = p.ny; h.nz = p.nz;
     h.nhx = p.nx / 2 + 1;
+    // The solve keeps kx < nx/2 only: Gamma0 is zero on the Nyquist column
+    // and the residual leaves it out, so the column is neither stored nor
+    // transformed along y and z.  Rows are padded to whole 128-byte lines.
+    h.nkx = p.nx / 2;
+    const int line = (int)(128 / sizeof(C2<R>));
+    h.nhp = (h.nkx + line - 1) / line * line;
     h.nvox = (long)p.nx * p.ny * p.nz;
     radix_plan(h.nx, h.px);
     radix_plan(h.ny, h.py);
@@ -1255,10 +1263,21 @@ extern "C" int cpf_solver_tiles(const cpf_solver *s, int rve, int *ty, int *tz)
 // ---------------------------------------------------------------------------
 // component operators (RVE 0)
 // ---------------------------------------------------------------------------
+// The component operators work on caller spectra [6][nz][ny][nx/2+1]: all
+// columns, unpadded rows.
+template <typename R>
+static RveHost op_host(const RveHost &solve)
+{
+    RveHost h = solve;
+    h.nkx = h.nhp = h.nhx;
+    set_tiles<R>(h, std::min(h.ty, h.nkx), std::min(h.tz, h.nkx));
+    return h;
+}
+
 template <typename R>
 static int op_fft_impl(cpf_solver *s, const void *field, void *spec)
 {
-    const RveHost &h = s->rv[0];
+    const RveHost h = op_host<R>(s->rv[0]);
     C2<R> *sp = (C2<R> *)spec;
     const RveDev<R> d = make_dev<R>(s, h, 0, 0, 0);
     RveDev<R> *tab = dptr<RveDev<R>>(s, s->off_opdev);
@@ -1283,7 +1302,7 @@ extern "C" int cpf_op_forward_fft(cpf_solver *s, const void *dev_field, void *de
 template <typename R>
 static int op_green_impl(cpf_solver *s, void *spec, void *outp, double *err2)
 {
-    const RveHost &h = s->rv[0];
+    const RveHost h = op_host<R>(s->rv[0]);
     C2<R> *sp = (C2<R> *)spec;
     const RveDev<R> d = make_dev<R>(s, h, 0, 0, 0);
     RveDev<R> *tab = dptr<RveDev<R>>(s, s->off_opdev);

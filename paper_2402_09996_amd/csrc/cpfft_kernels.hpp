@@ -44,6 +44,8 @@ struct Scalars {
 template <typename R>
 struct RveDev {
     int nx, ny, nz, nhx;
+    int nkx, nhp;              // kx columns held (nx/2 in the solve: the Nyquist column,
+                               // zeroed by Gamma0, is not stored) and row pitch
     int L, tpbx, nlines;       // x pass: lines per block, threads used
     int ty, nty, tz, ntz;      // y / z pass tiles (kx columns) and tile counts
     int bx0, by0, bz0;         // first block in the x, y and z pass grids
@@ -54,7 +56,7 @@ struct RveDev {
     const R *Qtab;             // [n_labels][9]
     R *eps[2];                 // strain [6][nvox]: committed = eps[cur]
     R *st[2];                  // state [6+2S][nvox]: committed = st[cur]
-    C2<R> *spec;               // [6][nz][ny][nhx]
+    C2<R> *spec;               // [6][nz][ny][nhp], columns kx < nkx
     const C2<R> *tw[3];        // twiddles exp(-2 pi i k / n) along x, y, z
     double *part_x;            // [x blocks][NPX]
     double *part_z;            // [z blocks]
@@ -77,20 +79,21 @@ __device__ __forceinline__ int find_rve(const RveDev<R> *__restrict__ rv, int nr
 // ---------------------------------------------------------------------------
 template <typename R>
 __device__ __forceinline__ void load_halfspec_pairs(const C2<R> *__restrict__ spec, C2<R> *buf,
-                                                    int nx, int ny, int nz, int nhx, int L,
+                                                    int nx, int ny, int nz, int nkx, int nhp, int L,
                                                     int li, int x, int y, int z, bool valid)
 {
     // Z_k = A_k + i B_k over the full x spectrum from the stored halves,
-    // using A_{N-k} = conj(A_k); DC and Nyquist bins keep their real parts.
-    const long plane = (long)nz * ny * nhx;
-    const long row = ((long)z * ny + y) * nhx;
+    // using A_{N-k} = conj(A_k); DC and Nyquist bins keep their real parts;
+    // bins not stored (k >= nkx) are zero.
+    const long plane = (long)nz * ny * nhp;
+    const long row = ((long)z * ny + y) * nhp;
     const bool mirror = x > nx / 2;
     const int k = mirror ? nx - x : x;
     const bool realbin = (k == 0) || ((nx & 1) == 0 && k == nx / 2);
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
         C2<R> z2 = {R(0), R(0)};
-        if (valid) {
+        if (valid && k < nkx) {
             C2<R> A = spec[(2 * p) * plane + row + k];
             C2<R> B = spec[(2 * p + 1) * plane + row + k];
             if (realbin) { A.y = R(0); B.y = R(0); }
@@ -103,13 +106,13 @@ __device__ __forceinline__ void load_halfspec_pairs(const C2<R> *__restrict__ sp
 
 template <typename R>
 __device__ __forceinline__ void store_halfspec_pairs(C2<R> *__restrict__ spec, const C2<R> *buf,
-                                                     int nx, int ny, int nz, int nhx, int L,
+                                                     int nx, int ny, int nz, int nkx, int nhp, int L,
                                                      int li, int x, int y, int z, bool valid)
 {
-    // Split Z = FFT(a + i b) into A = FFT(a), B = FFT(b) on k in [0, nx/2].
-    if (!valid || x >= nhx) return;
-    const long plane = (long)nz * ny * nhx;
-    const long row = ((long)z * ny + y) * nhx;
+    // Split Z = FFT(a + i b) into A = FFT(a), B = FFT(b) on k in [0, nkx).
+    if (!valid || x >= nkx) return;
+    const long plane = (long)nz * ny * nhp;
+    const long row = ((long)z * ny + y) * nhp;
     const int xm = x == 0 ? 0 : nx - x;
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
@@ -243,7 +246,7 @@ __global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R)) void k_xpass_iter(cons
     R corr[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
     if (!first) {
         if (tid < d.tpbx)
-            load_halfspec_pairs(d.spec, buf, d.nx, d.ny, d.nz, d.nhx, d.L, li, x, y, z, valid);
+            load_halfspec_pairs(d.spec, buf, d.nx, d.ny, d.nz, d.nkx, d.nhp, d.L, li, x, y, z, valid);
         __syncthreads();
         lds_fft<R, true, 8>(buf, 3 * d.L, d.nx, d.px, d.tw[0], tid, nthr);
         if (tid < d.tpbx) {
@@ -306,7 +309,7 @@ __global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R)) void k_xpass_iter(cons
     __syncthreads();
     lds_fft<R, false, 8>(buf, 3 * d.L, d.nx, d.px, d.tw[0], tid, nthr);
     if (tid < d.tpbx)
-        store_halfspec_pairs(d.spec, buf, d.nx, d.ny, d.nz, d.nhx, d.L, li, x, y, z, valid);
+        store_halfspec_pairs(d.spec, buf, d.nx, d.ny, d.nz, d.nkx, d.nhp, d.L, li, x, y, z, valid);
 }
 
 // Forward x transform of 6 real fields (component operator, one RVE).
@@ -331,7 +334,7 @@ __global__ __launch_bounds__(256) void k_xpass_fwd(const R *__restrict__ f, C2<R
     }
     __syncthreads();
     lds_fft<R, false, 8>(buf, 3 * d.L, d.nx, d.px, d.tw[0], tid, blockDim.x);
-    if (tid < d.tpbx) store_halfspec_pairs(spec, buf, d.nx, d.ny, d.nz, d.nhx, d.L, li, x, y, z, valid);
+    if (tid < d.tpbx) store_halfspec_pairs(spec, buf, d.nx, d.ny, d.nz, d.nkx, d.nhp, d.L, li, x, y, z, valid);
 }
 
 // Inverse x transform to 6 real fields, scaled by 1/nvox (component operator).
@@ -346,7 +349,7 @@ __global__ __launch_bounds__(256) void k_xpass_inv(const C2<R> *__restrict__ spe
     const bool valid = tid < d.tpbx && line < d.nlines;
     const int y = valid ? line % d.ny : 0, z = valid ? line / d.ny : 0;
     const long vox = (long)line * d.nx + x;
-    if (tid < d.tpbx) load_halfspec_pairs(spec, buf, d.nx, d.ny, d.nz, d.nhx, d.L, li, x, y, z, valid);
+    if (tid < d.tpbx) load_halfspec_pairs(spec, buf, d.nx, d.ny, d.nz, d.nkx, d.nhp, d.L, li, x, y, z, valid);
     __syncthreads();
     lds_fft<R, true, 8>(buf, 3 * d.L, d.nx, d.px, d.tw[0], tid, blockDim.x);
     if (valid) {
@@ -377,21 +380,21 @@ __global__ __launch_bounds__(256) void k_ypass(const RveDev<R> *__restrict__ rv,
     const int local = blockIdx.x - d.by0;
     const int tile = local % d.nty, zc = local / d.nty;
     const int z = zc % d.nz, c = zc / d.nz;
-    const int ny = d.ny, nhx = d.nhx;
+    const int ny = d.ny, nhp = d.nhp;
     const int kx0 = tile * d.ty;
-    const int tw_ = min(d.ty, nhx - kx0);
+    const int tw_ = min(d.ty, d.nkx - kx0);
     const int ls = ny + 1;
-    C2<R> *g = (spec_override ? spec_override : d.spec) + ((long)c * d.nz + z) * ny * nhx + kx0;
+    C2<R> *g = (spec_override ? spec_override : d.spec) + ((long)c * d.nz + z) * ny * nhp + kx0;
     const int tid = threadIdx.x, nthr = blockDim.x;
     for (int i = tid; i < ny * tw_; i += nthr) {
         const int y = i / tw_, col = i - y * tw_;
-        buf[col * ls + y] = g[(long)y * nhx + col];
+        buf[col * ls + y] = g[(long)y * nhp + col];
     }
     __syncthreads();
     lds_fft<R, INV, EPT>(buf, tw_, ls, d.py, d.tw[1], tid, nthr);
     for (int i = tid; i < ny * tw_; i += nthr) {
         const int y = i / tw_, col = i - y * tw_;
-        g[(long)y * nhx + col] = buf[col * ls + y];
+        g[(long)y * nhp + col] = buf[col * ls + y];
     }
 }
 
@@ -466,12 +469,12 @@ __global__ __launch_bounds__(256) void k_zpass_green(const RveDev<R> *__restrict
     const int local = blockIdx.x - d.bz0;
     const int tile = local % d.ntz, ky = local / d.ntz;
     const int kx0 = tile * d.tz;
-    const int tw_ = min(d.tz, d.nhx - kx0);
+    const int tw_ = min(d.tz, d.nkx - kx0);
     const int nz = d.nz, ls = nz + 1;
     C2<R> *spec = spec_override ? spec_override : d.spec;
-    const long plane = (long)d.nz * d.ny * d.nhx;
-    const long colbase = (long)ky * d.nhx + kx0;
-    const long zstride = (long)d.ny * d.nhx;
+    const long plane = (long)d.nz * d.ny * d.nhp;
+    const long colbase = (long)ky * d.nhp + kx0;
+    const long zstride = (long)d.ny * d.nhp;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int nrow = 6 * nz;
     for (int i = tid; i < nrow * tw_; i += nthr) {
