@@ -215,7 +215,7 @@ constexpr int VJP_F = 1;    // final sweep with sigma_bar_L - W mu, parameter gr
 // with every stage input and Newton root written to the scratch).  Dynamic
 // LDS: law_lds_bytes<R, NS>().
 template <typename R, int NS, int SPEC>
-__global__ __launch_bounds__(256) void k_law_record(AdjArgs<R> a, LawP<R> P)
+__global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_law_record(AdjArgs<R> a, LawP<R> P)
 {
     const RveDev<R> &d = a.rv[0];
     const long N = d.nvox;

@@ -176,14 +176,19 @@ __device__ __forceinline__ void voxel_law(const LawP<R> &P, const R Q[9], const 
 // Fused x pass of one iteration.  Block = L x-lines of nx voxels.
 // ---------------------------------------------------------------------------
 // Minimum resident blocks per CU for the law kernels (register budget):
-// two 256-thread blocks = 2 waves per SIMD.
+// three 256-thread blocks = 3 waves per SIMD = 168 registers per lane in
+// FP32 (a few spills, but the latency hiding of the third wave is worth
+// 20 %); one block in FP64.
 #ifndef CPF_XPASS_MINBLOCKS_F32
-#define CPF_XPASS_MINBLOCKS_F32 2
+#define CPF_XPASS_MINBLOCKS_F32 3
 #endif
 #ifndef CPF_XPASS_MINBLOCKS_F64
 #define CPF_XPASS_MINBLOCKS_F64 1
 #endif
-#define CPF_XPASS_MINBLOCKS(R) (sizeof(R) == 4 ? CPF_XPASS_MINBLOCKS_F32 : CPF_XPASS_MINBLOCKS_F64)
+// The general law (runtime Schmid tensors and stiffness) needs more
+// registers; it keeps two blocks in FP32.
+#define CPF_XPASS_MINBLOCKS(R, SPEC)                                                                  \
+    (sizeof(R) == 4 ? (SPEC == LAW_TABLE1 ? CPF_XPASS_MINBLOCKS_F32 : 2) : CPF_XPASS_MINBLOCKS_F64)
 #ifndef CPF_LAW_IN_LDS
 #define CPF_LAW_IN_LDS 0
 #endif
@@ -222,7 +227,7 @@ constexpr size_t xfft_lds_bytes()
 }
 
 template <typename R, int NS, int SPEC>
-__global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R)) void k_xpass_iter(const RveDev<R> *__restrict__ rv,
+__global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_xpass_iter(const RveDev<R> *__restrict__ rv,
                                                                             int nrve, LawP<R> Parg)
 {
     const int r = find_rve(rv, nrve, (int)blockIdx.x, 0);
@@ -644,7 +649,7 @@ __global__ __launch_bounds__(256) void k_bc_update(const RveDev<R> *__restrict__
 // Component operators and field outputs
 // ---------------------------------------------------------------------------
 template <typename R, int NS, int SPEC>
-__global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R)) void k_constitutive(
+__global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_constitutive(
     const int32_t *labels, const R *Qtab, const R *eps0, const R *eps1, const R *st0, R *st1, R *sig,
     LawP<R> Parg, long nvox, R dt, int M)
 {
