@@ -60,8 +60,9 @@ def law_flops(S: int, n_twin: int, M: int, nvox: int, n_active: float, n_newton:
 
 def fft_pass_bytes(nx: int, ny: int, nz: int, rbytes: int) -> float:
     """Algorithmic HBM bytes of one y or z pass: read + write of the
-    6-component half spectrum."""
-    return 2.0 * 6 * nz * ny * (nx // 2 + 1) * 2 * rbytes
+    6-component half spectrum as the solve stores it (kx < nx/2; the Nyquist
+    column is zero under the Green operator)."""
+    return 2.0 * 6 * nz * ny * (nx // 2) * 2 * rbytes
 
 
 def run_mode(cp, w, precision, K, W, tol, stag):
@@ -317,7 +318,7 @@ def main():
         roof = {"bound": "alu", "kernel": "k_xpass_iter<float,16>", "achieved": ach,
                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP32_PEAK_TFLOPS,
                 "traffic": traffic, "traffic_unit": "bytes per launch",
-                "algorithmic_bytes": 428.75 * nvox, "avg_launch_ms": avg_s * 1e3,
+                "algorithmic_bytes": 428.0 * nvox, "avg_launch_ms": avg_s * 1e3,
                 "flops_per_launch": flops}
     else:
         b = fft_pass_bytes(nx, ny, nz, 4)

@@ -550,8 +550,9 @@ __device__ __forceinline__ void rk_stage(const LawP<R> &P, const R e[6], R (&tep
 // Newton root per system, column of the thread with stride ls.
 template <typename R>
 struct LawLds {
-    R *o;
-    R *y;
+    R *o;       // [NS] overstress, then rate
+    R *y;       // [NS] Newton roots (warm starts)
+    R *e;       // [12] start strain and strain increment of the load step
     int ls;
 };
 
@@ -567,10 +568,35 @@ constexpr bool law_compact()
     return CPF_LAW_COMPACT != 0;
 }
 
+// Register relief through the LDS work area: hardening terms within a
+// stage, and the strain path of the step.
+#ifndef CPF_PARK_H_F32
+#define CPF_PARK_H_F32 0
+#endif
+#ifndef CPF_PARK_H_F64
+#define CPF_PARK_H_F64 1
+#endif
+#ifndef CPF_PARK_E_F32
+#define CPF_PARK_E_F32 1
+#endif
+#ifndef CPF_PARK_E_F64
+#define CPF_PARK_E_F64 1
+#endif
+template <typename R>
+constexpr bool law_park_h()
+{
+    return law_compact<R>() && (sizeof(R) == 4 ? CPF_PARK_H_F32 : CPF_PARK_H_F64);
+}
+template <typename R>
+constexpr bool law_park_e()
+{
+    return law_compact<R>() && (sizeof(R) == 4 ? CPF_PARK_E_F32 : CPF_PARK_E_F64);
+}
+
 template <typename R, int NS>
 constexpr size_t law_lds_bytes()
 {
-    return law_compact<R>() ? 2 * NS * 256 * sizeof(R) : 0;
+    return law_compact<R>() ? (2 * NS + 12) * 256 * sizeof(R) : 0;
 }
 
 // The same RK4 stage as rk_stage, with the Newton solves compacted: the
@@ -591,6 +617,8 @@ __device__ __forceinline__ void rk_stage_cmp(const LawP<R> &P, const R e[6], R (
 #pragma unroll
     for (int i = 0; i < 6; ++i) ee[i] = e[i] - tep[i];
     hooke_c<R, SPEC>(P.C, ee, sig);
+    // saturating hardening terms (parked in the LDS column until the family
+    // sums are complete when registers are short)
     R h[NS];
     R Hs = R(0), Ht = R(0), sumf = R(0);
 #pragma unroll
@@ -598,12 +626,14 @@ __device__ __forceinline__ void rk_stage_cmp(const LawP<R> &P, const R e[6], R (
         law_fence();
         const bool tw = is_twin<SPEC>(P, s);
         const R bl = tw ? P.ft.bl2e : P.fs.bl2e;
-        h[s] = R(1) - ex2(-bl * tv[s]);
+        const R hs = R(1) - ex2(-bl * tv[s]);
+        if constexpr (law_park_h<R>()) W.o[s * W.ls] = hs;
+        else h[s] = hs;
         if (tw) {
-            Ht += h[s];
+            Ht += hs;
             sumf += tv[s] * P.inv_gT;
         } else {
-            Hs += h[s];
+            Hs += hs;
         }
     }
     const R wslip = R(1) - sumf;
@@ -617,7 +647,8 @@ __device__ __forceinline__ void rk_stage_cmp(const LawP<R> &P, const R e[6], R (
         law_fence();
         const bool tw = is_twin<SPEC>(P, s);
         const FamP<R> &F = tw ? P.ft : P.fs;
-        const R r = P.tau0[s] + F.QL * (tw ? Ht : Hs) + F.QD * h[s];
+        const R hs = law_park_h<R>() ? W.o[s * W.ls] : h[s];
+        const R r = P.tau0[s] + F.QL * (tw ? Ht : Hs) + F.QD * hs;
         R tau = R(0);
 #pragma unroll
         for (int i = 0; i < 6; ++i)
@@ -696,6 +727,14 @@ __device__ void integrate(const LawP<R> &P, const R e0[6], const R e1[6], R (&ep
     for (int i = 0; i < 6; ++i) de[i] = e1[i] - e0[i];
 #pragma unroll
     for (int s = 0; s < NS; ++s) yw[s] = R(0);
+    if constexpr (law_park_e<R>()) {
+        // the strain path lives in LDS through the integration
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            W.e[i * W.ls] = e0[i];
+            W.e[(6 + i) * W.ls] = de[i];
+        }
+    }
 #pragma unroll 1
     for (int j = 0; j < M; ++j) {
         R tep[6], tv[NS], tal[NS], aep[6], av[NS], aal[NS];
@@ -712,8 +751,13 @@ __device__ void integrate(const LawP<R> &P, const R e0[6], const R e1[6], R (&ep
             const R wacc = (st == 0 || st == 3) ? h * R(1.0 / 6.0) : h * R(1.0 / 3.0);
             const R cnext = (st == 2) ? h : h * R(0.5);
             R e[6];
+            if constexpr (law_park_e<R>()) {
 #pragma unroll
-            for (int i = 0; i < 6; ++i) e[i] = e0[i] + sfrac * de[i];
+                for (int i = 0; i < 6; ++i) e[i] = W.e[i * W.ls] + sfrac * W.e[(6 + i) * W.ls];
+            } else {
+#pragma unroll
+                for (int i = 0; i < 6; ++i) e[i] = e0[i] + sfrac * de[i];
+            }
             if constexpr (law_compact<R>())
                 rk_stage_cmp<R, NS, SPEC>(P, e, tep, tv, tal, ep, v, al, aep, av, aal, warm, W, wacc, cnext,
                                           st < 3, nact, nnewt);

@@ -158,18 +158,38 @@ __device__ __forceinline__ void store_state(R *__restrict__ st, long nvox, long 
     }
 }
 
-// Local law at one voxel: lab strains in, lab stress out, state in place.
+#ifndef CPF_RELOAD_Q
+#define CPF_RELOAD_Q 1
+#endif
+// Local law at one voxel: lab strains in, lab stress out; the committed
+// state is read from st_in and the new state written to *st_out.  The
+// rotation and the output address are read again after the integration
+// (behind a compiler memory fence) instead of being held in registers
+// through it.
 template <typename R, int NS, int SPEC>
-__device__ __forceinline__ void voxel_law(const LawP<R> &P, const R Q[9], const R e0l[6],
-                                          const R e1l[6], R (&ep)[6], R (&v)[NS], R (&al)[NS],
-                                          R dt, int M, R sigl[6], int &nact, int &nnewt, const LawLds<R> &W)
+__device__ __forceinline__ void voxel_law(const LawP<R> &P, const R *Qrow, const R e0l[6], const R e1l[6],
+                                          const R *st_in, R *const *st_out, long nvox, long vox, R dt, int M,
+                                          R sigl[6], R (&v)[NS], int &nact, int &nnewt, const LawLds<R> &W)
 {
-    R e0[6], e1[6], sc[6];
-    rot_to_crystal(Q, e0l, e0);
-    rot_to_crystal(Q, e1l, e1);
+    R e0[6], e1[6], ep[6], al[NS];
+    {
+        R Q[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Q[i] = Qrow[i];
+        rot_to_crystal(Q, e0l, e0);
+        rot_to_crystal(Q, e1l, e1);
+        load_state<R, NS>(st_in, nvox, vox, P.nsys, Q, ep, v, al);
+    }
     integrate<R, NS, SPEC>(P, e0, e1, ep, v, al, dt, M, nact, nnewt, W);
+#if CPF_RELOAD_Q
+    asm volatile("" ::: "memory");
+#endif
+    R Q[9], sc[6];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Q[i] = Qrow[i];
     hooke(P, e1, ep, sc);
     rot_to_lab(Q, sc, sigl);
+    store_state<R, NS>(*st_out, nvox, vox, P.nsys, Q, ep, v, al);
 }
 
 // ---------------------------------------------------------------------------
@@ -210,12 +230,14 @@ __device__ __forceinline__ const LawP<R> &law_params(const LawP<R> &arg)
 }
 
 // The law's LDS work area of this thread inside a 256-thread block's
-// dynamic LDS, after `offset` bytes used by the kernel itself.
-template <typename R, int NS>
+// dynamic LDS, after `offset` bytes used by the kernel itself: (2 NS + 12)
+// words per thread, column-major (compile-time stride: plain shifts).
+template <typename R, int NS, int BD = 256>
 __device__ __forceinline__ LawLds<R> law_lds(unsigned char *smem, size_t offset)
 {
     R *base = reinterpret_cast<R *>(smem + offset);
-    return LawLds<R>{base + threadIdx.x, base + NS * 256 + threadIdx.x, 256};
+    const int t = threadIdx.x;
+    return LawLds<R>{base + t, base + NS * BD + t, base + 2 * NS * BD + t, BD};
 }
 
 // Bytes of the x pass FFT buffer in dynamic LDS (3 complex lines of up to
@@ -280,15 +302,10 @@ __global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_xpass_ite
 #pragma unroll
         for (int c = 0; c < 6; ++c) eps_k[c * d.nvox + vox] = e1[c];
         const int lab = d.labels[vox];
-        R Q[9];
-#pragma unroll
-        for (int i = 0; i < 9; ++i) Q[i] = d.Qtab[lab * 9 + i];
-        R ep[6], v[NS], al[NS];
-        load_state<R, NS>(d.st[cur], d.nvox, vox, P.nsys, Q, ep, v, al);
+        R v[NS];
         int nact = 0, nnewt = 0;
-        voxel_law<R, NS, SPEC>(P, Q, e0, e1, ep, v, al, R(sc->dt), sc->M, sig, nact, nnewt,
-                               law_lds<R, NS>(smem_raw, xfft_lds_bytes<R>()));
-        store_state<R, NS>(d.st[1 - cur], d.nvox, vox, P.nsys, Q, ep, v, al);
+        voxel_law<R, NS, SPEC>(P, d.Qtab + lab * 9, e0, e1, d.st[cur], &d.st[1 - cur], d.nvox, vox, R(sc->dt),
+                               sc->M, sig, v, nact, nnewt, law_lds<R, NS>(smem_raw, xfft_lds_bytes<R>()));
         part[9] = (double)nact;
         part[10] = (double)nnewt;
 #pragma unroll
@@ -658,20 +675,16 @@ __global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_constitut
     const long vox = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (vox >= nvox) return;
     const int lab = labels[vox];
-    R Q[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) Q[i] = Qtab[lab * 9 + i];
     R e0[6], e1[6], s[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
         e0[c] = eps0[c * nvox + vox];
         e1[c] = eps1[c * nvox + vox];
     }
-    R ep[6], v[NS], al[NS];
-    load_state<R, NS>(st0, nvox, vox, P.nsys, Q, ep, v, al);
+    R v[NS];
     int nact = 0, nnewt = 0;
-    voxel_law<R, NS, SPEC>(P, Q, e0, e1, ep, v, al, dt, M, s, nact, nnewt, law_lds<R, NS>(smem_raw, 0));
-    store_state<R, NS>(st1, nvox, vox, P.nsys, Q, ep, v, al);
+    voxel_law<R, NS, SPEC>(P, Qtab + lab * 9, e0, e1, st0, &st1, nvox, vox, dt, M, s, v, nact, nnewt,
+                           law_lds<R, NS>(smem_raw, 0));
 #pragma unroll
     for (int c = 0; c < 6; ++c) sig[c * nvox + vox] = s[c];
 }

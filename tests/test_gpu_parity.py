@@ -301,3 +301,72 @@ def test_workload2_full_size_sampled_parity(precision):
     hm = np.mean(np.sum(oracle.FROB_W[:, None] * sig.reshape(6, -1) * e_1.reshape(6, -1), axis=0))
     E = e_1.reshape(6, -1).mean(axis=1)
     assert hm == pytest.approx(np.sum(oracle.FROB_W * Sig * E), rel=1e-6 if precision == "fp32" else 1e-9)
+
+
+def test_max_grid_256_sampled_parity():
+    """The largest grid the library accepts (256^3, 16.8 M voxels, FP32 in
+    the benchmark's launch configuration): sampled voxels re-integrated by
+    the oracle law from the GPU's own inputs, equilibrium of the whole
+    stress field by an independent FP64 FFT, mixed conditions and
+    Hill-Mandel."""
+    torch = pytest.importorskip("torch")
+    print("case 256^3 fp32", flush=True)
+    C, law = rvegen.config_law()
+    S = rvegen.config_systems(True)
+    rve = rvegen.make_rve(256, 400, 20240299, twin_share=0.5)
+    path = rvegen.uniaxial_path(0.0014, 7)
+    w = rvegen.Workload("256^3", rve, S, C, law, path)
+    gs = _gpu_solver(w, "fp32", tol=1e-6, stag_tol=1e-4)
+    n_pre = 6
+    for n in range(n_pre):
+        gs.step(path, n)
+    rng = np.random.default_rng(12)
+    idx = torch.as_tensor(rng.choice(rve.labels.size, 512, replace=False), device="cuda")
+
+    def sample(names):
+        out = []
+        for k in names:
+            f = gs.field(k)
+            out.append(f.reshape(f.shape[0], -1)[:, idx].double().cpu().numpy())
+        return np.concatenate(out).T
+
+    e_n = sample(["strain"])
+    st_n = sample(["plastic_strain", "acc_slip", "back_strain"])
+    out = gs.step(path, n_pre)
+    assert out["iters"] > 1 and out["mean_v"] > 0
+    e_1 = sample(["strain"])
+    st_1 = sample(["plastic_strain", "acc_slip", "back_strain"])
+    sig_s = sample(["stress"])
+    mat = oracle.Material(rve.euler, C, S.n_miller, S.l_miller, S.family, S.tau0, law)
+    y0 = np.hstack([oracle.to_mandel(st_n[:, :6]), st_n[:, 6:]])
+    dt = path.t[n_pre + 1] - path.t[n_pre]
+    lab = rve.labels.ravel()[idx.cpu().numpy()]
+    y1, s1 = mat.update(lab, oracle.to_mandel(e_n), oracle.to_mandel(e_1), y0, dt, oracle.substeps(dt, 0.05))
+    assert _relerr(sig_s, oracle.from_mandel(s1)) < 1e-4
+    ns = S.family.shape[0]
+    assert _relerr(st_1[:, 6:6 + ns], y1[:, 6:6 + ns]) < 1e-3
+    # equilibrium of the whole field (FP64 FFT on the device, oracle's norm)
+    sig = gs.field("stress").double()
+    Sig = sig.reshape(6, -1).mean(dim=1)
+    sh = torch.fft.fftn(sig, dim=(1, 2, 3))
+    xi, ctrl = oracle.frequency_directions(rve.labels.shape)
+    xi = torch.as_tensor(xi, device="cuda")
+    ctrl = torch.as_tensor(ctrl, device="cuda")
+    I = (0, 1, 2, 1, 0, 0)
+    J = (0, 1, 2, 2, 2, 1)
+    num = 0.0
+    for i in range(3):
+        a = sum(sh[c] * xi[j] for c in range(6) for j in range(3)
+                if (I[c] == i and J[c] == j) or (J[c] == i and I[c] == j))
+        num += float((torch.abs(a) ** 2 * ctrl).sum())
+    del sh
+    Sig_np = Sig.cpu().numpy()
+    err_eq = math.sqrt(num) / (sig[0].numel() * oracle.frob(Sig_np))
+    assert err_eq < 1e-4
+    assert out["E"][0] == pytest.approx(path.target[n_pre, 0], rel=1e-12)
+    assert np.abs(Sig_np[1:]).max() < 1e-3 * abs(Sig_np[0])
+    e1 = gs.field("strain").double()
+    W = torch.as_tensor(oracle.FROB_W, device="cuda")
+    hm = float(((W[:, None] * sig.reshape(6, -1) * e1.reshape(6, -1)).sum(dim=0)).mean())
+    E = e1.reshape(6, -1).mean(dim=1).cpu().numpy()
+    assert hm == pytest.approx(float(np.sum(oracle.FROB_W * Sig_np * E)), rel=1e-6)
