@@ -293,6 +293,7 @@ struct cpf_solver {
     int adj_recomputed = 0;
     // pass grids over all RVEs
     int nbx_tot = 0, nby_tot = 0, nbz_tot = 0;
+    int y_elems = 0, z_elems = 0;   // largest ny * ty and 6 * nz * tz over the RVEs
     size_t lds_x = 0, lds_y = 0, lds_z = 0;
     // workspace
     unsigned char *ws = nullptr;
@@ -369,13 +370,25 @@ constexpr int EPT_Y = 16;
 template <typename R> constexpr int ept_z() { return sizeof(R) == 4 ? 24 : 12; }
 constexpr size_t LDS_LIMIT = 64 * 1024;
 
+// LDS of the y and z pass blocks: the tile (one padding element per line)
+// and the twiddles of the transform length.
+template <typename R>
+static size_t lds_y_bytes(const RveHost &h, int ty)
+{
+    return ((size_t)ty * (h.ny + 1) + h.ny) * sizeof(C2<R>);
+}
+template <typename R>
+static size_t lds_z_bytes(const RveHost &h, int tz)
+{
+    return (6 * (size_t)tz * (h.nz + 1) + h.nz) * sizeof(C2<R>);
+}
+
 template <typename R>
 static bool tiles_valid(const RveHost &h, int ty, int tz)
 {
-    const size_t cb = sizeof(C2<R>);
     return ty >= 1 && tz >= 1 && ty <= h.nkx && tz <= h.nkx && ty * h.ny <= EPT_Y * 256 &&
-           6 * tz * h.nz <= ept_z<R>() * 256 && (size_t)ty * (h.ny + 1) * cb <= LDS_LIMIT &&
-           6 * (size_t)tz * (h.nz + 1) * cb <= LDS_LIMIT;
+           6 * tz * h.nz <= ept_z<R>() * 256 && lds_y_bytes<R>(h, ty) <= LDS_LIMIT &&
+           lds_z_bytes<R>(h, tz) <= LDS_LIMIT;
 }
 
 template <typename R>
@@ -393,7 +406,8 @@ static void default_tiles(RveHost &h)
 {
     const bool f32 = sizeof(R) == 4;
     int ty = std::min(std::min(f32 ? 16 : 8, std::max(1, EPT_Y * 256 / h.ny)), h.nkx);
-    int tz = std::min(std::min(16, std::max(1, ept_z<R>() * 256 / (6 * h.nz))), h.nkx);
+    // z tiles for 12 elements per thread (the lighter z kernel in FP32)
+    int tz = std::min(std::min(16, std::max(1, 12 * 256 / (6 * h.nz))), h.nkx);
     while (!tiles_valid<R>(h, ty, tz) && tz > 1) --tz;
     while (!tiles_valid<R>(h, ty, tz) && ty > 1) --ty;
     set_tiles<R>(h, ty, tz);
@@ -403,17 +417,19 @@ static void default_tiles(RveHost &h)
 template <typename R>
 static void pass_grids(cpf_solver *s)
 {
-    const size_t cb = sizeof(C2<R>);
     s->nbx_tot = s->nby_tot = s->nbz_tot = 0;
     // x pass: FFT buffer, then the law's per-thread work area
     s->lds_x = xfft_lds_bytes<R>() + (law_compact<R>() ? (2 * (size_t)s->ns_inst + 12) * 256 * sizeof(R) : 0);
     s->lds_y = s->lds_z = 0;
+    s->y_elems = s->z_elems = 0;
     for (auto &h : s->rv) {
         s->nbx_tot += h.nbx;
         s->nby_tot += h.nty * h.nz * 6;
         s->nbz_tot += h.nbz;
-        s->lds_y = std::max(s->lds_y, (size_t)h.ty * (h.ny + 1) * cb);
-        s->lds_z = std::max(s->lds_z, 6 * (size_t)h.tz * (h.nz + 1) * cb);
+        s->lds_y = std::max(s->lds_y, lds_y_bytes<R>(h, h.ty));
+        s->y_elems = std::max(s->y_elems, h.ny * h.ty);
+        s->z_elems = std::max(s->z_elems, 6 * h.nz * h.tz);
+        s->lds_z = std::max(s->lds_z, lds_z_bytes<R>(h, h.tz));
     }
 }
 
@@ -871,34 +887,49 @@ static void launch_xiter_any(cpf_solver *s, const LawP<R> &P)
 // the autotuner pass a one-RVE table and an explicit spectrum
 template <typename R>
 static void launch_y(cpf_solver *s, bool inv, const RveDev<R> *table = nullptr, int nrve = 0, int grid = 0,
-                     size_t lds = 0, C2<R> *spec = nullptr)
+                     size_t lds = 0, C2<R> *spec = nullptr, int elems = 0)
 {
     if (!table) {
         table = dptr<RveDev<R>>(s, s->off_dev);
         nrve = (int)s->rv.size();
         grid = s->nby_tot;
         lds = s->lds_y;
+        elems = s->y_elems;
     }
-    if (inv)
-        hipLaunchKernelGGL((k_ypass<R, true, EPT_Y>), dim3(grid), dim3(256), lds, s->stream, table, nrve, spec);
-    else
-        hipLaunchKernelGGL((k_ypass<R, false, EPT_Y>), dim3(grid), dim3(256), lds, s->stream, table, nrve, spec);
+    // registers for 8 elements per thread when the tiles allow it
+    if (elems <= 8 * 256) {
+        if (inv)
+            hipLaunchKernelGGL((k_ypass<R, true, 8>), dim3(grid), dim3(256), lds, s->stream, table, nrve, spec);
+        else
+            hipLaunchKernelGGL((k_ypass<R, false, 8>), dim3(grid), dim3(256), lds, s->stream, table, nrve, spec);
+    } else {
+        if (inv)
+            hipLaunchKernelGGL((k_ypass<R, true, EPT_Y>), dim3(grid), dim3(256), lds, s->stream, table, nrve, spec);
+        else
+            hipLaunchKernelGGL((k_ypass<R, false, EPT_Y>), dim3(grid), dim3(256), lds, s->stream, table, nrve, spec);
+    }
 }
 
 template <typename R>
 static void launch_z(cpf_solver *s, int mode, const RveDev<R> *table = nullptr, int nrve = 0, int grid = 0,
-                     size_t lds = 0, C2<R> *spec = nullptr)
+                     size_t lds = 0, C2<R> *spec = nullptr, int elems = 0)
 {
     if (!table) {
         table = dptr<RveDev<R>>(s, s->off_dev);
         nrve = (int)s->rv.size();
         grid = s->nbz_tot;
         lds = s->lds_z;
+        elems = s->z_elems;
     }
     const R inv_mu0 = R(1.0 / s->mu0);
     const R coef = R((s->lam0 + s->mu0) / (s->mu0 * (s->lam0 + 2.0 * s->mu0)));
-    hipLaunchKernelGGL((k_zpass_green<R, ept_z<R>()>), dim3(grid), dim3(256), lds, s->stream, table, nrve,
-                       inv_mu0, coef, mode, spec);
+    constexpr int E = ept_z<R>(), EH = E / 2;
+    if (elems <= EH * 256)
+        hipLaunchKernelGGL((k_zpass_green<R, EH>), dim3(grid), dim3(256), lds, s->stream, table, nrve, inv_mu0, coef,
+                           mode, spec);
+    else
+        hipLaunchKernelGGL((k_zpass_green<R, E>), dim3(grid), dim3(256), lds, s->stream, table, nrve, inv_mu0, coef,
+                           mode, spec);
 }
 
 template <typename R>
@@ -1171,17 +1202,16 @@ static int time_pass(cpf_solver *s, int r, int ty, int tz, bool zpass, int reps,
     RveDev<R> d = make_dev<R>(s, h, 0, 0, 0);
     RveDev<R> *tab = dptr<RveDev<R>>(s, s->off_opdev);
     HIPCHK(hipMemcpyAsync(tab, &d, sizeof d, hipMemcpyHostToDevice, s->stream));
-    const size_t cb = sizeof(C2<R>);
     hipEvent_t a, b;
     HIPCHK(hipEventCreate(&a));
     HIPCHK(hipEventCreate(&b));
     for (int it = 0; it < reps + 1; ++it) {
         if (it == 1) HIPCHK(hipEventRecord(a, s->stream));
         if (zpass)
-            launch_z<R>(s, ZMODE_FWD | ZMODE_GREEN, tab, 1, h.ntz * h.ny, 6 * (size_t)tz * (h.nz + 1) * cb,
-                        d.spec);
+            launch_z<R>(s, ZMODE_FWD | ZMODE_GREEN, tab, 1, h.ntz * h.ny, lds_z_bytes<R>(h, tz), d.spec,
+                        6 * h.nz * tz);
         else
-            launch_y<R>(s, false, tab, 1, h.nty * h.nz * 6, (size_t)ty * (h.ny + 1) * cb, d.spec);
+            launch_y<R>(s, false, tab, 1, h.nty * h.nz * 6, lds_y_bytes<R>(h, ty), d.spec, h.ny * ty);
     }
     HIPCHK(hipEventRecord(b, s->stream));
     HIPCHK(hipEventSynchronize(b));
@@ -1282,10 +1312,9 @@ static int op_fft_impl(cpf_solver *s, const void *field, void *spec)
     const RveDev<R> d = make_dev<R>(s, h, 0, 0, 0);
     RveDev<R> *tab = dptr<RveDev<R>>(s, s->off_opdev);
     HIPCHK(hipMemcpyAsync(tab, &d, sizeof d, hipMemcpyHostToDevice, s->stream));
-    const size_t cb = sizeof(C2<R>);
     hipLaunchKernelGGL(k_xpass_fwd<R>, dim3(h.nbx), dim3(256), s->lds_x, s->stream, (const R *)field, sp, d);
-    launch_y<R>(s, false, tab, 1, h.nty * h.nz * 6, (size_t)h.ty * (h.ny + 1) * cb, sp);
-    launch_z<R>(s, ZMODE_FWD, tab, 1, h.nbz, 6 * (size_t)h.tz * (h.nz + 1) * cb, sp);
+    launch_y<R>(s, false, tab, 1, h.nty * h.nz * 6, lds_y_bytes<R>(h, h.ty), sp, h.ny * h.ty);
+    launch_z<R>(s, ZMODE_FWD, tab, 1, h.nbz, lds_z_bytes<R>(h, h.tz), sp, 6 * h.nz * h.tz);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s->stream));
     return CPF_OK;
@@ -1307,9 +1336,8 @@ static int op_green_impl(cpf_solver *s, void *spec, void *outp, double *err2)
     const RveDev<R> d = make_dev<R>(s, h, 0, 0, 0);
     RveDev<R> *tab = dptr<RveDev<R>>(s, s->off_opdev);
     HIPCHK(hipMemcpyAsync(tab, &d, sizeof d, hipMemcpyHostToDevice, s->stream));
-    const size_t cb = sizeof(C2<R>);
-    launch_z<R>(s, ZMODE_GREEN, tab, 1, h.nbz, 6 * (size_t)h.tz * (h.nz + 1) * cb, sp);
-    launch_y<R>(s, true, tab, 1, h.nty * h.nz * 6, (size_t)h.ty * (h.ny + 1) * cb, sp);
+    launch_z<R>(s, ZMODE_GREEN, tab, 1, h.nbz, lds_z_bytes<R>(h, h.tz), sp, 6 * h.nz * h.tz);
+    launch_y<R>(s, true, tab, 1, h.nty * h.nz * 6, lds_y_bytes<R>(h, h.ty), sp, h.ny * h.ty);
     hipLaunchKernelGGL(k_xpass_inv<R>, dim3(h.nbx), dim3(256), s->lds_x, s->stream, sp, (R *)outp, d);
     HIPCHK(hipGetLastError());
     if (err2) {

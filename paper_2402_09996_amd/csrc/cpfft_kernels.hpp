@@ -63,6 +63,18 @@ struct RveDev {
     Scalars *sc;
 };
 
+// XCD-aware block order.  Consecutive workgroups of a launch are dealt
+// round-robin to the 8 XCDs, each with its own L2.  Mapping workgroup b to
+// the logical block start(x) + b/8 on XCD x = b % 8 (start(x) = x q +
+// min(x, r), n = 8 q + r) is a bijection of [0, n) under which each XCD
+// runs a contiguous range of logical blocks in order, so blocks that share
+// cache lines (neighbouring kx tiles of one ky row) share one L2.
+__device__ __forceinline__ int xcd_block(int b, int n)
+{
+    const int q = n >> 3, r = n & 7, x = b & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
 template <typename R>
 __device__ __forceinline__ int find_rve(const RveDev<R> *__restrict__ rv, int nrve, int b, int pass)
 {
@@ -408,12 +420,15 @@ __global__ __launch_bounds__(256) void k_ypass(const RveDev<R> *__restrict__ rv,
     const int ls = ny + 1;
     C2<R> *g = (spec_override ? spec_override : d.spec) + ((long)c * d.nz + z) * ny * nhp + kx0;
     const int tid = threadIdx.x, nthr = blockDim.x;
+    // twiddles after the tile (the launch adds ny entries of LDS)
+    C2<R> *twl = buf + (size_t)d.ty * ls;
+    for (int i = tid; i < ny; i += nthr) twl[i] = d.tw[1][i];
     for (int i = tid; i < ny * tw_; i += nthr) {
         const int y = i / tw_, col = i - y * tw_;
         buf[col * ls + y] = g[(long)y * nhp + col];
     }
     __syncthreads();
-    lds_fft<R, INV, EPT>(buf, tw_, ls, d.py, d.tw[1], tid, nthr);
+    lds_fft<R, INV, EPT>(buf, tw_, ls, d.py, twl, tid, nthr);
     for (int i = tid; i < ny * tw_; i += nthr) {
         const int y = i / tw_, col = i - y * tw_;
         g[(long)y * nhp + col] = buf[col * ls + y];
@@ -483,12 +498,13 @@ template <typename R, int EPT>
 __global__ __launch_bounds__(256) void k_zpass_green(const RveDev<R> *__restrict__ rv, int nrve, R inv_mu0,
                                                      R coef, int mode, C2<R> *spec_override)
 {
-    const int r = find_rve(rv, nrve, (int)blockIdx.x, 2);
+    const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int r = find_rve(rv, nrve, blk, 2);
     const RveDev<R> &d = rv[r];
     if (!spec_override && d.sc->done) return;
     extern __shared__ unsigned char smem_raw[];
     C2<R> *buf = reinterpret_cast<C2<R> *>(smem_raw);
-    const int local = blockIdx.x - d.bz0;
+    const int local = blk - d.bz0;
     const int tile = local % d.ntz, ky = local / d.ntz;
     const int kx0 = tile * d.tz;
     const int tw_ = min(d.tz, d.nkx - kx0);
@@ -499,13 +515,16 @@ __global__ __launch_bounds__(256) void k_zpass_green(const RveDev<R> *__restrict
     const long zstride = (long)d.ny * d.nhp;
     const int tid = threadIdx.x, nthr = blockDim.x;
     const int nrow = 6 * nz;
+    // twiddles after the tile (the launch adds nz entries of LDS)
+    C2<R> *twl = buf + (size_t)6 * d.tz * ls;
+    for (int i = tid; i < nz; i += nthr) twl[i] = d.tw[2][i];
     for (int i = tid; i < nrow * tw_; i += nthr) {
         const int rr = i / tw_, col = i - rr * tw_;
         const int c = rr / nz, kz = rr - c * nz;
         buf[(c * tw_ + col) * ls + kz] = spec[c * plane + kz * zstride + colbase + col];
     }
     __syncthreads();
-    if (mode & ZMODE_FWD) lds_fft<R, false, EPT>(buf, 6 * tw_, ls, d.pz, d.tw[2], tid, nthr);
+    if (mode & ZMODE_FWD) lds_fft<R, false, EPT>(buf, 6 * tw_, ls, d.pz, twl, tid, nthr);
     if (!(mode & ZMODE_GREEN)) {
         for (int i = tid; i < nrow * tw_; i += nthr) {
             const int rr = i / tw_, col = i - rr * tw_;
@@ -528,7 +547,7 @@ __global__ __launch_bounds__(256) void k_zpass_green(const RveDev<R> *__restrict
     double e[1] = {err2};
     block_sum<1>(e, d.part_z + local);
     __syncthreads();
-    lds_fft<R, true, EPT>(buf, 6 * tw_, ls, d.pz, d.tw[2], tid, nthr);
+    lds_fft<R, true, EPT>(buf, 6 * tw_, ls, d.pz, twl, tid, nthr);
     for (int i = tid; i < nrow * tw_; i += nthr) {
         const int rr = i / tw_, col = i - rr * tw_;
         const int c = rr / nz, kz = rr - c * nz;
