@@ -941,7 +941,9 @@ static void launch_bc(cpf_solver *s)
     b.tol = s->opt.tol;
     b.stag_tol = s->opt.stag_tol;
     b.max_iter = s->opt.max_iter;
-    hipLaunchKernelGGL(k_bc_update<R>, dim3(s->rv.size()), dim3(256), 0, s->stream,
+    // 1024 threads: the block partials of a 128^3 x pass (8192 x 11
+    // doubles) are read in a few rounds
+    hipLaunchKernelGGL(k_bc_update<R>, dim3(s->rv.size()), dim3(1024), 0, s->stream,
                        dptr<RveDev<R>>(s, s->off_dev), b);
 }
 

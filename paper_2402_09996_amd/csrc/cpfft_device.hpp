@@ -189,10 +189,11 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-template <int NV>
+// MAXW: most waves per block (16 for 1024 threads).
+template <int NV, int MAXW = 16>
 __device__ void block_sum(double (&v)[NV], double *out /* NV values, thread 0 */)
 {
-    __shared__ double red[16][NV];
+    __shared__ double red[MAXW][NV];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int nw = (blockDim.x + 63) >> 6;
 #pragma unroll

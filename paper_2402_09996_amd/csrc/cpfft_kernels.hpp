@@ -252,12 +252,12 @@ __device__ __forceinline__ LawLds<R> law_lds(unsigned char *smem, size_t offset)
     return LawLds<R>{base + t, base + NS * BD + t, base + 2 * NS * BD + t, BD};
 }
 
-// Bytes of the x pass FFT buffer in dynamic LDS (3 complex lines of up to
-// 256 points).
+// Bytes of the x pass FFT area in dynamic LDS: 3 complex lines of up to
+// 256 points, then the twiddles of the line length.
 template <typename R>
 constexpr size_t xfft_lds_bytes()
 {
-    return 3 * 256 * sizeof(C2<R>);
+    return (3 * 256 + 256) * sizeof(C2<R>);
 }
 
 template <typename R, int NS, int SPEC>
@@ -282,12 +282,14 @@ __global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_xpass_ite
     const R *eps_n = d.eps[cur];
     R *eps_k = d.eps[1 - cur];
 
+    C2<R> *twl = buf + 3 * 256;     // twiddles of the x transforms
+    for (int i = tid; i < d.nx; i += nthr) twl[i] = d.tw[0][i];
     R corr[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
     if (!first) {
         if (tid < d.tpbx)
             load_halfspec_pairs(d.spec, buf, d.nx, d.ny, d.nz, d.nkx, d.nhp, d.L, li, x, y, z, valid);
         __syncthreads();
-        lds_fft<R, true, 8>(buf, 3 * d.L, d.nx, d.px, d.tw[0], tid, nthr);
+        lds_fft<R, true, 8>(buf, 3 * d.L, d.nx, d.px, twl, tid, nthr);
         if (tid < d.tpbx) {
 #pragma unroll
             for (int p = 0; p < 3; ++p) {
@@ -334,14 +336,14 @@ __global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_xpass_ite
         part[7] = vs;
         part[8] = ft;
     }
-    block_sum<NPX>(part, d.part_x + (long)(blockIdx.x - d.bx0) * NPX);
+    block_sum<NPX, 4>(part, d.part_x + (long)(blockIdx.x - d.bx0) * NPX);
 
     if (tid < d.tpbx) {
 #pragma unroll
         for (int p = 0; p < 3; ++p) buf[(p * d.L + li) * d.nx + x] = C2<R>{sig[2 * p], sig[2 * p + 1]};
     }
     __syncthreads();
-    lds_fft<R, false, 8>(buf, 3 * d.L, d.nx, d.px, d.tw[0], tid, nthr);
+    lds_fft<R, false, 8>(buf, 3 * d.L, d.nx, d.px, twl, tid, nthr);
     if (tid < d.tpbx)
         store_halfspec_pairs(d.spec, buf, d.nx, d.ny, d.nz, d.nkx, d.nhp, d.L, li, x, y, z, valid);
 }
@@ -608,7 +610,7 @@ __device__ __forceinline__ double frob2(const double a[6])
 // order), evaluate the residuals, decide convergence and correct the
 // stress-controlled mean strain.
 template <typename R>
-__global__ __launch_bounds__(256) void k_bc_update(const RveDev<R> *__restrict__ rv, BcArgs b)
+__global__ __launch_bounds__(1024) void k_bc_update(const RveDev<R> *__restrict__ rv, BcArgs b)
 {
     const RveDev<R> &d = rv[blockIdx.x];
     Scalars *sc = d.sc;
