@@ -553,7 +553,7 @@ template <typename R>
 struct LawLds {
     R *o;       // [NS] overstress, then rate
     R *y;       // [NS] Newton roots (warm starts)
-    R *e;       // [12] start strain and strain increment of the load step
+    R *e;       // [12] start and end strain of the load step
     int ls;
 };
 
@@ -733,7 +733,7 @@ __device__ void integrate(const LawP<R> &P, const R e0[6], const R e1[6], R (&ep
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
             W.e[i * W.ls] = e0[i];
-            W.e[(6 + i) * W.ls] = de[i];
+            W.e[(6 + i) * W.ls] = e1[i];
         }
     }
 #pragma unroll 1
@@ -754,7 +754,10 @@ __device__ void integrate(const LawP<R> &P, const R e0[6], const R e1[6], R (&ep
             R e[6];
             if constexpr (law_park_e<R>()) {
 #pragma unroll
-                for (int i = 0; i < 6; ++i) e[i] = W.e[i * W.ls] + sfrac * W.e[(6 + i) * W.ls];
+                for (int i = 0; i < 6; ++i) {
+                    const R a = W.e[i * W.ls];
+                    e[i] = a + sfrac * (W.e[(6 + i) * W.ls] - a);
+                }
             } else {
 #pragma unroll
                 for (int i = 0; i < 6; ++i) e[i] = e0[i] + sfrac * de[i];

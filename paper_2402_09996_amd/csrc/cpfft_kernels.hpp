@@ -199,6 +199,11 @@ __device__ __forceinline__ void voxel_law(const LawP<R> &P, const R *Qrow, const
     R Q[9], sc[6];
 #pragma unroll
     for (int i = 0; i < 9; ++i) Q[i] = Qrow[i];
+    if constexpr (law_park_e<R>()) {
+        // the end strain comes back from the LDS work area
+#pragma unroll
+        for (int i = 0; i < 6; ++i) e1[i] = W.e[(6 + i) * W.ls];
+    }
     hooke(P, e1, ep, sc);
     rot_to_lab(Q, sc, sigl);
     store_state<R, NS>(*st_out, nvox, vox, P.nsys, Q, ep, v, al);
