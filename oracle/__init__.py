@@ -559,13 +559,37 @@ class Solver:
     def gradient(self, path, target_xx, adj_tol: float = 1e-12, n_steps: Optional[int] = None):
         """Loss L = sum_n (Sigma_xx,n - target_xx[n])^2 over the load steps and
         its gradient with respect to theta[f] = (r0, Q, b, c, d, K, n) of the
-        slip (f = 0) and twin (f = 1) families.
+        slip (f = 0) and twin (f = 1) families: the adjoint below with the
+        cotangent dL/dSigma_n = 2 (Sigma_xx,n - target_n) e_xx."""
+        tgt = np.asarray(target_xx, dtype=np.float64)
 
-        Forward: the converged steps, recording (eps_n, y_n, eps_n+1).
+        def cot(Sig):
+            sb = np.zeros_like(Sig)
+            sb[:, 0] = 2.0 * (Sig[:, 0] - tgt[:Sig.shape[0]])
+            return sb
+
+        grad, Sig = self._adjoint(path, cot, adj_tol, n_steps)
+        L = float(np.sum((Sig[:, 0] - tgt[:Sig.shape[0]]) ** 2))
+        return L, grad, Sig[:, 0]
+
+    def vjp(self, path, sigma_bar, adj_tol: float = 1e-12, n_steps: Optional[int] = None):
+        """Vector-Jacobian product of the effective stress history: for a
+        cotangent sigma_bar[n][6] = dJ/dSigma_n (tensor components), the
+        gradient dJ/dtheta [2][7] of J = sum_n sigma_bar_n . Sigma_n, and the
+        history Sigma[n][6]."""
+        sb = np.asarray(sigma_bar, dtype=np.float64)
+        return self._adjoint(path, lambda Sig: sb[:Sig.shape[0]], adj_tol, n_steps)
+
+    def _adjoint(self, path, cotangent, adj_tol, n_steps):
+        """Discrete adjoint of the converged load steps.
+
+        Forward: the converged steps, recording (eps_n, y_n, eps_n+1); then
+        the cotangent Sigma_bar_n of every step's mean stress.
         Reverse, per step n (last to first), with the cotangents S_bar,
         eps_bar carried from step n+1:
           g  = d/d eps_{n+1} of [sigma_bar_L . sigma + S_bar . S] + eps_bar,
-               sigma_bar_L = dL/dSigma_n+1 / N at every voxel;
+               sigma_bar_L = Sigma_bar_n / N at every voxel (Mandel
+               components: divided by the Mandel weights);
           A  = d sigma_{n+1} / d eps_{n+1} per voxel (six reverse sweeps);
           mu in the admissible strain space (compatible, zero mean, free
                mean on stress-controlled components) with A^T mu - g weakly
@@ -577,16 +601,15 @@ class Solver:
         ns = path.target.shape[0] if n_steps is None else n_steps
         self.reset()
         rec = []
-        Sig = np.zeros(ns)
+        Sig = np.zeros((ns, 6))
         for n in range(ns):
             e0, y0 = self.eps.copy(), self.y.copy()
             self.step(path.t[n], path.t[n + 1], path.strain_ctrl[n], path.target[n])
             dt = path.t[n + 1] - path.t[n]
             M = self.opts.M if self.opts.M is not None else substeps(dt, self.opts.h_max)
             rec.append((e0, y0, self.eps.copy(), dt, M, np.asarray(path.strain_ctrl[n], bool)))
-            Sig[n] = self.Sigma[0]
-        tgt = np.asarray(target_xx, dtype=np.float64)[:ns]
-        L = float(np.sum((Sig - tgt) ** 2))
+            Sig[n] = self.Sigma
+        Sbar = np.asarray(cotangent(Sig), dtype=np.float64).reshape(ns, 6)
         N = self.n_vox
         D = self.mat.state_dim
         Sb = np.zeros((N, D))
@@ -597,8 +620,7 @@ class Solver:
         self.adj_iters = []
         for n in range(ns - 1, -1, -1):
             e0, y0, e1, dt, M, ectrl = rec[n]
-            sigL = np.zeros((N, 6))
-            sigL[:, 0] = 2.0 * (Sig[n] - tgt[n]) / N
+            sigL = np.broadcast_to(Sbar[n] / (N * MANDEL_W), (N, 6)).copy()
             _, g, _, _ = self.mat.update_vjp(lab, e0, e1, y0, dt, M, sigL, Sb)
             g = g + eb
             Arows = np.empty((N, 6, 6))
@@ -611,7 +633,7 @@ class Solver:
             grad += th
             Sb, eb = y0b, e0b
         self.reset()
-        return L, grad, Sig
+        return grad, Sig
 
     def _adjoint_equilibrium(self, Arows, g, sidx, tol):
         """mu (Mandel, per voxel) with A^T mu - g weakly equilibrated, by the

@@ -123,3 +123,39 @@ def test_discrete_adjoint_gradient_matches_finite_differences():
             scale = np.abs(grad[fam]).max()
             assert abs(grad[fam, k] - fd) <= 1e-6 * abs(fd) + 1e-5 * scale, (fam, name, grad[fam, k], fd)
     assert np.abs(grad[1]).max() > 0        # the twin family is active
+
+
+def test_vjp_general_cotangent_matches_finite_differences():
+    """J = sum_n Sigma_bar_n . Sigma_n with a cotangent on all six
+    components (shear included, tensor components) against central
+    differences of the forward solves, for parameters of both families."""
+    C, law = rvegen.config_law()
+    S = rvegen.config_systems(True)
+    rve = rvegen.make_rve((4, 4, 6), 3, 77, twin_share=0.5)
+    path = rvegen.uniaxial_path(0.006, 3, rate=1e-2)
+    w = rvegen.Workload("t", rve, S, C, law, path)
+    o = oracle.solver_for(w, oracle.Options(tol=1e-12))
+    sb = np.random.default_rng(3).standard_normal((3, 6))
+    grad, Sig = o.vjp(path, sb, adj_tol=1e-12)
+    assert np.abs(Sig[:, 3:]).max() > 0      # shear stresses are not zero
+
+    def J(fam, name, h):
+        l2, t0 = _perturbed(law, S, fam, name, h)
+        sv = oracle.Solver(rve.labels, rve.euler, C, S.n_miller, S.l_miller, S.family, t0, l2,
+                           oracle.Options(tol=1e-12))
+        return float(np.sum(sb * sv.run(path).Sigma))
+
+    for fam, name in ((0, "r0"), (0, "K"), (0, "c"), (1, "r0"), (1, "n")):
+        k = oracle.THETA_NAMES.index(name)
+        h = 1e-6 * max(abs(_base(law, fam, name)), 1.0)
+        fd = (J(fam, name, h) - J(fam, name, -h)) / (2 * h)
+        scale = np.abs(grad[fam]).max()
+        assert abs(grad[fam, k] - fd) <= 1e-6 * abs(fd) + 1e-5 * scale, (fam, name, grad[fam, k], fd)
+    # the stress-curve loss is the special cotangent 2 (Sigma_xx - target) e_xx
+    tgt = Sig[:, 0] * 1.02
+    L, g2, sxx = o.gradient(path, tgt, adj_tol=1e-12)
+    cot = np.zeros((3, 6))
+    cot[:, 0] = 2 * (Sig[:, 0] - tgt)
+    g3, _ = o.vjp(path, cot, adj_tol=1e-12)
+    assert np.allclose(g2, g3, rtol=1e-12, atol=1e-12 * np.abs(g2).max())
+    assert np.array_equal(sxx, Sig[:, 0])
