@@ -254,10 +254,37 @@ int cpf_adjoint_workspace_size(const cpf_solver *s, const cpf_path *path, int ch
 int cpf_adjoint_gradient(cpf_solver *s, const cpf_path *path, const double *target_xx,
                          int checkpoint_every, double adj_tol, void *dev_ws, size_t bytes,
                          double *loss, double *grad /*[2][7]*/, double *sigma_xx);
-/* Work of the last cpf_adjoint_gradient call on this solver: fixed-point
- * iterations of the forward steps (the first pass and the recomputed
- * steps), iterations of the adjoint equilibria, and the number of
- * recomputed steps (n_steps - ceil(n_steps / checkpoint_every) per call). */
+/* Vector-Jacobian product of the effective stress history with respect to
+ * the 14 law parameters (the general form of cpf_adjoint_gradient, for any
+ * loss of the mean stresses): sigma_bar[n_steps][6] (host) is the cotangent
+ * dJ/dSigma_n of each step's mean stress, tensor components
+ * (11,22,33,23,13,12); grad[14] (host, [2][7] as above) receives
+ * dJ/dtheta of J = sum_n sigma_bar_n . Sigma_n; sigma[n_steps][6] (host,
+ * may be NULL) receives the forward mean stresses.  The forward steps are
+ * solved again inside the call (with checkpoints); workspace, errors and
+ * the final solver state as for cpf_adjoint_gradient, plus
+ * CPF_E_INVALID_ARG for a non-finite sigma_bar. */
+int cpf_adjoint_vjp(cpf_solver *s, const cpf_path *path, const double *sigma_bar, int checkpoint_every,
+                    double adj_tol, void *dev_ws, size_t bytes, double *grad /*[2][7]*/, double *sigma);
+
+/* Committed state of every RVE (strain, plastic strain, accumulated slip,
+ * back strain, and the step's mean stress and strain), for checkpoints
+ * and restarts along a path.  dev_buf: device memory of at least
+ * cpf_state_size() bytes, 256-byte aligned, caller-owned.  Save copies the
+ * committed state into it; restore makes it the committed state again (the
+ * same solver, or one created from the same problems and options).  Both
+ * synchronize the bound stream.  Errors: CPF_E_BAD_STATE if not bound,
+ * CPF_E_WORKSPACE for a misaligned buffer, CPF_E_INVALID_ARG if restore
+ * finds no saved state in the buffer. */
+int cpf_state_size(const cpf_solver *s, size_t *bytes);
+int cpf_state_save(cpf_solver *s, void *dev_buf);
+int cpf_state_restore(cpf_solver *s, const void *dev_buf);
+
+/* Work of the last cpf_adjoint_gradient or cpf_adjoint_vjp call on this
+ * solver: fixed-point iterations of the forward steps (the first pass and
+ * the recomputed steps), iterations of the adjoint equilibria, and the
+ * number of recomputed steps (n_steps - ceil(n_steps / checkpoint_every)
+ * per call). */
 int cpf_adjoint_last_stats(const cpf_solver *s, long long *fwd_iters, long long *adj_iters,
                            int *recomputed_steps);
 

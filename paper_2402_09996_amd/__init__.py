@@ -25,7 +25,8 @@ FIELDS = {
     "back_strain": CPF_FIELD_BACK_STRAIN,
 }
 
-__all__ = ["Problem", "Solver", "CpfError", "FIELDS", "version", "StressCurveLoss", "with_theta"]
+__all__ = ["Problem", "Solver", "CpfError", "FIELDS", "version", "EffectiveStress", "StressCurveLoss",
+           "with_theta"]
 
 
 def version() -> int:
@@ -288,6 +289,45 @@ class Solver:
         del ws
         return loss.value, grad.reshape(2, 7), sxx
 
+    def vjp(self, path, sigma_bar, checkpoint_every: int = 10, adj_tol: float = 1e-10):
+        """dJ/dtheta [2][7] of J = sum_n sigma_bar[n] . Sigma_n (cotangent
+        sigma_bar[n_steps][6] of the mean stresses, tensor components) by the
+        discrete adjoint, and the mean stress history Sigma[n_steps][6]."""
+        import torch
+        pa = _PathArgs(path)
+        sb = _f64(sigma_bar)
+        if sb.shape != (pa.n, 6):
+            raise ValueError("sigma_bar must be [n_steps][6]")
+        need = self.adjoint_workspace_size(path, checkpoint_every)
+        ws = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        ptr = (ws.data_ptr() + 255) & ~255
+        self._order_after_torch()
+        grad = np.zeros(14)
+        sig = np.zeros((pa.n, 6))
+        check(_lib.lib().cpf_adjoint_vjp(self._h, ctypes.byref(pa.c), _ptr(sb, ctypes.c_double),
+                                         int(checkpoint_every), float(adj_tol), ctypes.c_void_p(ptr), need,
+                                         _ptr(grad, ctypes.c_double), _ptr(sig, ctypes.c_double)))
+        del ws
+        return grad.reshape(2, 7), sig
+
+    # -- committed state ---------------------------------------------------------
+    def save_state(self):
+        """The committed state of every RVE in a device buffer (torch uint8)."""
+        import torch
+        size = ctypes.c_size_t()
+        check(_lib.lib().cpf_state_size(self._h, ctypes.byref(size)))
+        buf = torch.empty(int(size.value) + 256, dtype=torch.uint8, device=self.device)
+        off = (-buf.data_ptr()) % 256
+        view = buf[off:off + int(size.value)]
+        self._order_after_torch()
+        check(_lib.lib().cpf_state_save(self._h, ctypes.c_void_p(view.data_ptr())))
+        return view
+
+    def restore_state(self, saved):
+        """Make a buffer from :meth:`save_state` the committed state again."""
+        self._order_after_torch()
+        check(_lib.lib().cpf_state_restore(self._h, ctypes.c_void_p(saved.data_ptr())))
+
     def adjoint_stats(self) -> dict:
         """Work of the last :meth:`gradient` call."""
         f, a, r = ctypes.c_longlong(), ctypes.c_longlong(), ctypes.c_int()
@@ -373,6 +413,45 @@ def with_theta(problem: Problem, theta) -> Problem:
             setattr(fam, name, float(th[f, k]))
     return Problem(problem.labels, problem.euler, problem.C_voigt, problem.n_miller,
                    problem.l_miller, problem.family, tau0, law)
+
+
+class EffectiveStress:
+    """torch.autograd binding of the solve: ``EffectiveStress.apply(theta,
+    problem, path, options)`` with theta a float64 tensor [2][7] (per family
+    r0, Q, b, c, d, K, n) returns the mean stress history Sigma[n_steps][6]
+    (tensor components) of the solve along ``path``; its backward is
+    :meth:`Solver.vjp` with the incoming cotangent, so any loss built from
+    Sigma in torch gets its parameter gradient from the discrete adjoint.
+    options: :class:`Solver` keyword arguments plus ``checkpoint_every`` and
+    ``adj_tol``."""
+
+    @staticmethod
+    def _function():
+        import torch
+
+        class _Fn(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, theta, problem, path, options):
+                opts = dict(options or {})
+                ck = opts.pop("checkpoint_every", 10)
+                at = opts.pop("adj_tol", 1e-10)
+                p = with_theta(problem, theta.detach().cpu().numpy())
+                s = Solver(p, **opts)
+                sig = s.run(path)["Sigma"]
+                ctx.solver, ctx.path, ctx.ck, ctx.at = s, path, ck, at
+                return torch.as_tensor(sig, dtype=theta.dtype, device=theta.device)
+
+            @staticmethod
+            def backward(ctx, gout):
+                g, _ = ctx.solver.vjp(ctx.path, gout.detach().double().cpu().numpy(),
+                                      checkpoint_every=ctx.ck, adj_tol=ctx.at)
+                return torch.as_tensor(g, dtype=gout.dtype, device=gout.device), None, None, None
+
+        return _Fn
+
+    @classmethod
+    def apply(cls, theta, problem, path, options=None):
+        return cls._function().apply(theta, problem, path, options)
 
 
 class StressCurveLoss:

@@ -108,6 +108,10 @@ SIGNATURES = {
     "cpf_op_constitutive": (_i, [_p, _p, _p, _p, _p, _p, _d, _i]),
     "cpf_adjoint_workspace_size": (_i, [_p, ctypes.POINTER(CpfPath), _i, ctypes.POINTER(ctypes.c_size_t)]),
     "cpf_adjoint_gradient": (_i, [_p, ctypes.POINTER(CpfPath), _dp, _i, _d, _p, ctypes.c_size_t, _dp, _dp, _dp]),
+    "cpf_adjoint_vjp": (_i, [_p, ctypes.POINTER(CpfPath), _dp, _i, _d, _p, ctypes.c_size_t, _dp, _dp]),
+    "cpf_state_size": (_i, [_p, ctypes.POINTER(ctypes.c_size_t)]),
+    "cpf_state_save": (_i, [_p, _p]),
+    "cpf_state_restore": (_i, [_p, _p]),
     "cpf_adjoint_last_stats": (_i, [_p, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong),
                                     ctypes.POINTER(_i)]),
 }

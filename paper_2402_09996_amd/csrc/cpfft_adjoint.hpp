@@ -203,7 +203,7 @@ struct AdjArgs {
     R *Sb;                   // [D][N] cotangent of S (in: S_n+1, out: S_n)
     R *eb;                   // [6][N] cotangent of eps (in: eps_n+1, out: eps_n)
     double *th_part;         // [blocks][NTH]
-    R sigL_xx;               // loss cotangent of sigma_xx at every voxel
+    R sigL[6];               // cotangent of the local stress at every voxel (Sigma_bar / N)
     R dt;
     int M;
 };
@@ -433,7 +433,7 @@ __global__ __launch_bounds__(256) void k_law_vjp(AdjArgs<R> a, LawP<R> P)
                 R sbl[6], sbc[6];
 #pragma unroll
                 for (int c = 0; c < 6; ++c)
-                    sbl[c] = r == 0 ? (c == 0 ? a.sigL_xx : R(0)) : (c == r - 1 ? R(1) : R(0));
+                    sbl[c] = r == 0 ? a.sigL[c] : (c == r - 1 ? R(1) : R(0));
                 cot_to_crystal(Q, sbl, sbc);
                 R ybep[6], ybv[NS], ybal[NS], e0b[6], e1b[6];
 #pragma unroll
@@ -462,7 +462,7 @@ __global__ __launch_bounds__(256) void k_law_vjp(AdjArgs<R> a, LawP<R> P)
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
                 const R w = c < 3 ? R(1) : R(2);
-                sbl[c] = (c == 0 ? a.sigL_xx : R(0)) - w * a.mu[c * N + vox];
+                sbl[c] = a.sigL[c] - w * a.mu[c * N + vox];
             }
             cot_to_crystal(Q, sbl, sbc);
             R e0b[6] = {R(0), R(0), R(0), R(0), R(0), R(0)}, e1b[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};

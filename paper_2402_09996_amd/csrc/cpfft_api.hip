@@ -1537,8 +1537,10 @@ static int adjoint_equilibrium(cpf_solver *s, const cpf_path *path, int n, const
 }
 
 template <typename R>
-static int adjoint_impl(cpf_solver *s, const cpf_path *path, const double *target, int C, double adj_tol,
-                        unsigned char *aws, double *loss, double *grad, double *sigxx)
+// target != nullptr: cotangent 2 (Sigma_11 - target_n) e_11 of the stress
+// curve loss (returned in *loss); else the caller's sbar[n][6].
+static int adjoint_impl(cpf_solver *s, const cpf_path *path, const double *target, const double *sbar, int C,
+                        double adj_tol, unsigned char *aws, double *loss, double *grad, double *sig_out)
 {
     const AdjLayout L = adj_layout<R>(s, path, C);
     RveHost &h = s->rv[0];
@@ -1546,7 +1548,7 @@ static int adjoint_impl(cpf_solver *s, const cpf_path *path, const double *targe
     const int D = s->D, ns = path->n_steps;
     const size_t fe = sizeof(R) * 6 * N, fs = sizeof(R) * D * N, slot = fe + fs;
     auto P = [&](size_t off) { return aws + off; };
-    std::vector<double> Sxx(ns);
+    std::vector<double> Sig((size_t)ns * 6), Sbar((size_t)ns * 6, 0.0);
     struct Ck { double Sigma[6], E[6]; int prev; };
     std::vector<Ck> ck(L.n_ckpt);
     cpf_step_out out;
@@ -1569,7 +1571,7 @@ static int adjoint_impl(cpf_solver *s, const cpf_path *path, const double *targe
         }
         rc = step_impl<R>(s, path, n, &out);
         if (rc) return rc;
-        Sxx[n] = out.Sigma[0];
+        for (int c = 0; c < 6; ++c) Sig[(size_t)n * 6 + c] = out.Sigma[c];
         s->adj_fwd_iters += out.iters;
     }
     {
@@ -1579,7 +1581,15 @@ static int adjoint_impl(cpf_solver *s, const cpf_path *path, const double *targe
         if (rc) return rc;
     }
     double Lsum = 0;
-    for (int n = 0; n < ns; ++n) Lsum += (Sxx[n] - target[n]) * (Sxx[n] - target[n]);
+    for (int n = 0; n < ns; ++n) {
+        if (target) {
+            const double r = Sig[(size_t)n * 6] - target[n];
+            Lsum += r * r;
+            Sbar[(size_t)n * 6] = 2.0 * r;
+        } else {
+            for (int c = 0; c < 6; ++c) Sbar[(size_t)n * 6 + c] = sbar[(size_t)n * 6 + c];
+        }
+    }
 
     // reverse
     AdjArgs<R> a;
@@ -1626,7 +1636,7 @@ static int adjoint_impl(cpf_solver *s, const cpf_path *path, const double *targe
             a.e0 = (const R *)sl;
             a.st0 = (const R *)(sl + fe);
             a.e1 = (const R *)start_of(n + 1);
-            a.sigL_xx = R(2.0 * (Sxx[n] - target[n]) / (double)N);
+            for (int c = 0; c < 6; ++c) a.sigL[c] = R(Sbar[(size_t)n * 6 + c] / (double)N);
             a.dt = R(path->t[n + 1] - path->t[n]);
             a.M = s->opt.rk4_M > 0 ? s->opt.rk4_M : substeps(path->t[n + 1] - path->t[n], s->opt.h_max);
             rc = launch_law_adj_any<R>(s, a, 0);
@@ -1649,24 +1659,27 @@ static int adjoint_impl(cpf_solver *s, const cpf_path *path, const double *targe
     rc = zero_state<R>(s);
     if (rc) return rc;
     HIPCHK(hipStreamSynchronize(s->stream));
-    *loss = Lsum;
+    if (loss) *loss = Lsum;
     for (int k = 0; k < NTH; ++k) grad[k] = G[k];
-    if (sigxx)
-        for (int n = 0; n < ns; ++n) sigxx[n] = Sxx[n];
+    if (sig_out)
+        for (size_t i = 0; i < Sig.size(); ++i) sig_out[i] = Sig[i];
     return CPF_OK;
 }
 
-extern "C" int cpf_adjoint_gradient(cpf_solver *s, const cpf_path *path, const double *target_xx,
-                                    int checkpoint_every, double adj_tol, void *dev_ws, size_t bytes, double *loss,
-                                    double *grad, double *sigma_xx)
+static int adjoint_entry(cpf_solver *s, const cpf_path *path, const double *target, const double *sbar,
+                         int checkpoint_every, double adj_tol, void *dev_ws, size_t bytes, double *loss,
+                         double *grad, double *sig_out)
 {
     if (!s || !s->bound) return fail(CPF_E_BAD_STATE, "solver not bound");
     if (s->rv.size() != 1) return fail(CPF_E_INVALID_ARG, "the adjoint needs a single-RVE solver");
-    if (!target_xx || !loss || !grad) return fail(CPF_E_INVALID_ARG, "null argument");
+    if ((!target && !sbar) || !grad) return fail(CPF_E_INVALID_ARG, "null argument");
     if (!(adj_tol > 0)) return fail(CPF_E_INVALID_ARG, "adj_tol must be > 0");
     size_t need = 0;
     int rc = cpf_adjoint_workspace_size(s, path, checkpoint_every, &need);
     if (rc) return rc;
+    if (sbar)
+        for (int i = 0; i < 6 * path->n_steps; ++i)
+            if (!std::isfinite(sbar[i])) return fail(CPF_E_INVALID_ARG, "sigma_bar[%d] is not finite", i);
     if (!dev_ws || bytes < need)
         return fail(CPF_E_WORKSPACE, "adjoint workspace of %zu bytes given, %zu needed", bytes, need);
     if (((uintptr_t)dev_ws) & 255) return fail(CPF_E_WORKSPACE, "adjoint workspace must be 256-byte aligned");
@@ -1674,10 +1687,10 @@ extern "C" int cpf_adjoint_gradient(cpf_solver *s, const cpf_path *path, const d
     const int g = s->graph_iters;
     s->graph_iters = 0;
     rc = s->prec == CPF_PREC_FP64
-             ? adjoint_impl<double>(s, path, target_xx, checkpoint_every, adj_tol, (unsigned char *)dev_ws, loss,
-                                    grad, sigma_xx)
-             : adjoint_impl<float>(s, path, target_xx, checkpoint_every, adj_tol, (unsigned char *)dev_ws, loss,
-                                   grad, sigma_xx);
+             ? adjoint_impl<double>(s, path, target, sbar, checkpoint_every, adj_tol, (unsigned char *)dev_ws,
+                                    loss, grad, sig_out)
+             : adjoint_impl<float>(s, path, target, sbar, checkpoint_every, adj_tol, (unsigned char *)dev_ws,
+                                   loss, grad, sig_out);
     s->graph_iters = g;
     if (rc) {
         // back to the undeformed state; the first error stays reported
@@ -1686,6 +1699,120 @@ extern "C" int cpf_adjoint_gradient(cpf_solver *s, const cpf_path *path, const d
         (void)hipStreamSynchronize(s->stream);
     }
     return rc;
+}
+
+extern "C" int cpf_adjoint_gradient(cpf_solver *s, const cpf_path *path, const double *target_xx,
+                                    int checkpoint_every, double adj_tol, void *dev_ws, size_t bytes, double *loss,
+                                    double *grad, double *sigma_xx)
+{
+    if (!target_xx || !loss || !grad) return fail(CPF_E_INVALID_ARG, "null argument");
+    std::vector<double> sig;
+    if (sigma_xx && path && path->n_steps > 0) sig.resize((size_t)path->n_steps * 6);
+    const int rc = adjoint_entry(s, path, target_xx, nullptr, checkpoint_every, adj_tol, dev_ws, bytes, loss, grad,
+                                 sig.empty() ? nullptr : sig.data());
+    if (!rc && !sig.empty())
+        for (int n = 0; n < path->n_steps; ++n) sigma_xx[n] = sig[(size_t)n * 6];
+    return rc;
+}
+
+extern "C" int cpf_adjoint_vjp(cpf_solver *s, const cpf_path *path, const double *sigma_bar, int checkpoint_every,
+                               double adj_tol, void *dev_ws, size_t bytes, double *grad, double *sigma)
+{
+    if (!sigma_bar || !grad) return fail(CPF_E_INVALID_ARG, "null argument");
+    return adjoint_entry(s, path, nullptr, sigma_bar, checkpoint_every, adj_tol, dev_ws, bytes, nullptr, grad,
+                         sigma);
+}
+
+// ---------------------------------------------------------------------------
+// committed state save / restore
+// ---------------------------------------------------------------------------
+struct SavedHead {
+    double Sigma[6], E[6];
+    int prev_iters, pad;
+};
+
+// Buffer layout: one SavedHead per RVE, then per RVE the committed strain
+// [6][N] and state [D][N] in the solver's precision, 256-byte sections.
+static size_t state_layout(const cpf_solver *s, std::vector<size_t> *off)
+{
+    const size_t rb = s->prec == CPF_PREC_FP64 ? 8 : 4;
+    size_t o = align256(sizeof(SavedHead) * s->rv.size());
+    for (const auto &h : s->rv) {
+        if (off) off->push_back(o);
+        o = align256(o + rb * 6 * (size_t)h.nvox);
+        if (off) off->push_back(o);
+        o = align256(o + rb * (size_t)s->D * h.nvox);
+    }
+    return o;
+}
+
+extern "C" int cpf_state_size(const cpf_solver *s, size_t *bytes)
+{
+    if (!s || !bytes) return fail(CPF_E_INVALID_ARG, "null argument");
+    *bytes = state_layout(s, nullptr);
+    return CPF_OK;
+}
+
+static int state_check(const cpf_solver *s, const void *buf)
+{
+    if (!s || !s->bound) return fail(CPF_E_BAD_STATE, "solver not bound");
+    if (!buf) return fail(CPF_E_INVALID_ARG, "null device buffer");
+    if (((uintptr_t)buf) & 255) return fail(CPF_E_WORKSPACE, "state buffer must be 256-byte aligned");
+    return CPF_OK;
+}
+
+extern "C" int cpf_state_save(cpf_solver *s, void *dev_buf)
+{
+    int rc = state_check(s, dev_buf);
+    if (rc) return rc;
+    std::vector<size_t> off;
+    state_layout(s, &off);
+    const size_t rb = s->prec == CPF_PREC_FP64 ? 8 : 4;
+    std::vector<SavedHead> head(s->rv.size());
+    unsigned char *b = (unsigned char *)dev_buf;
+    for (size_t r = 0; r < s->rv.size(); ++r) {
+        const RveHost &h = s->rv[r];
+        memcpy(head[r].Sigma, h.Sigma_n, sizeof h.Sigma_n);
+        memcpy(head[r].E, h.E_n, sizeof h.E_n);
+        head[r].prev_iters = h.prev_iters;
+        head[r].pad = 0;
+        HIPCHK(hipMemcpyAsync(b + off[2 * r], s->ws + h.off_eps[h.cur], rb * 6 * h.nvox, hipMemcpyDeviceToDevice,
+                              s->stream));
+        HIPCHK(hipMemcpyAsync(b + off[2 * r + 1], s->ws + h.off_st[h.cur], rb * s->D * h.nvox,
+                              hipMemcpyDeviceToDevice, s->stream));
+    }
+    HIPCHK(hipMemcpyAsync(b, head.data(), sizeof(SavedHead) * head.size(), hipMemcpyHostToDevice, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return CPF_OK;
+}
+
+extern "C" int cpf_state_restore(cpf_solver *s, const void *dev_buf)
+{
+    int rc = state_check(s, dev_buf);
+    if (rc) return rc;
+    std::vector<size_t> off;
+    state_layout(s, &off);
+    const size_t rb = s->prec == CPF_PREC_FP64 ? 8 : 4;
+    std::vector<SavedHead> head(s->rv.size());
+    const unsigned char *b = (const unsigned char *)dev_buf;
+    HIPCHK(hipMemcpyAsync(head.data(), b, sizeof(SavedHead) * head.size(), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    for (size_t r = 0; r < s->rv.size(); ++r)
+        for (int i = 0; i < 6; ++i)
+            if (!std::isfinite(head[r].Sigma[i]) || !std::isfinite(head[r].E[i]) || head[r].pad != 0)
+                return fail(CPF_E_INVALID_ARG, "state buffer does not hold a saved state of this solver");
+    for (size_t r = 0; r < s->rv.size(); ++r) {
+        RveHost &h = s->rv[r];
+        memcpy(h.Sigma_n, head[r].Sigma, sizeof h.Sigma_n);
+        memcpy(h.E_n, head[r].E, sizeof h.E_n);
+        h.prev_iters = std::max(1, head[r].prev_iters);
+        HIPCHK(hipMemcpyAsync(s->ws + h.off_eps[h.cur], b + off[2 * r], rb * 6 * h.nvox, hipMemcpyDeviceToDevice,
+                              s->stream));
+        HIPCHK(hipMemcpyAsync(s->ws + h.off_st[h.cur], b + off[2 * r + 1], rb * s->D * h.nvox,
+                              hipMemcpyDeviceToDevice, s->stream));
+    }
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return CPF_OK;
 }
 
 extern "C" int cpf_adjoint_last_stats(const cpf_solver *s, long long *fwd_iters, long long *adj_iters,

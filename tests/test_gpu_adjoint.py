@@ -142,3 +142,50 @@ def test_adjoint_argument_errors():
     b = cp.Solver([p, p], precision="fp64")
     with pytest.raises(cp.CpfError):
         b.gradient(w.path, tgt)
+
+
+def test_vjp_general_cotangent_matches_oracle():
+    """A cotangent on all six mean-stress components (shear included)."""
+    w = _case()
+    sb = np.random.default_rng(3).standard_normal((w.path.n_steps, 6))
+    s = cp.Solver(cp.Problem.from_workload(w), precision="fp64", tol=1e-12)
+    g, sig = s.vjp(w.path, sb, checkpoint_every=2, adj_tol=1e-12)
+    go, so = oracle.solver_for(w, oracle.Options(tol=1e-12)).vjp(w.path, sb, adj_tol=1e-12)
+    assert np.abs(sig - so).max() <= 1e-10 * np.abs(so).max()
+    for f in (0, 1):
+        assert np.abs(g[f] - go[f]).max() <= 1e-7 * np.abs(go[f]).max(), (f, g[f], go[f])
+    # the stress-curve loss is the cotangent 2 (Sigma_11 - target) e_11
+    tgt = sig[:, 0] * 1.03
+    L, g2, _ = s.gradient(w.path, tgt, checkpoint_every=2, adj_tol=1e-12)
+    cot = np.zeros_like(sb)
+    cot[:, 0] = 2 * (sig[:, 0] - tgt)
+    g3, _ = s.vjp(w.path, cot, checkpoint_every=2, adj_tol=1e-12)
+    assert np.array_equal(g2, g3)
+
+
+def test_effective_stress_autograd():
+    """Any torch loss of the mean stress history: the backward is the
+    device VJP with the loss's cotangent."""
+    w = _case()
+    p = cp.Problem.from_workload(w)
+    theta = torch.tensor(_theta(w), dtype=torch.float64, requires_grad=True)
+    opts = dict(precision="fp64", tol=1e-12, adj_tol=1e-12, checkpoint_every=2)
+    sig = cp.EffectiveStress.apply(theta, p, w.path, opts)
+    assert sig.shape == (w.path.n_steps, 6)
+    wts = torch.tensor([1.0, 0.5, 0.5, 2.0, 2.0, 2.0], dtype=torch.float64)
+    loss = ((sig - 0.9 * sig.detach()) ** 2 * wts).sum()
+    loss.backward()
+    cot = (2 * (sig.detach() - 0.9 * sig.detach()) * wts).numpy()
+    g, _ = cp.Solver(p, precision="fp64", tol=1e-12).vjp(w.path, cot, checkpoint_every=2, adj_tol=1e-12)
+    assert np.array_equal(theta.grad.numpy(), g)
+
+
+def test_vjp_argument_errors():
+    w = _case()
+    s = cp.Solver(cp.Problem.from_workload(w), precision="fp64")
+    with pytest.raises(ValueError):
+        s.vjp(w.path, np.zeros((w.path.n_steps, 5)))
+    bad = np.zeros((w.path.n_steps, 6))
+    bad[1, 2] = np.nan
+    with pytest.raises(cp.CpfError):
+        s.vjp(w.path, bad)
