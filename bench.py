@@ -249,6 +249,28 @@ def adjoint_leg(cp, steps, checkpoint_every=10):
     return out
 
 
+def histogram_leg(s32, nvox, reps=20, nbins=150, lo=100.0, hi=400.0):
+    """Distribution of the local von Mises stress of the committed 128^3
+    state (post-processing after the timed steps): the stress pass (reads
+    strain, plastic strain, label; writes the stress into the spectrum
+    area) and the histogram pass (reads it): 100 B per voxel in FP32."""
+    import numpy as np
+    import torch
+    c = s32.von_mises_histogram(nbins, lo, hi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        c = s32.von_mises_histogram(nbins, lo, hi)
+    dt = (time.perf_counter() - t0) / reps
+    byts = 100.0 * nvox
+    x = lo + (hi - lo) / nbins * (np.arange(nbins) + 0.5)
+    inside = c[1:-1].astype(np.float64)
+    return {"bins": nbins, "range_MPa": [lo, hi], "ms_per_call": dt * 1e3,
+            "GB/s": byts / dt / 1e9, "algorithmic_bytes": byts,
+            "below": int(c[0]), "above": int(c[-1]),
+            "mode_MPa": float(x[int(np.argmax(inside))]) if inside.sum() else None}
+
+
 def copy_probe(nbytes=1 << 30, reps=5):
     """Plain device-to-device copies of a known size: the reference for
     the FETCH_SIZE / WRITE_SIZE counters (bytes read and written per copy
@@ -357,6 +379,7 @@ def main():
             a = np.array([o["Sigma"][0] for o in r32["outs"]])
             b = np.array([o["Sigma"][0] for o in r64["outs"]])
             line["fp64"]["fp32_max_rel_err_Sigma_xx"] = float(np.abs(a - b).max() / np.abs(b).max())
+    line["seq_histogram"] = histogram_leg(s32, nvox)
     if args.batch_steps > 0:
         line["batched"] = batch_leg(cp, args.batch_steps)
     if args.adjoint_steps > 0:

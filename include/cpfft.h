@@ -267,6 +267,27 @@ int cpf_adjoint_gradient(cpf_solver *s, const cpf_path *path, const double *targ
 int cpf_adjoint_vjp(cpf_solver *s, const cpf_path *path, const double *sigma_bar, int checkpoint_every,
                     double adj_tol, void *dev_ws, size_t bytes, double *grad /*[2][7]*/, double *sigma);
 
+/* Distribution of the local von Mises stress of the committed state (the
+ * statistic of Section 5's probability density of sigma_eq, taken over all
+ * voxels of all realizations): counts[nbins + 2] (host, written) of
+ * sigma_eq = sqrt(3/2 dev(sigma):dev(sigma)), sigma = C:(eps - eps_p) per
+ * voxel, over RVE `rve` of the batch, or all RVEs for rve = -1.  Bin
+ * edges e_k = lo + k w, w = (hi - lo) / nbins (k = 0..nbins, FP64):
+ * counts[0]: sigma_eq < e_0; counts[1 + k]: e_k <= sigma_eq < e_k+1;
+ * counts[nbins + 1]: sigma_eq >= e_nbins or not finite.  The decision
+ * compares squares in FP64, sigma_eq^2 from the stress in the solver's
+ * precision by a fixed order of single correctly rounded operations (no
+ * fused multiply-add),
+ *   m = ((s11 + s22) + s33) / 3, d_i = s_ii - m,
+ *   sigma_eq^2 = 1.5 (((d1 d1 + d2 d2) + d3 d3)
+ *                     + 2 ((s23 s23 + s13 s13) + s12 s12)),
+ * against e_k e_k (edges <= 0 lie below every value), so the counts are
+ * reproducible bit for bit from the exported stress field.
+ * 1 <= nbins <= CPF_MAX_HIST_BINS, finite lo < hi.  Synchronizes the bound
+ * stream. */
+#define CPF_MAX_HIST_BINS 4096
+int cpf_seq_histogram(cpf_solver *s, int rve, int nbins, double lo, double hi, unsigned long long *counts);
+
 /* Committed state of every RVE (strain, plastic strain, accumulated slip,
  * back strain, and the step's mean stress and strain), for checkpoints
  * and restarts along a path.  dev_buf: device memory of at least

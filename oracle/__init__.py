@@ -349,6 +349,44 @@ def reg_rate(o, A, K, n, eta) -> float:
 # ---------------------------------------------------------------------------
 # Green operator (continuous, isotropic reference medium)
 # ---------------------------------------------------------------------------
+def von_mises_sq(stress: np.ndarray) -> np.ndarray:
+    """Square of the local von Mises stress 3/2 dev(s):dev(s) of stresses
+    [6][...] in tensor components (Section 5's sigma_eq, squared), FP64,
+    in a fixed order of single IEEE operations: m = ((s11 + s22) + s33) / 3,
+    d_i = s_ii - m, 1.5 (((d1 d1 + d2 d2) + d3 d3) + 2 ((s23 s23 + s13 s13)
+    + s12 s12))."""
+    s = [np.asarray(stress[c], dtype=np.float64) for c in range(6)]
+    m = ((s[0] + s[1]) + s[2]) / 3.0
+    d1, d2, d3 = s[0] - m, s[1] - m, s[2] - m
+    nrm = (d1 * d1 + d2 * d2) + d3 * d3
+    sh = (s[3] * s[3] + s[4] * s[4]) + s[5] * s[5]
+    return 1.5 * (nrm + 2.0 * sh)
+
+
+def von_mises(stress: np.ndarray) -> np.ndarray:
+    """Local von Mises stress sqrt(von_mises_sq)."""
+    return np.sqrt(von_mises_sq(stress))
+
+
+def von_mises_histogram(stress_fields, nbins: int, lo: float, hi: float) -> np.ndarray:
+    """Counts [nbins + 2] of the von Mises stress over the voxels of all
+    given stress fields ([6][...] each) for the bin edges e_k = lo + k w,
+    w = (hi - lo) / nbins: below e_0, in [e_k, e_k+1) for k < nbins, and the
+    rest (at or above e_nbins, or not finite).  Decided on squares: the
+    largest k with e_k^2 <= sigma_eq^2 (edges <= 0 below every value)."""
+    w = (float(hi) - float(lo)) / nbins
+    e = float(lo) + np.arange(nbins + 1, dtype=np.float64) * w
+    q = np.where(e > 0.0, e * e, -1.0)
+    counts = np.zeros(nbins + 2, dtype=np.uint64)
+    for f in stress_fields:
+        x = von_mises_sq(np.asarray(f).reshape(6, -1))
+        bad = ~np.isfinite(x)
+        j = np.searchsorted(q, x[~bad], side="right") - 1       # largest j with q[j] <= x
+        counts += np.bincount(j + 1, minlength=nbins + 2).astype(np.uint64)
+        counts[nbins + 1] += np.uint64(np.count_nonzero(bad))
+    return counts
+
+
 def frequency_directions(shape):
     """Unit frequency directions xi_hat [3,nz,ny,nx] (x,y,z order) and the
     mask of controlled frequencies (not zero, no Nyquist component)."""

@@ -310,6 +310,23 @@ class Solver:
         del ws
         return grad.reshape(2, 7), sig
 
+    def von_mises_histogram(self, nbins: int, lo: float, hi: float, rve: int = -1):
+        """Counts [nbins + 2] of the local von Mises stress of the committed
+        state over RVE ``rve`` (-1: every RVE of the batch): below lo, the
+        nbins bins of [lo, hi), and the rest."""
+        counts = np.zeros(int(nbins) + 2, dtype=np.uint64)
+        self._order_after_torch()
+        check(_lib.lib().cpf_seq_histogram(self._h, int(rve), int(nbins), float(lo), float(hi),
+                                           counts.ctypes.data_as(ctypes.POINTER(ctypes.c_ulonglong))))
+        return counts
+
+    def von_mises_pdf(self, nbins: int, lo: float, hi: float, rve: int = -1):
+        """Bin centres and the probability density of the local von Mises
+        stress (counts / (all voxels * bin width))."""
+        c = self.von_mises_histogram(nbins, lo, hi, rve).astype(np.float64)
+        w = (hi - lo) / nbins
+        return lo + w * (np.arange(nbins) + 0.5), c[1:-1] / (c.sum() * w)
+
     # -- committed state ---------------------------------------------------------
     def save_state(self):
         """The committed state of every RVE in a device buffer (torch uint8)."""

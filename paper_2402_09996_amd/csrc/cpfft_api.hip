@@ -298,7 +298,7 @@ struct cpf_solver {
     // workspace
     unsigned char *ws = nullptr;
     size_t ws_bytes = 0, total = 0;
-    size_t off_dev, off_si, off_opdev;
+    size_t off_dev, off_si, off_opdev, off_hist;
     hipStream_t stream = nullptr;
     bool bound = false;
     Scalars *hsc = nullptr;     // pinned host mirror of the per-RVE scalars
@@ -458,6 +458,7 @@ static void layout(cpf_solver *s)
     s->off_dev = take(sizeof(RveDev<R>) * n);
     s->off_si = take(sizeof(StepInit) * n);
     s->off_opdev = take(sizeof(RveDev<R>));
+    s->off_hist = take(sizeof(unsigned long long) * (CPF_MAX_HIST_BINS + 2) + sizeof(double) * (CPF_MAX_HIST_BINS + 1));
     s->total = o;
 }
 
@@ -1721,6 +1722,59 @@ extern "C" int cpf_adjoint_vjp(cpf_solver *s, const cpf_path *path, const double
     if (!sigma_bar || !grad) return fail(CPF_E_INVALID_ARG, "null argument");
     return adjoint_entry(s, path, nullptr, sigma_bar, checkpoint_every, adj_tol, dev_ws, bytes, nullptr, grad,
                          sigma);
+}
+
+// ---------------------------------------------------------------------------
+// von Mises stress histogram of the committed state
+// ---------------------------------------------------------------------------
+template <typename R>
+static int seq_hist_impl(cpf_solver *s, int rve, int nbins, double lo, double hi, unsigned long long *counts)
+{
+    unsigned long long *dc = dptr<unsigned long long>(s, s->off_hist);
+    double *dq = reinterpret_cast<double *>(dc + CPF_MAX_HIST_BINS + 2);
+    hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(16), dim3(256), 0, s->stream, dc, (long)nbins + 2, 0ull);
+    // squared bin edges: e_k = lo + k w, w = (hi - lo) / nbins; -1 where e_k <= 0
+    std::vector<double> q(nbins + 1);
+    const double w = (hi - lo) / nbins;
+    for (int k = 0; k <= nbins; ++k) {
+        const double e = lo + k * w;
+        q[k] = e > 0.0 ? e * e : -1.0;
+    }
+    HIPCHK(hipMemcpyAsync(dq, q.data(), sizeof(double) * q.size(), hipMemcpyHostToDevice, s->stream));
+    const LawP<R> P = make_law<R>(s);
+    for (int r = 0; r < (int)s->rv.size(); ++r) {
+        if (rve >= 0 && r != rve) continue;
+        const RveHost &h = s->rv[r];
+        // the stress field exactly as cpf_batch_field exports it, staged in
+        // the RVE's spectrum area (scratch between load steps: 6 nz ny nhp
+        // complex values hold 6 nvox reals)
+        R *sig = dptr<R>(s, h.off_spec);
+        hipLaunchKernelGGL(k_stress_field<R>, dim3((h.nvox + 255) / 256), dim3(256), 0, s->stream,
+                           dptr<int32_t>(s, h.off_labels), dptr<R>(s, h.off_Q), dptr<R>(s, h.off_eps[h.cur]),
+                           dptr<R>(s, h.off_st[h.cur]), sig, P, h.nvox);
+        const long blocks = std::min<long>((h.nvox + 255) / 256, 2048);
+        const size_t lds = sizeof(double) * (nbins + 1) + sizeof(unsigned int) * (nbins + 2);
+        hipLaunchKernelGGL(k_seq_hist<R>, dim3(blocks), dim3(256), lds, s->stream, (const R *)sig, h.nvox, nbins,
+                           (const double *)dq, dc);
+        HIPCHK(hipGetLastError());
+    }
+    HIPCHK(hipMemcpyAsync(counts, dc, sizeof(unsigned long long) * (nbins + 2), hipMemcpyDeviceToHost, s->stream));
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return CPF_OK;
+}
+
+extern "C" int cpf_seq_histogram(cpf_solver *s, int rve, int nbins, double lo, double hi,
+                                 unsigned long long *counts)
+{
+    if (!s || !s->bound) return fail(CPF_E_BAD_STATE, "solver not bound");
+    if (!counts) return fail(CPF_E_INVALID_ARG, "null argument");
+    if (rve < -1 || rve >= (int)s->rv.size()) return fail(CPF_E_INVALID_ARG, "rve %d out of range", rve);
+    if (nbins < 1 || nbins > CPF_MAX_HIST_BINS)
+        return fail(CPF_E_INVALID_ARG, "nbins %d: need 1..%d", nbins, CPF_MAX_HIST_BINS);
+    if (!std::isfinite(lo) || !std::isfinite(hi) || !(hi > lo))
+        return fail(CPF_E_INVALID_ARG, "need finite lo < hi");
+    return s->prec == CPF_PREC_FP64 ? seq_hist_impl<double>(s, rve, nbins, lo, hi, counts)
+                                    : seq_hist_impl<float>(s, rve, nbins, lo, hi, counts);
 }
 
 // ---------------------------------------------------------------------------

@@ -715,18 +715,17 @@ __global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_constitut
     for (int c = 0; c < 6; ++c) sig[c * nvox + vox] = s[c];
 }
 
-// sigma = C_lab : (eps - eps_p) from a committed strain and state
+// sigma = C_lab : (eps - eps_p) at one voxel from a committed strain and
+// state (lab frame, tensor components).
 template <typename R>
-__global__ __launch_bounds__(256) void k_stress_field(const int32_t *labels, const R *Qtab, const R *eps,
-                                                      const R *st, R *sig, LawP<R> P, long nvox)
+__device__ __forceinline__ void voxel_stress(const int32_t *labels, const R *Qtab, const R *eps, const R *st,
+                                             const LawP<R> &P, long nvox, long vox, R sl[6])
 {
-    const long vox = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (vox >= nvox) return;
     const int lab = labels[vox];
     R Q[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) Q[i] = Qtab[lab * 9 + i];
-    R el[6], epl[6], ec[6], epc[6], sc[6], sl[6];
+    R el[6], epl[6], ec[6], epc[6], sc[6];
 #pragma unroll
     for (int c = 0; c < 6; ++c) {
         el[c] = eps[c * nvox + vox];
@@ -736,8 +735,78 @@ __global__ __launch_bounds__(256) void k_stress_field(const int32_t *labels, con
     rot_to_crystal(Q, epl, epc);
     hooke(P, ec, epc, sc);
     rot_to_lab(Q, sc, sl);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_stress_field(const int32_t *labels, const R *Qtab, const R *eps,
+                                                      const R *st, R *sig, LawP<R> P, long nvox)
+{
+    const long vox = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (vox >= nvox) return;
+    R sl[6];
+    voxel_stress<R>(labels, Qtab, eps, st, P, nvox, vox, sl);
 #pragma unroll
     for (int c = 0; c < 6; ++c) sig[c * nvox + vox] = sl[c];
+}
+
+// Square of the von Mises stress in FP64 by a fixed order of single,
+// correctly rounded operations (no contraction), so that a host
+// computation in the same order gives the same number:
+//   m = ((s11 + s22) + s33) / 3,  d_i = s_ii - m,
+//   J = ((d1 d1 + d2 d2) + d3 d3) + 2 ((s23 s23 + s13 s13) + s12 s12),
+//   sigma_eq^2 = 1.5 J.
+template <typename R>
+__device__ __forceinline__ double von_mises_sq_exact(const R s[6])
+{
+    const double a = s[0], b = s[1], c = s[2], d = s[3], e = s[4], f = s[5];
+    const double m = __ddiv_rn(__dadd_rn(__dadd_rn(a, b), c), 3.0);
+    const double d1 = __dsub_rn(a, m), d2 = __dsub_rn(b, m), d3 = __dsub_rn(c, m);
+    const double nrm = __dadd_rn(__dadd_rn(__dmul_rn(d1, d1), __dmul_rn(d2, d2)), __dmul_rn(d3, d3));
+    const double sh = __dadd_rn(__dadd_rn(__dmul_rn(d, d), __dmul_rn(e, e)), __dmul_rn(f, f));
+    return __dmul_rn(1.5, __dadd_rn(nrm, __dmul_rn(2.0, sh)));
+}
+
+// Histogram of the von Mises stress of a stress field [6][nvox] against
+// squared bin edges q[0..nbins] (non-decreasing; -1 for edges <= 0): with
+// j the largest index such that q[j] <= sigma_eq^2, counts[0] if there is
+// none, counts[1 + j] for j < nbins, counts[nbins + 1] for j = nbins or a
+// non-finite value.  Comparing squares keeps square roots (not correctly
+// rounded on the device) out of the decision.  Block-local counts in LDS,
+// added to the device counts at the end (integer atomics: the result does
+// not depend on the order).
+template <typename R>
+__global__ __launch_bounds__(256) void k_seq_hist(const R *__restrict__ sig, long nvox, int nbins,
+                                                  const double *__restrict__ qedge, unsigned long long *counts)
+{
+    extern __shared__ double lds_q[];
+    unsigned int *hist = reinterpret_cast<unsigned int *>(lds_q + nbins + 1);
+    const int nb = nbins + 2;
+    for (int i = threadIdx.x; i <= nbins; i += blockDim.x) lds_q[i] = qedge[i];
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) hist[i] = 0u;
+    __syncthreads();
+    for (long vox = (long)blockIdx.x * blockDim.x + threadIdx.x; vox < nvox; vox += (long)gridDim.x * blockDim.x) {
+        R sl[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) sl[c] = sig[c * nvox + vox];
+        const double x = von_mises_sq_exact<R>(sl);
+        int k;
+        if (!(x == x) || x == INFINITY) {
+            k = nbins + 1;
+        } else {
+            // largest j with lds_q[j] <= x, -1 if none
+            int a = -1, b = nbins;
+            while (a < b) {
+                const int mid = (a + b + 1) >> 1;
+                if (lds_q[mid] <= x) a = mid;
+                else b = mid - 1;
+            }
+            k = a + 1;
+        }
+        atomicAdd(&hist[k], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += blockDim.x)
+        if (hist[i]) atomicAdd(&counts[i], (unsigned long long)hist[i]);
 }
 
 template <typename R>

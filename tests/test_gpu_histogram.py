@@ -1,0 +1,58 @@
+"""The device histogram of the local von Mises stress equals, count for
+count, the oracle's histogram of the exported stress fields (both evaluate
+sigma_eq and the bin in FP64 in the same order), for single RVEs and whole
+batches."""
+import numpy as np
+import pytest
+
+import oracle
+import rvegen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+cp = pytest.importorskip("paper_2402_09996_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    cp._lib.lib()
+    yield
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_histogram_matches_oracle_bitwise(precision):
+    C, law = rvegen.config_law()
+    S = rvegen.config_systems(True)
+    path = rvegen.uniaxial_path(0.008, 8)
+    wl = [rvegen.Workload("h%d" % i, rvegen.make_rve(sh, 6, 60 + i, twin_share=0.5), S, C, law, path)
+          for i, sh in enumerate([(16, 16, 16), (12, 24, 32)])]
+    kw = dict(tol=1e-10 if precision == "fp64" else 1e-6, stag_tol=0.0 if precision == "fp64" else 1e-4)
+    s = cp.Solver([cp.Problem.from_workload(w) for w in wl], precision=precision, **kw)
+    for n in range(path.n_steps):
+        out = s.step_batch(path, n)
+    assert all(o["mean_v"] > 0 for o in out)         # plastic
+    fields = [s.field_of(i, "stress").double().cpu().numpy() for i in range(len(wl))]
+    q = np.concatenate([oracle.von_mises(f.reshape(6, -1)) for f in fields])
+    for nb, lo, hi in ((97, 0.9 * q.min(), 1.1 * q.max()), (4096, q.min(), q.max()),
+                       (7, np.median(q) - 5.0, np.median(q) + 5.0)):
+        print("bins", nb, lo, hi, flush=True)
+        ref_all = oracle.von_mises_histogram(fields, nb, lo, hi)
+        assert int(ref_all.sum()) == sum(f[0].size for f in fields)
+        assert np.array_equal(s.von_mises_histogram(nb, lo, hi), ref_all)
+        for i in range(len(wl)):
+            assert np.array_equal(s.von_mises_histogram(nb, lo, hi, rve=i),
+                                  oracle.von_mises_histogram([fields[i]], nb, lo, hi))
+    x, pdf = s.von_mises_pdf(97, 0.9 * q.min(), 1.1 * q.max())
+    assert abs(pdf.sum() * (x[1] - x[0]) - 1.0) < 1e-12
+
+
+def test_histogram_argument_errors():
+    w = rvegen.workload(0)
+    s = cp.Solver(cp.Problem.from_workload(w), precision="fp64")
+    for args in ((0, 0.0, 1.0), (5000, 0.0, 1.0), (10, 1.0, 1.0), (10, np.nan, 1.0)):
+        with pytest.raises(cp.CpfError):
+            s.von_mises_histogram(*args)
+    with pytest.raises(cp.CpfError):
+        s.von_mises_histogram(10, 0.0, 1.0, rve=3)
