@@ -363,8 +363,8 @@ def von_mises_sq(stress: np.ndarray) -> np.ndarray:
     return 1.5 * (nrm + 2.0 * sh)
 
 
-def von_mises(stress: np.ndarray) -> np.ndarray:
-    """Local von Mises stress sqrt(von_mises_sq)."""
+def von_mises_field(stress: np.ndarray) -> np.ndarray:
+    """Local von Mises stress sqrt(von_mises_sq) of stresses [6][...]."""
     return np.sqrt(von_mises_sq(stress))
 
 

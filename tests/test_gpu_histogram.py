@@ -34,7 +34,7 @@ def test_histogram_matches_oracle_bitwise(precision):
         out = s.step_batch(path, n)
     assert all(o["mean_v"] > 0 for o in out)         # plastic
     fields = [s.field_of(i, "stress").double().cpu().numpy() for i in range(len(wl))]
-    q = np.concatenate([oracle.von_mises(f.reshape(6, -1)) for f in fields])
+    q = np.concatenate([oracle.von_mises_field(f.reshape(6, -1)) for f in fields])
     for nb, lo, hi in ((97, 0.9 * q.min(), 1.1 * q.max()), (4096, q.min(), q.max()),
                        (7, np.median(q) - 5.0, np.median(q) + 5.0)):
         print("bins", nb, lo, hi, flush=True)

@@ -14,16 +14,16 @@ def _tensor_to_comps(T):
 def test_closed_forms():
     a = np.array([250.0, -37.5, 1e-3])
     z = np.zeros_like(a)
-    assert np.allclose(oracle.von_mises([a, z, z, z, z, z]), np.abs(a), rtol=2e-16, atol=0)
-    assert np.allclose(oracle.von_mises([z, a, z, z, z, z]), np.abs(a), rtol=2e-16, atol=0)
+    assert np.allclose(oracle.von_mises_field([a, z, z, z, z, z]), np.abs(a), rtol=2e-16, atol=0)
+    assert np.allclose(oracle.von_mises_field([z, a, z, z, z, z]), np.abs(a), rtol=2e-16, atol=0)
     tau = np.array([10.0, -4.0])
     z2 = np.zeros_like(tau)
-    assert np.allclose(oracle.von_mises([z2, z2, z2, z2, z2, tau]), np.sqrt(3) * np.abs(tau), rtol=4e-16)
-    assert np.allclose(oracle.von_mises([z2, z2, z2, tau, z2, z2]), np.sqrt(3) * np.abs(tau), rtol=4e-16)
+    assert np.allclose(oracle.von_mises_field([z2, z2, z2, z2, z2, tau]), np.sqrt(3) * np.abs(tau), rtol=4e-16)
+    assert np.allclose(oracle.von_mises_field([z2, z2, z2, tau, z2, z2]), np.sqrt(3) * np.abs(tau), rtol=4e-16)
     p = np.array([100.0, -3.0])
-    assert np.all(oracle.von_mises([p, p, p, z2, z2, z2]) == 0.0)
+    assert np.all(oracle.von_mises_field([p, p, p, z2, z2, z2]) == 0.0)
     # equal biaxial = uniaxial of the same magnitude
-    assert np.allclose(oracle.von_mises([tau, tau, z2, z2, z2, z2]), np.abs(tau), rtol=4e-16)
+    assert np.allclose(oracle.von_mises_field([tau, tau, z2, z2, z2, z2]), np.abs(tau), rtol=4e-16)
 
 
 def test_invariance_under_rotation_and_pressure():
@@ -31,9 +31,9 @@ def test_invariance_under_rotation_and_pressure():
     A = rng.standard_normal((3, 3)) * 100
     T = 0.5 * (A + A.T)
     Q, _ = np.linalg.qr(rng.standard_normal((3, 3)))
-    q0 = oracle.von_mises(_tensor_to_comps(T)[:, None])
-    q1 = oracle.von_mises(_tensor_to_comps(Q @ T @ Q.T)[:, None])
-    q2 = oracle.von_mises(_tensor_to_comps(T + 321.0 * np.eye(3))[:, None])
+    q0 = oracle.von_mises_field(_tensor_to_comps(T)[:, None])
+    q1 = oracle.von_mises_field(_tensor_to_comps(Q @ T @ Q.T)[:, None])
+    q2 = oracle.von_mises_field(_tensor_to_comps(T + 321.0 * np.eye(3))[:, None])
     assert abs(q1[0] - q0[0]) < 1e-12 * q0[0] and abs(q2[0] - q0[0]) < 1e-12 * q0[0]
     # via the deviatoric principal values: sqrt(3/2) |eigs(dev T)|
     dev = T - np.trace(T) / 3 * np.eye(3)

@@ -361,6 +361,16 @@ def test_voigt_reuss_bounds_and_hill_mandel():
     sig, eps = R.fields["stress"], R.fields["strain"]
     hm = np.mean(np.sum(oracle.FROB_W[:, None, None, None] * sig * eps, axis=0))
     assert hm == pytest.approx(np.sum(oracle.FROB_W * R.Sigma[0] * R.E[0]), rel=1e-11)
+    # the per-step statistics: von Mises of the mean stress and mean of the
+    # local von Mises, here from full 3x3 tensors sqrt(3/2 dev:dev)
+    def vm(t):
+        T = np.array([[t[0], t[5], t[4]], [t[5], t[1], t[3]], [t[4], t[3], t[2]]])
+        D = T - np.trace(T) / 3 * np.eye(3)
+        return np.sqrt(1.5 * np.sum(D * D))
+    assert R.sig_eq_of_mean[0] == pytest.approx(vm(R.Sigma[0]), rel=1e-13)
+    local = [vm(sig[:, z, y, x]) for z in range(8) for y in range(8) for x in range(8)]
+    assert R.mean_sig_eq[0] == pytest.approx(np.mean(local), rel=1e-13)
+    assert R.mean_sig_eq[0] > R.sig_eq_of_mean[0]     # convexity, heterogeneous field
 
 
 def test_axis_permutation_and_shift_invariance():
