@@ -19,6 +19,9 @@ the design notes of the repository):
   (lam0, mu0); frequencies xi_j = m_j / N_j with m_j in (-N_j/2, N_j/2];
   Gamma0 = 0 at xi = 0 and at every frequency with a Nyquist component
   (m_j = N_j/2, N_j even), which keeps the real field real.
+* Discrete variant (option): the Green operator of the rotated
+  finite-difference scheme, the continuous formula at the unit vector of
+  s_j = sin(q_j/2) prod_{l != j} cos(q_l/2); zero where s = 0.
 * Reference medium: k0 = (1/9) 1:C:1 (Voigt bulk), mu0 = mean of the
   extreme deviatoric shear moduli of C, lam0 = k0 - 2 mu0 / 3.
 * Basic scheme: eps^{k+1} = eps^k - Gamma0 * sigma^k + dE^k, with the
@@ -406,6 +409,48 @@ def frequency_directions(shape):
     return xi_hat, ctrl
 
 
+def frequency_directions_rotated(shape):
+    """Directions of the rotated finite-difference scheme (Willot, 2015),
+    the discrete variant of the Green operator: [3,nz,ny,nx] and the mask
+    of controlled frequencies.
+
+    In that scheme the derivative along j at a voxel centre is the mean of
+    the four differences along the voxel edges parallel to j.  Its Fourier
+    symbol is 2i exp(i (q1+q2+q3)/2) s_j with q_j = 2 pi m_j / N_j and
+      s_j = sin(q_j / 2) prod_{l != j} cos(q_l / 2).
+    The common complex factor cancels in Gamma0, which is therefore the
+    continuous formula evaluated at the real unit vector s / |s|.  s = 0 at
+    the zero frequency and wherever two or more components are at Nyquist
+    (cos(pi/2) = 0, set exactly); there Gamma0 is zero and those
+    frequencies are not controlled.  A single Nyquist component is
+    controlled (unlike the continuous operator)."""
+    nz, ny, nx = shape
+    sin_h, cos_h = [], []
+    for N in (nx, ny, nz):
+        k = np.arange(N)
+        m = np.where(k <= N // 2, k, k - N).astype(np.float64)
+        half = np.pi * m / N                       # q / 2
+        nyq = 2 * m == N
+        sin_h.append(np.where(nyq, 1.0, np.sin(half)))
+        cos_h.append(np.where(nyq, 0.0, np.cos(half)))
+    Sx, Sy, Sz = np.meshgrid(sin_h[2], sin_h[1], sin_h[0], indexing="ij")[::-1]
+    Cx, Cy, Cz = np.meshgrid(cos_h[2], cos_h[1], cos_h[0], indexing="ij")[::-1]
+    s = np.stack([Sx * Cy * Cz, Sy * Cx * Cz, Sz * Cx * Cy])
+    nrm = np.sqrt(np.sum(s * s, axis=0))
+    ctrl = nrm > 0
+    return np.where(ctrl, s / np.where(ctrl, nrm, 1.0), 0.0), ctrl
+
+
+def green_directions(shape, green: str = "continuous"):
+    """Unit directions and controlled-frequency mask of the chosen Green
+    operator: 'continuous' (the default) or 'rotated'."""
+    if green == "continuous":
+        return frequency_directions(shape)
+    if green == "rotated":
+        return frequency_directions_rotated(shape)
+    raise ValueError("green must be 'continuous' or 'rotated'")
+
+
 def gamma0_apply(tau_hat: np.ndarray, lam0: float, mu0: float,
                  xi_hat: Optional[np.ndarray] = None,
                  ctrl: Optional[np.ndarray] = None) -> np.ndarray:
@@ -459,6 +504,7 @@ class Options:
     M: Optional[int] = None           # fixed RK4 substeps, overrides h_max
     lam0: Optional[float] = None      # reference medium override
     mu0: Optional[float] = None
+    green: str = "continuous"         # or "rotated" (discrete Green operator)
 
 
 class NotConverged(RuntimeError):
@@ -495,7 +541,7 @@ class Solver:
             lam0, mu0 = self.opts.lam0, self.opts.mu0
         self.lam0, self.mu0 = lam0, mu0
         self.K0 = iso_stiffness(lam0, mu0)
-        self.xi_hat, self.ctrl = frequency_directions(self.shape)
+        self.xi_hat, self.ctrl = green_directions(self.shape, self.opts.green)
         self.slip = self.mat.family == 0
         self.twin = self.mat.family == 1
         self.reset()

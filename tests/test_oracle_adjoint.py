@@ -125,16 +125,19 @@ def test_discrete_adjoint_gradient_matches_finite_differences():
     assert np.abs(grad[1]).max() > 0        # the twin family is active
 
 
-def test_vjp_general_cotangent_matches_finite_differences():
+@pytest.mark.parametrize("green", ["continuous", "rotated"])
+def test_vjp_general_cotangent_matches_finite_differences(green):
     """J = sum_n Sigma_bar_n . Sigma_n with a cotangent on all six
     components (shear included, tensor components) against central
-    differences of the forward solves, for parameters of both families."""
+    differences of the forward solves, for parameters of both families,
+    with either Green operator (the adjoint equilibrium uses the same
+    operator as the forward solve)."""
     C, law = rvegen.config_law()
     S = rvegen.config_systems(True)
     rve = rvegen.make_rve((4, 4, 6), 3, 77, twin_share=0.5)
     path = rvegen.uniaxial_path(0.006, 3, rate=1e-2)
     w = rvegen.Workload("t", rve, S, C, law, path)
-    o = oracle.solver_for(w, oracle.Options(tol=1e-12))
+    o = oracle.solver_for(w, oracle.Options(tol=1e-12, green=green))
     sb = np.random.default_rng(3).standard_normal((3, 6))
     grad, Sig = o.vjp(path, sb, adj_tol=1e-12)
     assert np.abs(Sig[:, 3:]).max() > 0      # shear stresses are not zero
@@ -142,7 +145,7 @@ def test_vjp_general_cotangent_matches_finite_differences():
     def J(fam, name, h):
         l2, t0 = _perturbed(law, S, fam, name, h)
         sv = oracle.Solver(rve.labels, rve.euler, C, S.n_miller, S.l_miller, S.family, t0, l2,
-                           oracle.Options(tol=1e-12))
+                           oracle.Options(tol=1e-12, green=green))
         return float(np.sum(sb * sv.run(path).Sigma))
 
     for fam, name in ((0, "r0"), (0, "K"), (0, "c"), (1, "r0"), (1, "n")):
