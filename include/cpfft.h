@@ -105,7 +105,23 @@ typedef struct cpf_options {
     double lam0, mu0;  /* > 0: reference medium override (MPa)               */
     double stag_tol;   /* FP32: accept a stalled residual below this (0: off)*/
     int check_every;   /* iterations queued per host convergence poll (0: auto) */
+    int green;         /* CPF_GREEN_*: which Green operator (Section 3)      */
 } cpf_options;
+
+/* Green operator of the fixed point (Section 3 names only "the Green
+ * operator" of the reference medium).
+ * CPF_GREEN_CONTINUOUS: the continuous isotropic operator at the unit
+ *   frequency direction; zero at the zero frequency and at every frequency
+ *   with a Nyquist component.
+ * CPF_GREEN_ROTATED: its discrete variant of the rotated finite-difference
+ *   scheme (Willot, 2015): the same formula at the unit vector of
+ *   s_j = sin(q_j/2) prod_{l != j} cos(q_l/2), q_j = 2 pi m_j / N_j; zero
+ *   only at the zero frequency and where two or more components are at
+ *   Nyquist.  The solver then also stores and transforms the kx = nx/2
+ *   column of the spectrum.  The equilibrium residual uses the same
+ *   directions. */
+#define CPF_GREEN_CONTINUOUS 0
+#define CPF_GREEN_ROTATED 1
 
 /* Loading path: n_steps increments; t has n_steps+1 times (s).  For step
  * n, strain_ctrl[n][i] = 1 prescribes the mean strain component i to

@@ -138,7 +138,10 @@ def _outs_to_dict(outs, n):
     return r
 
 
-def _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_every):
+GREEN = {"continuous": 0, "rotated": 1}
+
+
+def _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_every, green="continuous"):
     o = _lib.CpfOptions()
     _lib.lib().cpf_options_default(ctypes.byref(o))
     o.precision = CPF_PREC_FP64 if precision == "fp64" else CPF_PREC_FP32
@@ -146,6 +149,9 @@ def _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_
     if mu0 is not None:
         o.lam0, o.mu0 = float(lam0), float(mu0)
     o.stag_tol, o.check_every = float(stag_tol), int(check_every)
+    if green not in GREEN:
+        raise ValueError("green must be one of %s" % sorted(GREEN))
+    o.green = GREEN[green]
     return o
 
 
@@ -159,7 +165,8 @@ class Solver:
                  max_iter: int = 1000, h_max: float = 0.05, rk4_M: int = 0,
                  lam0: Optional[float] = None, mu0: Optional[float] = None,
                  stag_tol: float = 0.0, check_every: int = 0, device: str = "cuda:0",
-                 stream=None, graph_iters: int = 0, autotune: bool = False):
+                 stream=None, graph_iters: int = 0, autotune: bool = False,
+                 green: str = "continuous"):
         import torch
         L = _lib.lib()
         probs = list(problem) if isinstance(problem, (list, tuple)) else [problem]
@@ -168,7 +175,8 @@ class Solver:
         self.n_rve = len(probs)
         self.precision = precision
         self.dtype = {"fp64": torch.float64, "fp32": torch.float32}[precision]
-        o = _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_every)
+        o = _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_every, green)
+        self.green_operator = green
         h = ctypes.c_void_p()
         arr = (ctypes.c_void_p * self.n_rve)(*[p._h.value for p in probs])
         check(L.cpf_batch_create(self.n_rve, arr, ctypes.byref(o), ctypes.byref(h)))

@@ -79,6 +79,7 @@ extern "C" void cpf_options_default(cpf_options *o)
     o->mu0 = 0.0;
     o->stag_tol = 0.0;
     o->check_every = 0;
+    o->green = CPF_GREEN_CONTINUOUS;
 }
 
 // ---------------------------------------------------------------------------
@@ -541,15 +542,18 @@ static bool same_material(const cpf_problem &a, const cpf_problem &b)
 }
 
 template <typename R>
-static void init_rve(RveHost &h, const cpf_problem &p)
+static void init_rve(RveHost &h, const cpf_problem &p, int green)
 {
     h.pb = p;
     h.nx = p.nx; h.ny = p.ny; h.nz = p.nz;
     h.nhx = p.nx / 2 + 1;
-    // The solve keeps kx < nx/2 only: Gamma0 is zero on the Nyquist column
-    // and the residual leaves it out, so the column is neither stored nor
-    // transformed along y and z.  Rows are padded to whole 128-byte lines.
-    h.nkx = p.nx / 2;
+    // With the continuous operator the solve keeps the columns below the
+    // Nyquist one (kx < nx/2 for even nx, all nx/2 + 1 for odd nx): Gamma0
+    // is zero on the Nyquist column and the residual leaves it out, so the
+    // column is neither stored nor transformed along y and z.  The rotated
+    // operator acts on it, so it is kept.  Rows are padded to whole
+    // 128-byte lines.
+    h.nkx = (green == CPF_GREEN_ROTATED || (p.nx & 1)) ? p.nx / 2 + 1 : p.nx / 2;
     const int line = (int)(128 / sizeof(C2<R>));
     h.nhp = (h.nkx + line - 1) / line * line;
     h.nvox = (long)p.nx * p.ny * p.nz;
@@ -579,6 +583,8 @@ extern "C" int cpf_batch_create(int n, const cpf_problem *const *probs, const cp
         return fail(CPF_E_INVALID_ARG, "unknown precision %d", o.precision);
     if (!(o.tol > 0) || o.max_iter < 1 || (o.rk4_M <= 0 && !(o.h_max > 0)) || o.rk4_M > 100000)
         return fail(CPF_E_INVALID_ARG, "need tol > 0, max_iter >= 1 and rk4_M > 0 or h_max > 0");
+    if (o.green != CPF_GREEN_CONTINUOUS && o.green != CPF_GREEN_ROTATED)
+        return fail(CPF_E_INVALID_ARG, "unknown Green operator %d", o.green);
     cpf_solver *s = new (std::nothrow) cpf_solver();
     if (!s) return fail(CPF_E_INVALID_ARG, "out of host memory");
     const cpf_problem &p0 = *probs[0];
@@ -591,8 +597,8 @@ extern "C" int cpf_batch_create(int n, const cpf_problem *const *probs, const cp
     s->n_twin = p0.n_twin;
     s->rv.resize(n);
     for (int i = 0; i < n; ++i) {
-        if (s->prec == CPF_PREC_FP64) init_rve<double>(s->rv[i], *probs[i]);
-        else init_rve<float>(s->rv[i], *probs[i]);
+        if (s->prec == CPF_PREC_FP64) init_rve<double>(s->rv[i], *probs[i], o.green);
+        else init_rve<float>(s->rv[i], *probs[i], o.green);
     }
     if (s->prec == CPF_PREC_FP64) { layout<double>(s); pass_grids<double>(s); }
     else { layout<float>(s); pass_grids<float>(s); }
@@ -924,6 +930,7 @@ static void launch_z(cpf_solver *s, int mode, const RveDev<R> *table = nullptr, 
     }
     const R inv_mu0 = R(1.0 / s->mu0);
     const R coef = R((s->lam0 + s->mu0) / (s->mu0 * (s->lam0 + 2.0 * s->mu0)));
+    if ((mode & ZMODE_GREEN) && s->opt.green == CPF_GREEN_ROTATED) mode |= ZMODE_ROTATED;
     constexpr int E = ept_z<R>(), EH = E / 2;
     if (elems <= EH * 256)
         hipLaunchKernelGGL((k_zpass_green<R, EH>), dim3(grid), dim3(256), lds, s->stream, table, nrve, inv_mu0, coef,

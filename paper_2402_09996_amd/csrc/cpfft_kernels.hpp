@@ -44,8 +44,8 @@ struct Scalars {
 template <typename R>
 struct RveDev {
     int nx, ny, nz, nhx;
-    int nkx, nhp;              // kx columns held (nx/2 in the solve: the Nyquist column,
-                               // zeroed by Gamma0, is not stored) and row pitch
+    int nkx, nhp;              // kx columns held (the continuous operator's solve leaves
+                               // out the Nyquist column, which it zeroes) and row pitch
     int L, tpbx, nlines;       // x pass: lines per block, threads used
     int ty, nty, tz, ntz;      // y / z pass tiles (kx columns) and tile counts
     int bx0, by0, bz0;         // first block in the x, y and z pass grids
@@ -453,21 +453,48 @@ struct GreenArgs {
     R coef;         // (lam0 + mu0) / (mu0 (lam0 + 2 mu0))
 };
 
+// sin and cos of the half angle pi m / N of frequency m (exact 1 and 0 at
+// Nyquist, m = N/2)
+__device__ __forceinline__ void half_angle(int m, int n, float &sn, float &cs)
+{
+    if (2 * m == n) { sn = 1.0f; cs = 0.0f; return; }
+    sincospif((float)m / (float)n, &sn, &cs);
+}
+__device__ __forceinline__ void half_angle(int m, int n, double &sn, double &cs)
+{
+    if (2 * m == n) { sn = 1.0; cs = 0.0; return; }
+    sincospi((double)m / (double)n, &sn, &cs);
+}
+
 template <typename R>
 __device__ __forceinline__ void green_point(C2<R> (&s)[6], int kx, int ky, int kz, const GreenArgs<R> &g,
-                                            double &err2)
+                                            bool rotated, double &err2)
 {
-    // frequency m_j in (-N_j/2, N_j/2]; direction of (m_x/N_x, m_y/N_y, m_z/N_z)
+    // frequency m_j in (-N_j/2, N_j/2]
     const int my = ky <= g.ny / 2 ? ky : ky - g.ny;
     const int mz = kz <= g.nz / 2 ? kz : kz - g.nz;
-    const bool nyq = ((g.nx & 1) == 0 && 2 * kx == g.nx) || ((g.ny & 1) == 0 && 2 * ky == g.ny) ||
-                     ((g.nz & 1) == 0 && 2 * kz == g.nz);
-    if (nyq || (kx == 0 && my == 0 && mz == 0)) {
+    const int qx = (g.nx & 1) == 0 && 2 * kx == g.nx, qy = (g.ny & 1) == 0 && 2 * ky == g.ny,
+              qz = (g.nz & 1) == 0 && 2 * kz == g.nz;
+    // continuous operator: zero at any Nyquist component; rotated: zero
+    // where two or more components are at Nyquist (s = 0 there)
+    const bool zero = rotated ? qx + qy + qz >= 2 : (qx | qy | qz) != 0;
+    if (zero || (kx == 0 && my == 0 && mz == 0)) {
 #pragma unroll
         for (int c = 0; c < 6; ++c) s[c] = C2<R>{R(0), R(0)};
         return;
     }
-    R x1 = R(kx) / R(g.nx), x2 = R(my) / R(g.ny), x3 = R(mz) / R(g.nz);
+    R x1, x2, x3;
+    if (rotated) {
+        // rotated scheme: s_j = sin(q_j/2) prod_{l != j} cos(q_l/2)
+        R sx, cx, sy, cy, sz, cz;
+        half_angle(kx, g.nx, sx, cx);
+        half_angle(my, g.ny, sy, cy);
+        half_angle(mz, g.nz, sz, cz);
+        x1 = sx * cy * cz; x2 = sy * cx * cz; x3 = sz * cx * cy;
+    } else {
+        // direction of (m_x/N_x, m_y/N_y, m_z/N_z)
+        x1 = R(kx) / R(g.nx); x2 = R(my) / R(g.ny); x3 = R(mz) / R(g.nz);
+    }
     const R inr = R(1) / sqrt(x1 * x1 + x2 * x2 + x3 * x3);
     x1 *= inr; x2 *= inr; x3 *= inr;
     // a = tau . xi, b = xi . a
@@ -478,7 +505,9 @@ __device__ __forceinline__ void green_point(C2<R> (&s)[6], int kx, int ky, int k
     a2.y = s[5].y * x1 + s[1].y * x2 + s[3].y * x3;
     a3.x = s[4].x * x1 + s[3].x * x2 + s[2].x * x3;
     a3.y = s[4].y * x1 + s[3].y * x2 + s[2].y * x3;
-    const double w = kx == 0 ? 1.0 : 2.0;   // Hermitian partner in the half spectrum
+    // Hermitian partner in the half spectrum (the kx = 0 and Nyquist columns
+    // hold their own)
+    const double w = (kx == 0 || qx) ? 1.0 : 2.0;
     err2 += w * ((double)a1.x * a1.x + (double)a1.y * a1.y + (double)a2.x * a2.x +
                  (double)a2.y * a2.y + (double)a3.x * a3.x + (double)a3.y * a3.y);
     const C2<R> b = {a1.x * x1 + a2.x * x2 + a3.x * x3, a1.y * x1 + a2.y * x2 + a3.y * x3};
@@ -500,6 +529,7 @@ __device__ __forceinline__ void green_point(C2<R> (&s)[6], int kx, int ky, int k
 // use one each (with spec_override).
 constexpr int ZMODE_FWD = 1;
 constexpr int ZMODE_GREEN = 2;
+constexpr int ZMODE_ROTATED = 4;   // with ZMODE_GREEN: the rotated-scheme operator
 
 template <typename R, int EPT>
 __global__ __launch_bounds__(256) void k_zpass_green(const RveDev<R> *__restrict__ rv, int nrve, R inv_mu0,
@@ -547,7 +577,7 @@ __global__ __launch_bounds__(256) void k_zpass_green(const RveDev<R> *__restrict
         C2<R> s[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) s[c] = buf[(c * tw_ + col) * ls + kz];
-        green_point<R>(s, kx0 + col, ky, kz, g, err2);
+        green_point<R>(s, kx0 + col, ky, kz, g, (mode & ZMODE_ROTATED) != 0, err2);
 #pragma unroll
         for (int c = 0; c < 6; ++c) buf[(c * tw_ + col) * ls + kz] = s[c];
     }
