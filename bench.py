@@ -65,10 +65,10 @@ def fft_pass_bytes(nx: int, ny: int, nz: int, rbytes: int) -> float:
     return 2.0 * 6 * nz * ny * (nx // 2) * 2 * rbytes
 
 
-def run_mode(cp, w, precision, K, W, tol, stag):
+def run_mode(cp, w, precision, K, W, tol, stag, green="continuous"):
     import torch
     prob = cp.Problem.from_workload(w)
-    s = cp.Solver(prob, precision=precision, tol=tol, stag_tol=stag)
+    s = cp.Solver(prob, precision=precision, tol=tol, stag_tol=stag, green=green)
     for n in range(W):
         s.step(w.path, n)
     s.reset()
@@ -82,8 +82,8 @@ def run_mode(cp, w, precision, K, W, tol, stag):
         act += float(o["n_active"])
         newt += float(o["n_newton"])
         outs.append(o)
-        print("[bench] %s step %d iters %d Sigma_xx %.4f err %.2e" %
-              (precision, n, o["iters"], o["Sigma"][0], max(o["err_eq"], o["err_bc"])),
+        print("[bench] %s %s step %d iters %d Sigma_xx %.4f err %.2e" %
+              (precision, green, n, o["iters"], o["Sigma"][0], max(o["err_eq"], o["err_bc"])),
               file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
@@ -249,6 +249,28 @@ def adjoint_leg(cp, steps, checkpoint_every=10):
     return out
 
 
+def green_leg(cp, w, KG, W, r32, K, nvox):
+    """The same FP32 workload with the rotated-scheme Green operator:
+    iterations, throughput and time per load step against the continuous
+    operator's run (which stores 64 of the 65 kx columns of a 128^3 grid;
+    the rotated operator needs all 65)."""
+    import numpy as np
+    s, r = run_mode(cp, w, "fp32", KG, W, 1e-6, 1e-4, green="rotated")
+    kern = r["kernels"]
+    it = max(1, r["iters"])
+    out = {"steps": KG, "iterations": r["iters"], "value": r["iters"] * nvox / r["wall"],
+           "unit": "voxel-iterations/s", "ms_per_step": r["wall"] / KG * 1e3,
+           "kernel_avg_ms": {k: kern[k][0] / it for k in kern}}
+    if KG == K:
+        out["iterations_vs_continuous"] = r["iters"] / max(1, r32["iters"])
+        out["wall_vs_continuous"] = r["wall"] / r32["wall"]
+        a = np.array([o["Sigma"][0] for o in r["outs"]])
+        b = np.array([o["Sigma"][0] for o in r32["outs"]])
+        out["max_rel_diff_Sigma_xx_vs_continuous"] = float(np.abs(a - b).max() / np.abs(b).max())
+    del s
+    return out
+
+
 def histogram_leg(s32, nvox, reps=20, nbins=150, lo=0.0, hi=1500.0):
     """Distribution of the local von Mises stress of the committed 128^3
     state (post-processing after the timed steps): the stress pass (reads
@@ -294,6 +316,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--adjoint-steps", type=int, default=50)
+    ap.add_argument("--green-steps", type=int, default=None,
+                    help="load steps of the rotated-operator FP32 leg (default: --steps)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run plain 1 GiB device copies (calibrates the HBM byte counters)")
     args = ap.parse_args()
@@ -379,6 +403,9 @@ def main():
             a = np.array([o["Sigma"][0] for o in r32["outs"]])
             b = np.array([o["Sigma"][0] for o in r64["outs"]])
             line["fp64"]["fp32_max_rel_err_Sigma_xx"] = float(np.abs(a - b).max() / np.abs(b).max())
+    KG = args.green_steps if args.green_steps is not None else K
+    if KG > 0:
+        line["rotated_green"] = green_leg(cp, w, KG, min(W, 1), r32, K, nvox)
     line["seq_histogram"] = histogram_leg(s32, nvox)
     if args.batch_steps > 0:
         line["batched"] = batch_leg(cp, args.batch_steps)
