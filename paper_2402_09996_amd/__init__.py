@@ -26,7 +26,7 @@ FIELDS = {
 }
 
 __all__ = ["Problem", "Solver", "CpfError", "FIELDS", "version", "EffectiveStress", "StressCurveLoss",
-           "with_theta"]
+           "with_theta", "generate_microstructure", "micro_thin", "micro_label", "micro_graph", "micro_slabs"]
 
 
 def version() -> int:
@@ -514,3 +514,111 @@ class StressCurveLoss:
     @classmethod
     def apply(cls, theta, problem, path, target_xx, options=None):
         return cls._function().apply(theta, problem, path, target_xx, options)
+
+
+# ---------------------------------------------------------------------------
+# Stochastic microstructure model (Section 2), include/cpfft_micro.h
+# ---------------------------------------------------------------------------
+def _micro_params(shape, lam, r, p_neigh, p_incl, delta, theta, seed, q):
+    p = _lib.CpfMicroParams()
+    p.nz, p.ny, p.nx = (int(v) for v in shape)
+    p.q = int(q)
+    p.lambda_, p.r = float(lam), float(r)
+    p.p_neigh, p.p_incl = float(p_neigh), float(p_incl)
+    p.delta_lo, p.delta_hi = float(delta[0]), float(delta[1])
+    p.theta = float(theta)
+    p.seed = int(seed) & ((1 << 64) - 1)
+    return p
+
+
+def generate_microstructure(shape, lam: float, r: float, p_neigh: float = 0.0, p_incl: float = 0.0,
+                            delta=(0.1, 0.3), theta: float = 1.2180652849668427, seed: int = 1, q: int = 16,
+                            device: str = "cuda:0", stream=None) -> dict:
+    """One realization of the Section 2 model on the device.
+
+    shape (nz, ny, nx) voxels; lam: primary Poisson intensity per voxel^3;
+    r: hard-core radius (voxels); p_neigh, p_incl: twin parameters;
+    delta: relative inclusion thickness bounds; theta: twin angle (radians,
+    default 69.79 degrees).  Returns labels (device int32 tensor
+    [nz][ny][nx]), rotations [n_labels][3][3] (crystal to lab), euler
+    [n_labels][3] (Bunge), pairs [n_pairs][3] and the counts of
+    cpf_micro_info."""
+    import torch
+    L = _lib.lib()
+    p = _micro_params(shape, lam, r, p_neigh, p_incl, delta, theta, seed, q)
+    size = ctypes.c_size_t()
+    check(L.cpf_micro_workspace_size(ctypes.byref(p), ctypes.byref(size)))
+    dev = torch.device(device)
+    ws = torch.empty(int(size.value) + 256, dtype=torch.uint8, device=dev)
+    base = (ws.data_ptr() + 255) & ~255
+    labels = torch.empty(tuple(int(v) for v in shape), dtype=torch.int32, device=dev)
+    st = stream if stream is not None else torch.cuda.current_stream(dev)
+    mu = float(lam) * labels.numel()
+    max_labels = 2 * (int(mu + 20.0 * mu ** 0.5 + 20.0) + 1)
+    rot = np.zeros((max_labels, 9))
+    eul = np.zeros((max_labels, 3))
+    pairs = np.zeros((max_labels // 2, 3), dtype=np.int32)
+    info = _lib.CpfMicroInfo()
+    check(L.cpf_micro_generate(ctypes.byref(p), ctypes.c_void_p(base), int(size.value),
+                               ctypes.c_void_p(st.cuda_stream), ctypes.c_void_p(labels.data_ptr()),
+                               max_labels, _ptr(rot, ctypes.c_double), _ptr(eul, ctypes.c_double),
+                               _ptr(pairs, ctypes.c_int32), ctypes.byref(info)))
+    n = info.n_labels
+    out = {k: getattr(info, k) for k, _ in _lib.CpfMicroInfo._fields_}
+    out.update(labels=labels, rotations=rot[:n].reshape(n, 3, 3).copy(), euler=eul[:n].copy(),
+               pairs=pairs[:info.n_pairs].copy())
+    return out
+
+
+def _stream_ptr(stream, t):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream(t.device)
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def micro_thin(points, L, r_q: float, stream=None):
+    """Matern type II keep flags of device points int32 [n][4] in the box L
+    (lattice units): uint8 [n] device tensor."""
+    import torch
+    keep = torch.empty(points.shape[0], dtype=torch.uint8, device=points.device)
+    check(_lib.lib().cpf_micro_thin(int(points.shape[0]), ctypes.c_void_p(points.data_ptr()), int(L[0]),
+                                    int(L[1]), int(L[2]), float(r_q), ctypes.c_void_p(keep.data_ptr()),
+                                    _stream_ptr(stream, points)))
+    return keep
+
+
+def micro_label(shape, q: int, seeds, stream=None):
+    """Periodic Voronoi labels [nz][ny][nx] of device generators int32
+    [n][4]; returns (labels, number of tiles that searched every seed)."""
+    import torch
+    labels = torch.empty(tuple(int(v) for v in shape), dtype=torch.int32, device=seeds.device)
+    fb = torch.zeros(1, dtype=torch.int32, device=seeds.device)
+    nz, ny, nx = shape
+    check(_lib.lib().cpf_micro_label(int(nx), int(ny), int(nz), int(q), int(seeds.shape[0]),
+                                     ctypes.c_void_p(seeds.data_ptr()), ctypes.c_void_p(labels.data_ptr()),
+                                     ctypes.c_void_p(fb.data_ptr()), _stream_ptr(stream, seeds)))
+    return labels, fb
+
+
+def micro_graph(labels, n: int, stream=None):
+    """Face adjacency bit matrix uint32 [n][(n+31)/32] (as int32) and
+    voxel counts [n] (as int64) of a device label grid."""
+    import torch
+    nz, ny, nx = labels.shape
+    W = (n + 31) // 32
+    adj = torch.empty((n, W), dtype=torch.int32, device=labels.device)
+    vol = torch.empty(n, dtype=torch.int64, device=labels.device)
+    check(_lib.lib().cpf_micro_graph(int(nx), int(ny), int(nz), ctypes.c_void_p(labels.data_ptr()), int(n),
+                                     ctypes.c_void_p(adj.data_ptr()), ctypes.c_void_p(vol.data_ptr()),
+                                     _stream_ptr(stream, labels)))
+    return adj, vol
+
+
+def micro_slabs(labels, q: int, n: int, slab_of, slabs, stream=None):
+    """Apply inclusion slabs in place: slab_of int32 [n] (-1 or slab
+    index), slabs float64 [m][8] (n0 n1 n2 x0 y0 z0 half child), device."""
+    nz, ny, nx = labels.shape
+    check(_lib.lib().cpf_micro_slabs(int(nx), int(ny), int(nz), int(q), ctypes.c_void_p(labels.data_ptr()),
+                                     int(n), ctypes.c_void_p(slab_of.data_ptr()), ctypes.c_void_p(slabs.data_ptr()),
+                                     _stream_ptr(stream, labels)))
+    return labels

@@ -77,7 +77,19 @@ class CpfStepOut(ctypes.Structure):
     ]
 
 
-# name -> (restype, argtypes); every symbol include/cpfft.h declares
+class CpfMicroParams(ctypes.Structure):
+    _fields_ = [("nx", _i), ("ny", _i), ("nz", _i), ("q", _i), ("lambda_", _d), ("r", _d),
+                ("p_neigh", _d), ("p_incl", _d), ("delta_lo", _d), ("delta_hi", _d), ("theta", _d),
+                ("seed", ctypes.c_uint64)]
+
+
+class CpfMicroInfo(ctypes.Structure):
+    _fields_ = [("n_primary", _i), ("n_grains", _i), ("n_neigh_drawn", _i), ("n_pairs", _i),
+                ("n_inclusions", _i), ("n_labels", _i), ("draws", ctypes.c_longlong),
+                ("fallback_tiles", _i)]
+
+
+# name -> (restype, argtypes); every symbol include/*.h declares
 SIGNATURES = {
     "cpf_version": (_i, []),
     "cpf_error_string": (ctypes.c_char_p, [_i]),
@@ -113,6 +125,13 @@ SIGNATURES = {
     "cpf_state_size": (_i, [_p, ctypes.POINTER(ctypes.c_size_t)]),
     "cpf_state_save": (_i, [_p, _p]),
     "cpf_state_restore": (_i, [_p, _p]),
+    "cpf_micro_workspace_size": (_i, [ctypes.POINTER(CpfMicroParams), ctypes.POINTER(ctypes.c_size_t)]),
+    "cpf_micro_generate": (_i, [ctypes.POINTER(CpfMicroParams), _p, ctypes.c_size_t, _p, _p, _i, _dp, _dp,
+                                _ip, ctypes.POINTER(CpfMicroInfo)]),
+    "cpf_micro_thin": (_i, [_i, _p, _i, _i, _i, _d, _p, _p]),
+    "cpf_micro_label": (_i, [_i, _i, _i, _i, _i, _p, _p, _p, _p]),
+    "cpf_micro_graph": (_i, [_i, _i, _i, _p, _i, _p, _p, _p]),
+    "cpf_micro_slabs": (_i, [_i, _i, _i, _i, _p, _i, _p, _p, _p]),
     "cpf_adjoint_last_stats": (_i, [_p, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong),
                                     ctypes.POINTER(_i)]),
 }

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libcpfft.so")
-SOURCES = ["cpfft_api.hip"]
+SOURCES = ["cpfft_api.hip", "cpfft_micro.hip"]
 HEADERS = ["cpfft_device.hpp", "cpfft_kernels.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

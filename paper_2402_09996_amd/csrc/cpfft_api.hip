@@ -67,6 +67,13 @@ extern "C" const char *cpf_error_string(int code)
 
 extern "C" const char *cpf_last_error_message(void) { return g_err.c_str(); }
 
+// for the microstructure entry points (another translation unit)
+int cpf_internal_fail(int code, const char *msg)
+{
+    g_err = msg;
+    return code;
+}
+
 extern "C" void cpf_options_default(cpf_options *o)
 {
     if (!o) return;

@@ -88,7 +88,7 @@ def test_voronoi_labels_against_periodic_kdtree():
 def test_voronoi_tie_goes_to_the_lowest_index():
     q = 16
     # two generators symmetric about the centre of voxel (2, 0, 0)
-    seeds = np.array([[40 + 24, 8, 8], [40 - 24, 8, 8], [40, 8, 8 + 200]])
+    seeds = np.array([[40 + 24, 8, 8], [40 - 24, 8, 8], [120, 8, 8]])
     lab = M.voronoi_labels((1, 1, 8), seeds, q)
     assert lab[0, 0, 2] == 0
     seeds2 = seeds[[1, 0, 2]]
