@@ -271,6 +271,53 @@ def green_leg(cp, w, KG, W, r32, K, nvox):
     return out
 
 
+def micro_leg(cp, n=256, grains=1920.0, r=5.0, reps=3):
+    """The stochastic microstructure model at the paper's window: 256^3
+    voxels, hard-core radius 5 voxels, 1920 expected grains (the primary
+    intensity from the type II relation lambda_h = (1 - exp(-lambda V_r)) /
+    V_r), the three twin configurations.  Wall time of a whole realization
+    (host draws and twin logic included), and the device time of the
+    Voronoi labelling alone (HIP events) for the same generator count."""
+    import numpy as np
+    import torch
+    Vr = 4.0 / 3.0 * math.pi * r ** 3
+    lam_h = grains / n ** 3
+    lam_p = -math.log(1.0 - lam_h * Vr) / Vr
+    theta = math.radians(69.79)
+    out = {"grid": [n, n, n], "r_voxels": r, "expected_grains": grains, "primary_lambda": lam_p,
+           "delta": [0.1, 0.3], "configs": {}}
+    for name, pn, pi in (("neighbouring", 1.0, 0.0), ("inclusion", 0.0, 1.0), ("none", 0.0, 0.0)):
+        best, g = None, None
+        for k in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            g = cp.generate_microstructure((n, n, n), lam_p, r, pn, pi, (0.1, 0.3), theta, 1000 + k)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            best = dt if best is None else min(best, dt)
+        out["configs"][name] = {"ms_per_realization": best * 1e3, "grains": g["n_grains"],
+                                "pairs": g["n_pairs"], "inclusions": g["n_inclusions"],
+                                "fallback_tiles": g["fallback_tiles"]}
+    # the labelling kernel alone, same generator count, events on the stream it runs on
+    q = 16
+    ng = out["configs"]["none"]["grains"]
+    rng = np.random.default_rng(5)
+    pts = np.zeros((ng, 4), np.int32)
+    pts[:, :3] = rng.integers(0, n * q, (ng, 3))
+    seeds = torch.from_numpy(pts).cuda()
+    cp.micro_label((n, n, n), q, seeds)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        cp.micro_label((n, n, n), q, seeds)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    out["label_kernel"] = {"ms": ms, "voxels_per_s": n ** 3 / (ms * 1e-3), "generators": ng,
+                           "label_write_GB/s": 4.0 * n ** 3 / (ms * 1e-3) / 1e9}
+    return out
+
+
 def histogram_leg(s32, nvox, reps=20, nbins=150, lo=0.0, hi=1500.0):
     """Distribution of the local von Mises stress of the committed 128^3
     state (post-processing after the timed steps): the stress pass (reads
@@ -316,6 +363,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--adjoint-steps", type=int, default=50)
+    ap.add_argument("--no-micro", action="store_true", help="skip the microstructure generator leg")
     ap.add_argument("--green-steps", type=int, default=None,
                     help="load steps of the rotated-operator FP32 leg (default: --steps)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -407,6 +455,8 @@ def main():
     if KG > 0:
         line["rotated_green"] = green_leg(cp, w, KG, min(W, 1), r32, K, nvox)
     line["seq_histogram"] = histogram_leg(s32, nvox)
+    if not args.no_micro:
+        line["microstructure"] = micro_leg(cp)
     if args.batch_steps > 0:
         line["batched"] = batch_leg(cp, args.batch_steps)
     if args.adjoint_steps > 0:

@@ -8,7 +8,7 @@
  *     live on a lattice of q points per voxel edge: integer coordinates in
  *     [0, q n_d); voxel (i, j, k) has centre (q i + q/2, q j + q/2,
  *     q k + q/2).  q is even and q * max(n_d) <= 65536, so squared
- *     minimum-image distances are exact 32-bit integers.
+ *     minimum-image distances are exact 32-bit integers; nx ny nz <= 2^31.
  *   - Labels are int32 [nz][ny][nx], x fastest (the solver's layout).
  *   - Rotations are row-major 3x3, crystal to lab (v_lab = O v_crystal).
  *   - Device pointers must be valid on the current HIP device; `stream` is
@@ -49,7 +49,7 @@ typedef struct cpf_micro_info {
     int n_inclusions;        /* inclusion twins made                           */
     int n_labels;            /* n_grains + n_inclusions                        */
     long long draws;         /* 64-bit words taken from the stream             */
-    int fallback_tiles;      /* tessellation tiles that searched every seed    */
+    int fallback_tiles;      /* 16^3 voxel groups whose candidate list overflowed */
 } cpf_micro_info;
 
 /* Device workspace for cpf_micro_generate (bytes; depends on the window,
@@ -107,9 +107,9 @@ int cpf_micro_thin(int n, const int32_t *dev_pts, int Lx, int Ly, int Lz, double
  * of Section 2.1): the generator at the least squared minimum-image
  * distance, the lowest index among equals.  dev_seeds: int32 [n][4],
  * coordinates in [0, q n_d); dev_labels: int32 [nz][ny][nx].
- * dev_fallback (may be NULL): int32 counter, incremented per tile whose
- * candidate list overflowed (those tiles search every generator; the
- * result is the same). */
+ * dev_fallback (may be NULL): int32 counter, incremented per 16^3 group
+ * of voxels whose candidate list overflowed (its tiles then search every
+ * generator; the result is the same). */
 int cpf_micro_label(int nx, int ny, int nz, int q, int n, const int32_t *dev_seeds, int32_t *dev_labels,
                     int32_t *dev_fallback, void *stream);
 

@@ -2,8 +2,8 @@
 // C-ABI of include/cpfft_micro.h.
 //
 // The voxel work runs in four kernels: Matern thinning of the primary
-// points, the periodic Voronoi labels (tiles of 8x8x8 voxels searching a
-// candidate list of generators), the grain graph with grain volumes, and
+// points, the periodic Voronoi labels (16^3 groups and 8^3 tiles searching
+// candidate lists of generators), the grain graph with grain volumes, and
 // the inclusion slabs.  The graph-level steps (drawing twin pairs and
 // orientations, one grain at a time from one random stream) run on the
 // host between the launches.
@@ -61,113 +61,152 @@ __device__ __forceinline__ unsigned int periodic_d2(int ax, int ay, int az, int 
 }
 
 // Matern type II with the index as the mark: i survives iff no j < i lies
-// within r (squared lattice distance <= r2).
+// within r (squared lattice distance <= r2).  One wave per point: the
+// lanes split the earlier points and vote.
 __global__ __launch_bounds__(256) void k_thin(const int4 *__restrict__ pts, int n, int Lx, int Ly, int Lz,
                                               double r2, uint8_t *__restrict__ keep)
 {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const int lane = threadIdx.x & 63;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i >= n) return;   // whole waves leave together
     const int4 p = pts[i];
-    bool k = true;
-    for (int j = 0; j < i && k; ++j) {
+    bool hit = false;
+    for (int j = lane; j < i; j += 64) {
         const int4 o = pts[j];
-        if ((double)periodic_d2(p.x, p.y, p.z, o.x, o.y, o.z, Lx, Ly, Lz) <= r2) k = false;
+        hit = hit || (double)periodic_d2(p.x, p.y, p.z, o.x, o.y, o.z, Lx, Ly, Lz) <= r2;
     }
-    keep[i] = k ? 1 : 0;
+    const bool any = __any(hit);
+    if (lane == 0) keep[i] = any ? 0 : 1;
 }
 
 constexpr int VT = 8;            // tile edge (voxels)
-constexpr int VCAP = 1024;       // candidate list capacity
-constexpr int VD2 = 4096;        // generators whose tile-centre distance is kept in LDS
+constexpr int VG = 2 * VT;       // group edge: 2x2x2 tiles per block
+constexpr int VCAP = 1024;       // tile candidate list capacity
+constexpr int VGCAP = 2048;      // group candidate list capacity
+constexpr int VD2 = 4096;        // generators whose group-centre distance is kept in LDS
 
-// One block per 8x8x8 tile, two voxels per thread.  With c the centre of
-// the tile's voxel centres, R the half diagonal of their box and D the
-// least distance from c to a generator, every voxel's nearest generators
-// (ties included) lie within D + 2R of c: the block collects those
-// candidates, then each voxel takes the least (squared distance, index)
-// among them.  Tiles with more candidates than the list holds search all
-// generators.
+// Candidate screening: for a box of voxel centres with centre c and half
+// diagonal R, and any generator at distance D from c, every voxel's nearest
+// generators (ties included) lie within D + 2R of c (|s - c| <= |s - v| +
+// R <= |s* - v| + R <= D + 2R).  Each block screens all generators once for
+// its 16^3 group (D the least distance found), then, for each 8^3 tile of
+// the group, the group's list (D the least distance over that list: an
+// upper bound of the true one, which keeps the argument valid); each voxel
+// takes the least (squared distance, index) over its tile's list.  A list
+// that overflows is replaced by the list it was taken from (the group's,
+// or all generators).
 __global__ __launch_bounds__(256) void k_voronoi(const int4 *__restrict__ seeds, int n, int nx, int ny, int nz,
-                                                 int q, int ntx, int nty, int32_t *__restrict__ labels,
+                                                 int q, int ngx, int ngy, int32_t *__restrict__ labels,
                                                  int32_t *fallback)
 {
-    __shared__ int4 cpos[VCAP];
-    __shared__ int cidx[VCAP];
     __shared__ unsigned int d2c[VD2];
+    __shared__ int gidx[VGCAP];
+    __shared__ int cidx[VCAP];
     __shared__ unsigned int dmin;
-    __shared__ int ncand;
+    __shared__ int ncnt;
     const int tid = threadIdx.x;
     const int b = blockIdx.x;
-    const int tx = b % ntx, ty = (b / ntx) % nty, tz = b / (ntx * nty);
-    const int x0 = tx * VT, y0 = ty * VT, z0 = tz * VT;
-    const int ex = min(VT, nx - x0), ey = min(VT, ny - y0), ez = min(VT, nz - z0);
+    const int gx = b % ngx, gy = (b / ngx) % ngy, gz = b / (ngx * ngy);
+    const int ox = gx * VG, oy = gy * VG, oz = gz * VG;
     const int Lx = q * nx, Ly = q * ny, Lz = q * nz;
     const int h = q / 2;
-    // tile centre: integer since q is even
-    const int cx = x0 * q + h + (ex - 1) * h, cy = y0 * q + h + (ey - 1) * h, cz = z0 * q + h + (ez - 1) * h;
-    if (tid == 0) {
-        dmin = 0xffffffffu;
-        ncand = 0;
-    }
-    __syncthreads();
-    unsigned int my = 0xffffffffu;
-    for (int j = tid; j < n; j += blockDim.x) {
-        const int4 s = seeds[j];
-        const unsigned int d2 = periodic_d2(cx, cy, cz, s.x, s.y, s.z, Lx, Ly, Lz);
-        if (j < VD2) d2c[j] = d2;
-        my = min(my, d2);
-    }
-    atomicMin(&dmin, my);
-    __syncthreads();
-    // D + 2R with a margin of 2 lattice units over the rounding of the roots
-    const double R = 0.5 * (double)q * sqrt((double)((ex - 1) * (ex - 1) + (ey - 1) * (ey - 1) + (ez - 1) * (ez - 1)));
-    const double bound = sqrt((double)dmin) + 2.0 * R + 2.0;
-    const double bound2 = bound * bound;
-    for (int j = tid; j < n; j += blockDim.x) {
-        const int4 s = seeds[j];
-        const unsigned int d2 = j < VD2 ? d2c[j] : periodic_d2(cx, cy, cz, s.x, s.y, s.z, Lx, Ly, Lz);
-        if ((double)d2 <= bound2) {
-            const int slot = atomicAdd(&ncand, 1);
-            if (slot < VCAP) {
-                cpos[slot] = s;
-                cidx[slot] = j;
+    auto radius = [&](int ex, int ey, int ez) {
+        return 0.5 * (double)q * sqrt((double)((ex - 1) * (ex - 1) + (ey - 1) * (ey - 1) + (ez - 1) * (ez - 1)));
+    };
+
+    // group list
+    {
+        const int ex = min(VG, nx - ox), ey = min(VG, ny - oy), ez = min(VG, nz - oz);
+        const int cx = ox * q + h + (ex - 1) * h, cy = oy * q + h + (ey - 1) * h, cz = oz * q + h + (ez - 1) * h;
+        if (tid == 0) {
+            dmin = 0xffffffffu;
+            ncnt = 0;
+        }
+        __syncthreads();
+        unsigned int my = 0xffffffffu;
+        for (int j = tid; j < n; j += blockDim.x) {
+            const int4 s = seeds[j];
+            const unsigned int d2 = periodic_d2(cx, cy, cz, s.x, s.y, s.z, Lx, Ly, Lz);
+            if (j < VD2) d2c[j] = d2;
+            my = min(my, d2);
+        }
+        atomicMin(&dmin, my);
+        __syncthreads();
+        // a margin of 2 lattice units over the rounding of the roots
+        const double bd = sqrt((double)dmin) + 2.0 * radius(ex, ey, ez) + 2.0;
+        const double b2 = bd * bd;
+        for (int j = tid; j < n; j += blockDim.x) {
+            unsigned int d2;
+            if (j < VD2) {
+                d2 = d2c[j];
+            } else {
+                const int4 s = seeds[j];
+                d2 = periodic_d2(cx, cy, cz, s.x, s.y, s.z, Lx, Ly, Lz);
+            }
+            if ((double)d2 <= b2) {
+                const int slot = atomicAdd(&ncnt, 1);
+                if (slot < VGCAP) gidx[slot] = j;
             }
         }
+        __syncthreads();
     }
-    __syncthreads();
-    const int nc = ncand;
-    const bool full = nc > VCAP;
-    if (full && tid == 0 && fallback) atomicAdd(fallback, 1);
+    const int ng = ncnt;
+    const bool gfull = ng > VGCAP;
+    const int nl = gfull ? n : ng;             // the list the tiles screen
+    if (gfull && tid == 0 && fallback) atomicAdd(fallback, 1);
+
     const int lx = tid & 7, ly = (tid >> 3) & 7, lz0 = tid >> 6;
+    for (int t = 0; t < 8; ++t) {
+        const int x0 = ox + (t & 1) * VT, y0 = oy + ((t >> 1) & 1) * VT, z0 = oz + (t >> 2) * VT;
+        if (x0 >= nx || y0 >= ny || z0 >= nz) continue;   // uniform over the block
+        const int ex = min(VT, nx - x0), ey = min(VT, ny - y0), ez = min(VT, nz - z0);
+        const int cx = x0 * q + h + (ex - 1) * h, cy = y0 * q + h + (ey - 1) * h, cz = z0 * q + h + (ez - 1) * h;
+        __syncthreads();   // the previous tile's list is no longer read
+        if (tid == 0) {
+            dmin = 0xffffffffu;
+            ncnt = 0;
+        }
+        __syncthreads();
+        unsigned int my = 0xffffffffu;
+        for (int k = tid; k < nl; k += blockDim.x) {
+            const int4 s = seeds[gfull ? k : gidx[k]];
+            my = min(my, periodic_d2(cx, cy, cz, s.x, s.y, s.z, Lx, Ly, Lz));
+        }
+        atomicMin(&dmin, my);
+        __syncthreads();
+        const double bd = sqrt((double)dmin) + 2.0 * radius(ex, ey, ez) + 2.0;
+        const double b2 = bd * bd;
+        for (int k = tid; k < nl; k += blockDim.x) {
+            const int j = gfull ? k : gidx[k];
+            const int4 s = seeds[j];
+            if ((double)periodic_d2(cx, cy, cz, s.x, s.y, s.z, Lx, Ly, Lz) <= b2) {
+                const int slot = atomicAdd(&ncnt, 1);
+                if (slot < VCAP) cidx[slot] = j;
+            }
+        }
+        __syncthreads();
+        const int nc = ncnt;
+        const bool tfull = nc > VCAP;
+        const int nv = tfull ? nl : nc;
 #pragma unroll
-    for (int v = 0; v < 2; ++v) {
-        const int lz = lz0 + 4 * v;
-        if (lx >= ex || ly >= ey || lz >= ez) continue;
-        const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-        const int px = x * q + h, py = y * q + h, pz = z * q + h;
-        unsigned int best = 0xffffffffu;
-        int bi = 0x7fffffff;
-        if (!full) {
-            for (int k = 0; k < nc; ++k) {
-                const int4 s = cpos[k];
+        for (int v = 0; v < 2; ++v) {
+            const int lz = lz0 + 4 * v;
+            if (lx >= ex || ly >= ey || lz >= ez) continue;
+            const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+            const int px = x * q + h, py = y * q + h, pz = z * q + h;
+            unsigned int best = 0xffffffffu;
+            int bi = 0x7fffffff;
+            for (int k = 0; k < nv; ++k) {
+                const int j = tfull ? (gfull ? k : gidx[k]) : cidx[k];
+                const int4 s = seeds[j];
                 const unsigned int d2 = periodic_d2(px, py, pz, s.x, s.y, s.z, Lx, Ly, Lz);
-                const int j = cidx[k];
                 if (d2 < best || (d2 == best && j < bi)) {
                     best = d2;
                     bi = j;
                 }
             }
-        } else {
-            for (int j = 0; j < n; ++j) {
-                const int4 s = seeds[j];
-                const unsigned int d2 = periodic_d2(px, py, pz, s.x, s.y, s.z, Lx, Ly, Lz);
-                if (d2 < best) {   // ascending j: the first minimum is the lowest index
-                    best = d2;
-                    bi = j;
-                }
-            }
+            labels[((long)z * ny + y) * nx + x] = bi;
         }
-        labels[((long)z * ny + y) * nx + x] = bi;
     }
 }
 
@@ -199,14 +238,42 @@ __global__ __launch_bounds__(256) void k_graph(const int32_t *__restrict__ lab, 
     }
     const long nvox = (long)nx * ny * nz;
     const long v0 = (long)blockIdx.x * chunk, v1 = min(nvox, v0 + chunk);
-    for (long v = v0 + tid; v < v1; v += blockDim.x) {
-        const int x = (int)(v % nx);
+    // coordinates of the first voxel once, then advanced by the stride
+    // with 32-bit carries (no 64-bit division in the loop)
+    int x = 0, y = 0, z = 0;
+    if (v0 + tid < v1) {
+        const long v = v0 + tid;
+        x = (int)(v % nx);
         const long r = v / nx;
-        const int y = (int)(r % ny), z = (int)(r / ny);
+        y = (int)(r % ny);
+        z = (int)(r / ny);
+    }
+    for (long v = v0 + tid; v < v1; v += blockDim.x) {
+        if (v != v0 + tid) {
+            x += (int)blockDim.x;
+            const unsigned cx = (unsigned)x / (unsigned)nx;
+            x -= (int)(cx * nx);
+            y += (int)cx;
+            const unsigned cy = (unsigned)y / (unsigned)ny;
+            y -= (int)(cy * ny);
+            z += (int)cy;
+        }
         const int g = lab[v];
-        if ((unsigned)g >= (unsigned)n) continue;   // labels outside [0, n) are not counted
-        if (lds_counts) atomicAdd(&cnt[g], 1u);
-        else atomicAdd(&vol[g], 1ull);
+        const bool ok = (unsigned)g < (unsigned)n;   // labels outside [0, n) are not counted
+        // one counter update for a wave whose voxels share a label (the
+        // common case inside grains), else one per lane
+        const int g0 = __shfl(g, 0);
+        const unsigned c = (unsigned)__popcll(__ballot(1));   // active lanes (a prefix of the wave)
+        if (__all(g == g0)) {
+            if ((threadIdx.x & 63) == 0 && ok) {
+                if (lds_counts) atomicAdd(&cnt[g], c);
+                else atomicAdd(&vol[g], (unsigned long long)c);
+            }
+        } else if (ok) {
+            if (lds_counts) atomicAdd(&cnt[g], 1u);
+            else atomicAdd(&vol[g], 1ull);
+        }
+        if (!ok) continue;
         const long nbx = v - x + (x + 1 == nx ? 0 : x + 1);
         const long nby = v + (long)((y + 1 == ny ? 0 : y + 1) - y) * nx;
         const long nbz = v + (long)((z + 1 == nz ? 0 : z + 1) - z) * nx * ny;
@@ -232,17 +299,18 @@ __global__ __launch_bounds__(256) void k_slabs(int32_t *__restrict__ lab, int nx
                                                const int32_t *__restrict__ slab_of,
                                                const double *__restrict__ slabs)
 {
-    const long nvox = (long)nx * ny * nz;
-    const long v = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (v >= nvox) return;
+    // grid: x covers one z plane, y the planes
+    const unsigned plane = (unsigned)nx * (unsigned)ny;
+    const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= plane) return;
+    const int z = (int)blockIdx.y;
+    const long v = (long)z * plane + i;
     const int g = lab[v];
     if (g < 0 || g >= n) return;
     const int s = slab_of[g];
     if (s < 0) return;
     const double *S = slabs + 8 * (long)s;
-    const int x = (int)(v % nx);
-    const long r = v / nx;
-    const int y = (int)(r % ny), z = (int)(r / ny);
+    const int x = (int)(i % (unsigned)nx), y = (int)(i / (unsigned)nx);
     const double c[3] = {(double)(x * q + q / 2), (double)(y * q + q / 2), (double)(z * q + q / 2)};
     const double L[3] = {(double)q * nx, (double)q * ny, (double)q * nz};
     double d[3];
@@ -410,7 +478,8 @@ struct P4 {
 static bool params_ok(const cpf_micro_params *p)
 {
     return p && p->nx >= 1 && p->ny >= 1 && p->nz >= 1 && p->q >= 2 && (p->q & 1) == 0 &&
-           (long)p->q * std::max(p->nx, std::max(p->ny, p->nz)) <= 65536 && p->lambda >= 0.0 &&
+           (long)p->q * std::max(p->nx, std::max(p->ny, p->nz)) <= 65536 &&
+           (long)p->nx * p->ny * p->nz <= (1L << 31) && p->lambda >= 0.0 &&
            std::isfinite(p->lambda) && p->r >= 0.0 && std::isfinite(p->r) && p->p_neigh >= 0.0 &&
            p->p_neigh <= 1.0 && p->p_incl >= 0.0 && p->p_incl <= 1.0 && p->delta_lo >= 0.0 &&
            p->delta_lo <= p->delta_hi && p->delta_hi <= 1.0 && p->theta > 0.0 && p->theta < M_PI;
@@ -449,10 +518,10 @@ static WsLayout ws_layout(const cpf_micro_params *p)
 static int launch_label(int nx, int ny, int nz, int q, int n, const int32_t *seeds, int32_t *labels, int32_t *fb,
                         hipStream_t st)
 {
-    const int ntx = (nx + VT - 1) / VT, nty = (ny + VT - 1) / VT, ntz = (nz + VT - 1) / VT;
-    const long blocks = (long)ntx * nty * ntz;
+    const int ngx = (nx + VG - 1) / VG, ngy = (ny + VG - 1) / VG, ngz = (nz + VG - 1) / VG;
+    const long blocks = (long)ngx * ngy * ngz;   // < 2^31: at most 2^31 voxels
     hipLaunchKernelGGL(k_voronoi, dim3((unsigned)blocks), dim3(256), 0, st, (const int4 *)seeds, n, nx, ny, nz, q,
-                       ntx, nty, labels, fb);
+                       ngx, ngy, labels, fb);
     MCHK(hipGetLastError());
     return CPF_OK;
 }
@@ -491,7 +560,7 @@ extern "C" int cpf_micro_thin(int n, const int32_t *dev_pts, int Lx, int Ly, int
         Lz > 65536 || !(r_q >= 0.0) || !std::isfinite(r_q))
         return failf(CPF_E_INVALID_ARG, "cpf_micro_thin: bad arguments");
     if (n == 0) return CPF_OK;
-    hipLaunchKernelGGL(k_thin, dim3((n + 255) / 256), dim3(256), 0, (hipStream_t)stream, (const int4 *)dev_pts, n,
+    hipLaunchKernelGGL(k_thin, dim3((n + 3) / 4), dim3(256), 0, (hipStream_t)stream, (const int4 *)dev_pts, n,
                        Lx, Ly, Lz, r_q * r_q, dev_keep);
     MCHK(hipGetLastError());
     return CPF_OK;
@@ -501,7 +570,7 @@ extern "C" int cpf_micro_label(int nx, int ny, int nz, int q, int n, const int32
                                int32_t *dev_fallback, void *stream)
 {
     if (nx < 1 || ny < 1 || nz < 1 || q < 2 || (q & 1) || (long)q * std::max(nx, std::max(ny, nz)) > 65536 ||
-        n < 1 || !dev_seeds || !dev_labels)
+        (long)nx * ny * nz > (1L << 31) || n < 1 || !dev_seeds || !dev_labels)
         return failf(CPF_E_INVALID_ARG, "cpf_micro_label: bad arguments");
     return launch_label(nx, ny, nz, q, n, dev_seeds, dev_labels, dev_fallback, (hipStream_t)stream);
 }
@@ -517,11 +586,12 @@ extern "C" int cpf_micro_graph(int nx, int ny, int nz, const int32_t *dev_labels
 extern "C" int cpf_micro_slabs(int nx, int ny, int nz, int q, int32_t *dev_labels, int n, const int32_t *dev_slab_of,
                                const double *dev_slabs, void *stream)
 {
-    if (nx < 1 || ny < 1 || nz < 1 || q < 2 || (q & 1) || n < 1 || !dev_labels || !dev_slab_of || !dev_slabs)
+    if (nx < 1 || ny < 1 || nz < 1 || q < 2 || (q & 1) || (long)nx * ny * nz > (1L << 31) || n < 1 ||
+        !dev_labels || !dev_slab_of || !dev_slabs)
         return failf(CPF_E_INVALID_ARG, "cpf_micro_slabs: bad arguments");
-    const long nvox = (long)nx * ny * nz;
-    hipLaunchKernelGGL(k_slabs, dim3((unsigned)((nvox + 255) / 256)), dim3(256), 0, (hipStream_t)stream,
-                       dev_labels, nx, ny, nz, q, n, dev_slab_of, dev_slabs);
+    const long plane = (long)nx * ny;
+    hipLaunchKernelGGL(k_slabs, dim3((unsigned)((plane + 255) / 256), (unsigned)nz), dim3(256), 0,
+                       (hipStream_t)stream, dev_labels, nx, ny, nz, q, n, dev_slab_of, dev_slabs);
     MCHK(hipGetLastError());
     return CPF_OK;
 }
@@ -556,7 +626,7 @@ extern "C" int cpf_micro_generate(const cpf_micro_params *p, void *dev_workspace
     info->n_primary = np;
     if (np < 1) return failf(CPF_E_INVALID_ARG, "the primary process drew no point (lambda too small)");
     MCHK(hipMemcpyAsync(ws + L.pts, pts.data(), sizeof(P4) * np, hipMemcpyHostToDevice, st));
-    hipLaunchKernelGGL(k_thin, dim3((np + 255) / 256), dim3(256), 0, st, (const int4 *)(ws + L.pts), np, Lx, Ly,
+    hipLaunchKernelGGL(k_thin, dim3((np + 3) / 4), dim3(256), 0, st, (const int4 *)(ws + L.pts), np, Lx, Ly,
                        Lz, (p->r * q) * (p->r * q), (uint8_t *)(ws + L.keep));
     MCHK(hipGetLastError());
     std::vector<uint8_t> keep(np);
@@ -588,7 +658,13 @@ extern "C" int cpf_micro_generate(const cpf_micro_params *p, void *dev_workspace
     MCHK(hipMemcpyAsync(&nfb, fb, sizeof nfb, hipMemcpyDeviceToHost, st));
     MCHK(hipStreamSynchronize(st));
     info->fallback_tiles = nfb;
-    auto adjacent = [&](int a, int b) { return (adj[(size_t)a * W + (b >> 5)] >> (b & 31)) & 1u; };
+    // neighbour lists, ascending, and the number of free neighbours
+    std::vector<std::vector<int>> nbrs(nw);
+    for (int a = 0; a < nw; ++a)
+        for (int b = 0; b < nw; ++b)
+            if ((adj[(size_t)a * W + (b >> 5)] >> (b & 31)) & 1u) nbrs[a].push_back(b);
+    std::vector<int> free_nb(nw);
+    for (int a = 0; a < nw; ++a) free_nb[a] = (int)nbrs[a].size();
 
     // neighbouring twins
     std::vector<M3> rot(nw);
@@ -600,19 +676,13 @@ extern "C" int cpf_micro_generate(const cpf_micro_params *p, void *dev_workspace
         std::vector<int> cand, nb;
         while (npairs < nn) {
             cand.clear();
-            for (int k = 0; k < nw; ++k) {
-                if (assigned[k]) continue;
-                for (int m = 0; m < nw; ++m)
-                    if (!assigned[m] && adjacent(k, m)) {
-                        cand.push_back(k);
-                        break;
-                    }
-            }
+            for (int k = 0; k < nw; ++k)
+                if (!assigned[k] && free_nb[k] > 0) cand.push_back(k);
             if (cand.empty()) break;
             const int k = cand[rs.below((uint32_t)cand.size())];
             nb.clear();
-            for (int m = 0; m < nw; ++m)
-                if (!assigned[m] && adjacent(k, m)) nb.push_back(m);
+            for (int m : nbrs[k])
+                if (!assigned[m]) nb.push_back(m);
             const int l = nb[rs.below((uint32_t)nb.size())];
             const int a = rs.below(2);
             const double psi = 2.0 * M_PI * rs.uniform();
@@ -634,6 +704,8 @@ extern "C" int cpf_micro_generate(const cpf_micro_params *p, void *dev_workspace
             rot[k] = Ok;
             rot[l] = twin_of(Ok, a, p->theta);
             assigned[k] = assigned[l] = 1;
+            for (int m : nbrs[k]) --free_nb[m];
+            for (int m : nbrs[l]) --free_nb[m];
             if (pairs_out && npairs < max_labels / 2) {
                 pairs_out[3 * npairs] = k;
                 pairs_out[3 * npairs + 1] = l;
@@ -705,9 +777,10 @@ extern "C" int cpf_micro_generate(const cpf_micro_params *p, void *dev_workspace
     if (ninc > 0) {
         MCHK(hipMemcpyAsync(ws + L.slab_of, slab_of.data(), sizeof(int32_t) * nw, hipMemcpyHostToDevice, st));
         MCHK(hipMemcpyAsync(ws + L.slabs, slabs.data(), sizeof(double) * slabs.size(), hipMemcpyHostToDevice, st));
-        const long nvox = (long)nx * ny * nz;
-        hipLaunchKernelGGL(k_slabs, dim3((unsigned)((nvox + 255) / 256)), dim3(256), 0, st, dev_labels, nx, ny, nz,
-                           q, nw, (const int32_t *)(ws + L.slab_of), (const double *)(ws + L.slabs));
+        const long plane = (long)nx * ny;
+        hipLaunchKernelGGL(k_slabs, dim3((unsigned)((plane + 255) / 256), (unsigned)nz), dim3(256), 0, st,
+                           dev_labels, nx, ny, nz, q, nw, (const int32_t *)(ws + L.slab_of),
+                           (const double *)(ws + L.slabs));
         MCHK(hipGetLastError());
     }
     MCHK(hipStreamSynchronize(st));
