@@ -364,6 +364,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--adjoint-steps", type=int, default=50)
     ap.add_argument("--no-micro", action="store_true", help="skip the microstructure generator leg")
+    ap.add_argument("--micro-only", action="store_true", help="only run the microstructure generator leg")
     ap.add_argument("--green-steps", type=int, default=None,
                     help="load steps of the rotated-operator FP32 leg (default: --steps)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -371,6 +372,10 @@ def main():
     args = ap.parse_args()
     if args.copy_probe:
         copy_probe()
+        return
+    if args.micro_only:
+        import paper_2402_09996_amd as cp
+        print(json.dumps({"microstructure": micro_leg(cp)}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path "
