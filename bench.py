@@ -33,7 +33,7 @@ FP64_PEAK_TFLOPS = 78.6
 # HBM bytes per launch of the x pass (the dominant kernel) at 128^3 FP32,
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy (factors
 # 0.5 and 1.0); valid only for the library sources they were taken on.
-XPASS_TRAFFIC = {"src": "ade857985906053b", "read_bytes": 632.2e6, "write_bytes": 579.6e6}
+XPASS_TRAFFIC = {"src": "4abb907e8e778b86", "read_bytes": 632.2e6, "write_bytes": 579.6e6}
 
 
 def library_source_hash() -> str:
@@ -318,6 +318,54 @@ def micro_leg(cp, n=256, grains=1920.0, r=5.0, reps=3):
     return out
 
 
+def paper_leg(cp, steps=100, configs=("neighbouring",), n=256, seed=7, axes=(0,)):
+    """The paper's parameter set (tetragonal stiffness, Table 1 with tau0
+    130/200/130 MPa, twin-fraction law; b = 10, q = 1) on a generated 256^3
+    realization (1920 expected grains, r = 5 voxels), FP32: uniaxial
+    shortening along x (or y, z) to 0.5 % at 1e-3 /s in ``steps`` load
+    steps (the paper uses 1000).  Per configuration and axis: load-step
+    time, throughput and the von Mises stress of the mean stress at ten
+    points of the curve."""
+    import numpy as np
+    import torch
+    import rvegen
+    Vr = 4.0 / 3.0 * math.pi * 5.0 ** 3
+    lam_p = -math.log(1.0 - 1920.0 / n ** 3 * Vr) / Vr
+    C, law = rvegen.paper_law()
+    S = rvegen.table1_systems(True)
+    out = {"grid": [n, n, n], "steps": steps, "total_strain": -0.005, "precision": "fp32", "configs": {}}
+    for name, axis in [(c, a) for c in configs for a in axes]:
+        path = rvegen.uniaxial_path(-0.005, steps, axis=axis)
+        pn, pi = {"neighbouring": (1.0, 0.0), "inclusion": (0.0, 1.0), "none": (0.0, 0.0)}[name]
+        g = cp.generate_microstructure((n, n, n), lam_p, 5.0, pn, pi, (0.1, 0.3), math.radians(69.79), seed)
+        prob = cp.Problem(g["labels"].cpu().numpy(), g["euler"], C, S.n_miller, S.l_miller, S.family, S.tau0,
+                          law)
+        s = cp.Solver(prob, precision="fp32", tol=1e-6, stag_tol=1e-4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        iters, seq = 0, []
+        for k in range(steps):
+            o = s.step(path, k)
+            iters += int(o["iters"])
+            seq.append(float(o["sig_eq_of_mean"]))
+            if k % 10 == 9:
+                print("[bench] paper %s axis %d step %d iters %d sigma_eq %.2f" % (name, axis, k, o["iters"],
+                                                                                    seq[-1]),
+                      file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        pick = [int(round((j + 1) * steps / 10)) - 1 for j in range(10)]
+        out["configs"][name + ("" if tuple(axes) == (0,) else "_" + "xyz"[axis])] = {
+            "labels": int(g["n_labels"]), "pairs": int(g["n_pairs"]), "inclusions": int(g["n_inclusions"]),
+            "iterations": iters, "ms_per_step": wall / steps * 1e3,
+            "voxel_iterations_per_s": iters * n ** 3 / wall,
+            "curve": [[0.5 * (j + 1) / 10, seq[k]] for j, k in enumerate(pick)],
+            "final_mean_f": float(o["mean_f"]), "final_mean_v": float(o["mean_v"])}
+        del s, prob, g
+        torch.cuda.empty_cache()
+    return out
+
+
 def histogram_leg(s32, nvox, reps=20, nbins=150, lo=0.0, hi=1500.0):
     """Distribution of the local von Mises stress of the committed 128^3
     state (post-processing after the timed steps): the stress pass (reads
@@ -365,6 +413,12 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=50)
     ap.add_argument("--no-micro", action="store_true", help="skip the microstructure generator leg")
     ap.add_argument("--micro-only", action="store_true", help="only run the microstructure generator leg")
+    ap.add_argument("--paper-steps", type=int, default=100,
+                    help="load steps of the paper-parameter 256^3 leg (0: skip)")
+    ap.add_argument("--paper-configs", default="neighbouring",
+                    help="twin configurations of that leg: comma list of none,neighbouring,inclusion or 'all'")
+    ap.add_argument("--paper-only", action="store_true", help="only run the paper-parameter leg")
+    ap.add_argument("--paper-axes", default="x", help="load axis of that leg: x or 'all' (x, y, z)")
     ap.add_argument("--green-steps", type=int, default=None,
                     help="load steps of the rotated-operator FP32 leg (default: --steps)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -376,6 +430,13 @@ def main():
     if args.micro_only:
         import paper_2402_09996_amd as cp
         print(json.dumps({"microstructure": micro_leg(cp)}), flush=True)
+        return
+    if args.paper_only:
+        import paper_2402_09996_amd as cp
+        cf = ("none", "neighbouring", "inclusion") if args.paper_configs == "all" else \
+            tuple(args.paper_configs.split(","))
+        ax = (0, 1, 2) if args.paper_axes == "all" else (0,)
+        print(json.dumps({"paper_set": paper_leg(cp, args.paper_steps, cf, axes=ax)}), flush=True)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path "
@@ -462,6 +523,10 @@ def main():
     line["seq_histogram"] = histogram_leg(s32, nvox)
     if not args.no_micro:
         line["microstructure"] = micro_leg(cp)
+    if args.paper_steps > 0:
+        cf = ("none", "neighbouring", "inclusion") if args.paper_configs == "all" else \
+            tuple(args.paper_configs.split(","))
+        line["paper_set"] = paper_leg(cp, args.paper_steps, cf)
     if args.batch_steps > 0:
         line["batched"] = batch_leg(cp, args.batch_steps)
     if args.adjoint_steps > 0:
