@@ -366,6 +366,34 @@ def paper_leg(cp, steps=100, configs=("neighbouring",), n=256, seed=7, axes=(0,)
     return out
 
 
+def eta_leg(cp, etas=(1e2, 1e3, 2e3, 5e3, 1e4, 3e4, 1e5, 3e5, 1e6)):
+    """Fig. 3 analogue: yield stress of a single-crystal material point (a
+    one-orientation 2x2x2 RVE, Bunge (0.3, 0.7, 1.1)) against eta, FP64,
+    paper parameter set, tension along x at 1e-3 /s to 0.5 % in 20 steps of
+    one RK4 step each; yield at 0.02 % axial plastic strain.  Too small an
+    eta diverges (reported as null)."""
+    import numpy as np
+    import rvegen
+    out = {"steps": 20, "rk4_substeps": 1, "offset": 2e-4, "yield_MPa": {}}
+    for eta in etas:
+        C, law = rvegen.paper_law()
+        law.eta = eta
+        S = rvegen.table1_systems(True)
+        prob = cp.Problem(np.zeros((2, 2, 2), np.int32), np.array([[0.3, 0.7, 1.1]]), C, S.n_miller,
+                          S.l_miller, S.family, S.tau0, law)
+        try:
+            R = cp.Solver(prob, precision="fp64", tol=1e-12, rk4_M=1).run(rvegen.uniaxial_path(0.005, 20))
+        except cp.CpfError:
+            out["yield_MPa"]["%g" % eta] = None
+            continue
+        E11, S11 = R["E"][:, 0], R["Sigma"][:, 0]
+        ep = E11 - S11 / (S11[0] / E11[0])
+        k = int(np.argmax(ep >= 2e-4))
+        a = (2e-4 - ep[k - 1]) / (ep[k] - ep[k - 1])
+        out["yield_MPa"]["%g" % eta] = float(S11[k - 1] + a * (S11[k] - S11[k - 1]))
+    return out
+
+
 def histogram_leg(s32, nvox, reps=20, nbins=150, lo=0.0, hi=1500.0):
     """Distribution of the local von Mises stress of the committed 128^3
     state (post-processing after the timed steps): the stress pass (reads
@@ -429,7 +457,7 @@ def main():
         return
     if args.micro_only:
         import paper_2402_09996_amd as cp
-        print(json.dumps({"microstructure": micro_leg(cp)}), flush=True)
+        print(json.dumps({"microstructure": micro_leg(cp), "eta_sweep": eta_leg(cp)}), flush=True)
         return
     if args.paper_only:
         import paper_2402_09996_amd as cp
@@ -523,6 +551,7 @@ def main():
     line["seq_histogram"] = histogram_leg(s32, nvox)
     if not args.no_micro:
         line["microstructure"] = micro_leg(cp)
+        line["eta_sweep"] = eta_leg(cp)
     if args.paper_steps > 0:
         cf = ("none", "neighbouring", "inclusion") if args.paper_configs == "all" else \
             tuple(args.paper_configs.split(","))
