@@ -115,6 +115,12 @@ static bool radix_plan(int n, FftPlan &P)
     if (r % 4 == 0) { P.radix[P.npass++] = 4; r /= 4; }
     if (r % 2 == 0) { P.radix[P.npass++] = 2; r /= 2; }
     while (r % 3 == 0 && P.npass < MAXPASS) { P.radix[P.npass++] = 3; r /= 3; }
+    int ns = 1;
+    for (int p = 0; p < P.npass; ++p) {
+        P.mag_m[p] = fdiv_magic((unsigned)(n / P.radix[p]));
+        P.mag_ns[p] = fdiv_magic((unsigned)ns);
+        ns *= P.radix[p];
+    }
     return r == 1 && n >= 2;
 }
 

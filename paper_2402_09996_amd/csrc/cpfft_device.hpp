@@ -32,10 +32,18 @@ __device__ __forceinline__ C2<R> rot90(C2<R> a)
     return INV ? C2<R>{-a.y, a.x} : C2<R>{a.y, -a.x};
 }
 
+// Exact quotients by a multiply-high: for 0 <= n < 2^16 and 2 <= d < 2^16,
+// floor(n / d) = (n M) >> 32 with M = ceil(2^32 / d) (the rounding error
+// n (M d - 2^32) / (d 2^32) stays below 1/d).  M = 0 stands for d = 1.
+__host__ __device__ __forceinline__ unsigned fdiv_magic(unsigned d) { return d <= 1u ? 0u : 0xFFFFFFFFu / d + 1u; }
+__device__ __forceinline__ unsigned fdiv(unsigned n, unsigned M) { return M ? __umulhi(n, M) : n; }
+
 struct FftPlan {
     int n;
     int npass;
     int radix[MAXPASS];
+    unsigned mag_m[MAXPASS];   // fdiv_magic(n / radix[p])
+    unsigned mag_ns[MAXPASS];  // fdiv_magic(product of the radices before pass p)
 };
 
 // ---------------------------------------------------------------------------
@@ -115,8 +123,8 @@ __device__ __forceinline__ void dft(C2<R> *v)
 // tw[k] = exp(-2 pi i k / N).
 // ---------------------------------------------------------------------------
 template <typename R, bool INV, int RAD, int MAXB>
-__device__ __forceinline__ void fft_pass(C2<R> *buf, int nlines, int ls, int N, int Ns,
-                                         const C2<R> *__restrict__ tw, int tid, int nthr)
+__device__ __forceinline__ void fft_pass(C2<R> *buf, int nlines, int ls, int N, int Ns, unsigned mag_m,
+                                         unsigned mag_ns, const C2<R> *__restrict__ tw, int tid, int nthr)
 {
     const int m = N / RAD;
     const int nb = nlines * m;
@@ -126,7 +134,7 @@ __device__ __forceinline__ void fft_pass(C2<R> *buf, int nlines, int ls, int N, 
     for (int b = 0; b < MAXB; ++b) {
         const int i = tid + b * nthr;
         if (i < nb) {
-            const int line = i / m, j = i - line * m;
+            const int line = (int)fdiv((unsigned)i, mag_m), j = i - line * m;
             const C2<R> *src = buf + line * ls + j;
 #pragma unroll
             for (int q = 0; q < RAD; ++q) v[b][q] = src[q * m];
@@ -137,8 +145,8 @@ __device__ __forceinline__ void fft_pass(C2<R> *buf, int nlines, int ls, int N, 
     for (int b = 0; b < MAXB; ++b) {
         const int i = tid + b * nthr;
         if (i < nb) {
-            const int line = i / m, j = i - line * m;
-            const int k = j % Ns;
+            const int line = (int)fdiv((unsigned)i, mag_m), j = i - line * m;
+            const int k = j - (int)fdiv((unsigned)j, mag_ns) * Ns;
             if (k) {
 #pragma unroll
                 for (int q = 1; q < RAD; ++q) {
@@ -166,14 +174,15 @@ __device__ void lds_fft(C2<R> *buf, int nlines, int ls, const FftPlan &P,
     int Ns = 1;
     for (int p = 0; p < P.npass; ++p) {
         const int r = P.radix[p];
+        const unsigned mm = P.mag_m[p], mn = P.mag_ns[p];
         if (r == 8)
-            fft_pass<R, INV, 8, (EPT + 7) / 8>(buf, nlines, ls, P.n, Ns, tw, tid, nthr);
+            fft_pass<R, INV, 8, (EPT + 7) / 8>(buf, nlines, ls, P.n, Ns, mm, mn, tw, tid, nthr);
         else if (r == 4)
-            fft_pass<R, INV, 4, (EPT + 3) / 4>(buf, nlines, ls, P.n, Ns, tw, tid, nthr);
+            fft_pass<R, INV, 4, (EPT + 3) / 4>(buf, nlines, ls, P.n, Ns, mm, mn, tw, tid, nthr);
         else if (r == 3)
-            fft_pass<R, INV, 3, (EPT + 2) / 3>(buf, nlines, ls, P.n, Ns, tw, tid, nthr);
+            fft_pass<R, INV, 3, (EPT + 2) / 3>(buf, nlines, ls, P.n, Ns, mm, mn, tw, tid, nthr);
         else
-            fft_pass<R, INV, 2, (EPT + 1) / 2>(buf, nlines, ls, P.n, Ns, tw, tid, nthr);
+            fft_pass<R, INV, 2, (EPT + 1) / 2>(buf, nlines, ls, P.n, Ns, mm, mn, tw, tid, nthr);
         Ns *= r;
     }
 }

@@ -430,14 +430,15 @@ __global__ __launch_bounds__(256) void k_ypass(const RveDev<R> *__restrict__ rv,
     // twiddles after the tile (the launch adds ny entries of LDS)
     C2<R> *twl = buf + (size_t)d.ty * ls;
     for (int i = tid; i < ny; i += nthr) twl[i] = d.tw[1][i];
+    const unsigned mt = fdiv_magic((unsigned)tw_);   // indices stay below 2^16
     for (int i = tid; i < ny * tw_; i += nthr) {
-        const int y = i / tw_, col = i - y * tw_;
+        const int y = (int)fdiv((unsigned)i, mt), col = i - y * tw_;
         buf[col * ls + y] = g[(long)y * nhp + col];
     }
     __syncthreads();
     lds_fft<R, INV, EPT>(buf, tw_, ls, d.py, twl, tid, nthr);
     for (int i = tid; i < ny * tw_; i += nthr) {
-        const int y = i / tw_, col = i - y * tw_;
+        const int y = (int)fdiv((unsigned)i, mt), col = i - y * tw_;
         g[(long)y * nhp + col] = buf[col * ls + y];
     }
 }
@@ -555,17 +556,19 @@ __global__ __launch_bounds__(256) void k_zpass_green(const RveDev<R> *__restrict
     // twiddles after the tile (the launch adds nz entries of LDS)
     C2<R> *twl = buf + (size_t)6 * d.tz * ls;
     for (int i = tid; i < nz; i += nthr) twl[i] = d.tw[2][i];
+    // exact quotients by multiply-high (indices stay below 2^16)
+    const unsigned mt = fdiv_magic((unsigned)tw_), mz = fdiv_magic((unsigned)nz);
     for (int i = tid; i < nrow * tw_; i += nthr) {
-        const int rr = i / tw_, col = i - rr * tw_;
-        const int c = rr / nz, kz = rr - c * nz;
+        const int rr = (int)fdiv((unsigned)i, mt), col = i - rr * tw_;
+        const int c = (int)fdiv((unsigned)rr, mz), kz = rr - c * nz;
         buf[(c * tw_ + col) * ls + kz] = spec[c * plane + kz * zstride + colbase + col];
     }
     __syncthreads();
     if (mode & ZMODE_FWD) lds_fft<R, false, EPT>(buf, 6 * tw_, ls, d.pz, twl, tid, nthr);
     if (!(mode & ZMODE_GREEN)) {
         for (int i = tid; i < nrow * tw_; i += nthr) {
-            const int rr = i / tw_, col = i - rr * tw_;
-            const int c = rr / nz, kz = rr - c * nz;
+            const int rr = (int)fdiv((unsigned)i, mt), col = i - rr * tw_;
+            const int c = (int)fdiv((unsigned)rr, mz), kz = rr - c * nz;
             spec[c * plane + kz * zstride + colbase + col] = buf[(c * tw_ + col) * ls + kz];
         }
         return;
@@ -573,7 +576,7 @@ __global__ __launch_bounds__(256) void k_zpass_green(const RveDev<R> *__restrict
     const GreenArgs<R> g = {d.nx, d.ny, d.nz, inv_mu0, coef};
     double err2 = 0.0;
     for (int i = tid; i < tw_ * nz; i += nthr) {
-        const int col = i / nz, kz = i - col * nz;
+        const int col = (int)fdiv((unsigned)i, mz), kz = i - col * nz;
         C2<R> s[6];
 #pragma unroll
         for (int c = 0; c < 6; ++c) s[c] = buf[(c * tw_ + col) * ls + kz];
@@ -586,8 +589,8 @@ __global__ __launch_bounds__(256) void k_zpass_green(const RveDev<R> *__restrict
     __syncthreads();
     lds_fft<R, true, EPT>(buf, 6 * tw_, ls, d.pz, twl, tid, nthr);
     for (int i = tid; i < nrow * tw_; i += nthr) {
-        const int rr = i / tw_, col = i - rr * tw_;
-        const int c = rr / nz, kz = rr - c * nz;
+        const int rr = (int)fdiv((unsigned)i, mt), col = i - rr * tw_;
+        const int c = (int)fdiv((unsigned)rr, mz), kz = rr - c * nz;
         spec[c * plane + kz * zstride + colbase + col] = buf[(c * tw_ + col) * ls + kz];
     }
 }
