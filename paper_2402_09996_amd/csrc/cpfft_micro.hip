@@ -515,6 +515,95 @@ static WsLayout ws_layout(const cpf_micro_params *p)
     return L;
 }
 
+// Generators binned on a periodic grid of cells (for the ray search).
+struct CellGrid {
+    int nc[3];
+    double cs[3];
+    std::vector<int> start, items;
+};
+
+static CellGrid make_cells(const std::vector<P4> &seeds, const double L[3])
+{
+    CellGrid G;
+    for (int i = 0; i < 3; ++i) {
+        G.nc[i] = std::max(1, (int)(L[i] / 256.0));   // cells of about 16 voxels at q = 16
+        G.cs[i] = L[i] / G.nc[i];
+    }
+    const int ncell = G.nc[0] * G.nc[1] * G.nc[2];
+    auto cell_of = [&](const P4 &s) {
+        const int c[3] = {std::min(G.nc[0] - 1, (int)(s.x / G.cs[0])), std::min(G.nc[1] - 1, (int)(s.y / G.cs[1])),
+                          std::min(G.nc[2] - 1, (int)(s.z / G.cs[2]))};
+        return (c[2] * G.nc[1] + c[1]) * G.nc[0] + c[0];
+    };
+    G.start.assign(ncell + 1, 0);
+    for (const P4 &s : seeds) ++G.start[cell_of(s) + 1];
+    for (int c = 0; c < ncell; ++c) G.start[c + 1] += G.start[c];
+    G.items.resize(seeds.size());
+    std::vector<int> fill(G.start.begin(), G.start.end() - 1);
+    for (int m = 0; m < (int)seeds.size(); ++m) G.items[fill[cell_of(seeds[m])]++] = m;
+    return G;
+}
+
+// Exact exit parameter of the ray sg + t dir from the periodic Voronoi cell
+// of generator g: t = min over (m, image) != (g, 0) with D.dir > 0 of
+// |D|^2 / (2 D.dir).  Every such t is at least |D|/2, so with t_up the
+// value over the grid neighbours (an upper bound) only images with
+// |D| <= 2 t_up can matter; the cells covering that box (plus one cell each
+// side) are searched, or every generator and image when the box spans half
+// the window or more.  The result is the
+// same minimum as the search over every generator and image.
+static double ray_exit(int g, const double sg[3], const double dir[3], const std::vector<P4> &seeds,
+                       const std::vector<int> &nb, const CellGrid &G, const double L[3])
+{
+    auto t_of = [&](int m, double sx, double sy, double sz, double &t) {
+        const double df[3] = {seeds[m].x + sx - sg[0], seeds[m].y + sy - sg[1], seeds[m].z + sz - sg[2]};
+        const double den = df[0] * dir[0] + df[1] * dir[1] + df[2] * dir[2];
+        if (den > 0.0) {
+            const double num = df[0] * df[0] + df[1] * df[1] + df[2] * df[2];
+            t = std::min(t, num / (2.0 * den));
+        }
+    };
+    double tup = INFINITY;
+    for (int m : nb)
+        for (int ix = -1; ix <= 1; ++ix)
+            for (int iy = -1; iy <= 1; ++iy)
+                for (int iz = -1; iz <= 1; ++iz) t_of(m, ix * L[0], iy * L[1], iz * L[2], tup);
+    const double R = 2.0 * tup;
+    double t = INFINITY;
+    if (!(R < 0.5 * std::min(L[0], std::min(L[1], L[2])))) {
+        for (int ix = -1; ix <= 1; ++ix)
+            for (int iy = -1; iy <= 1; ++iy)
+                for (int iz = -1; iz <= 1; ++iz)
+                    for (int m = 0; m < (int)seeds.size(); ++m) {
+                        if (m == g && ix == 0 && iy == 0 && iz == 0) continue;
+                        t_of(m, ix * L[0], iy * L[1], iz * L[2], t);
+                    }
+        return t;
+    }
+    int lo[3], hi[3];
+    for (int i = 0; i < 3; ++i) {   // one more cell each side covers the rounding of the binning
+        lo[i] = (int)std::floor((sg[i] - R) / G.cs[i]) - 1;
+        hi[i] = (int)std::floor((sg[i] + R) / G.cs[i]) + 1;
+    }
+    for (int cz = lo[2]; cz <= hi[2]; ++cz)
+        for (int cy = lo[1]; cy <= hi[1]; ++cy)
+            for (int cx = lo[0]; cx <= hi[0]; ++cx) {
+                const int c[3] = {cx, cy, cz};
+                int w[3], sh[3];
+                for (int i = 0; i < 3; ++i) {
+                    sh[i] = (int)std::floor((double)c[i] / G.nc[i]);
+                    w[i] = c[i] - sh[i] * G.nc[i];
+                }
+                const int cell = (w[2] * G.nc[1] + w[1]) * G.nc[0] + w[0];
+                for (int q = G.start[cell]; q < G.start[cell + 1]; ++q) {
+                    const int m = G.items[q];
+                    if (m == g && sh[0] == 0 && sh[1] == 0 && sh[2] == 0) continue;
+                    t_of(m, sh[0] * L[0], sh[1] * L[1], sh[2] * L[2], t);
+                }
+            }
+    return t;
+}
+
 static int launch_label(int nx, int ny, int nz, int q, int n, const int32_t *seeds, int32_t *labels, int32_t *fb,
                         hipStream_t st)
 {
@@ -727,6 +816,7 @@ extern "C" int cpf_micro_generate(const cpf_micro_params *p, void *dev_workspace
     int ninc = 0;
     if (p->p_incl > 0.0) {
         const double Ld[3] = {(double)Lx, (double)Ly, (double)Lz};
+        const CellGrid grid = make_cells(seeds, Ld);
         for (int g = 0; g < nw; ++g) {
             if (!(rs.uniform() < p->p_incl)) continue;
             const int a = rs.below(2);
@@ -735,22 +825,11 @@ extern "C" int cpf_micro_generate(const cpf_micro_params *p, void *dev_workspace
             const double rho = std::sqrt(std::max(0.0, 1.0 - zc * zc));
             const double dir[3] = {rho * std::cos(phi), rho * std::sin(phi), zc};
             const double u = rs.uniform();
-            // exit point of the ray from the generator through the cell
+            // exit point of the ray from the generator through the cell: the
+            // least t = |D|^2 / (2 D.dir) over the other generators and their
+            // periodic images D ahead of the ray
             const double sg[3] = {(double)seeds[g].x, (double)seeds[g].y, (double)seeds[g].z};
-            double tbest = INFINITY;
-            for (int ix = -1; ix <= 1; ++ix)
-                for (int iy = -1; iy <= 1; ++iy)
-                    for (int iz = -1; iz <= 1; ++iz)
-                        for (int m = 0; m < nw; ++m) {
-                            if (m == g && ix == 0 && iy == 0 && iz == 0) continue;
-                            const double df[3] = {seeds[m].x + ix * Ld[0] - sg[0], seeds[m].y + iy * Ld[1] - sg[1],
-                                                  seeds[m].z + iz * Ld[2] - sg[2]};
-                            const double den = df[0] * dir[0] + df[1] * dir[1] + df[2] * dir[2];
-                            if (den > 0.0) {
-                                const double num = df[0] * df[0] + df[1] * df[1] + df[2] * df[2];
-                                tbest = std::min(tbest, num / (2.0 * den));
-                            }
-                        }
+            const double tbest = ray_exit(g, sg, dir, seeds, nbrs[g], grid, Ld);
             double x0[3];
             for (int i = 0; i < 3; ++i) {
                 const double xi = sg[i] + tbest * dir[i];
