@@ -86,6 +86,13 @@ def lib():
         L.orc_reg_rate.argtypes = [ctypes.c_double] * 5
         L.orc_rate.restype = None
         L.orc_rate.argtypes = [ctypes.POINTER(_Material), ctypes.c_int, dp, dp, dp]
+        ip = ctypes.POINTER(ctypes.c_int)
+        L.orc_cp_probe.restype = ctypes.c_int
+        L.orc_cp_probe.argtypes = [ctypes.POINTER(_Material), ctypes.c_long, ip, dp, dp, dp, dp, dp,
+                                   ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int, ip]
+        L.orc_cp_update_j.restype = ctypes.c_int
+        L.orc_cp_update_j.argtypes = [ctypes.POINTER(_Material), ctypes.c_long, ip, dp, dp, dp, dp, dp,
+                                      ctypes.c_double, ctypes.c_int, ip]
         L.orc_cp_update.restype = ctypes.c_int
         L.orc_cp_update.argtypes = [ctypes.POINTER(_Material), ctypes.c_long,
                                     ctypes.POINTER(ctypes.c_int), dp, dp, dp, dp, dp,
@@ -308,6 +315,43 @@ class Material:
         return y1, sig
 
 
+    def _prep(self, labels, eps0, eps1, y0):
+        labels = np.ascontiguousarray(np.asarray(labels, dtype=np.int32).ravel())
+        n = labels.shape[0]
+        eps0 = np.ascontiguousarray(np.broadcast_to(eps0, (n, 6)), dtype=np.float64)
+        eps1 = np.ascontiguousarray(np.broadcast_to(eps1, (n, 6)), dtype=np.float64)
+        y0 = np.ascontiguousarray(y0, dtype=np.float64)
+        return labels, n, eps0, eps1, y0
+
+    def probe(self, labels, eps0, eps1, y0, dt, M, tol, maxd):
+        """Frozen error-controlled substeps (orc_cp_probe): per point the
+        least M 2^j whose result agrees with twice the count; returns
+        (y1, sig, j)."""
+        labels, n, eps0, eps1, y0 = self._prep(labels, eps0, eps1, y0)
+        y1 = np.empty_like(y0)
+        sig = np.empty((n, 6))
+        j = np.zeros(n, dtype=np.int32)
+        ip = ctypes.POINTER(ctypes.c_int)
+        rc = lib().orc_cp_probe(ctypes.byref(self._s), n, labels.ctypes.data_as(ip), _dp(eps0), _dp(eps1),
+                                _dp(y0), _dp(y1), _dp(sig), float(dt), int(M), float(tol), int(maxd),
+                                j.ctypes.data_as(ip))
+        if rc != 0:
+            raise ValueError("orc_cp_probe rejected its input")
+        return y1, sig, j
+
+    def update_j(self, labels, eps0, eps1, y0, dt, M, j):
+        """``update`` with per-point substep counts M 2^j."""
+        labels, n, eps0, eps1, y0 = self._prep(labels, eps0, eps1, y0)
+        y1 = np.empty_like(y0)
+        sig = np.empty((n, 6))
+        j = np.ascontiguousarray(j, dtype=np.int32)
+        ip = ctypes.POINTER(ctypes.c_int)
+        rc = lib().orc_cp_update_j(ctypes.byref(self._s), n, labels.ctypes.data_as(ip), _dp(eps0), _dp(eps1),
+                                   _dp(y0), _dp(y1), _dp(sig), float(dt), int(M), j.ctypes.data_as(ip))
+        if rc != 0:
+            raise ValueError("orc_cp_update_j rejected its input")
+        return y1, sig
+
     # -- reverse mode -------------------------------------------------------
     def rate_vjp(self, label: int, eps_mandel, y, kbar):
         """Cotangents (y_bar, eps_bar, theta_bar[2][7]) of dy/dt = F(eps, y)
@@ -505,6 +549,8 @@ class Options:
     lam0: Optional[float] = None      # reference medium override
     mu0: Optional[float] = None
     green: str = "continuous"         # or "rotated" (discrete Green operator)
+    rk_tol: float = 0.0               # > 0: frozen error-controlled substep counts per load step
+    rk_max_doublings: int = 4
 
 
 class NotConverged(RuntimeError):
@@ -595,7 +641,13 @@ class Solver:
         E = self.E + dE
         eps = self.eps + to_mandel(dE)
         for k in range(o.max_iter):
-            y1, sig = self.mat.update(self.labels, self.eps, eps, self.y, dt, M)
+            if o.rk_tol > 0 and k == 0:
+                y1, sig, self.substep_j = self.mat.probe(self.labels, self.eps, eps, self.y, dt, M,
+                                                         o.rk_tol, o.rk_max_doublings)
+            elif o.rk_tol > 0:
+                y1, sig = self.mat.update_j(self.labels, self.eps, eps, self.y, dt, M, self.substep_j)
+            else:
+                y1, sig = self.mat.update(self.labels, self.eps, eps, self.y, dt, M)
             sig_t = from_mandel(sig)
             Sigma = sig_t.mean(axis=0)
             sig_hat, err_eq, err_bc = self.errors(sig_t, Sigma, sidx, target)

@@ -191,6 +191,78 @@ void orc_integrate_point(const orc_material *mt, int lab, const double eps0[6],
     }
 }
 
+/*
+ * Frozen error-controlled substeps (an option: the paper uses a fixed
+ * count).  At the first fixed-point iteration of a load step, each point
+ * takes the least count M_v = M 2^j, j = 0..maxd, whose RK4 result y(M_v)
+ * agrees with y(2 M_v) within Richardson's bound: e(M_v) <= (15 tol)^2,
+ * where e is the largest of the squared Frobenius norm of the plastic
+ * strain difference and the squared differences of each v and alpha
+ * (quantities that do not depend on the frame); j = maxd when none does.
+ * The point's result at that iteration is y(M_v), and the count stays for
+ * the rest of the load step, so the stress remains a smooth function of the
+ * strain iterate.
+ */
+static double subst_err2(int S, const double *a, const double *b)
+{
+    double f = 0.0, m = 0.0;
+    for (int i = 0; i < 6; ++i) f += (a[i] - b[i]) * (a[i] - b[i]);
+    for (int q = 6; q < 6 + 2 * S; ++q) {
+        const double d2 = (a[q] - b[q]) * (a[q] - b[q]);
+        if (d2 > m) m = d2;
+    }
+    return f > m ? f : m;
+}
+
+int orc_cp_probe(const orc_material *mt, long n_pts, const int *labels, const double *eps0,
+                 const double *eps1, const double *y0, double *y1, double *sig1, double dt, int M,
+                 double tol, int maxd, int *jsel)
+{
+    if (mt->n_sys < 0 || mt->n_sys > ORC_MAXS || M < 1 || !(tol > 0.0) || maxd < 0 || maxd > 10)
+        return -1;
+    const int S = mt->n_sys, D = 6 + 2 * S;
+    for (long p = 0; p < n_pts; ++p)
+        if (labels[p] < 0 || labels[p] >= mt->n_labels)
+            return -1;
+    const double lim = (15.0 * tol) * (15.0 * tol);
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long p = 0; p < n_pts; ++p) {
+        double ya[6 + 2 * ORC_MAXS], yb[6 + 2 * ORC_MAXS], sa[6], sb[6];
+        orc_integrate_point(mt, labels[p], eps0 + 6 * p, eps1 + 6 * p, y0 + D * p, ya, sa, dt, M);
+        int j = 0;
+        for (; j < maxd; ++j) {
+            orc_integrate_point(mt, labels[p], eps0 + 6 * p, eps1 + 6 * p, y0 + D * p, yb, sb, dt,
+                                M << (j + 1));
+            const double e = subst_err2(S, ya, yb);
+            if (e <= lim) break;
+            memcpy(ya, yb, sizeof(double) * D);
+            memcpy(sa, sb, sizeof sa);
+        }
+        jsel[p] = j;
+        memcpy(y1 + D * p, ya, sizeof(double) * D);
+        memcpy(sig1 + 6 * p, sa, sizeof sa);
+    }
+    return 0;
+}
+
+/* All points with their own substep counts M 2^jsel[p]. */
+int orc_cp_update_j(const orc_material *mt, long n_pts, const int *labels, const double *eps0,
+                    const double *eps1, const double *y0, double *y1, double *sig1, double dt, int M,
+                    const int *jsel)
+{
+    if (mt->n_sys < 0 || mt->n_sys > ORC_MAXS || M < 1)
+        return -1;
+    const int D = 6 + 2 * mt->n_sys;
+    for (long p = 0; p < n_pts; ++p)
+        if (labels[p] < 0 || labels[p] >= mt->n_labels || jsel[p] < 0 || jsel[p] > 10)
+            return -1;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (long p = 0; p < n_pts; ++p)
+        orc_integrate_point(mt, labels[p], eps0 + 6 * p, eps1 + 6 * p, y0 + D * p, y1 + D * p,
+                            sig1 + 6 * p, dt, M << jsel[p]);
+    return 0;
+}
+
 /* All points of a grid (OpenMP over points).  Arrays are point-major:
  * eps [n][6], state [n][6+2S], sig [n][6].  Returns 0, or -1 on bad input. */
 int orc_cp_update(const orc_material *mt, long n_pts, const int *labels,
