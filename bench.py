@@ -394,6 +394,40 @@ def eta_leg(cp, etas=(1e2, 1e3, 2e3, 5e3, 1e4, 3e4, 1e5, 3e5, 1e6)):
     return out
 
 
+def substeps_leg(cp, w, KS, r32, K, nvox, rk_tol=1e-8):
+    """The same FP32 workload with frozen error-controlled substep counts
+    (rk_tol on the state, Richardson's bound): iterations, time per load
+    step, the mean substep count of the last step and the difference of
+    Sigma_xx from the fixed-count run."""
+    import numpy as np
+    import torch
+    prob = cp.Problem.from_workload(w)
+    s = cp.Solver(prob, precision="fp32", tol=1e-6, stag_tol=1e-4, rk_tol=rk_tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, outs = 0, []
+    for n in range(KS):
+        o = s.step(w.path, n)
+        iters += int(o["iters"])
+        outs.append(o)
+        if n % 10 == 9:
+            print("[bench] substeps step %d iters %d Sigma_xx %.4f" % (n, o["iters"], o["Sigma"][0]),
+                  file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    counts = s.field("substeps").double().cpu().numpy().ravel()
+    out = {"rk_tol": rk_tol, "steps": KS, "iterations": iters, "ms_per_step": wall / KS * 1e3,
+           "value": iters * nvox / wall, "unit": "voxel-iterations/s",
+           "substeps_last_step": {"mean": float(counts.mean()), "max": float(counts.max()),
+                                  "share_refined": float((counts > counts.min()).mean())}}
+    if KS == K:
+        a = np.array([o["Sigma"][0] for o in outs])
+        b = np.array([o["Sigma"][0] for o in r32["outs"]])
+        out["max_rel_diff_Sigma_xx_vs_fixed"] = float(np.abs(a - b).max() / np.abs(b).max())
+        out["wall_vs_fixed"] = wall / r32["wall"]
+    return out
+
+
 def histogram_leg(s32, nvox, reps=20, nbins=150, lo=0.0, hi=1500.0):
     """Distribution of the local von Mises stress of the committed 128^3
     state (post-processing after the timed steps): the stress pass (reads
@@ -548,6 +582,7 @@ def main():
     KG = args.green_steps if args.green_steps is not None else K
     if KG > 0:
         line["rotated_green"] = green_leg(cp, w, KG, min(W, 1), r32, K, nvox)
+        line["error_controlled_substeps"] = substeps_leg(cp, w, KG, r32, K, nvox)
     line["seq_histogram"] = histogram_leg(s32, nvox)
     if not args.no_micro:
         line["microstructure"] = micro_leg(cp)

@@ -64,6 +64,7 @@ extern "C" {
 #define CPF_FIELD_PLASTIC_STRAIN 2 /* 6 components                     */
 #define CPF_FIELD_ACC_SLIP 3       /* n_sys components (v)             */
 #define CPF_FIELD_BACK_STRAIN 4    /* n_sys components (alpha)         */
+#define CPF_FIELD_SUBSTEPS 5       /* 1 component: RK4 substeps of the current load step */
 
 #define CPF_MAX_SYSTEMS 32
 
@@ -106,7 +107,22 @@ typedef struct cpf_options {
     double stag_tol;   /* FP32: accept a stalled residual below this (0: off)*/
     int check_every;   /* iterations queued per host convergence poll (0: auto) */
     int green;         /* CPF_GREEN_*: which Green operator (Section 3)      */
+    double rk_tol;     /* > 0: frozen error-controlled substep counts, below */
 } cpf_options;
+
+/* Error-controlled substeps (an option; the paper integrates each load
+ * step with a fixed number of RK4 substeps).  With rk_tol > 0, at the first
+ * fixed-point iteration of every load step each voxel takes the least count
+ * M 2^j, j = 0 .. CPF_RK_MAX_DOUBLINGS, whose RK4 result agrees with that
+ * of twice the count within Richardson's bound: the larger of the squared
+ * Frobenius norm of the plastic strain difference and the squared
+ * differences of each v and alpha is at most (15 rk_tol)^2 (j = the maximum
+ * when none does).  The voxel keeps the result of that count, and the count
+ * stays for the rest of the load step, so the stress stays a smooth
+ * function of the strain iterate and the fixed point converges as with a
+ * fixed count.  The adjoint entry points need rk_tol = 0.  The counts of
+ * the current step are exported as CPF_FIELD_SUBSTEPS. */
+#define CPF_RK_MAX_DOUBLINGS 4
 
 /* Green operator of the fixed point (Section 3 names only "the Green
  * operator" of the reference medium).

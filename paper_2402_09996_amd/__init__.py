@@ -14,7 +14,7 @@ import numpy as np
 
 from . import _lib
 from ._lib import (CPF_FIELD_ACC_SLIP, CPF_FIELD_BACK_STRAIN, CPF_FIELD_PLASTIC_STRAIN,
-                   CPF_FIELD_STRAIN, CPF_FIELD_STRESS, CPF_PREC_FP32, CPF_PREC_FP64,
+                   CPF_FIELD_STRAIN, CPF_FIELD_STRESS, CPF_FIELD_SUBSTEPS, CPF_PREC_FP32, CPF_PREC_FP64,
                    CpfError, check)
 
 FIELDS = {
@@ -23,6 +23,7 @@ FIELDS = {
     "plastic_strain": CPF_FIELD_PLASTIC_STRAIN,
     "acc_slip": CPF_FIELD_ACC_SLIP,
     "back_strain": CPF_FIELD_BACK_STRAIN,
+    "substeps": CPF_FIELD_SUBSTEPS,
 }
 
 __all__ = ["Problem", "Solver", "CpfError", "FIELDS", "version", "EffectiveStress", "StressCurveLoss",
@@ -141,7 +142,8 @@ def _outs_to_dict(outs, n):
 GREEN = {"continuous": 0, "rotated": 1}
 
 
-def _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_every, green="continuous"):
+def _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_every, green="continuous",
+             rk_tol=0.0):
     o = _lib.CpfOptions()
     _lib.lib().cpf_options_default(ctypes.byref(o))
     o.precision = CPF_PREC_FP64 if precision == "fp64" else CPF_PREC_FP32
@@ -152,6 +154,7 @@ def _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_
     if green not in GREEN:
         raise ValueError("green must be one of %s" % sorted(GREEN))
     o.green = GREEN[green]
+    o.rk_tol = float(rk_tol)
     return o
 
 
@@ -166,7 +169,7 @@ class Solver:
                  lam0: Optional[float] = None, mu0: Optional[float] = None,
                  stag_tol: float = 0.0, check_every: int = 0, device: str = "cuda:0",
                  stream=None, graph_iters: int = 0, autotune: bool = False,
-                 green: str = "continuous"):
+                 green: str = "continuous", rk_tol: float = 0.0):
         import torch
         L = _lib.lib()
         probs = list(problem) if isinstance(problem, (list, tuple)) else [problem]
@@ -175,7 +178,7 @@ class Solver:
         self.n_rve = len(probs)
         self.precision = precision
         self.dtype = {"fp64": torch.float64, "fp32": torch.float32}[precision]
-        o = _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_every, green)
+        o = _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_every, green, rk_tol)
         self.green_operator = green
         h = ctypes.c_void_p()
         arr = (ctypes.c_void_p * self.n_rve)(*[p._h.value for p in probs])
@@ -232,7 +235,7 @@ class Solver:
         k = FIELDS[name]
         nz, ny, nx = self.problems[rve].shape
         nc = 6 if k in (CPF_FIELD_STRESS, CPF_FIELD_STRAIN, CPF_FIELD_PLASTIC_STRAIN) \
-            else self.problem.n_sys
+            else 1 if k == CPF_FIELD_SUBSTEPS else self.problem.n_sys
         out = torch.empty((nc, nz, ny, nx), dtype=self.dtype, device=self.device)
         check(_lib.lib().cpf_batch_field(self._h, int(rve), k, ctypes.c_void_p(out.data_ptr())))
         return out
@@ -258,7 +261,7 @@ class Solver:
         import torch
         k = FIELDS[name]
         nc = 6 if k in (CPF_FIELD_STRESS, CPF_FIELD_STRAIN, CPF_FIELD_PLASTIC_STRAIN) \
-            else self.problem.n_sys
+            else 1 if k == CPF_FIELD_SUBSTEPS else self.problem.n_sys
         out = torch.empty((nc, self.nz, self.ny, self.nx), dtype=self.dtype, device=self.device)
         check(_lib.lib().cpf_solver_field(self._h, k, ctypes.c_void_p(out.data_ptr())))
         return out

@@ -30,6 +30,7 @@ CPF_FIELD_STRAIN = 1
 CPF_FIELD_PLASTIC_STRAIN = 2
 CPF_FIELD_ACC_SLIP = 3
 CPF_FIELD_BACK_STRAIN = 4
+CPF_FIELD_SUBSTEPS = 5
 
 CPF_MAX_SYSTEMS = 32
 
@@ -60,7 +61,7 @@ class CpfOptions(ctypes.Structure):
     _fields_ = [
         ("precision", _i), ("tol", _d), ("max_iter", _i), ("h_max", _d),
         ("rk4_M", _i), ("lam0", _d), ("mu0", _d), ("stag_tol", _d),
-        ("check_every", _i), ("green", _i),
+        ("check_every", _i), ("green", _i), ("rk_tol", _d),
     ]
 
 

@@ -87,6 +87,7 @@ extern "C" void cpf_options_default(cpf_options *o)
     o->stag_tol = 0.0;
     o->check_every = 0;
     o->green = CPF_GREEN_CONTINUOUS;
+    o->rk_tol = 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -287,7 +288,7 @@ struct RveHost {
     FftPlan px, py, pz;
     int L, tpbx, nbx, ty, nty, tz, ntz, nbz;
     bool tiles_fixed = false;   // set explicitly or by the autotuner
-    size_t off_labels, off_Q, off_eps[2], off_st[2], off_spec, off_tw[3], off_px, off_pz, off_sc;
+    size_t off_labels, off_Q, off_eps[2], off_st[2], off_spec, off_tw[3], off_px, off_pz, off_sc, off_mv;
     int cur = 0;
     double Sigma_n[6], E_n[6];
     int prev_iters = 8;
@@ -467,6 +468,7 @@ static void layout(cpf_solver *s)
         h.off_px = take(sizeof(double) * NPX * h.nbx);
         h.off_pz = take(sizeof(double) * h.nhx * h.ny);   // room for the smallest z tile
         h.off_sc = take(sizeof(Scalars));
+        h.off_mv = take(sizeof(int32_t) * h.nvox);
     }
     const size_t n = s->rv.size();
     s->off_dev = take(sizeof(RveDev<R>) * n);
@@ -498,6 +500,7 @@ static RveDev<R> make_dev(cpf_solver *s, const RveHost &h, int bx0, int by0, int
     d.eps[1] = dptr<R>(s, h.off_eps[1]);
     d.st[0] = dptr<R>(s, h.off_st[0]);
     d.st[1] = dptr<R>(s, h.off_st[1]);
+    d.mv = dptr<int32_t>(s, h.off_mv);
     d.spec = dptr<C2<R>>(s, h.off_spec);
     for (int a = 0; a < 3; ++a) d.tw[a] = dptr<C2<R>>(s, h.off_tw[a]);
     d.part_x = dptr<double>(s, h.off_px);
@@ -598,6 +601,8 @@ extern "C" int cpf_batch_create(int n, const cpf_problem *const *probs, const cp
         return fail(CPF_E_INVALID_ARG, "need tol > 0, max_iter >= 1 and rk4_M > 0 or h_max > 0");
     if (o.green != CPF_GREEN_CONTINUOUS && o.green != CPF_GREEN_ROTATED)
         return fail(CPF_E_INVALID_ARG, "unknown Green operator %d", o.green);
+    if (!(o.rk_tol >= 0.0) || !std::isfinite(o.rk_tol))
+        return fail(CPF_E_INVALID_ARG, "rk_tol must be finite and >= 0");
     cpf_solver *s = new (std::nothrow) cpf_solver();
     if (!s) return fail(CPF_E_INVALID_ARG, "out of host memory");
     const cpf_problem &p0 = *probs[0];
@@ -883,8 +888,16 @@ static void stress_block_inverse(const double K0[36], const int sidx[6], double 
 template <typename R, int NS, int SPEC>
 static void launch_xiter(cpf_solver *s, const LawP<R> &P)
 {
-    hipLaunchKernelGGL((k_xpass_iter<R, NS, SPEC>), dim3(s->nbx_tot), dim3(256), s->lds_x, s->stream,
-                       dptr<RveDev<R>>(s, s->off_dev), (int)s->rv.size(), P);
+    if (s->opt.rk_tol > 0.0) {
+        // frozen error-controlled substeps: Richardson's bound (15 tol)^2 on
+        // the squared state difference, at most CPF_RK_MAX_DOUBLINGS doublings
+        const double lim2 = (15.0 * s->opt.rk_tol) * (15.0 * s->opt.rk_tol);
+        hipLaunchKernelGGL((k_xpass_iter<R, NS, SPEC, true>), dim3(s->nbx_tot), dim3(256), s->lds_x, s->stream,
+                           dptr<RveDev<R>>(s, s->off_dev), (int)s->rv.size(), P, lim2, CPF_RK_MAX_DOUBLINGS);
+    } else {
+        hipLaunchKernelGGL((k_xpass_iter<R, NS, SPEC, false>), dim3(s->nbx_tot), dim3(256), s->lds_x, s->stream,
+                           dptr<RveDev<R>>(s, s->off_dev), (int)s->rv.size(), P, 0.0, 0);
+    }
 }
 
 template <typename R>
@@ -1182,6 +1195,11 @@ static int field_impl(cpf_solver *s, int r, int field, void *dev_out)
         HIPCHK(hipMemcpyAsync(o, st + (6 + nsys) * nv, sizeof(R) * nsys * nv, hipMemcpyDeviceToDevice,
                               s->stream));
         break;
+    case CPF_FIELD_SUBSTEPS:
+        hipLaunchKernelGGL(k_substeps_field<R>, dim3((nv + 255) / 256), dim3(256), 0, s->stream,
+                           dptr<int32_t>(s, h.off_mv), dptr<Scalars>(s, h.off_sc), o, nv, s->opt.rk_tol > 0.0 ? 1 : 0);
+        HIPCHK(hipGetLastError());
+        break;
     default:
         return fail(CPF_E_INVALID_ARG, "unknown field %d", field);
     }
@@ -1469,6 +1487,8 @@ extern "C" int cpf_adjoint_workspace_size(const cpf_solver *s, const cpf_path *p
 {
     if (!s || !bytes) return fail(CPF_E_INVALID_ARG, "null argument");
     if (s->rv.size() != 1) return fail(CPF_E_INVALID_ARG, "the adjoint needs a single-RVE solver");
+    if (s->opt.rk_tol > 0.0)
+        return fail(CPF_E_INVALID_ARG, "the adjoint replays fixed substep counts: rk_tol must be 0");
     int rc = check_path(path);
     if (rc) return rc;
     if (checkpoint_every < 1) return fail(CPF_E_INVALID_ARG, "checkpoint_every must be >= 1");

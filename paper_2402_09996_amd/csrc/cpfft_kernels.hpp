@@ -56,6 +56,8 @@ struct RveDev {
     const R *Qtab;             // [n_labels][9]
     R *eps[2];                 // strain [6][nvox]: committed = eps[cur]
     R *st[2];                  // state [6+2S][nvox]: committed = st[cur]
+    int32_t *mv;               // [nvox] substep exponent j (count M 2^j) of the current
+                               // load step, with error-controlled substeps
     C2<R> *spec;               // [6][nz][ny][nhp], columns kx < nkx
     const C2<R> *tw[3];        // twiddles exp(-2 pi i k / n) along x, y, z
     double *part_x;            // [x blocks][NPX]
@@ -209,6 +211,81 @@ __device__ __forceinline__ void voxel_law(const LawP<R> &P, const R *Qrow, const
     store_state<R, NS>(*st_out, nvox, vox, P.nsys, Q, ep, v, al);
 }
 
+// Frozen error-controlled substep counts (an option; the paper uses a fixed
+// count): at the first iteration of a load step each voxel takes the least
+// count M 2^j, j <= maxd, whose result agrees with that of twice the count
+// within lim2 -- the larger of the squared Frobenius norm of the plastic
+// strain difference and the squared differences of each v and alpha, all
+// independent of the frame -- keeps the result of that count and stores j
+// for the later iterations of the step.  The counts differ between lanes;
+// the law path has no block barrier (only wave votes over active lanes).
+template <typename R, int NS, int SPEC>
+__device__ __forceinline__ void voxel_law_probe(const LawP<R> &P, const R *Qrow, const R e0l[6], const R e1l[6],
+                                                const R *st_in, R *const *st_out, long nvox, long vox, R dt,
+                                                int M, double lim2, int maxd, int32_t *jout, R sigl[6],
+                                                R (&v)[NS], int &nact, int &nnewt, const LawLds<R> &W)
+{
+    // The candidate result lives in the trial-state buffer (this voxel's
+    // own slots), so only one state is held in registers at a time.
+    R *so = *st_out;
+    R e0[6], e1[6];
+    {
+        R Q[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Q[i] = Qrow[i];
+        rot_to_crystal(Q, e0l, e0);
+        rot_to_crystal(Q, e1l, e1);
+    }
+    int j = 0;
+#pragma unroll 1
+    for (int a = 0; a <= maxd; ++a) {
+        R ep[6], al[NS], Q[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Q[i] = Qrow[i];
+        load_state<R, NS>(st_in, nvox, vox, P.nsys, Q, ep, v, al);
+        integrate<R, NS, SPEC>(P, e0, e1, ep, v, al, dt, M << a, nact, nnewt, W);
+#if CPF_RELOAD_Q
+        asm volatile("" ::: "memory");
+#endif
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Q[i] = Qrow[i];
+        if (a > 0) {
+            // compare with the stored result of half the count
+            R epl[6];
+            rot_to_lab(Q, ep, epl);
+            double f = 0.0, m = 0.0;
+#pragma unroll
+            for (int i = 0; i < 6; ++i) {
+                const double d = (double)epl[i] - (double)so[i * nvox + vox];
+                f += (i < 3 ? 1.0 : 2.0) * d * d;
+            }
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                if (q < P.nsys) {
+                    const double dv = (double)v[q] - (double)so[(6 + q) * nvox + vox];
+                    const double da = (double)al[q] - (double)so[(6 + P.nsys + q) * nvox + vox];
+                    m = fmax(m, fmax(dv * dv, da * da));
+                }
+            }
+            if (fmax(f, m) <= lim2) break;   // keep the stored result, count M 2^(a-1)
+            j = a;
+        }
+        store_state<R, NS>(so, nvox, vox, P.nsys, Q, ep, v, al);
+    }
+    *jout = j;
+    // the kept result: state from the trial buffer, stress from its plastic strain
+    R Q[9], ep[6], al[NS], sc[6];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) Q[i] = Qrow[i];
+    load_state<R, NS>(so, nvox, vox, P.nsys, Q, ep, v, al);
+    if constexpr (law_park_e<R>()) {
+#pragma unroll
+        for (int i = 0; i < 6; ++i) e1[i] = W.e[(6 + i) * W.ls];
+    }
+    hooke(P, e1, ep, sc);
+    rot_to_lab(Q, sc, sigl);
+}
+
 // ---------------------------------------------------------------------------
 // Fused x pass of one iteration.  Block = L x-lines of nx voxels.
 // ---------------------------------------------------------------------------
@@ -265,9 +342,9 @@ constexpr size_t xfft_lds_bytes()
     return (3 * 256 + 256) * sizeof(C2<R>);
 }
 
-template <typename R, int NS, int SPEC>
-__global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_xpass_iter(const RveDev<R> *__restrict__ rv,
-                                                                            int nrve, LawP<R> Parg)
+template <typename R, int NS, int SPEC, bool ADAPT = false>
+__global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_xpass_iter(
+    const RveDev<R> *__restrict__ rv, int nrve, LawP<R> Parg, double rk_lim2, int rk_maxd)
 {
     const int r = find_rve(rv, nrve, (int)blockIdx.x, 0);
     const RveDev<R> &d = rv[r];
@@ -323,8 +400,20 @@ __global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_xpass_ite
         const int lab = d.labels[vox];
         R v[NS];
         int nact = 0, nnewt = 0;
-        voxel_law<R, NS, SPEC>(P, d.Qtab + lab * 9, e0, e1, d.st[cur], &d.st[1 - cur], d.nvox, vox, R(sc->dt),
-                               sc->M, sig, v, nact, nnewt, law_lds<R, NS>(smem_raw, xfft_lds_bytes<R>()));
+        if constexpr (ADAPT) {
+            if (first)
+                voxel_law_probe<R, NS, SPEC>(P, d.Qtab + lab * 9, e0, e1, d.st[cur], &d.st[1 - cur], d.nvox, vox,
+                                             R(sc->dt), sc->M, rk_lim2, rk_maxd, d.mv + vox, sig, v, nact, nnewt,
+                                             law_lds<R, NS>(smem_raw, xfft_lds_bytes<R>()));
+            else
+                voxel_law<R, NS, SPEC>(P, d.Qtab + lab * 9, e0, e1, d.st[cur], &d.st[1 - cur], d.nvox, vox,
+                                       R(sc->dt), sc->M << d.mv[vox], sig, v, nact, nnewt,
+                                       law_lds<R, NS>(smem_raw, xfft_lds_bytes<R>()));
+        } else {
+            voxel_law<R, NS, SPEC>(P, d.Qtab + lab * 9, e0, e1, d.st[cur], &d.st[1 - cur], d.nvox, vox,
+                                   R(sc->dt), sc->M, sig, v, nact, nnewt,
+                                   law_lds<R, NS>(smem_raw, xfft_lds_bytes<R>()));
+        }
         part[9] = (double)nact;
         part[10] = (double)nnewt;
 #pragma unroll
@@ -840,6 +929,15 @@ __global__ __launch_bounds__(256) void k_seq_hist(const R *__restrict__ sig, lon
     __syncthreads();
     for (int i = threadIdx.x; i < nb; i += blockDim.x)
         if (hist[i]) atomicAdd(&counts[i], (unsigned long long)hist[i]);
+}
+
+// substep counts of the current load step as field values (M 2^j)
+template <typename R>
+__global__ __launch_bounds__(256) void k_substeps_field(const int32_t *mv, const Scalars *sc, R *out, long nvox,
+                                                        int adaptive)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nvox) out[i] = R(adaptive ? sc->M << mv[i] : sc->M);
 }
 
 template <typename R>
