@@ -289,6 +289,7 @@ struct RveHost {
     int L, tpbx, nbx, ty, nty, tz, ntz, nbz;
     bool tiles_fixed = false;   // set explicitly or by the autotuner
     size_t off_labels, off_Q, off_eps[2], off_st[2], off_spec, off_tw[3], off_px, off_pz, off_sc, off_mv;
+    size_t off_pb;
     int cur = 0;
     double Sigma_n[6], E_n[6];
     int prev_iters = 8;
@@ -469,6 +470,7 @@ static void layout(cpf_solver *s)
         h.off_pz = take(sizeof(double) * h.nhx * h.ny);   // room for the smallest z tile
         h.off_sc = take(sizeof(Scalars));
         h.off_mv = take(sizeof(int32_t) * h.nvox);
+        h.off_pb = take(sizeof(double) * (NPX + 1) * BC_CHUNKS);
     }
     const size_t n = s->rv.size();
     s->off_dev = take(sizeof(RveDev<R>) * n);
@@ -505,6 +507,7 @@ static RveDev<R> make_dev(cpf_solver *s, const RveHost &h, int bx0, int by0, int
     for (int a = 0; a < 3; ++a) d.tw[a] = dptr<C2<R>>(s, h.off_tw[a]);
     d.part_x = dptr<double>(s, h.off_px);
     d.part_z = dptr<double>(s, h.off_pz);
+    d.part_b = dptr<double>(s, h.off_pb);
     d.sc = dptr<Scalars>(s, h.off_sc);
     return d;
 }
@@ -975,9 +978,12 @@ static void launch_bc(cpf_solver *s)
     b.tol = s->opt.tol;
     b.stag_tol = s->opt.stag_tol;
     b.max_iter = s->opt.max_iter;
-    // 1024 threads: the block partials of a 128^3 x pass (8192 x 11
-    // doubles) are read in a few rounds
-    hipLaunchKernelGGL(k_bc_update<R>, dim3(s->rv.size()), dim3(1024), 0, s->stream,
+    // two stages: BC_CHUNKS blocks per RVE sum fixed chunks of the block
+    // partials (a 128^3 x pass leaves 8192 x 11 doubles), one wave per RVE
+    // sums the chunks and updates the scalars
+    hipLaunchKernelGGL(k_bc_partials<R>, dim3(s->rv.size() * BC_CHUNKS), dim3(256), 0, s->stream,
+                       dptr<RveDev<R>>(s, s->off_dev));
+    hipLaunchKernelGGL(k_bc_update<R>, dim3(s->rv.size()), dim3(64), 0, s->stream,
                        dptr<RveDev<R>>(s, s->off_dev), b);
 }
 

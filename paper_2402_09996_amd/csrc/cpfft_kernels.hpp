@@ -62,6 +62,7 @@ struct RveDev {
     const C2<R> *tw[3];        // twiddles exp(-2 pi i k / n) along x, y, z
     double *part_x;            // [x blocks][NPX]
     double *part_z;            // [z blocks]
+    double *part_b;            // [BC_CHUNKS][NPX + 1]: the x and z block sums in fixed chunks
     Scalars *sc;
 };
 
@@ -733,26 +734,48 @@ __device__ __forceinline__ double frob2(const double a[6])
     return a[0] * a[0] + a[1] * a[1] + a[2] * a[2] + 2.0 * (a[3] * a[3] + a[4] * a[4] + a[5] * a[5]);
 }
 
-// One block per RVE: reduce the block sums of the x and z passes (fixed
-// order), evaluate the residuals, decide convergence and correct the
-// stress-controlled mean strain.
+// First stage of the scalar reduction: BC_CHUNKS blocks per RVE each sum a
+// fixed contiguous chunk of the x-pass block sums (NPX values each) and of
+// the z-pass residual sums, in a fixed order.
+constexpr int BC_CHUNKS = 32;
+
 template <typename R>
-__global__ __launch_bounds__(1024) void k_bc_update(const RveDev<R> *__restrict__ rv, BcArgs b)
+__global__ __launch_bounds__(256) void k_bc_partials(const RveDev<R> *__restrict__ rv)
+{
+    const RveDev<R> &d = rv[blockIdx.x / BC_CHUNKS];
+    const int c = blockIdx.x % BC_CHUNKS;
+    if (d.sc->done) return;
+    const int nbx = (d.nlines + d.L - 1) / d.L, nbz = d.ntz * d.ny;
+    const int x0 = (int)((long)nbx * c / BC_CHUNKS), x1 = (int)((long)nbx * (c + 1) / BC_CHUNKS);
+    const int z0 = (int)((long)nbz * c / BC_CHUNKS), z1 = (int)((long)nbz * (c + 1) / BC_CHUNKS);
+    double acc[NPX + 1];
+#pragma unroll
+    for (int i = 0; i < NPX + 1; ++i) acc[i] = 0.0;
+    for (int j = x0 + threadIdx.x; j < x1; j += blockDim.x)
+#pragma unroll
+        for (int i = 0; i < NPX; ++i) acc[i] += d.part_x[(long)j * NPX + i];
+    for (int j = z0 + threadIdx.x; j < z1; j += blockDim.x) acc[NPX] += d.part_z[j];
+    block_sum<NPX + 1, 4>(acc, d.part_b + (long)c * (NPX + 1));
+}
+
+// One block per RVE: sum the chunk sums (fixed order), evaluate the
+// residuals, decide convergence and correct the stress-controlled mean
+// strain.
+template <typename R>
+__global__ __launch_bounds__(64) void k_bc_update(const RveDev<R> *__restrict__ rv, BcArgs b)
 {
     const RveDev<R> &d = rv[blockIdx.x];
     Scalars *sc = d.sc;
     if (sc->done) return;
-    const int nbx = (d.nlines + d.L - 1) / d.L, nbz = d.ntz * d.ny;
     const double nvox = (double)d.nvox;
     double acc[NPX + 1];
 #pragma unroll
     for (int i = 0; i < NPX + 1; ++i) acc[i] = 0.0;
-    for (int j = threadIdx.x; j < nbx; j += blockDim.x)
+    for (int j = threadIdx.x; j < BC_CHUNKS; j += blockDim.x)
 #pragma unroll
-        for (int i = 0; i < NPX; ++i) acc[i] += d.part_x[(long)j * NPX + i];
-    for (int j = threadIdx.x; j < nbz; j += blockDim.x) acc[NPX] += d.part_z[j];
+        for (int i = 0; i < NPX + 1; ++i) acc[i] += d.part_b[(long)j * (NPX + 1) + i];
     __shared__ double tot[NPX + 1];
-    block_sum<NPX + 1>(acc, tot);
+    block_sum<NPX + 1, 1>(acc, tot);
     __syncthreads();
     if (threadIdx.x != 0) return;
 
