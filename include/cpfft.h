@@ -108,7 +108,21 @@ typedef struct cpf_options {
     int check_every;   /* iterations queued per host convergence poll (0: auto) */
     int green;         /* CPF_GREEN_*: which Green operator (Section 3)      */
     double rk_tol;     /* > 0: frozen error-controlled substep counts, below */
+    int aa_depth;      /* > 0: Anderson-accelerated fixed point, below       */
 } cpf_options;
+
+/* Anderson acceleration of the fixed point (an option; the paper's scheme
+ * is the basic one; Walker and Ni, 2011).  With aa_depth = m in 1..8, the
+ * iterate after x_k is x_k + f_k - sum_s gamma_s (dX_s + dF_s) instead of
+ * the basic x_k + f_k, where f_j = -Gamma0 * sigma(x_j) + dE_j is the basic
+ * step, dX, dF are the differences of the last (up to) m iterates and
+ * steps of the load step, and gamma solves (G + lam I) gamma = dF^T f_k,
+ * G = dF^T dF (Frobenius products over the voxels, FP64), lam = 1e-14
+ * trace(G) / m_k (a degenerate system falls back to the basic step); the
+ * mean strain is mixed with the same coefficients.  Converged results are
+ * those of the basic scheme to the tolerance; iterations are fewer.  Costs
+ * (2 m + 2) strain fields of workspace per RVE and a pass over them per
+ * iteration.  The adjoint entry points need aa_depth = 0. */
 
 /* Error-controlled substeps (an option; the paper integrates each load
  * step with a fixed number of RK4 substeps).  With rk_tol > 0, at the first

@@ -551,6 +551,7 @@ class Options:
     green: str = "continuous"         # or "rotated" (discrete Green operator)
     rk_tol: float = 0.0               # > 0: frozen error-controlled substep counts per load step
     rk_max_doublings: int = 4
+    aa_depth: int = 0                 # > 0: Anderson-accelerated fixed point of that depth
 
 
 class NotConverged(RuntimeError):
@@ -618,6 +619,42 @@ class Solver:
         corr = ifft3_real(eh)
         return np.moveaxis(corr, 0, -1).reshape(self.n_vox, 6)
 
+    @staticmethod
+    def _anderson(hist, x, f, E, dE, m):
+        """One Anderson-accelerated update of the fixed point x <- x + f
+        (f = -Gamma0 * sigma + dE, the basic scheme's step), depth m (Walker
+        and Ni, 2011): with the differences dX_i = x_{i+1} - x_i and
+        dF_i = f_{i+1} - f_i of the last (up to) m iterations, gamma solves
+        (G + lam I) gamma = dF^T f, G = dF^T dF (Euclidean products of the
+        Mandel fields, lam = 1e-14 trace(G) / m_k), and
+        x_new = x + f - sum_i gamma_i (dX_i + dF_i); the mean strain E is
+        mixed with the same coefficients (its steps are the mean parts
+        dE).  A system that is not positive definite (no Cholesky factor)
+        takes the basic step."""
+        hist.append((x.copy(), f.copy(), E.copy(), dE.copy()))
+        if len(hist) > m + 1:
+            hist.pop(0)
+        mk = len(hist) - 1
+        if mk == 0:
+            return x + f, E + dE
+        dF = np.stack([(hist[i + 1][1] - hist[i][1]).ravel() for i in range(mk)], axis=1)
+        dX = np.stack([(hist[i + 1][0] - hist[i][0]).ravel() for i in range(mk)], axis=1)
+        G = dF.T @ dF
+        tr = np.trace(G)
+        if not tr > 0:
+            return x + f, E + dE               # degenerate history: the basic step
+        lam = 1e-14 * tr / mk
+        try:
+            L = np.linalg.cholesky(G + lam * np.eye(mk))
+        except np.linalg.LinAlgError:
+            return x + f, E + dE
+        gam = np.linalg.solve(L.T, np.linalg.solve(L, dF.T @ f.ravel()))
+        x_new = x.ravel() + f.ravel() - (dX + dF) @ gam
+        dEX = np.stack([hist[i + 1][2] - hist[i][2] for i in range(mk)], axis=1)
+        ddE = np.stack([hist[i + 1][3] - hist[i][3] for i in range(mk)], axis=1)
+        E_new = E + dE - (dEX + ddE) @ gam
+        return x_new.reshape(x.shape), E_new
+
     def _stress_correction(self, sidx, rhs) -> np.ndarray:
         dE = np.zeros(6)
         S = np.nonzero(sidx)[0]
@@ -640,6 +677,7 @@ class Solver:
         dE += self._stress_correction(sidx, rhs)
         E = self.E + dE
         eps = self.eps + to_mandel(dE)
+        hist = []                            # Anderson: (x, f, E, dE) of earlier iterations
         for k in range(o.max_iter):
             if o.rk_tol > 0 and k == 0:
                 y1, sig, self.substep_j = self.mat.probe(self.labels, self.eps, eps, self.y, dt, M,
@@ -657,8 +695,11 @@ class Solver:
                 break
             corr = self.correction(sig_hat)
             dE = self._stress_correction(sidx, target - Sigma)
-            E = E + dE
-            eps = eps - to_mandel(corr) + to_mandel(dE)
+            if o.aa_depth > 0:
+                eps, E = self._anderson(hist, eps, -to_mandel(corr) + to_mandel(dE), E, dE, o.aa_depth)
+            else:
+                E = E + dE
+                eps = eps - to_mandel(corr) + to_mandel(dE)
         else:
             raise NotConverged("no convergence in %d iterations" % o.max_iter)
         self.eps, self.y, self.sig = eps, y1, sig

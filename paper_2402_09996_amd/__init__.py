@@ -143,7 +143,7 @@ GREEN = {"continuous": 0, "rotated": 1}
 
 
 def _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_every, green="continuous",
-             rk_tol=0.0):
+             rk_tol=0.0, aa_depth=0):
     o = _lib.CpfOptions()
     _lib.lib().cpf_options_default(ctypes.byref(o))
     o.precision = CPF_PREC_FP64 if precision == "fp64" else CPF_PREC_FP32
@@ -155,6 +155,7 @@ def _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_
         raise ValueError("green must be one of %s" % sorted(GREEN))
     o.green = GREEN[green]
     o.rk_tol = float(rk_tol)
+    o.aa_depth = int(aa_depth)
     return o
 
 
@@ -169,7 +170,7 @@ class Solver:
                  lam0: Optional[float] = None, mu0: Optional[float] = None,
                  stag_tol: float = 0.0, check_every: int = 0, device: str = "cuda:0",
                  stream=None, graph_iters: int = 0, autotune: bool = False,
-                 green: str = "continuous", rk_tol: float = 0.0):
+                 green: str = "continuous", rk_tol: float = 0.0, aa_depth: int = 0):
         import torch
         L = _lib.lib()
         probs = list(problem) if isinstance(problem, (list, tuple)) else [problem]
@@ -178,7 +179,8 @@ class Solver:
         self.n_rve = len(probs)
         self.precision = precision
         self.dtype = {"fp64": torch.float64, "fp32": torch.float32}[precision]
-        o = _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_every, green, rk_tol)
+        o = _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_every, green, rk_tol,
+                     aa_depth)
         self.green_operator = green
         h = ctypes.c_void_p()
         arr = (ctypes.c_void_p * self.n_rve)(*[p._h.value for p in probs])

@@ -61,7 +61,7 @@ class CpfOptions(ctypes.Structure):
     _fields_ = [
         ("precision", _i), ("tol", _d), ("max_iter", _i), ("h_max", _d),
         ("rk4_M", _i), ("lam0", _d), ("mu0", _d), ("stag_tol", _d),
-        ("check_every", _i), ("green", _i), ("rk_tol", _d),
+        ("check_every", _i), ("green", _i), ("rk_tol", _d), ("aa_depth", _i),
     ]
 
 

@@ -88,6 +88,7 @@ extern "C" void cpf_options_default(cpf_options *o)
     o->check_every = 0;
     o->green = CPF_GREEN_CONTINUOUS;
     o->rk_tol = 0.0;
+    o->aa_depth = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -290,6 +291,7 @@ struct RveHost {
     bool tiles_fixed = false;   // set explicitly or by the autotuner
     size_t off_labels, off_Q, off_eps[2], off_st[2], off_spec, off_tw[3], off_px, off_pz, off_sc, off_mv;
     size_t off_pb;
+    size_t off_aa = 0, off_aax = 0, off_aaf = 0, off_aadx = 0, off_aadf = 0, off_aap = 0, off_aac = 0;
     int cur = 0;
     double Sigma_n[6], E_n[6];
     int prev_iters = 8;
@@ -471,6 +473,16 @@ static void layout(cpf_solver *s)
         h.off_sc = take(sizeof(Scalars));
         h.off_mv = take(sizeof(int32_t) * h.nvox);
         h.off_pb = take(sizeof(double) * (NPX + 1) * BC_CHUNKS);
+        if (s->opt.aa_depth > 0) {
+            const size_t f6 = sizeof(R) * 6 * h.nvox;
+            h.off_aa = take(sizeof(AaState));
+            h.off_aax = take(f6);
+            h.off_aaf = take(f6);
+            h.off_aadx = take(f6 * s->opt.aa_depth);
+            h.off_aadf = take(f6 * s->opt.aa_depth);
+            h.off_aap = take(sizeof(double) * 2 * AA_MAX * h.nbx);
+            h.off_aac = take(sizeof(double) * 2 * AA_MAX * 32);
+        }
     }
     const size_t n = s->rv.size();
     s->off_dev = take(sizeof(RveDev<R>) * n);
@@ -508,6 +520,14 @@ static RveDev<R> make_dev(cpf_solver *s, const RveHost &h, int bx0, int by0, int
     d.part_x = dptr<double>(s, h.off_px);
     d.part_z = dptr<double>(s, h.off_pz);
     d.part_b = dptr<double>(s, h.off_pb);
+    d.aa_depth = s->opt.aa_depth;
+    d.aa = s->opt.aa_depth > 0 ? dptr<AaState>(s, h.off_aa) : nullptr;
+    d.aa_x = s->opt.aa_depth > 0 ? dptr<R>(s, h.off_aax) : nullptr;
+    d.aa_f = s->opt.aa_depth > 0 ? dptr<R>(s, h.off_aaf) : nullptr;
+    d.aa_dX = s->opt.aa_depth > 0 ? dptr<R>(s, h.off_aadx) : nullptr;
+    d.aa_dF = s->opt.aa_depth > 0 ? dptr<R>(s, h.off_aadf) : nullptr;
+    d.aa_part = s->opt.aa_depth > 0 ? dptr<double>(s, h.off_aap) : nullptr;
+    d.aa_chunk = s->opt.aa_depth > 0 ? dptr<double>(s, h.off_aac) : nullptr;
     d.sc = dptr<Scalars>(s, h.off_sc);
     return d;
 }
@@ -606,6 +626,8 @@ extern "C" int cpf_batch_create(int n, const cpf_problem *const *probs, const cp
         return fail(CPF_E_INVALID_ARG, "unknown Green operator %d", o.green);
     if (!(o.rk_tol >= 0.0) || !std::isfinite(o.rk_tol))
         return fail(CPF_E_INVALID_ARG, "rk_tol must be finite and >= 0");
+    if (o.aa_depth < 0 || o.aa_depth > AA_MAX)
+        return fail(CPF_E_INVALID_ARG, "aa_depth must be in [0, %d]", AA_MAX);
     cpf_solver *s = new (std::nothrow) cpf_solver();
     if (!s) return fail(CPF_E_INVALID_ARG, "out of host memory");
     const cpf_problem &p0 = *probs[0];
@@ -990,6 +1012,14 @@ static void launch_bc(cpf_solver *s)
 template <typename R>
 static int launch_iteration(cpf_solver *s, const LawP<R> &P)
 {
+    if (s->opt.aa_depth > 0) {
+        // Anderson: step of the last iterate, its dot products, the small solve
+        const RveDev<R> *tab = dptr<RveDev<R>>(s, s->off_dev);
+        const int nrve = (int)s->rv.size();
+        hipLaunchKernelGGL(k_aa_resid<R>, dim3(s->nbx_tot), dim3(256), xfft_lds_bytes<R>(), s->stream, tab, nrve);
+        hipLaunchKernelGGL(k_aa_partials<R>, dim3(nrve * 32), dim3(256), 0, s->stream, tab);
+        hipLaunchKernelGGL(k_aa_solve<R>, dim3(nrve), dim3(64), 0, s->stream, tab);
+    }
     TIMED(s, 0, launch_xiter_any<R>(s, P));
     TIMED(s, 1, launch_y<R>(s, false));
     TIMED(s, 2, launch_z<R>(s, ZMODE_FWD | ZMODE_GREEN));
@@ -1495,6 +1525,8 @@ extern "C" int cpf_adjoint_workspace_size(const cpf_solver *s, const cpf_path *p
     if (s->rv.size() != 1) return fail(CPF_E_INVALID_ARG, "the adjoint needs a single-RVE solver");
     if (s->opt.rk_tol > 0.0)
         return fail(CPF_E_INVALID_ARG, "the adjoint replays fixed substep counts: rk_tol must be 0");
+    if (s->opt.aa_depth > 0)
+        return fail(CPF_E_INVALID_ARG, "the adjoint runs the basic fixed point: aa_depth must be 0");
     int rc = check_path(path);
     if (rc) return rc;
     if (checkpoint_every < 1) return fail(CPF_E_INVALID_ARG, "checkpoint_every must be >= 1");

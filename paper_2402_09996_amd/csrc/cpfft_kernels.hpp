@@ -38,6 +38,23 @@ struct Scalars {
     double work_active, work_newton;   // law work counters summed over the step
 };
 
+// Anderson acceleration of the fixed point (an option): the last AA_MAX
+// differences of iterates and basic-scheme steps of one RVE, and the small
+// least-squares system built from them (FP64).
+constexpr int AA_MAX = 8;
+struct AaState {
+    int depth;                   // m (0: off)
+    int count;                   // stored differences (<= m)
+    int head;                    // ring slot of the oldest difference
+    int slot;                    // slot written by the current iteration (-1: none)
+    int have_prev;               // an earlier iterate and step are stored
+    int nk;                      // differences used by the current update
+    double G[AA_MAX][AA_MAX];    // dF_s . dF_t by ring slots
+    double gamma[AA_MAX];        // coefficients by ring slot
+    double E_prev[6], dE_prev[6];
+    double dEX[AA_MAX][6], ddE[AA_MAX][6];   // mean-strain parts of dX and dF
+};
+
 // One RVE of a (possibly one-element) batch as the kernels see it.  Every
 // pass launches one grid over all RVEs; block b belongs to the RVE whose
 // first block of that pass (bx0/by0/bz0) is the largest one <= b.
@@ -63,6 +80,12 @@ struct RveDev {
     double *part_x;            // [x blocks][NPX]
     double *part_z;            // [z blocks]
     double *part_b;            // [BC_CHUNKS][NPX + 1]: the x and z block sums in fixed chunks
+    AaState *aa;               // Anderson state (null: off)
+    int aa_depth;              // m
+    R *aa_x, *aa_f;            // last iterate and its basic step [6][nvox]
+    R *aa_dX, *aa_dF;          // difference rings [m][6][nvox]
+    double *aa_part;           // [x blocks][2 AA_MAX] block dot products
+    double *aa_chunk;          // [BC_CHUNKS][2 AA_MAX]
     Scalars *sc;
 };
 
@@ -368,7 +391,10 @@ __global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_xpass_ite
     C2<R> *twl = buf + 3 * 256;     // twiddles of the x transforms
     for (int i = tid; i < d.nx; i += nthr) twl[i] = d.tw[0][i];
     R corr[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-    if (!first) {
+    // Anderson mode: the iterate comes from the stored step and difference
+    // rings (k_aa_resid did the inverse x transform); uniform per block
+    const bool aam = d.aa != nullptr && !first;
+    if (!first && !aam) {
         if (tid < d.tpbx)
             load_halfspec_pairs(d.spec, buf, d.nx, d.ny, d.nz, d.nkx, d.nhp, d.L, li, x, y, z, valid);
         __syncthreads();
@@ -391,10 +417,27 @@ __global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_xpass_ite
     if (valid) {
         const R *base = first ? eps_n : eps_k;
         R e1[6], e0[6];
+        if (aam) {
+            // x_k = x_{k-1} + f_{k-1} - sum_s gamma_s (dX_s + dF_s)
+            const AaState *aa = d.aa;
+            const int nk = aa->nk, hd = aa->head, m = d.aa_depth;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) {
-            e1[c] = base[c * d.nvox + vox] - corr[c] + R(sc->dE[c]);
-            e0[c] = eps_n[c * d.nvox + vox];
+            for (int c = 0; c < 6; ++c) e1[c] = eps_k[c * d.nvox + vox] + d.aa_f[c * d.nvox + vox];
+            for (int t = 0; t < nk; ++t) {
+                const int sl = (hd + t) % m;
+                const R g = R(aa->gamma[sl]);
+                const long o = (long)sl * 6 * d.nvox + vox;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) e1[c] -= g * (d.aa_dX[o + c * d.nvox] + d.aa_dF[o + c * d.nvox]);
+            }
+#pragma unroll
+            for (int c = 0; c < 6; ++c) e0[c] = eps_n[c * d.nvox + vox];
+        } else {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                e1[c] = base[c * d.nvox + vox] - corr[c] + R(sc->dE[c]);
+                e0[c] = eps_n[c * d.nvox + vox];
+            }
         }
 #pragma unroll
         for (int c = 0; c < 6; ++c) eps_k[c * d.nvox + vox] = e1[c];
@@ -721,6 +764,14 @@ __global__ void k_begin_step(const RveDev<R> *__restrict__ rv, const StepInit *_
     sc->err_eq = sc->err_bc = 0.0;
     sc->mean_sig_eq = sc->mean_v = sc->mean_f = 0.0;
     sc->work_active = sc->work_newton = 0.0;
+    AaState *aa = rv[blockIdx.x].aa;
+    if (aa) {
+        aa->count = 0;
+        aa->head = 0;
+        aa->slot = -1;
+        aa->have_prev = 0;
+        aa->nk = 0;
+    }
 }
 
 struct BcArgs {
@@ -732,6 +783,223 @@ struct BcArgs {
 __device__ __forceinline__ double frob2(const double a[6])
 {
     return a[0] * a[0] + a[1] * a[1] + a[2] * a[2] + 2.0 * (a[3] * a[3] + a[4] * a[4] + a[5] * a[5]);
+}
+
+// ---------------------------------------------------------------------------
+// Anderson acceleration (an option; Walker and Ni, 2011): with x_j the
+// iterates and f_j = -Gamma0 * sigma(x_j) + dE_j the basic scheme's steps,
+// x_{k+1} = x_k + f_k - sum_s gamma_s (dX_s + dF_s) over the last (up to)
+// m differences dX = x_{j+1} - x_j, dF = f_{j+1} - f_j, gamma solving
+// (G + lam I) gamma = dF^T f_k, G = dF^T dF (Frobenius products of the
+// fields), lam = 1e-14 trace(G) / m_k.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void aa_ring_after(const AaState &a, int m, int &slot, int &cnt, int &head)
+{
+    // ring after inserting one difference (only when an earlier step exists)
+    if (a.count < m) {
+        slot = (a.head + a.count) % m;
+        cnt = a.count + 1;
+        head = a.head;
+    } else {
+        slot = a.head;
+        cnt = m;
+        head = (a.head + 1) % m;
+    }
+}
+
+// Per x-line block: the inverse x transform of the spectrum (the step of
+// the last iterate), the new differences into the rings, and the block
+// sums of dF_s . f (slots 0..m-1) and dF_s . dF_new (AA_MAX + slot).
+template <typename R>
+__global__ __launch_bounds__(256) void k_aa_resid(const RveDev<R> *__restrict__ rv, int nrve)
+{
+    const int r = find_rve(rv, nrve, (int)blockIdx.x, 0);
+    const RveDev<R> &d = rv[r];
+    Scalars *sc = d.sc;
+    if (!d.aa || sc->done || sc->iter == 0) return;
+    extern __shared__ unsigned char smem_raw[];
+    C2<R> *buf = reinterpret_cast<C2<R> *>(smem_raw);
+    const int tid = threadIdx.x, nthr = blockDim.x;
+    const int li = tid / d.nx, x = tid - li * d.nx;
+    const int line = (blockIdx.x - d.bx0) * d.L + li;
+    const bool valid = tid < d.tpbx && line < d.nlines;
+    const int y = valid ? line % d.ny : 0, z = valid ? line / d.ny : 0;
+    const long vox = (long)line * d.nx + x;
+    C2<R> *twl = buf + 3 * 256;
+    for (int i = tid; i < d.nx; i += nthr) twl[i] = d.tw[0][i];
+    if (tid < d.tpbx) load_halfspec_pairs(d.spec, buf, d.nx, d.ny, d.nz, d.nkx, d.nhp, d.L, li, x, y, z, valid);
+    __syncthreads();
+    lds_fft<R, true, 8>(buf, 3 * d.L, d.nx, d.px, twl, tid, nthr);
+    const AaState &a = *d.aa;
+    const int m = d.aa_depth;
+    const bool have = a.have_prev != 0;
+    int slot = -1, cnt = 0, head = 0;
+    if (have) aa_ring_after(a, m, slot, cnt, head);
+    double part[2 * AA_MAX];
+#pragma unroll
+    for (int i = 0; i < 2 * AA_MAX; ++i) part[i] = 0.0;
+    if (valid) {
+        R f[6], dF[6];
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            const C2<R> zz = buf[(p * d.L + li) * d.nx + x];
+            f[2 * p] = -zz.x * d.inv_nvox + R(sc->dE[2 * p]);
+            f[2 * p + 1] = -zz.y * d.inv_nvox + R(sc->dE[2 * p + 1]);
+        }
+        const R *eps_k = d.eps[1 - sc->cur];
+        if (have) {
+            const long o = (long)slot * 6 * d.nvox + vox;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) {
+                const long i = (long)c * d.nvox + vox;
+                dF[c] = f[c] - d.aa_f[i];
+                d.aa_dF[o + c * d.nvox] = dF[c];
+                d.aa_dX[o + c * d.nvox] = eps_k[i] - d.aa_x[i];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            const long i = (long)c * d.nvox + vox;
+            d.aa_f[i] = f[c];
+            d.aa_x[i] = eps_k[i];
+        }
+        if (have) {
+            for (int t = 0; t < cnt; ++t) {
+                const int sl = (head + t) % m;
+                const long o = (long)sl * 6 * d.nvox + vox;
+                double p1 = 0.0, p2 = 0.0;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    const double w = c < 3 ? 1.0 : 2.0;   // Frobenius product in tensor components
+                    const double g = sl == slot ? (double)dF[c] : (double)d.aa_dF[o + c * d.nvox];
+                    p1 += w * g * (double)f[c];
+                    p2 += w * g * (double)dF[c];
+                }
+                // slots < AA_MAX: constant indices keep part[] in registers
+#pragma unroll
+                for (int q = 0; q < AA_MAX; ++q)
+                    if (q == sl) {
+                        part[q] += p1;
+                        part[AA_MAX + q] += p2;
+                    }
+            }
+        }
+    }
+    block_sum<2 * AA_MAX, 4>(part, d.aa_part + (long)(blockIdx.x - d.bx0) * 2 * AA_MAX);
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_aa_partials(const RveDev<R> *__restrict__ rv)
+{
+    const RveDev<R> &d = rv[blockIdx.x / 32];
+    const int c = blockIdx.x % 32;
+    if (!d.aa || d.sc->done || d.sc->iter == 0) return;
+    const int nbx = (d.nlines + d.L - 1) / d.L;
+    const int x0 = (int)((long)nbx * c / 32), x1 = (int)((long)nbx * (c + 1) / 32);
+    double acc[2 * AA_MAX];
+#pragma unroll
+    for (int i = 0; i < 2 * AA_MAX; ++i) acc[i] = 0.0;
+    for (int j = x0 + threadIdx.x; j < x1; j += blockDim.x)
+#pragma unroll
+        for (int i = 0; i < 2 * AA_MAX; ++i) acc[i] += d.aa_part[(long)j * 2 * AA_MAX + i];
+    block_sum<2 * AA_MAX, 4>(acc, d.aa_chunk + (long)c * 2 * AA_MAX);
+}
+
+// One wave per RVE: the Gram row of the new difference, the regularized
+// normal equations by Cholesky (FP64), and the same mixing of the mean
+// strain E (sc->E holds the basic step's E_{k-1} + dE_{k-1}).
+template <typename R>
+__global__ __launch_bounds__(64) void k_aa_solve(const RveDev<R> *__restrict__ rv)
+{
+    const RveDev<R> &d = rv[blockIdx.x];
+    Scalars *sc = d.sc;
+    if (!d.aa || sc->done || sc->iter == 0) return;
+    double acc[2 * AA_MAX];
+#pragma unroll
+    for (int i = 0; i < 2 * AA_MAX; ++i) acc[i] = 0.0;
+    for (int j = threadIdx.x; j < 32; j += blockDim.x)
+#pragma unroll
+        for (int i = 0; i < 2 * AA_MAX; ++i) acc[i] += d.aa_chunk[(long)j * 2 * AA_MAX + i];
+    __shared__ double tot[2 * AA_MAX];
+    block_sum<2 * AA_MAX, 1>(acc, tot);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    AaState &a = *d.aa;
+    const int m = d.aa_depth;
+    double Ek[6], dEk[6];
+    for (int i = 0; i < 6; ++i) {
+        dEk[i] = sc->dE[i];
+        Ek[i] = sc->E[i] - sc->dE[i];   // E of the last iterate
+    }
+    if (!a.have_prev) {
+        for (int i = 0; i < 6; ++i) {
+            a.E_prev[i] = Ek[i];
+            a.dE_prev[i] = dEk[i];
+        }
+        a.have_prev = 1;
+        a.nk = 0;
+        a.slot = -1;
+        return;   // basic step: E stays E_{k-1} + dE_{k-1}
+    }
+    int slot, cnt, head;
+    aa_ring_after(a, m, slot, cnt, head);
+    for (int t = 0; t < cnt; ++t) {
+        const int sl = (head + t) % m;
+        a.G[slot][sl] = tot[AA_MAX + sl];
+        a.G[sl][slot] = tot[AA_MAX + sl];
+    }
+    for (int i = 0; i < 6; ++i) {
+        a.dEX[slot][i] = Ek[i] - a.E_prev[i];
+        a.ddE[slot][i] = dEk[i] - a.dE_prev[i];
+        a.E_prev[i] = Ek[i];
+        a.dE_prev[i] = dEk[i];
+    }
+    a.count = cnt;
+    a.head = head;
+    a.slot = slot;
+    // (G + lam I) g = b over the slots in ring order, Cholesky L L^T
+    double A[AA_MAX][AA_MAX], b[AA_MAX], tr = 0.0;
+    for (int t = 0; t < cnt; ++t) tr += a.G[(head + t) % m][(head + t) % m];
+    const double lam = 1e-14 * tr / cnt;
+    bool ok = tr > 0.0;
+    for (int t = 0; t < cnt; ++t) {
+        const int st = (head + t) % m;
+        b[t] = tot[st];
+        for (int u = 0; u < cnt; ++u) A[t][u] = a.G[st][(head + u) % m] + (t == u ? lam : 0.0);
+    }
+    for (int t = 0; t < cnt && ok; ++t) {
+        for (int u = 0; u <= t; ++u) {
+            double sum = A[t][u];
+            for (int q = 0; q < u; ++q) sum -= A[t][q] * A[u][q];
+            if (t == u) {
+                if (!(sum > 0.0)) { ok = false; break; }
+                A[t][t] = sqrt(sum);
+            } else {
+                A[t][u] = sum / A[u][u];
+            }
+        }
+    }
+    if (!ok) {
+        a.nk = 0;   // degenerate history: the basic step
+        return;
+    }
+    double g[AA_MAX];
+    for (int t = 0; t < cnt; ++t) {
+        double sum = b[t];
+        for (int q = 0; q < t; ++q) sum -= A[t][q] * g[q];
+        g[t] = sum / A[t][t];
+    }
+    for (int t = cnt - 1; t >= 0; --t) {
+        double sum = g[t];
+        for (int q = t + 1; q < cnt; ++q) sum -= A[q][t] * g[q];
+        g[t] = sum / A[t][t];
+    }
+    for (int t = 0; t < cnt; ++t) {
+        const int st = (head + t) % m;
+        a.gamma[st] = g[t];
+        for (int i = 0; i < 6; ++i) sc->E[i] -= g[t] * (a.dEX[st][i] + a.ddE[st][i]);
+    }
+    a.nk = cnt;
 }
 
 // First stage of the scalar reduction: BC_CHUNKS blocks per RVE each sum a
