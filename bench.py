@@ -428,6 +428,37 @@ def substeps_leg(cp, w, KS, r32, K, nvox, rk_tol=1e-8):
     return out
 
 
+def anderson_leg(cp, w, KA, r32, K, nvox, depth=4):
+    """The same FP32 workload with the Anderson-accelerated fixed point:
+    iterations, time per load step (the figure of merit here: the
+    throughput per iteration drops by the extra passes) and the difference
+    of Sigma_xx from the basic scheme's run."""
+    import numpy as np
+    import torch
+    s = cp.Solver(cp.Problem.from_workload(w), precision="fp32", tol=1e-6, stag_tol=1e-4, aa_depth=depth)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    iters, outs = 0, []
+    for n in range(KA):
+        o = s.step(w.path, n)
+        iters += int(o["iters"])
+        outs.append(o)
+        if n % 10 == 9:
+            print("[bench] anderson step %d iters %d Sigma_xx %.4f" % (n, o["iters"], o["Sigma"][0]),
+                  file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    out = {"depth": depth, "steps": KA, "iterations": iters, "ms_per_step": wall / KA * 1e3,
+           "value": iters * nvox / wall, "unit": "voxel-iterations/s"}
+    if KA == K:
+        a = np.array([o["Sigma"][0] for o in outs])
+        b = np.array([o["Sigma"][0] for o in r32["outs"]])
+        out["iterations_vs_basic"] = iters / max(1, r32["iters"])
+        out["wall_vs_basic"] = wall / r32["wall"]
+        out["max_rel_diff_Sigma_xx_vs_basic"] = float(np.abs(a - b).max() / np.abs(b).max())
+    return out
+
+
 def histogram_leg(s32, nvox, reps=20, nbins=150, lo=0.0, hi=1500.0):
     """Distribution of the local von Mises stress of the committed 128^3
     state (post-processing after the timed steps): the stress pass (reads
@@ -583,6 +614,7 @@ def main():
     if KG > 0:
         line["rotated_green"] = green_leg(cp, w, KG, min(W, 1), r32, K, nvox)
         line["error_controlled_substeps"] = substeps_leg(cp, w, KG, r32, K, nvox)
+        line["anderson"] = anderson_leg(cp, w, KG, r32, K, nvox)
     line["seq_histogram"] = histogram_leg(s32, nvox)
     if not args.no_micro:
         line["microstructure"] = micro_leg(cp)
