@@ -33,7 +33,7 @@ FP64_PEAK_TFLOPS = 78.6
 # HBM bytes per launch of the x pass (the dominant kernel) at 128^3 FP32,
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy (factors
 # 0.5 and 1.0); valid only for the library sources they were taken on.
-XPASS_TRAFFIC = {"src": "6aa562d6c7ccf1f1", "read_bytes": 628.4e6, "write_bytes": 579.4e6}
+XPASS_TRAFFIC = {"src": "ed06eeebc0c0f65e", "read_bytes": 728.9e6, "write_bytes": 663.6e6}
 
 
 def library_source_hash() -> str:
