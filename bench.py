@@ -33,7 +33,7 @@ FP64_PEAK_TFLOPS = 78.6
 # HBM bytes per launch of the x pass (the dominant kernel) at 128^3 FP32,
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy (factors
 # 0.5 and 1.0); valid only for the library sources they were taken on.
-XPASS_TRAFFIC = {"src": "ed06eeebc0c0f65e", "read_bytes": 728.9e6, "write_bytes": 663.6e6}
+XPASS_TRAFFIC = {"src": "4ff83e70162112c6", "read_bytes": 628.2e6, "write_bytes": 579.4e6}
 
 
 def library_source_hash() -> str:
@@ -568,7 +568,7 @@ def main():
         ach = flops / avg_s / 1e12
         same = library_source_hash() == XPASS_TRAFFIC["src"] and (nz, ny, nx) == (128, 128, 128)
         traffic = XPASS_TRAFFIC["read_bytes"] + XPASS_TRAFFIC["write_bytes"] if same else None
-        roof = {"bound": "alu", "kernel": "k_xpass_iter<float,16>", "achieved": ach,
+        roof = {"bound": "alu", "kernel": "k_xpass_iter<float,16,1,false,false>", "achieved": ach,
                 "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ach / FP32_PEAK_TFLOPS,
                 "traffic": traffic, "traffic_unit": "bytes per launch",
                 "algorithmic_bytes": 428.0 * nvox, "avg_launch_ms": avg_s * 1e3,

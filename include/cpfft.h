@@ -122,7 +122,8 @@ typedef struct cpf_options {
  * mean strain is mixed with the same coefficients.  Converged results are
  * those of the basic scheme to the tolerance; iterations are fewer.  Costs
  * (2 m + 2) strain fields of workspace per RVE and a pass over them per
- * iteration.  The adjoint entry points need aa_depth = 0. */
+ * iteration.  The adjoint entry points need aa_depth = 0, and it excludes
+ * rk_tol > 0. */
 
 /* Error-controlled substeps (an option; the paper integrates each load
  * step with a fixed number of RK4 substeps).  With rk_tol > 0, at the first

@@ -628,6 +628,8 @@ extern "C" int cpf_batch_create(int n, const cpf_problem *const *probs, const cp
         return fail(CPF_E_INVALID_ARG, "rk_tol must be finite and >= 0");
     if (o.aa_depth < 0 || o.aa_depth > AA_MAX)
         return fail(CPF_E_INVALID_ARG, "aa_depth must be in [0, %d]", AA_MAX);
+    if (o.aa_depth > 0 && o.rk_tol > 0.0)
+        return fail(CPF_E_INVALID_ARG, "Anderson acceleration and error-controlled substeps are exclusive");
     cpf_solver *s = new (std::nothrow) cpf_solver();
     if (!s) return fail(CPF_E_INVALID_ARG, "out of host memory");
     const cpf_problem &p0 = *probs[0];
@@ -919,6 +921,9 @@ static void launch_xiter(cpf_solver *s, const LawP<R> &P)
         const double lim2 = (15.0 * s->opt.rk_tol) * (15.0 * s->opt.rk_tol);
         hipLaunchKernelGGL((k_xpass_iter<R, NS, SPEC, true>), dim3(s->nbx_tot), dim3(256), s->lds_x, s->stream,
                            dptr<RveDev<R>>(s, s->off_dev), (int)s->rv.size(), P, lim2, CPF_RK_MAX_DOUBLINGS);
+    } else if (s->opt.aa_depth > 0) {
+        hipLaunchKernelGGL((k_xpass_iter<R, NS, SPEC, false, true>), dim3(s->nbx_tot), dim3(256), s->lds_x,
+                           s->stream, dptr<RveDev<R>>(s, s->off_dev), (int)s->rv.size(), P, 0.0, 0);
     } else {
         hipLaunchKernelGGL((k_xpass_iter<R, NS, SPEC, false>), dim3(s->nbx_tot), dim3(256), s->lds_x, s->stream,
                            dptr<RveDev<R>>(s, s->off_dev), (int)s->rv.size(), P, 0.0, 0);
@@ -1019,6 +1024,7 @@ static int launch_iteration(cpf_solver *s, const LawP<R> &P)
         hipLaunchKernelGGL(k_aa_resid<R>, dim3(s->nbx_tot), dim3(256), xfft_lds_bytes<R>(), s->stream, tab, nrve);
         hipLaunchKernelGGL(k_aa_partials<R>, dim3(nrve * 32), dim3(256), 0, s->stream, tab);
         hipLaunchKernelGGL(k_aa_solve<R>, dim3(nrve), dim3(64), 0, s->stream, tab);
+        hipLaunchKernelGGL(k_aa_update<R>, dim3(s->nbx_tot), dim3(256), 0, s->stream, tab, nrve);
     }
     TIMED(s, 0, launch_xiter_any<R>(s, P));
     TIMED(s, 1, launch_y<R>(s, false));

@@ -366,7 +366,7 @@ constexpr size_t xfft_lds_bytes()
     return (3 * 256 + 256) * sizeof(C2<R>);
 }
 
-template <typename R, int NS, int SPEC, bool ADAPT = false>
+template <typename R, int NS, int SPEC, bool ADAPT = false, bool AAM = false>
 __global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_xpass_iter(
     const RveDev<R> *__restrict__ rv, int nrve, LawP<R> Parg, double rk_lim2, int rk_maxd)
 {
@@ -391,9 +391,9 @@ __global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_xpass_ite
     C2<R> *twl = buf + 3 * 256;     // twiddles of the x transforms
     for (int i = tid; i < d.nx; i += nthr) twl[i] = d.tw[0][i];
     R corr[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-    // Anderson mode: the iterate comes from the stored step and difference
-    // rings (k_aa_resid did the inverse x transform); uniform per block
-    const bool aam = d.aa != nullptr && !first;
+    // Anderson mode (AAM): k_aa_update has written the iterate into eps_k
+    // (and k_aa_resid did the inverse x transform)
+    const bool aam = AAM && !first;
     if (!first && !aam) {
         if (tid < d.tpbx)
             load_halfspec_pairs(d.spec, buf, d.nx, d.ny, d.nz, d.nkx, d.nhp, d.L, li, x, y, z, valid);
@@ -417,21 +417,12 @@ __global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_xpass_ite
     if (valid) {
         const R *base = first ? eps_n : eps_k;
         R e1[6], e0[6];
-        if (aam) {
-            // x_k = x_{k-1} + f_{k-1} - sum_s gamma_s (dX_s + dF_s)
-            const AaState *aa = d.aa;
-            const int nk = aa->nk, hd = aa->head, m = d.aa_depth;
+        if constexpr (AAM) {
 #pragma unroll
-            for (int c = 0; c < 6; ++c) e1[c] = eps_k[c * d.nvox + vox] + d.aa_f[c * d.nvox + vox];
-            for (int t = 0; t < nk; ++t) {
-                const int sl = (hd + t) % m;
-                const R g = R(aa->gamma[sl]);
-                const long o = (long)sl * 6 * d.nvox + vox;
-#pragma unroll
-                for (int c = 0; c < 6; ++c) e1[c] -= g * (d.aa_dX[o + c * d.nvox] + d.aa_dF[o + c * d.nvox]);
+            for (int c = 0; c < 6; ++c) {
+                e1[c] = aam ? base[c * d.nvox + vox] : base[c * d.nvox + vox] + R(sc->dE[c]);
+                e0[c] = eps_n[c * d.nvox + vox];
             }
-#pragma unroll
-            for (int c = 0; c < 6; ++c) e0[c] = eps_n[c * d.nvox + vox];
         } else {
 #pragma unroll
             for (int c = 0; c < 6; ++c) {
@@ -1000,6 +991,37 @@ __global__ __launch_bounds__(64) void k_aa_solve(const RveDev<R> *__restrict__ r
         for (int i = 0; i < 6; ++i) sc->E[i] -= g[t] * (a.dEX[st][i] + a.ddE[st][i]);
     }
     a.nk = cnt;
+}
+
+// The Anderson iterate x_k = x_{k-1} + f_{k-1} - sum_s gamma_s (dX_s +
+// dF_s), written over the iterate buffer (k_aa_resid has kept x_{k-1}).
+template <typename R>
+__global__ __launch_bounds__(256) void k_aa_update(const RveDev<R> *__restrict__ rv, int nrve)
+{
+    const int r = find_rve(rv, nrve, (int)blockIdx.x, 0);
+    const RveDev<R> &d = rv[r];
+    Scalars *sc = d.sc;
+    if (!d.aa || sc->done || sc->iter == 0) return;
+    const int tid = threadIdx.x;
+    const int li = tid / d.nx, x = tid - li * d.nx;
+    const int line = (blockIdx.x - d.bx0) * d.L + li;
+    if (tid >= d.tpbx || line >= d.nlines) return;
+    const long vox = (long)line * d.nx + x;
+    const AaState &a = *d.aa;
+    const int nk = a.nk, hd = a.head, m = d.aa_depth;
+    R *eps_k = d.eps[1 - sc->cur];
+    R e[6];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) e[c] = d.aa_x[c * d.nvox + vox] + d.aa_f[c * d.nvox + vox];
+    for (int t = 0; t < nk; ++t) {
+        const int sl = (hd + t) % m;
+        const R g = R(a.gamma[sl]);
+        const long o = (long)sl * 6 * d.nvox + vox;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) e[c] -= g * (d.aa_dX[o + c * d.nvox] + d.aa_dF[o + c * d.nvox]);
+    }
+#pragma unroll
+    for (int c = 0; c < 6; ++c) eps_k[c * d.nvox + vox] = e[c];
 }
 
 // First stage of the scalar reduction: BC_CHUNKS blocks per RVE each sum a

@@ -85,6 +85,8 @@ def test_argument_checks():
     p = cp.Problem.from_workload(w)
     with pytest.raises(cp.CpfError):
         cp.Solver(p, precision="fp64", aa_depth=9)
+    with pytest.raises(cp.CpfError):
+        cp.Solver(p, precision="fp64", aa_depth=4, rk_tol=1e-6)
     s = cp.Solver(p, precision="fp64", aa_depth=4)
     with pytest.raises(cp.CpfError):
         s.gradient(w.path, np.ones(w.path.n_steps))
