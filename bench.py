@@ -318,7 +318,7 @@ def micro_leg(cp, n=256, grains=1920.0, r=5.0, reps=3):
     return out
 
 
-def paper_leg(cp, steps=100, configs=("neighbouring",), n=256, seed=7, axes=(0,)):
+def paper_leg(cp, steps=100, configs=("neighbouring",), n=256, seed=7, axes=(0,), aa_depth=0):
     """The paper's parameter set (tetragonal stiffness, Table 1 with tau0
     130/200/130 MPa, twin-fraction law; b = 10, q = 1) on a generated 256^3
     realization (1920 expected grains, r = 5 voxels), FP32: uniaxial
@@ -333,14 +333,15 @@ def paper_leg(cp, steps=100, configs=("neighbouring",), n=256, seed=7, axes=(0,)
     lam_p = -math.log(1.0 - 1920.0 / n ** 3 * Vr) / Vr
     C, law = rvegen.paper_law()
     S = rvegen.table1_systems(True)
-    out = {"grid": [n, n, n], "steps": steps, "total_strain": -0.005, "precision": "fp32", "configs": {}}
+    out = {"grid": [n, n, n], "steps": steps, "total_strain": -0.005, "precision": "fp32",
+           "anderson_depth": aa_depth, "configs": {}}
     for name, axis in [(c, a) for c in configs for a in axes]:
         path = rvegen.uniaxial_path(-0.005, steps, axis=axis)
         pn, pi = {"neighbouring": (1.0, 0.0), "inclusion": (0.0, 1.0), "none": (0.0, 0.0)}[name]
         g = cp.generate_microstructure((n, n, n), lam_p, 5.0, pn, pi, (0.1, 0.3), math.radians(69.79), seed)
         prob = cp.Problem(g["labels"].cpu().numpy(), g["euler"], C, S.n_miller, S.l_miller, S.family, S.tau0,
                           law)
-        s = cp.Solver(prob, precision="fp32", tol=1e-6, stag_tol=1e-4)
+        s = cp.Solver(prob, precision="fp32", tol=1e-6, stag_tol=1e-4, aa_depth=aa_depth)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         iters, seq = 0, []
@@ -512,6 +513,7 @@ def main():
                     help="twin configurations of that leg: comma list of none,neighbouring,inclusion or 'all'")
     ap.add_argument("--paper-only", action="store_true", help="only run the paper-parameter leg")
     ap.add_argument("--paper-axes", default="x", help="load axis of that leg: x or 'all' (x, y, z)")
+    ap.add_argument("--paper-aa", type=int, default=0, help="Anderson depth of that leg (0: basic scheme)")
     ap.add_argument("--green-steps", type=int, default=None,
                     help="load steps of the rotated-operator FP32 leg (default: --steps)")
     ap.add_argument("--copy-probe", action="store_true",
@@ -529,7 +531,8 @@ def main():
         cf = ("none", "neighbouring", "inclusion") if args.paper_configs == "all" else \
             tuple(args.paper_configs.split(","))
         ax = (0, 1, 2) if args.paper_axes == "all" else (0,)
-        print(json.dumps({"paper_set": paper_leg(cp, args.paper_steps, cf, axes=ax)}), flush=True)
+        print(json.dumps({"paper_set": paper_leg(cp, args.paper_steps, cf, axes=ax, aa_depth=args.paper_aa)}),
+              flush=True)
         return
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the solver has no multi-GPU path "
