@@ -90,3 +90,12 @@ def test_argument_checks():
     s = cp.Solver(p, precision="fp64", aa_depth=4)
     with pytest.raises(cp.CpfError):
         s.gradient(w.path, np.ones(w.path.n_steps))
+
+
+def test_anderson_with_the_rotated_operator():
+    w = _w((8, 8, 8))
+    gs = cp.Solver(cp.Problem.from_workload(w), precision="fp64", tol=1e-12, aa_depth=4, green="rotated")
+    R = gs.run(w.path)
+    ref = oracle.solver_for(w, oracle.Options(tol=1e-12, aa_depth=4, green="rotated")).run(w.path)
+    assert _relerr(R["Sigma"], ref.Sigma) < 1e-10
+    assert np.abs(np.asarray(R["iters"]) - ref.iters).max() <= 1

@@ -38,7 +38,8 @@ def _relerr(a, b):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("green,shape", [("rotated", (8, 8, 8)), ("rotated", (12, 16, 24)),
                                          ("rotated", (6, 18, 32)), ("rotated", (9, 6, 27)),
-                                         ("continuous", (9, 6, 27)), ("rotated", (4, 2, 3))])
+                                         ("continuous", (9, 6, 27)), ("rotated", (4, 2, 3)),
+                                         ("rotated", (64, 128, 256))])
 def test_green_operator_matches_oracle(green, shape, precision):
     print("case", green, shape, precision, flush=True)
     w = _wl(shape, 3, 6)

@@ -93,3 +93,13 @@ def test_argument_checks():
     s = cp.Solver(p, precision="fp64", rk_tol=1e-6)
     with pytest.raises(cp.CpfError):
         s.gradient(w.path, np.ones(w.path.n_steps))
+
+
+def test_substeps_with_the_rotated_operator():
+    w = _w((6, 6, 6))
+    gs = cp.Solver(cp.Problem.from_workload(w), precision="fp64", tol=1e-11, rk_tol=1e-8, green="rotated")
+    R = gs.run(w.path)
+    o = oracle.solver_for(w, oracle.Options(tol=1e-11, rk_tol=1e-8, green="rotated"))
+    ref = o.run(w.path)
+    assert _relerr(R["Sigma"], ref.Sigma) < 1e-10
+    assert np.array_equal(R["iters"], ref.iters)
