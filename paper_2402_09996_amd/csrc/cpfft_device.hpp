@@ -397,6 +397,151 @@ __device__ __forceinline__ bool is_twin(const LawP<R> &P, int s)
     else return (P.twin_mask >> s) & 1u;
 }
 
+// Factored Schmid contractions of the Table 1 set.  Every slip tensor has
+// one diagonal entry +-A and one -+A (A = 1/sqrt6) and two shear entries
+// +-A/2; every twin tensor has the diagonal (B, B, -2B) (B = 1/sqrt18) and
+// the shear entries (+-B/2, +-B/2, +-B).  With sa = A sigma, a resolved
+// shear stress is then a signed diagonal difference of sa plus two signed
+// shear components (slip), or (B/A) times d02 + d12 plus three signed terms
+// (twin); the plastic strain rate collects signed sums of the rates per
+// pattern before one multiplication.  Only the rounding order differs
+// from the plain contraction.
+#ifndef CPF_T1_FACTOR
+#define CPF_T1_FACTOR 1
+#endif
+constexpr double T1_A = 0.40824829046386302;
+constexpr double T1_B = 0.23570226039551589;
+constexpr double T1_BA = T1_B / T1_A;   // 1/sqrt3
+
+constexpr bool t1_pattern_ok()
+{
+    for (int s = 0; s < 16; ++s) {
+        if (s < 12) {
+            int np = 0, nn = 0, nsh = 0;
+            for (int i = 0; i < 3; ++i) {
+                if (T1_M[s][i] == T1_A) ++np;
+                else if (T1_M[s][i] == -T1_A) ++nn;
+                else if (T1_M[s][i] != 0.0) return false;
+            }
+            for (int i = 3; i < 6; ++i) {
+                if (T1_M[s][i] == T1_A / 2 || T1_M[s][i] == -T1_A / 2) ++nsh;
+                else if (T1_M[s][i] != 0.0) return false;
+            }
+            if (np != 1 || nn != 1 || nsh != 2) return false;
+        } else {
+            if (T1_M[s][0] != T1_B || T1_M[s][1] != T1_B || T1_M[s][2] != -2 * T1_B) return false;
+            for (int i = 3; i < 6; ++i) {
+                const double e = i == 5 ? T1_B : T1_B / 2;
+                if (T1_M[s][i] != e && T1_M[s][i] != -e) return false;
+            }
+        }
+    }
+    return true;
+}
+static_assert(t1_pattern_ok(), "Table 1 Schmid tensors do not have the factored pattern");
+
+template <int SPEC>
+constexpr bool t1_factor()
+{
+    return SPEC == LAW_TABLE1 && CPF_T1_FACTOR != 0;
+}
+
+// Diagonal pair of slip system s (p < q: 0 = (0,1), 1 = (0,2), 2 = (1,2))
+// and the sign of its entry at p.
+__host__ __device__ constexpr int t1_pair(int s)
+{
+    return T1_M[s][2] == 0.0 ? 0 : T1_M[s][1] == 0.0 ? 1 : 2;
+}
+__host__ __device__ constexpr bool t1_pair_pos(int s)
+{
+    return T1_M[s][t1_pair(s) == 2 ? 1 : 0] > 0.0;
+}
+
+// sa = A sigma, dd = (sa0 - sa1, sa0 - sa2, sa1 - sa2), tT = dd1 + dd2,
+// u5 = 2 sa5.
+template <typename R>
+struct T1Sig {
+    R sa[6], dd[3], tT, u5;
+};
+template <typename R>
+__device__ __forceinline__ T1Sig<R> t1_sig(const R sig[6])
+{
+    T1Sig<R> t;
+#pragma unroll
+    for (int i = 0; i < 6; ++i) t.sa[i] = R(T1_A) * sig[i];
+    t.dd[0] = t.sa[0] - t.sa[1];
+    t.dd[1] = t.sa[0] - t.sa[2];
+    t.dd[2] = t.sa[1] - t.sa[2];
+    t.tT = t.dd[1] + t.dd[2];
+    t.u5 = t.sa[5] + t.sa[5];
+    return t;
+}
+template <typename R>
+__device__ __forceinline__ R t1_tau(int s, const T1Sig<R> &t)
+{
+    if (s < 12) {
+        const R d = t.dd[t1_pair(s)];
+        R x = t1_pair_pos(s) ? d : -d;
+#pragma unroll
+        for (int i = 3; i < 6; ++i) {
+            if (T1_M[s][i] > 0.0) x += t.sa[i];
+            else if (T1_M[s][i] < 0.0) x -= t.sa[i];
+        }
+        return x;
+    }
+    R x = t.tT;
+    x = T1_M[s][3] > 0.0 ? x + t.sa[3] : x - t.sa[3];
+    x = T1_M[s][4] > 0.0 ? x + t.sa[4] : x - t.sa[4];
+    x = T1_M[s][5] > 0.0 ? x + t.u5 : x - t.u5;
+    return R(T1_BA) * x;
+}
+
+// Signed rate sums of the factored plastic strain rate.
+template <typename R>
+struct T1Acc {
+    R G[3], Hs[3], W, Ht[3];
+};
+template <typename R>
+__device__ __forceinline__ void t1_acc_init(T1Acc<R> &a)
+{
+    // -0 is the additive identity: the first sums fold to moves
+#pragma unroll
+    for (int i = 0; i < 3; ++i) a.G[i] = a.Hs[i] = a.Ht[i] = R(-0.0);
+    a.W = R(-0.0);
+}
+template <typename R>
+__device__ __forceinline__ void t1_acc_add(T1Acc<R> &a, int s, R gd)
+{
+    if (s < 12) {
+        const int k = t1_pair(s);
+        a.G[k] = t1_pair_pos(s) ? a.G[k] + gd : a.G[k] - gd;
+#pragma unroll
+        for (int i = 3; i < 6; ++i) {
+            if (T1_M[s][i] > 0.0) a.Hs[i - 3] += gd;
+            else if (T1_M[s][i] < 0.0) a.Hs[i - 3] -= gd;
+        }
+    } else {
+        a.W += gd;
+#pragma unroll
+        for (int i = 3; i < 6; ++i) a.Ht[i - 3] = T1_M[s][i] > 0.0 ? a.Ht[i - 3] + gd : a.Ht[i - 3] - gd;
+    }
+}
+// dep = wslip sum_slip gd m + sum_twin gd m
+template <typename R>
+__device__ __forceinline__ void t1_acc_dep(const T1Acc<R> &a, R wslip, R dep[6])
+{
+    const R ws = wslip * R(T1_A);
+    const R g01 = ws * a.G[0], g02 = ws * a.G[1], g12 = ws * a.G[2];
+    const R bw = R(T1_B) * a.W;
+    dep[0] = (g01 + g02) + bw;
+    dep[1] = (g12 - g01) + bw;
+    dep[2] = R(-2) * bw - (g02 + g12);
+    const R wh = wslip * R(T1_A / 2);
+    dep[3] = wh * a.Hs[0] + R(T1_B / 2) * a.Ht[0];
+    dep[4] = wh * a.Hs[1] + R(T1_B / 2) * a.Ht[1];
+    dep[5] = wh * a.Hs[2] + R(T1_B) * a.Ht[2];
+}
+
 template <typename R, int SPEC>
 __device__ __forceinline__ void hooke_c(const R (&C)[36], const R ee[6], R sig[6])
 {
@@ -650,8 +795,11 @@ __device__ __forceinline__ void rk_stage_cmp(const LawP<R> &P, const R e[6], R (
     const R Atw = P.twin_mode ? P.Kc_gT * (P.fm - sumf) : R(1);
     const R etaAtw = P.eta * Atw;
     const R inv_etaAtw = P.twin_mode ? fdiv(R(1), etaAtw) : P.inv_eta;
-    // overstress of every system
-    uint32_t act = 0, neg = 0;
+    // overstress of every system, stored with the sign of the slip rate
+    // (zero for inactive systems)
+    uint32_t act = 0;
+    T1Sig<R> t1;
+    if constexpr (t1_factor<SPEC>()) t1 = t1_sig(sig);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         law_fence();
@@ -660,16 +808,21 @@ __device__ __forceinline__ void rk_stage_cmp(const LawP<R> &P, const R e[6], R (
         const R hs = law_park_h<R>() ? W.o[s * W.ls] : h[s];
         const R r = P.tau0[s] + F.QL * (tw ? Ht : Hs) + F.QD * hs;
         R tau = R(0);
+        if constexpr (t1_factor<SPEC>()) {
+            tau = t1_tau(s, t1);
+        } else {
 #pragma unroll
-        for (int i = 0; i < 6; ++i)
-            if (schmid_nonzero<SPEC>(s, i))
-                tau += (i < 3 ? sig[i] : R(2) * sig[i]) * schmid<R, SPEC>(P.m, s, i);
+            for (int i = 0; i < 6; ++i)
+                if (schmid_nonzero<SPEC>(s, i))
+                    tau += (i < 3 ? sig[i] : R(2) * sig[i]) * schmid<R, SPEC>(P.m, s, i);
+        }
         const R tx = tau - F.c * tal[s];
         const R o = tw ? tx - r : fabs(tx) - r;
         const R A = tw ? Atw : R(1);
-        if (o > R(0) && A > R(0)) act |= 1u << s;
-        if (!tw && tx < R(0)) neg |= 1u << s;
-        W.o[s * W.ls] = o;
+        const bool on = o > R(0) && A > R(0);
+        if (on) act |= 1u << s;
+        const R os = (!tw && tx < R(0)) ? -o : o;
+        W.o[s * W.ls] = on ? os : R(0);
     }
     nact += __popc(act);
     // Newton solves of the active systems, one system per lane per pass
@@ -681,27 +834,28 @@ __device__ __forceinline__ void rk_stage_cmp(const LawP<R> &P, const R e[6], R (
             const bool tw = SPEC == LAW_TABLE1 ? s >= 12 : ((P.twin_mask >> s) & 1u) != 0u;
             const FamP<R> &Fs = P.fs;
             const FamP<R> &Ft = P.ft;
-            const R o = W.o[s * W.ls];
+            const R os = W.o[s * W.ls];
+            const R o = fabs(os);
             R yw = ((warm >> s) & 1u) ? W.y[s * W.ls] : R(0);
             const R g = newton_root<R>(o, tw ? Atw : R(1), tw ? inv_etaAtw : P.inv_eta, tw ? etaAtw : P.eta,
                                        P.inv_eta, tw ? Ft.K : Fs.K, tw ? Ft.invK : Fs.invK, tw ? Ft.n : Fs.n,
                                        tw ? Ft.inv_n : Fs.inv_n, tw ? Ft.nm1 : Fs.nm1,
                                        tw ? Ft.nm1_int : Fs.nm1_int, P.newton_rtol, yw, nnewt);
             W.y[s * W.ls] = yw;
-            W.o[s * W.ls] = g;
+            W.o[s * W.ls] = os < R(0) ? -g : g;
         }
     }
     warm = act;
-    // rates of the internal variables
+    // rates of the internal variables (signed rates from the LDS column)
     R dep[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
+    T1Acc<R> acc;
+    if constexpr (t1_factor<SPEC>()) t1_acc_init(acc);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         law_fence();
         const bool tw = is_twin<SPEC>(P, s);
         const FamP<R> &F = tw ? P.ft : P.fs;
-        const R gl = W.o[s * W.ls];
-        const R g = ((act >> s) & 1u) ? gl : R(0);
-        const R gd = ((neg >> s) & 1u) ? -g : g;
+        const R gd = W.o[s * W.ls];
         const R ag = fabs(gd);
         const R dal = gd - F.d * ag * tal[s];
         av[s] += wacc * ag;
@@ -710,11 +864,16 @@ __device__ __forceinline__ void rk_stage_cmp(const LawP<R> &P, const R e[6], R (
             tv[s] = yv[s] + cnext * ag;
             tal[s] = yal[s] + cnext * dal;
         }
-        const R wg = tw ? gd : wslip * gd;
+        if constexpr (t1_factor<SPEC>()) {
+            t1_acc_add(acc, s, gd);
+        } else {
+            const R wg = tw ? gd : wslip * gd;
 #pragma unroll
-        for (int i = 0; i < 6; ++i)
-            if (schmid_nonzero<SPEC>(s, i)) dep[i] += wg * schmid<R, SPEC>(P.m, s, i);
+            for (int i = 0; i < 6; ++i)
+                if (schmid_nonzero<SPEC>(s, i)) dep[i] += wg * schmid<R, SPEC>(P.m, s, i);
+        }
     }
+    if constexpr (t1_factor<SPEC>()) t1_acc_dep(acc, wslip, dep);
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         aep[i] += wacc * dep[i];

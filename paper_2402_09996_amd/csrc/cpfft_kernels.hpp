@@ -1185,20 +1185,23 @@ __global__ __launch_bounds__(256) void k_stress_field(const int32_t *labels, con
 }
 
 // Square of the von Mises stress in FP64 by a fixed order of single,
-// correctly rounded operations (no contraction), so that a host
-// computation in the same order gives the same number:
+// correctly rounded operations, so that a host computation in the same
+// order gives the same number (plain operators in a scope with contraction
+// off: the rounding intrinsics of the HIP headers are plain operators
+// compiled under the default contraction, which fuses them once inlined):
 //   m = ((s11 + s22) + s33) / 3,  d_i = s_ii - m,
 //   J = ((d1 d1 + d2 d2) + d3 d3) + 2 ((s23 s23 + s13 s13) + s12 s12),
 //   sigma_eq^2 = 1.5 J.
 template <typename R>
 __device__ __forceinline__ double von_mises_sq_exact(const R s[6])
 {
+#pragma clang fp contract(off)
     const double a = s[0], b = s[1], c = s[2], d = s[3], e = s[4], f = s[5];
-    const double m = __ddiv_rn(__dadd_rn(__dadd_rn(a, b), c), 3.0);
-    const double d1 = __dsub_rn(a, m), d2 = __dsub_rn(b, m), d3 = __dsub_rn(c, m);
-    const double nrm = __dadd_rn(__dadd_rn(__dmul_rn(d1, d1), __dmul_rn(d2, d2)), __dmul_rn(d3, d3));
-    const double sh = __dadd_rn(__dadd_rn(__dmul_rn(d, d), __dmul_rn(e, e)), __dmul_rn(f, f));
-    return __dmul_rn(1.5, __dadd_rn(nrm, __dmul_rn(2.0, sh)));
+    const double m = ((a + b) + c) / 3.0;
+    const double d1 = a - m, d2 = b - m, d3 = c - m;
+    const double nrm = (d1 * d1 + d2 * d2) + d3 * d3;
+    const double sh = (d * d + e * e) + f * f;
+    return 1.5 * (nrm + 2.0 * sh);
 }
 
 // Histogram of the von Mises stress of a stress field [6][nvox] against

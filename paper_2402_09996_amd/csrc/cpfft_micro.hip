@@ -21,8 +21,10 @@
 #include "../../include/cpfft.h"
 #include "../../include/cpfft_micro.h"
 
-// Host arithmetic in the order written: the Poisson inversion and the
-// lattice draws must give the same integers wherever they are evaluated.
+// Arithmetic in the order written, host and device (no fused multiply-add):
+// the Poisson inversion and the lattice draws must give the same integers
+// wherever they are evaluated, and the slab test the same decision as a
+// host evaluation in the same order.
 #pragma clang fp contract(off)
 
 // error state shared with the solver's entry points
@@ -316,12 +318,12 @@ __global__ __launch_bounds__(256) void k_slabs(int32_t *__restrict__ lab, int nx
     double d[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
-        double t = __dsub_rn(c[k], S[3 + k]);
-        if (t > 0.5 * L[k]) t = __dsub_rn(t, L[k]);
-        else if (t < -0.5 * L[k]) t = __dadd_rn(t, L[k]);
+        double t = c[k] - S[3 + k];
+        if (t > 0.5 * L[k]) t = t - L[k];
+        else if (t < -0.5 * L[k]) t = t + L[k];
         d[k] = t;
     }
-    const double t = __dadd_rn(__dadd_rn(__dmul_rn(S[0], d[0]), __dmul_rn(S[1], d[1])), __dmul_rn(S[2], d[2]));
+    const double t = (S[0] * d[0] + S[1] * d[1]) + S[2] * d[2];
     if (fabs(t) <= S[6]) lab[v] = (int32_t)S[7];
 }
 
