@@ -242,6 +242,7 @@ __global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_law_recor
     const R h = a.dt / R(M), invM = R(1) / R(M);
     R de[6], yw[NS];
     uint32_t warm = 0;
+    law_fam_store(P, W);
 #pragma unroll
     for (int i = 0; i < 6; ++i) de[i] = e1[i] - e0[i];
 #pragma unroll

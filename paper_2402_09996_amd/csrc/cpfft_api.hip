@@ -437,7 +437,7 @@ static void pass_grids(cpf_solver *s)
 {
     s->nbx_tot = s->nby_tot = s->nbz_tot = 0;
     // x pass: FFT buffer, then the law's per-thread work area
-    s->lds_x = xfft_lds_bytes<R>() + (law_compact<R>() ? (2 * (size_t)s->ns_inst + 12) * 256 * sizeof(R) : 0);
+    s->lds_x = xfft_lds_bytes<R>() + law_lds_bytes_ns<R>(s->ns_inst);
     s->lds_y = s->lds_z = 0;
     s->y_elems = s->z_elems = 0;
     for (auto &h : s->rv) {

@@ -708,8 +708,21 @@ struct LawLds {
     R *o;       // [NS] overstress, then rate
     R *y;       // [NS] Newton roots (warm starts)
     R *e;       // [12] start and end strain of the load step
+    R *fam;     // [2][LAW_FAM_WORDS] Norton constants of the slip and twin
+                // families, one copy per wave (shared by its lanes)
     int ls;
 };
+
+// The Newton passes of the compacted stage take the constants of each
+// lane's family from a small per-wave table instead of selecting every one
+// of them between two scalar registers (two instructions each: a scalar
+// source must be moved to a vector register first).  Per family: K, 1/K,
+// n, 1/n, n - 1, the integer exponent (as a value of R; FP64 only) and two
+// words of padding (16-byte aligned rows).
+constexpr int LAW_FAM_WORDS = 8;
+#ifndef CPF_LAW_FAM_TABLE
+#define CPF_LAW_FAM_TABLE 1
+#endif
 
 // Whether the law kernels solve the active systems of a stage compacted per
 // lane (2 NS words of LDS per thread: 32 KB per 256-thread block in FP32 and
@@ -742,16 +755,57 @@ constexpr bool law_park_h()
 {
     return law_compact<R>() && (sizeof(R) == 4 ? CPF_PARK_H_F32 : CPF_PARK_H_F64);
 }
+// The strain path is not parked in FP64 beyond 16 systems: the x pass's
+// LDS (FFT lines, 2 NS columns, 12 strain rows) would exceed the 160 KB a
+// block may use.
 template <typename R>
+constexpr bool law_park_e_ns(int ns)
+{
+    return law_compact<R>() && (sizeof(R) == 4 ? CPF_PARK_E_F32 : CPF_PARK_E_F64) && !(sizeof(R) == 8 && ns > 16);
+}
+template <typename R, int NS>
 constexpr bool law_park_e()
 {
-    return law_compact<R>() && (sizeof(R) == 4 ? CPF_PARK_E_F32 : CPF_PARK_E_F64);
+    return law_park_e_ns<R>(NS);
+}
+template <typename R>
+constexpr int law_e_rows(int ns)
+{
+    return law_park_e_ns<R>(ns) ? 12 : 0;
 }
 
+// Bytes of the law's LDS work area of a 256-thread block: the per-thread
+// columns, then the family tables of its four waves.
+template <typename R>
+constexpr size_t law_lds_bytes_ns(int ns)
+{
+    return law_compact<R>() ? ((2 * (size_t)ns + law_e_rows<R>(ns)) * 256 + 4 * 2 * LAW_FAM_WORDS) * sizeof(R)
+                            : 0;
+}
 template <typename R, int NS>
 constexpr size_t law_lds_bytes()
 {
-    return law_compact<R>() ? (2 * NS + 12) * 256 * sizeof(R) : 0;
+    return law_lds_bytes_ns<R>(NS);
+}
+
+// Fill this wave's family table (every lane writes the same values; the
+// wave reads only its own table, after its own writes).
+template <typename R>
+__device__ __forceinline__ void law_fam_store(const LawP<R> &P, const LawLds<R> &W)
+{
+    if constexpr (law_compact<R>() && CPF_LAW_FAM_TABLE) {
+        const FamP<R> *F[2] = {&P.fs, &P.ft};
+#pragma unroll
+        for (int f = 0; f < 2; ++f) {
+            R *t = W.fam + f * LAW_FAM_WORDS;
+            t[0] = F[f]->K;
+            t[1] = F[f]->invK;
+            t[2] = F[f]->n;
+            t[3] = F[f]->inv_n;
+            t[4] = F[f]->nm1;
+            if constexpr (sizeof(R) == 8) t[5] = R(F[f]->nm1_int);
+        }
+    }
 }
 
 // The same RK4 stage as rk_stage, with the Newton solves compacted: the
@@ -837,10 +891,19 @@ __device__ __forceinline__ void rk_stage_cmp(const LawP<R> &P, const R e[6], R (
             const R os = W.o[s * W.ls];
             const R o = fabs(os);
             R yw = ((warm >> s) & 1u) ? W.y[s * W.ls] : R(0);
-            const R g = newton_root<R>(o, tw ? Atw : R(1), tw ? inv_etaAtw : P.inv_eta, tw ? etaAtw : P.eta,
-                                       P.inv_eta, tw ? Ft.K : Fs.K, tw ? Ft.invK : Fs.invK, tw ? Ft.n : Fs.n,
-                                       tw ? Ft.inv_n : Fs.inv_n, tw ? Ft.nm1 : Fs.nm1,
-                                       tw ? Ft.nm1_int : Fs.nm1_int, P.newton_rtol, yw, nnewt);
+            R g;
+            if constexpr (CPF_LAW_FAM_TABLE) {
+                const R *ft = W.fam + (tw ? LAW_FAM_WORDS : 0);
+                const int nm1_int = sizeof(R) == 8 ? (int)ft[5] : -1;
+                g = newton_root<R>(o, tw ? Atw : R(1), tw ? inv_etaAtw : P.inv_eta, tw ? etaAtw : P.eta,
+                                   P.inv_eta, ft[0], ft[1], ft[2], ft[3], ft[4], nm1_int, P.newton_rtol, yw,
+                                   nnewt);
+            } else {
+                g = newton_root<R>(o, tw ? Atw : R(1), tw ? inv_etaAtw : P.inv_eta, tw ? etaAtw : P.eta,
+                                   P.inv_eta, tw ? Ft.K : Fs.K, tw ? Ft.invK : Fs.invK, tw ? Ft.n : Fs.n,
+                                   tw ? Ft.inv_n : Fs.inv_n, tw ? Ft.nm1 : Fs.nm1,
+                                   tw ? Ft.nm1_int : Fs.nm1_int, P.newton_rtol, yw, nnewt);
+            }
             W.y[s * W.ls] = yw;
             W.o[s * W.ls] = os < R(0) ? -g : g;
         }
@@ -896,7 +959,8 @@ __device__ void integrate(const LawP<R> &P, const R e0[6], const R e1[6], R (&ep
     for (int i = 0; i < 6; ++i) de[i] = e1[i] - e0[i];
 #pragma unroll
     for (int s = 0; s < NS; ++s) yw[s] = R(0);
-    if constexpr (law_park_e<R>()) {
+    law_fam_store(P, W);
+    if constexpr (law_park_e<R, NS>()) {
         // the strain path lives in LDS through the integration
 #pragma unroll
         for (int i = 0; i < 6; ++i) {
@@ -920,7 +984,7 @@ __device__ void integrate(const LawP<R> &P, const R e0[6], const R e1[6], R (&ep
             const R wacc = (st == 0 || st == 3) ? h * R(1.0 / 6.0) : h * R(1.0 / 3.0);
             const R cnext = (st == 2) ? h : h * R(0.5);
             R e[6];
-            if constexpr (law_park_e<R>()) {
+            if constexpr (law_park_e<R, NS>()) {
 #pragma unroll
                 for (int i = 0; i < 6; ++i) {
                     const R a = W.e[i * W.ls];

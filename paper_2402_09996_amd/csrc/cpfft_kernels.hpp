@@ -225,7 +225,7 @@ __device__ __forceinline__ void voxel_law(const LawP<R> &P, const R *Qrow, const
     R Q[9], sc[6];
 #pragma unroll
     for (int i = 0; i < 9; ++i) Q[i] = Qrow[i];
-    if constexpr (law_park_e<R>()) {
+    if constexpr (law_park_e<R, NS>()) {
         // the end strain comes back from the LDS work area
 #pragma unroll
         for (int i = 0; i < 6; ++i) e1[i] = W.e[(6 + i) * W.ls];
@@ -302,7 +302,7 @@ __device__ __forceinline__ void voxel_law_probe(const LawP<R> &P, const R *Qrow,
 #pragma unroll
     for (int i = 0; i < 9; ++i) Q[i] = Qrow[i];
     load_state<R, NS>(so, nvox, vox, P.nsys, Q, ep, v, al);
-    if constexpr (law_park_e<R>()) {
+    if constexpr (law_park_e<R, NS>()) {
 #pragma unroll
         for (int i = 0; i < 6; ++i) e1[i] = W.e[(6 + i) * W.ls];
     }
@@ -348,14 +348,17 @@ __device__ __forceinline__ const LawP<R> &law_params(const LawP<R> &arg)
 }
 
 // The law's LDS work area of this thread inside a 256-thread block's
-// dynamic LDS, after `offset` bytes used by the kernel itself: (2 NS + 12)
-// words per thread, column-major (compile-time stride: plain shifts).
+// dynamic LDS, after `offset` bytes used by the kernel itself: 2 NS words
+// per thread (plus 12 when the strain path is parked), column-major
+// (compile-time stride: plain shifts), then the family tables of the
+// block's four waves.
 template <typename R, int NS, int BD = 256>
 __device__ __forceinline__ LawLds<R> law_lds(unsigned char *smem, size_t offset)
 {
     R *base = reinterpret_cast<R *>(smem + offset);
     const int t = threadIdx.x;
-    return LawLds<R>{base + t, base + NS * BD + t, base + 2 * NS * BD + t, BD};
+    R *fam = base + (2 * NS + law_e_rows<R>(NS)) * BD + (t >> 6) * 2 * LAW_FAM_WORDS;
+    return LawLds<R>{base + t, base + NS * BD + t, base + 2 * NS * BD + t, fam, BD};
 }
 
 // Bytes of the x pass FFT area in dynamic LDS: 3 complex lines of up to
