@@ -709,16 +709,18 @@ struct LawLds {
     R *y;       // [NS] Newton roots (warm starts)
     R *e;       // [12] start and end strain of the load step
     R *fam;     // [2][LAW_FAM_WORDS] Norton constants of the slip and twin
-                // families, one copy per wave (shared by its lanes)
+                // families, one copy per block
     int ls;
 };
 
 // The Newton passes of the compacted stage take the constants of each
-// lane's family from a small per-wave table instead of selecting every one
+// lane's family from a small table in LDS instead of selecting every one
 // of them between two scalar registers (two instructions each: a scalar
 // source must be moved to a vector register first).  Per family: K, 1/K,
 // n, 1/n, n - 1, the integer exponent (as a value of R; FP64 only) and two
-// words of padding (16-byte aligned rows).
+// words of padding (16-byte aligned rows).  One table per block (64 bytes
+// in FP32): three FP32 law blocks per CU leave no room for a table per
+// wave in the 160 KB of LDS.
 constexpr int LAW_FAM_WORDS = 8;
 #ifndef CPF_LAW_FAM_TABLE
 #define CPF_LAW_FAM_TABLE 1
@@ -775,12 +777,11 @@ constexpr int law_e_rows(int ns)
 }
 
 // Bytes of the law's LDS work area of a 256-thread block: the per-thread
-// columns, then the family tables of its four waves.
+// columns, then the family table.
 template <typename R>
 constexpr size_t law_lds_bytes_ns(int ns)
 {
-    return law_compact<R>() ? ((2 * (size_t)ns + law_e_rows<R>(ns)) * 256 + 4 * 2 * LAW_FAM_WORDS) * sizeof(R)
-                            : 0;
+    return law_compact<R>() ? ((2 * (size_t)ns + law_e_rows<R>(ns)) * 256 + 2 * LAW_FAM_WORDS) * sizeof(R) : 0;
 }
 template <typename R, int NS>
 constexpr size_t law_lds_bytes()
@@ -788,8 +789,9 @@ constexpr size_t law_lds_bytes()
     return law_lds_bytes_ns<R>(NS);
 }
 
-// Fill this wave's family table (every lane writes the same values; the
-// wave reads only its own table, after its own writes).
+// Fill the block's family table.  Every lane of every wave writes the
+// same values before its own first read, so no barrier is needed: a read
+// sees either its own wave's write or an identical one.
 template <typename R>
 __device__ __forceinline__ void law_fam_store(const LawP<R> &P, const LawLds<R> &W)
 {

@@ -350,14 +350,13 @@ __device__ __forceinline__ const LawP<R> &law_params(const LawP<R> &arg)
 // The law's LDS work area of this thread inside a 256-thread block's
 // dynamic LDS, after `offset` bytes used by the kernel itself: 2 NS words
 // per thread (plus 12 when the strain path is parked), column-major
-// (compile-time stride: plain shifts), then the family tables of the
-// block's four waves.
+// (compile-time stride: plain shifts), then the family table.
 template <typename R, int NS, int BD = 256>
 __device__ __forceinline__ LawLds<R> law_lds(unsigned char *smem, size_t offset)
 {
     R *base = reinterpret_cast<R *>(smem + offset);
     const int t = threadIdx.x;
-    R *fam = base + (2 * NS + law_e_rows<R>(NS)) * BD + (t >> 6) * 2 * LAW_FAM_WORDS;
+    R *fam = base + (2 * NS + law_e_rows<R>(NS)) * BD;
     return LawLds<R>{base + t, base + NS * BD + t, base + 2 * NS * BD + t, fam, BD};
 }
 
