@@ -851,6 +851,8 @@ __device__ __forceinline__ void rk_stage_cmp(const LawP<R> &P, const R e[6], R (
     const R Atw = P.twin_mode ? P.Kc_gT * (P.fm - sumf) : R(1);
     const R etaAtw = P.eta * Atw;
     const R inv_etaAtw = P.twin_mode ? fdiv(R(1), etaAtw) : P.inv_eta;
+    // latent hardening per family (one product per family, not per system)
+    const R QLHs = P.fs.QL * Hs, QLHt = P.ft.QL * Ht;
     // overstress of every system, stored with the sign of the slip rate
     // (zero for inactive systems)
     uint32_t act = 0;
@@ -862,7 +864,7 @@ __device__ __forceinline__ void rk_stage_cmp(const LawP<R> &P, const R e[6], R (
         const bool tw = is_twin<SPEC>(P, s);
         const FamP<R> &F = tw ? P.ft : P.fs;
         const R hs = law_park_h<R>() ? W.o[s * W.ls] : h[s];
-        const R r = P.tau0[s] + F.QL * (tw ? Ht : Hs) + F.QD * hs;
+        const R r = (P.tau0[s] + (tw ? QLHt : QLHs)) + F.QD * hs;
         R tau = R(0);
         if constexpr (t1_factor<SPEC>()) {
             tau = t1_tau(s, t1);
@@ -877,7 +879,9 @@ __device__ __forceinline__ void rk_stage_cmp(const LawP<R> &P, const R e[6], R (
         const R A = tw ? Atw : R(1);
         const bool on = o > R(0) && A > R(0);
         if (on) act |= 1u << s;
-        const R os = (!tw && tx < R(0)) ? -o : o;
+        // an active slip system has |tx| > r >= 0, so the sign bit of tx is
+        // the sign of the rate
+        const R os = tw ? o : copysign(o, tx);
         W.o[s * W.ls] = on ? os : R(0);
     }
     nact += __popc(act);
