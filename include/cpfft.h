@@ -335,6 +335,30 @@ int cpf_adjoint_vjp(cpf_solver *s, const cpf_path *path, const double *sigma_bar
 #define CPF_MAX_HIST_BINS 4096
 int cpf_seq_histogram(cpf_solver *s, int rve, int nbins, double lo, double hi, unsigned long long *counts);
 
+/* For callers that cannot allocate memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid allocation): the histogram of
+ * cpf_seq_histogram, with the same bins and the same decision rule, of a
+ * stress field the caller holds, without a solver or a workspace.  The
+ * call allocates nothing: its device counts and squared edges live in one
+ * fixed array of CPF_HIST_SCRATCH_BYTES per GPU (held by the library until
+ * the process ends), hence the limit nbins <= CPF_MAX_HIST_BINS.
+ *
+ * dev_sig: device [6][nvox] stress components (11,22,33,23,13,12), double
+ *   for precision CPF_PREC_FP64, float for CPF_PREC_FP32, caller-owned
+ *   (read only); nvox >= 0 (0 gives all-zero counts).
+ * counts[nbins + 2]: host, written as for cpf_seq_histogram.
+ * hip_stream: a stream of the current device (NULL = default); the work is
+ *   ordered on it and the call synchronizes it before returning.
+ * Every call on one GPU uses that GPU's array, which keeps the last call's
+ * contents (each call clears the counts first): calls that overlap on one
+ * GPU (other host threads, other streams) race and must be serialized by
+ * the caller.  Errors: CPF_E_INVALID_ARG for a null pointer, a bad
+ * precision, nvox < 0, nbins outside 1..CPF_MAX_HIST_BINS, or not
+ * (finite lo < hi); CPF_E_HIP for runtime failures. */
+#define CPF_HIST_SCRATCH_BYTES 66048
+int cpf_seq_histogram_field(const void *dev_sig, int precision, long long nvox, int nbins, double lo, double hi,
+                            unsigned long long *counts, void *hip_stream);
+
 /* Committed state of every RVE (strain, plastic strain, accumulated slip,
  * back strain, and the step's mean stress and strain), for checkpoints
  * and restarts along a path.  dev_buf: device memory of at least

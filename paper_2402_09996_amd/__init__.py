@@ -27,7 +27,7 @@ FIELDS = {
 }
 
 __all__ = ["Problem", "Solver", "CpfError", "FIELDS", "version", "EffectiveStress", "StressCurveLoss",
-           "with_theta", "generate_microstructure", "micro_thin", "micro_label", "micro_graph", "micro_slabs"]
+           "with_theta", "von_mises_histogram_field", "generate_microstructure", "micro_thin", "micro_label", "micro_graph", "micro_slabs"]
 
 
 def version() -> int:
@@ -573,6 +573,26 @@ def generate_microstructure(shape, lam: float, r: float, p_neigh: float = 0.0, p
     out.update(labels=labels, rotations=rot[:n].reshape(n, 3, 3).copy(), euler=eul[:n].copy(),
                pairs=pairs[:info.n_pairs].copy())
     return out
+
+
+def von_mises_histogram_field(stress, nbins: int, lo: float, hi: float, stream=None):
+    """Counts [nbins + 2] of the local von Mises stress of a device stress
+    field ``stress`` (torch float32/float64, [6][...] components 11, 22,
+    33, 23, 13, 12), with the bins of :meth:`Solver.von_mises_histogram`;
+    no solver and no workspace (cpf_seq_histogram_field allocates nothing)."""
+    import torch
+    if stress.dtype not in (torch.float32, torch.float64) or not stress.is_cuda:
+        raise TypeError("stress must be a float32 or float64 device tensor")
+    if stress.shape[0] != 6 or not stress.is_contiguous():
+        raise ValueError("stress must be a contiguous [6][...] tensor")
+    prec = CPF_PREC_FP64 if stress.dtype == torch.float64 else CPF_PREC_FP32
+    counts = np.zeros(int(nbins) + 2, dtype=np.uint64)
+    with torch.cuda.device(stress.device):
+        check(_lib.lib().cpf_seq_histogram_field(ctypes.c_void_p(stress.data_ptr()), prec, stress[0].numel(),
+                                                 int(nbins), float(lo), float(hi),
+                                                 counts.ctypes.data_as(ctypes.POINTER(ctypes.c_ulonglong)),
+                                                 _stream_ptr(stream, stress)))
+    return counts
 
 
 def _stream_ptr(stream, t):

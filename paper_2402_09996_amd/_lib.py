@@ -123,6 +123,8 @@ SIGNATURES = {
     "cpf_adjoint_gradient": (_i, [_p, ctypes.POINTER(CpfPath), _dp, _i, _d, _p, ctypes.c_size_t, _dp, _dp, _dp]),
     "cpf_adjoint_vjp": (_i, [_p, ctypes.POINTER(CpfPath), _dp, _i, _d, _p, ctypes.c_size_t, _dp, _dp]),
     "cpf_seq_histogram": (_i, [_p, _i, _i, _d, _d, ctypes.POINTER(ctypes.c_ulonglong)]),
+    "cpf_seq_histogram_field": (_i, [_p, _i, ctypes.c_longlong, _i, _d, _d, ctypes.POINTER(ctypes.c_ulonglong),
+                                     _p]),
     "cpf_state_size": (_i, [_p, ctypes.POINTER(ctypes.c_size_t)]),
     "cpf_state_save": (_i, [_p, _p]),
     "cpf_state_restore": (_i, [_p, _p]),

@@ -1862,6 +1862,89 @@ extern "C" int cpf_seq_histogram(cpf_solver *s, int rve, int nbins, double lo, d
 }
 
 // ---------------------------------------------------------------------------
+// The same histogram of a caller's stress field, with no workspace: the
+// device counts and squared edges live in one fixed array per GPU.
+// ---------------------------------------------------------------------------
+static constexpr size_t HIST_COUNTS_BYTES = sizeof(unsigned long long) * (CPF_MAX_HIST_BINS + 2);
+static constexpr size_t HIST_EDGES_OFF = (HIST_COUNTS_BYTES + 255) / 256 * 256;
+static_assert(HIST_EDGES_OFF + sizeof(double) * (CPF_MAX_HIST_BINS + 1) <= CPF_HIST_SCRATCH_BYTES,
+              "histogram scratch too small");
+
+// Device array of the allocation-free histogram.  In host code this name
+// is only a stand-in: the address on each device comes from
+// hipGetSymbolAddress (scratch_ptr below) and is what kernels receive.
+static __device__ __align__(256) unsigned char scratch[CPF_HIST_SCRATCH_BYTES];
+
+static constexpr int SCRATCH_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static unsigned char *g_scratch_dev[SCRATCH_MAX_DEVICES];   // per device, set on first use
+
+// Address of `scratch` on the current device (looked up once per device,
+// with that device current).
+static int scratch_ptr(unsigned char **out)
+{
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= SCRATCH_MAX_DEVICES) return fail(CPF_E_INVALID_ARG, "device %d out of range", dev);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void *p = nullptr;
+        HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) return fail(CPF_E_HIP, "hipGetSymbolAddress returned no address");
+        g_scratch_dev[dev] = static_cast<unsigned char *>(p);
+    }
+    *out = g_scratch_dev[dev];
+    return CPF_OK;
+}
+
+// Squared bin edges e_k = lo + k w (-1 where e_k <= 0), each operation
+// rounded on its own as in the host loop of seq_hist_impl.
+__global__ void k_hist_edges(double lo, double w, int nbins, double *q)
+{
+#pragma clang fp contract(off)
+    for (int k = blockIdx.x * blockDim.x + threadIdx.x; k <= nbins; k += gridDim.x * blockDim.x) {
+        const double e = lo + (double)k * w;
+        q[k] = e > 0.0 ? e * e : -1.0;
+    }
+}
+
+extern "C" int cpf_seq_histogram_field(const void *dev_sig, int precision, long long nvox, int nbins, double lo,
+                                       double hi, unsigned long long *counts, void *hip_stream)
+{
+    if (!counts || (nvox > 0 && !dev_sig)) return fail(CPF_E_INVALID_ARG, "null argument");
+    if (precision != CPF_PREC_FP64 && precision != CPF_PREC_FP32)
+        return fail(CPF_E_INVALID_ARG, "precision %d", precision);
+    if (nvox < 0) return fail(CPF_E_INVALID_ARG, "nvox %lld < 0", nvox);
+    if (nbins < 1 || nbins > CPF_MAX_HIST_BINS)
+        return fail(CPF_E_INVALID_ARG, "nbins %d: need 1..%d (the fixed device array holds at most %d bins)",
+                    nbins, CPF_MAX_HIST_BINS, CPF_MAX_HIST_BINS);
+    if (!std::isfinite(lo) || !std::isfinite(hi) || !(hi > lo))
+        return fail(CPF_E_INVALID_ARG, "need finite lo < hi");
+    unsigned char *base = nullptr;
+    if (int rc = scratch_ptr(&base)) return rc;
+    hipStream_t st = static_cast<hipStream_t>(hip_stream);
+    unsigned long long *dc = reinterpret_cast<unsigned long long *>(base);
+    double *dq = reinterpret_cast<double *>(base + HIST_EDGES_OFF);
+    // the array keeps the previous call's counts: clear them (a kernel, no memset node)
+    hipLaunchKernelGGL(k_fill<unsigned long long>, dim3(16), dim3(256), 0, st, dc, (long)nbins + 2, 0ull);
+    hipLaunchKernelGGL(k_hist_edges, dim3((nbins + 256) / 256), dim3(256), 0, st, lo, (hi - lo) / nbins, nbins, dq);
+    if (nvox > 0) {
+        const long blocks = std::min<long>((nvox + 255) / 256, 2048);
+        const size_t lds = sizeof(double) * (nbins + 1) + sizeof(unsigned int) * (nbins + 2);
+        if (precision == CPF_PREC_FP64)
+            hipLaunchKernelGGL(k_seq_hist<double>, dim3(blocks), dim3(256), lds, st, (const double *)dev_sig,
+                               (long)nvox, nbins, (const double *)dq, dc);
+        else
+            hipLaunchKernelGGL(k_seq_hist<float>, dim3(blocks), dim3(256), lds, st, (const float *)dev_sig,
+                               (long)nvox, nbins, (const double *)dq, dc);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(counts, dc, sizeof(unsigned long long) * (nbins + 2), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return CPF_OK;
+}
+
+// ---------------------------------------------------------------------------
 // committed state save / restore
 // ---------------------------------------------------------------------------
 struct SavedHead {

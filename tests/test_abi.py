@@ -120,3 +120,22 @@ def test_solver_lifecycle_errors_before_binding():
     assert L.cpf_solver_field(s, 0, None) == _lib.CPF_E_BAD_STATE
     L.cpf_solver_destroy(s)
     L.cpf_problem_destroy(p)
+
+
+def test_histogram_field_rejects_bad_arguments_on_the_host():
+    """The allocation-free histogram checks its arguments before any device
+    call (a fake device pointer is never touched)."""
+    L = _lib.lib()
+    counts = (ctypes.c_ulonglong * 8)()
+    fake = ctypes.c_void_p(0x1000)
+    E = _lib.CPF_E_INVALID_ARG
+    assert L.cpf_seq_histogram_field(fake, 0, 10, 0, 0.0, 1.0, counts, None) == E            # nbins < 1
+    assert L.cpf_seq_histogram_field(fake, 0, 10, 4097, 0.0, 1.0, counts, None) == E         # beyond the array
+    assert b"fixed device array" in L.cpf_last_error_message()
+    assert L.cpf_seq_histogram_field(fake, 2, 10, 6, 0.0, 1.0, counts, None) == E            # precision
+    assert L.cpf_seq_histogram_field(fake, 0, -1, 6, 0.0, 1.0, counts, None) == E            # nvox < 0
+    assert L.cpf_seq_histogram_field(fake, 0, 10, 6, 1.0, 1.0, counts, None) == E            # lo == hi
+    assert L.cpf_seq_histogram_field(fake, 0, 10, 6, float("nan"), 1.0, counts, None) == E
+    assert L.cpf_seq_histogram_field(None, 0, 10, 6, 0.0, 1.0, counts, None) == E            # null field
+    assert L.cpf_seq_histogram_field(fake, 0, 10, 6, 0.0, 1.0, None, None) == E              # null counts
+
