@@ -175,6 +175,10 @@ typedef struct cpf_step_out {
     double n_newton;  /* rate evaluations above yield, Newton iterations   */
     int iters;        /* constitutive evaluations (fixed-point iterations) */
     int status;       /* CPF_OK, CPF_E_NOT_CONVERGED or CPF_E_NAN          */
+    int stagnated;    /* 1: ended by the stalled-residual acceptance
+                         (stag_tol), with err above tol                    */
+    int host_syncs;   /* host waits on the device during the step (polls of
+                         the step status; the same for every member)       */
 } cpf_step_out;
 
 typedef struct cpf_problem cpf_problem;
@@ -222,9 +226,17 @@ int cpf_batch_size(const cpf_solver *s, int *n);
 /* Load step n for every member; outs has one entry per member. */
 int cpf_batch_step(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *outs);
 int cpf_batch_field(cpf_solver *s, int rve, int field, void *dev_out);
-/* Launch iterations as one captured HIP graph of iters_per_launch
- * iterations (all members, device-side early exit); 0 returns to direct
- * launches.  Kernel timing does not see inside graphs. */
+/* Launch iterations as captured HIP graphs (all members, device-side early
+ * exit: the kernels of iterations after the step has ended return at
+ * once).  iters_per_launch = G > 0: graphs of G iterations, replayed until
+ * the step ends (one host poll per replay).  CPF_GRAPH_ADAPTIVE: each load
+ * step replays a graph of the least power-of-two length (8 .. 1024)
+ * covering 1.25 times the previous step's largest iteration count plus 2,
+ * so that a step is normally one replay and one host poll; graphs are
+ * captured per length on first use and kept.  0 returns to direct launches
+ * (chunks of the previous step's iteration count between polls).  Kernel
+ * timing does not see inside graphs. */
+#define CPF_GRAPH_ADAPTIVE (-1)
 int cpf_solver_set_graph(cpf_solver *s, int iters_per_launch);
 /* Pick the y and z pass tile widths (kx columns per block) of every
  * member's grid size by timing the candidates on the bound workspace

@@ -27,7 +27,7 @@ FIELDS = {
 }
 
 __all__ = ["Problem", "Solver", "CpfError", "FIELDS", "version", "EffectiveStress", "StressCurveLoss",
-           "with_theta", "von_mises_histogram_field", "generate_microstructure", "micro_thin", "micro_label", "micro_graph", "micro_slabs"]
+           "theta_of", "with_theta", "von_mises_histogram_field", "generate_microstructure", "micro_thin", "micro_label", "micro_graph", "micro_slabs"]
 
 
 def version() -> int:
@@ -133,7 +133,9 @@ def _outs_to_dict(outs, n):
     r = {"Sigma": np.array([list(outs[i].Sigma) for i in range(n)]).reshape(n, 6),
          "E": np.array([list(outs[i].E) for i in range(n)]).reshape(n, 6),
          "iters": np.array([outs[i].iters for i in range(n)], dtype=np.int64),
-         "status": np.array([outs[i].status for i in range(n)], dtype=np.int64)}
+         "status": np.array([outs[i].status for i in range(n)], dtype=np.int64),
+         "stagnated": np.array([outs[i].stagnated for i in range(n)], dtype=np.int64),
+         "host_syncs": np.array([outs[i].host_syncs for i in range(n)], dtype=np.int64)}
     for k in keys:
         r[k] = np.array([getattr(outs[i], k) for i in range(n)])
     return r
@@ -221,7 +223,12 @@ class Solver:
         check(_lib.lib().cpf_solver_tiles(self._h, int(rve), ctypes.byref(ty), ctypes.byref(tz)))
         return ty.value, tz.value
 
-    def set_graph(self, iters_per_launch: int):
+    def set_graph(self, iters_per_launch):
+        """Graph launches of ``iters_per_launch`` iterations per replay,
+        ``"adaptive"`` (a length per step from the previous step's count:
+        normally one replay per step), or 0 (direct launches)."""
+        if iters_per_launch == "adaptive":
+            iters_per_launch = _lib.CPF_GRAPH_ADAPTIVE
         check(_lib.lib().cpf_solver_set_graph(self._h, int(iters_per_launch)))
 
     def step_batch(self, path, n: int) -> list[dict]:
@@ -429,16 +436,34 @@ class Solver:
             self._h = None
 
 
+def theta_of(problem: Problem) -> np.ndarray:
+    """The law parameters theta[2][7] of ``problem``: per family (slip,
+    twin) r0, Q, b, c, d, K, n, where r0 is the family's lowest initial
+    resolved shear stress tau0 (0 for a family without systems)."""
+    th = np.zeros((2, 7))
+    for f, fam in enumerate((problem.law.slip, problem.law.twin)):
+        sel = problem.tau0[problem.family == f]
+        th[f, 0] = float(sel.min()) if sel.size else 0.0
+        for k, name in enumerate(Solver.THETA_NAMES[1:], start=1):
+            th[f, k] = float(getattr(fam, name))
+    return th
+
+
 def with_theta(problem: Problem, theta) -> Problem:
     """A copy of ``problem`` whose law parameters are theta[2][7]: per family
-    (slip, twin) r0 (initial critical resolved shear stress of all its
-    systems), Q, b, c, d, K, n."""
+    (slip, twin) r0, Q, b, c, d, K, n.  r0 moves every tau0 of the family by
+    the same amount, theta[f][0] - theta_of(problem)[f][0], so systems keep
+    their offsets (Section 3's ordinary and superdislocation resistances
+    differ by a constant), the problem's own theta gives back the problem,
+    and the derivative with respect to r0 is that of a uniform shift, as
+    the adjoint computes it."""
     import copy
     th = np.asarray(theta, dtype=np.float64).reshape(2, 7)
+    ref = theta_of(problem)
     law = copy.deepcopy(problem.law)
     tau0 = problem.tau0.copy()
     for f, fam in enumerate((law.slip, law.twin)):
-        tau0[problem.family == f] = th[f, 0]
+        tau0[problem.family == f] += th[f, 0] - ref[f, 0]
         for k, name in enumerate(Solver.THETA_NAMES[1:], start=1):
             setattr(fam, name, float(th[f, k]))
     return Problem(problem.labels, problem.euler, problem.C_voigt, problem.n_miller,

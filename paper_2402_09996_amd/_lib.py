@@ -33,6 +33,7 @@ CPF_FIELD_BACK_STRAIN = 4
 CPF_FIELD_SUBSTEPS = 5
 
 CPF_MAX_SYSTEMS = 32
+CPF_GRAPH_ADAPTIVE = -1
 
 _d = ctypes.c_double
 _i = ctypes.c_int
@@ -74,7 +75,7 @@ class CpfStepOut(ctypes.Structure):
         ("Sigma", _d * 6), ("E", _d * 6),
         ("sig_eq_of_mean", _d), ("mean_sig_eq", _d), ("mean_v", _d), ("mean_f", _d),
         ("err_eq", _d), ("err_bc", _d), ("n_active", _d), ("n_newton", _d),
-        ("iters", _i), ("status", _i),
+        ("iters", _i), ("status", _i), ("stagnated", _i), ("host_syncs", _i),
     ]
 
 

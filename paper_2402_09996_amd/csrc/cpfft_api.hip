@@ -321,10 +321,11 @@ struct cpf_solver {
     bool bound = false;
     Scalars *hsc = nullptr;     // pinned host mirror of the per-RVE scalars
     StepInit *hsi = nullptr;    // pinned per-RVE step records
-    // graph of G iterations (0: direct launches)
+    // graph launches: G > 0 iterations per replay, CPF_GRAPH_ADAPTIVE
+    // lengths from the previous step, 0 direct launches; captured graphs
+    // by length
     int graph_iters = 0;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t graph_exec = nullptr;
+    std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
     // kernel timing
     bool timing = false;
     double t_ms[CPF_NKERNELS] = {0};
@@ -689,10 +690,11 @@ extern "C" int cpf_solver_workspace_size(const cpf_solver *s, size_t *bytes)
 
 static void drop_graph(cpf_solver *s)
 {
-    if (s->graph_exec) (void)hipGraphExecDestroy(s->graph_exec);
-    if (s->graph) (void)hipGraphDestroy(s->graph);
-    s->graph_exec = nullptr;
-    s->graph = nullptr;
+    for (auto &g : s->graphs) {
+        if (g.second.second) (void)hipGraphExecDestroy(g.second.second);
+        if (g.second.first) (void)hipGraphDestroy(g.second.first);
+    }
+    s->graphs.clear();
 }
 
 extern "C" void cpf_solver_destroy(cpf_solver *s)
@@ -736,8 +738,8 @@ extern "C" int cpf_solver_get_timing(const cpf_solver *s, double *ms, long long 
 extern "C" int cpf_solver_set_graph(cpf_solver *s, int iters_per_launch)
 {
     if (!s) return fail(CPF_E_INVALID_ARG, "null solver");
-    if (iters_per_launch < 0 || iters_per_launch > 1024)
-        return fail(CPF_E_INVALID_ARG, "iterations per graph launch must be in [0, 1024]");
+    if ((iters_per_launch < 0 && iters_per_launch != CPF_GRAPH_ADAPTIVE) || iters_per_launch > 1024)
+        return fail(CPF_E_INVALID_ARG, "iterations per graph launch must be in [0, 1024] or CPF_GRAPH_ADAPTIVE");
     if (s->bound) HIPCHK(hipStreamSynchronize(s->stream));
     drop_graph(s);
     s->graph_iters = iters_per_launch;
@@ -1034,26 +1036,56 @@ static int launch_iteration(cpf_solver *s, const LawP<R> &P)
     return CPF_OK;
 }
 
-// Capture graph_iters iterations of the batch into one executable graph.
+// The executable graph of `len` iterations of the batch (captured on first
+// use, kept until the graphs are dropped).  Every kernel reads the step's
+// flags and buffer indices from device memory, so one graph serves every
+// load step.
 template <typename R>
-static int build_graph(cpf_solver *s, const LawP<R> &P)
+static int graph_of(cpf_solver *s, const LawP<R> &P, int len, hipGraphExec_t *out)
 {
-    drop_graph(s);
+    auto it = s->graphs.find(len);
+    if (it != s->graphs.end()) {
+        *out = it->second.second;
+        return CPF_OK;
+    }
     if (!s->stream)
         return fail(CPF_E_INVALID_ARG, "graph launches need a solver bound to a non-default stream");
     const bool was_timing = s->timing;
     s->timing = false;   // events are not recorded inside the graph
     HIPCHK(hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal));
     int rc = CPF_OK;
-    for (int i = 0; i < s->graph_iters && rc == CPF_OK; ++i) rc = launch_iteration<R>(s, P);
+    for (int i = 0; i < len && rc == CPF_OK; ++i) rc = launch_iteration<R>(s, P);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(s->stream, &g);
     s->timing = was_timing;
-    if (rc) return rc;
+    if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
     if (e != hipSuccess) return fail(CPF_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
-    s->graph = g;
-    HIPCHK(hipGraphInstantiate(&s->graph_exec, s->graph, nullptr, nullptr, 0));
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(CPF_E_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
+    }
+    s->graphs[len] = {g, x};
+    *out = x;
     return CPF_OK;
+}
+
+// Adaptive graph length: the least power of two (8 .. 1024) covering what
+// the step is expected to need from here: 1.25 times the previous step's
+// largest iteration count plus 2, less what is already queued; once that
+// guess is used up, as many as are queued (the total doubles per replay).
+static int adaptive_len(int prev, int queued, int max_iter)
+{
+    int want = prev > 0 ? (prev * 5 + 3) / 4 + 2 - queued : 16 - queued;
+    want = std::max(want, std::max(8, queued));
+    want = std::min(want, max_iter + 1 - queued);
+    int len = 8;
+    while (len < want && len < 1024) len *= 2;
+    return len;
 }
 
 static int check_path(const cpf_path *p)
@@ -1106,17 +1138,17 @@ static int step_impl(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *o
                        dptr<StepInit>(s, s->off_si));
 
     const LawP<R> P = make_law<R>(s);
-    if (s->graph_iters > 0 && !s->graph_exec) {
-        int rc = build_graph<R>(s, P);
-        if (rc) return rc;
-    }
-    int queued = 0, prev = 0;
+    int queued = 0, prev = 0, syncs = 0;
     for (const auto &h : s->rv) prev = std::max(prev, h.prev_iters);
     int chunk = s->opt.check_every > 0 ? s->opt.check_every : std::max(2, prev);
     for (;;) {
-        if (s->graph_exec) {
-            HIPCHK(hipGraphLaunch(s->graph_exec, s->stream));
-            queued += s->graph_iters;
+        if (s->graph_iters != 0) {
+            const int len = s->graph_iters > 0 ? s->graph_iters : adaptive_len(prev, queued, s->opt.max_iter);
+            hipGraphExec_t x = nullptr;
+            int rc = graph_of<R>(s, P, len, &x);
+            if (rc) return rc;
+            HIPCHK(hipGraphLaunch(x, s->stream));
+            queued += len;
         } else {
             for (int c = 0; c < chunk; ++c, ++queued) {
                 int rc = launch_iteration<R>(s, P);
@@ -1128,6 +1160,7 @@ static int step_impl(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *o
             HIPCHK(hipMemcpyAsync(s->hsc + r, s->ws + s->rv[r].off_sc, sizeof(Scalars), hipMemcpyDeviceToHost,
                                   s->stream));
         HIPCHK(hipStreamSynchronize(s->stream));
+        ++syncs;
         {
             int rc = timed_collect(s);
             if (rc) return rc;
@@ -1159,6 +1192,8 @@ static int step_impl(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *o
             out->n_newton = h.work_newton;
             out->iters = h.iter;
             out->status = h.status;
+            out->stagnated = h.stagnated;
+            out->host_syncs = syncs;
         }
         if (h.status != 0 && worst == CPF_OK) {
             worst = h.status;

@@ -139,3 +139,22 @@ def test_histogram_field_rejects_bad_arguments_on_the_host():
     assert L.cpf_seq_histogram_field(None, 0, 10, 6, 0.0, 1.0, counts, None) == E            # null field
     assert L.cpf_seq_histogram_field(fake, 0, 10, 6, 0.0, 1.0, None, None) == E              # null counts
 
+
+def test_theta_round_trip_keeps_per_system_offsets():
+    """with_theta moves a family's resistances together (host only)."""
+    import paper_2402_09996_amd as cp
+    C, law = rvegen.paper_law()
+    S = rvegen.table1_systems(True)
+    rve = rvegen.make_rve((4, 4, 4), 2, 3)
+    p = cp.Problem(rve.labels, rve.euler, C, S.n_miller, S.l_miller, S.family, S.tau0, law)
+    th = cp.theta_of(p)
+    assert th[0, 0] == 130.0 and th[1, 0] == 130.0 and th[0, 6] == law.slip.n
+    q = cp.with_theta(p, th)
+    assert np.array_equal(q.tau0, p.tau0)
+    th2 = th.copy()
+    th2[0, 0] += 5.0
+    th2[1, 2] = 7.0
+    q = cp.with_theta(p, th2)
+    assert np.array_equal(q.tau0 - p.tau0, np.where(S.family == 0, 5.0, 0.0))
+    assert q.law.twin.b == 7.0 and p.law.twin.b != 7.0
+    assert np.array_equal(cp.theta_of(q), th2)

@@ -189,3 +189,36 @@ def test_vjp_argument_errors():
     bad[1, 2] = np.nan
     with pytest.raises(cp.CpfError):
         s.vjp(w.path, bad)
+
+
+def test_autograd_on_the_paper_systems_keeps_per_system_tau0():
+    """Table 1 with the paper's resistances (130 MPa ordinary, 200 MPa
+    superdislocations, 130 MPa twins): at theta_of(problem) the autograd
+    forward is the plain solve, and the r0 gradient is the derivative of a
+    uniform shift of the family's resistances (central differences)."""
+    C, law = rvegen.paper_law()
+    S = rvegen.table1_systems(True)
+    rve = rvegen.make_rve((4, 4, 6), 3, 77, twin_share=0.5)
+    path = rvegen.uniaxial_path(0.006, 3, rate=1e-2)
+    w = rvegen.Workload("adj_paper", rve, S, C, law, path)
+    p = cp.Problem.from_workload(w)
+    th0 = cp.theta_of(p)
+    assert th0[0, 0] == 130.0 and th0[1, 0] == 130.0
+    plain = cp.Solver(p, precision="fp64", tol=1e-12).run(path)["Sigma"]
+    theta = torch.tensor(th0, dtype=torch.float64, requires_grad=True)
+    opts = dict(precision="fp64", tol=1e-12, adj_tol=1e-12, checkpoint_every=2)
+    sig = cp.EffectiveStress.apply(theta, p, path, opts)
+    assert np.array_equal(sig.detach().numpy(), plain)
+    sig[:, 0].sum().backward()
+    g = theta.grad.numpy()
+
+    def j(th):
+        return float(cp.Solver(cp.with_theta(p, th), precision="fp64", tol=1e-12).run(path)["Sigma"][:, 0].sum())
+
+    for f in (0, 1):
+        tp, tm = th0.copy(), th0.copy()
+        tp[f, 0] += 1e-3
+        tm[f, 0] -= 1e-3
+        fd = (j(tp) - j(tm)) / 2e-3
+        print("r0 family", f, "adjoint", g[f, 0], "fd", fd, flush=True)
+        assert abs(g[f, 0] - fd) <= 1e-5 * abs(fd) + 1e-8 * np.abs(g).max()

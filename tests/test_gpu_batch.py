@@ -66,7 +66,7 @@ def test_batch_member_matches_oracle():
     assert [outs[n][i]["iters"] for n in range(path.n_steps)] == list(ref.iters)
 
 
-@pytest.mark.parametrize("graph_iters", [3, 64])
+@pytest.mark.parametrize("graph_iters", [3, 64, "adaptive"])
 def test_graph_replays_equal_direct_launches(graph_iters):
     """Each load step replays the captured graph one or more times, with the
     host's own step setup and synchronizations between replays; every
@@ -81,6 +81,24 @@ def test_graph_replays_equal_direct_launches(graph_iters):
             assert direct[n][i]["iters"] == graphed[n][i]["iters"]
     for a, b in zip(fd, fg):
         assert np.array_equal(a, b)
+    if graph_iters == "adaptive":
+        # after the first step the graph length mostly covers the step
+        syncs = [graphed[n][0]["host_syncs"] for n in range(path.n_steps)]
+        print("host syncs per step", syncs, [graphed[n][0]["iters"] for n in range(path.n_steps)], flush=True)
+        assert all(x <= 2 for x in syncs[1:]), syncs
+
+
+def test_stalled_residual_acceptance_is_reported():
+    """FP32 with an unreachable tolerance ends each step by the stalled
+    residual acceptance: status 0, the flag set, residual above tol."""
+    wl, path = _members()
+    _, outs, _ = _run_batch(wl[:2], path, "fp32", tol=1e-13, stag_tol=1e-4)
+    for n in range(path.n_steps):
+        for o in outs[n]:
+            assert o["status"] == 0 and o["stagnated"] == 1
+            assert 1e-13 < max(o["err_eq"], o["err_bc"]) < 1e-4
+    _, outs, _ = _run_batch(wl[:2], path, "fp64", tol=1e-10)
+    assert all(o["stagnated"] == 0 for step in outs for o in step)
 
 
 def test_autotuned_tiles_are_valid_and_do_not_change_results():
