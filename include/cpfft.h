@@ -244,6 +244,11 @@ int cpf_solver_set_graph(cpf_solver *s, int iters_per_launch);
  * committed state.  *n_timed receives the number of timed configurations. */
 int cpf_solver_autotune(cpf_solver *s, int *n_timed);
 int cpf_solver_tiles(const cpf_solver *s, int rve, int *ty, int *tz);
+/* Set the y and z pass tile widths of RVE `rve` by hand (for timing
+ * studies; results do not depend on the tiles).  CPF_E_INVALID_ARG if
+ * the tiles exceed the kx columns, the kernels' elements per thread or
+ * their LDS.  Synchronizes the bound stream; drops captured graphs. */
+int cpf_solver_set_tiles(cpf_solver *s, int rve, int ty, int tz);
 
 /* Kernel timing (profiling aid).  While enabled, each kernel launch of the
  * iteration is bracketed by HIP events on the bound stream and its device
@@ -257,7 +262,9 @@ int cpf_solver_get_timing(const cpf_solver *s, double *ms /*[5]*/, long long *la
 
 /* Component operators on the bound solver, for parity checks of single
  * steps of the iteration.  Device arrays in the solver's precision.
- * fields [c][nz][ny][nx]; spectra complex [c][nz][ny][nx/2+1] (re, im). */
+ * fields [c][nz][ny][nx]; spectra complex [nz][ny][nx/2+1][c] (re, im):
+ * the six components of a frequency adjacent, as the solver stores its
+ * own spectrum. */
 /* Forward 3D DFT (unnormalized) of 6 real fields: spec = F[field]. */
 int cpf_op_forward_fft(cpf_solver *s, const void *dev_field, void *dev_spec);
 /* One Green-operator application: out = F^-1[Gamma0(xi) : spec](x), with

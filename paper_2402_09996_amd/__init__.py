@@ -223,6 +223,10 @@ class Solver:
         check(_lib.lib().cpf_solver_tiles(self._h, int(rve), ctypes.byref(ty), ctypes.byref(tz)))
         return ty.value, tz.value
 
+    def set_tiles(self, ty: int, tz: int, rve: int = 0):
+        """y and z pass tile widths (kx columns per block) of one RVE."""
+        check(_lib.lib().cpf_solver_set_tiles(self._h, int(rve), int(ty), int(tz)))
+
     def set_graph(self, iters_per_launch):
         """Graph launches of ``iters_per_launch`` iterations per replay,
         ``"adaptive"`` (a length per step from the previous step's count:
@@ -396,17 +400,19 @@ class Solver:
         half spectrum [6][nz][ny][nx/2+1] (torch complex tensor)."""
         import torch
         f = f.to(device=self.device, dtype=self.dtype).contiguous()
-        spec = torch.empty((6, self.nz, self.ny, self.nhx, 2), dtype=self.dtype, device=self.device)
+        # the library's layout is [nz][ny][nx/2+1][6]; returned as a view
+        spec = torch.empty((self.nz, self.ny, self.nhx, 6, 2), dtype=self.dtype, device=self.device)
         self._order_after_torch()
         check(_lib.lib().cpf_op_forward_fft(self._h, ctypes.c_void_p(f.data_ptr()),
                                             ctypes.c_void_p(spec.data_ptr())))
-        return torch.view_as_complex(spec)
+        return torch.view_as_complex(spec).permute(3, 0, 1, 2)
 
     def green(self, spec):
         """F^-1[Gamma0 : spec] on the grid and the residual sum.  `spec` is a
         complex half spectrum; a copy is consumed."""
         import torch
-        s = torch.view_as_real(spec.to(self.device)).to(self.dtype).contiguous().clone()
+        # [6][nz][ny][nx/2+1] complex to the library's [nz][ny][nx/2+1][6]
+        s = torch.view_as_real(spec.to(self.device).permute(1, 2, 3, 0)).to(self.dtype).contiguous().clone()
         out = torch.empty((6, self.nz, self.ny, self.nx), dtype=self.dtype, device=self.device)
         err2 = ctypes.c_double()
         self._order_after_torch()

@@ -115,6 +115,7 @@ SIGNATURES = {
     "cpf_solver_set_graph": (_i, [_p, _i]),
     "cpf_solver_autotune": (_i, [_p, ctypes.POINTER(_i)]),
     "cpf_solver_tiles": (_i, [_p, _i, ctypes.POINTER(_i), ctypes.POINTER(_i)]),
+    "cpf_solver_set_tiles": (_i, [_p, _i, _i, _i]),
     "cpf_solver_set_timing": (_i, [_p, _i]),
     "cpf_solver_get_timing": (_i, [_p, _dp, ctypes.POINTER(ctypes.c_longlong)]),
     "cpf_op_forward_fft": (_i, [_p, _p, _p]),

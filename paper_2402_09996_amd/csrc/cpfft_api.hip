@@ -311,7 +311,8 @@ struct cpf_solver {
     int adj_recomputed = 0;
     // pass grids over all RVEs
     int nbx_tot = 0, nby_tot = 0, nbz_tot = 0;
-    int y_elems = 0, z_elems = 0;   // largest ny * ty and 6 * nz * tz over the RVEs
+    int y_elems = 0, z_elems = 0;   // largest 6 ny ty and 6 nz tz over the RVEs
+    int y_kinds = 0, z_kinds = 0;   // y / z kernels needed: bit 0 fixed-length, bit 1 generic
     size_t lds_x = 0, lds_y = 0, lds_z = 0;
     // workspace
     unsigned char *ws = nullptr;
@@ -384,29 +385,57 @@ static int timed_collect(cpf_solver *s)
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-// Elements per thread the y and z pass kernels are compiled for.
-constexpr int EPT_Y = 16;
-template <typename R> constexpr int ept_z() { return sizeof(R) == 4 ? 24 : 12; }
+// Elements per thread the y and z pass kernels are compiled for (blocks of
+// 256 threads; each kernel also has instantiations for a half and a
+// quarter of that).
+constexpr int EPT_Y = 24;
+constexpr int EPT_Z = 24;
 constexpr size_t LDS_LIMIT = 64 * 1024;
 
-// LDS of the y and z pass blocks: the tile (one padding element per line)
-// and the twiddles of the transform length.
+// Whether the fixed-length kernels do an RVE's y (z) pass: a common length
+// and a tile no wider than theirs.
+template <typename R>
+static bool yfix_of(const RveHost &h, int ty)
+{
+    return fixed_len(h.ny) && ty <= fixed_tile_of<R>(h.ny);
+}
+template <typename R>
+static bool zfix_of(const RveHost &h, int tz)
+{
+    return fixed_len(h.nz) && tz <= fixed_tile_of<R>(h.nz);
+}
+
+// LDS of the y and z pass blocks: the tile (6 components; the fixed-length
+// kernels' own tile width) and the twiddles of the transform length.
 template <typename R>
 static size_t lds_y_bytes(const RveHost &h, int ty)
 {
-    return ((size_t)ty * (h.ny + 1) + h.ny) * sizeof(C2<R>);
+    const int w = yfix_of<R>(h, ty) ? fixed_tile_of<R>(h.ny) : ty;
+    return (6 * (size_t)w * h.ny + h.ny) * sizeof(C2<R>);
 }
 template <typename R>
 static size_t lds_z_bytes(const RveHost &h, int tz)
 {
-    return (6 * (size_t)tz * (h.nz + 1) + h.nz) * sizeof(C2<R>);
+    const int w = zfix_of<R>(h, tz) ? fixed_tile_of<R>(h.nz) : tz;
+    return (6 * (size_t)w * h.nz + h.nz) * sizeof(C2<R>);
+}
+// which kernels a pass needs: bit 0 the fixed-length one, bit 1 the generic one
+template <typename R>
+static int y_kinds(const RveHost &h, int ty)
+{
+    return yfix_of<R>(h, ty) ? 1 : 2;
+}
+template <typename R>
+static int z_kinds(const RveHost &h, int tz)
+{
+    return zfix_of<R>(h, tz) ? 1 : 2;
 }
 
 template <typename R>
 static bool tiles_valid(const RveHost &h, int ty, int tz)
 {
-    return ty >= 1 && tz >= 1 && ty <= h.nkx && tz <= h.nkx && ty * h.ny <= EPT_Y * 256 &&
-           6 * tz * h.nz <= ept_z<R>() * 256 && lds_y_bytes<R>(h, ty) <= LDS_LIMIT &&
+    return ty >= 1 && tz >= 1 && ty <= h.nkx && tz <= h.nkx && 6 * ty * h.ny <= EPT_Y * 256 &&
+           6 * tz * h.nz <= EPT_Z * Z_THREADS && lds_y_bytes<R>(h, ty) <= LDS_LIMIT &&
            lds_z_bytes<R>(h, tz) <= LDS_LIMIT;
 }
 
@@ -424,11 +453,15 @@ template <typename R>
 static void default_tiles(RveHost &h)
 {
     const bool f32 = sizeof(R) == 4;
-    int ty = std::min(std::min(f32 ? 16 : 8, std::max(1, EPT_Y * 256 / h.ny)), h.nkx);
-    // z tiles for 12 elements per thread (the lighter z kernel in FP32)
-    int tz = std::min(std::min(16, std::max(1, 12 * 256 / (6 * h.nz))), h.nkx);
-    while (!tiles_valid<R>(h, ty, tz) && tz > 1) --tz;
-    while (!tiles_valid<R>(h, ty, tz) && ty > 1) --ty;
+    // rows of 4 columns (6 components each: 192 bytes in FP32) where the
+    // registers and the LDS allow it
+    (void)f32;
+    int ty = std::min(std::min(4, std::max(1, EPT_Y * 256 / (6 * h.ny))), h.nkx);
+    int tz = std::min(std::min(4, std::max(1, EPT_Z * Z_THREADS / (6 * h.nz))), h.nkx);
+    if (fixed_len(h.ny)) ty = std::min(fixed_tile_of<R>(h.ny), h.nkx);
+    if (fixed_len(h.nz)) tz = std::min(fixed_tile_of<R>(h.nz), h.nkx);
+    while (!tiles_valid<R>(h, ty, tz) && tz > 1) tz = (tz + 1) / 2;
+    while (!tiles_valid<R>(h, ty, tz) && ty > 1) ty = (ty + 1) / 2;
     set_tiles<R>(h, ty, tz);
 }
 
@@ -441,12 +474,15 @@ static void pass_grids(cpf_solver *s)
     s->lds_x = xfft_lds_bytes<R>() + law_lds_bytes_ns<R>(s->ns_inst);
     s->lds_y = s->lds_z = 0;
     s->y_elems = s->z_elems = 0;
+    s->y_kinds = s->z_kinds = 0;
     for (auto &h : s->rv) {
+        s->y_kinds |= y_kinds<R>(h, h.ty);
+        s->z_kinds |= z_kinds<R>(h, h.tz);
         s->nbx_tot += h.nbx;
-        s->nby_tot += h.nty * h.nz * 6;
+        s->nby_tot += h.nty * h.nz;
         s->nbz_tot += h.nbz;
         s->lds_y = std::max(s->lds_y, lds_y_bytes<R>(h, h.ty));
-        s->y_elems = std::max(s->y_elems, h.ny * h.ty);
+        s->y_elems = std::max(s->y_elems, 6 * h.ny * h.ty);
         s->z_elems = std::max(s->z_elems, 6 * h.nz * h.tz);
         s->lds_z = std::max(s->lds_z, lds_z_bytes<R>(h, h.tz));
     }
@@ -505,6 +541,8 @@ static RveDev<R> make_dev(cpf_solver *s, const RveHost &h, int bx0, int by0, int
     d.nkx = h.nkx; d.nhp = h.nhp;
     d.L = h.L; d.tpbx = h.tpbx; d.nlines = h.ny * h.nz;
     d.ty = h.ty; d.nty = h.nty; d.tz = h.tz; d.ntz = h.ntz;
+    d.yfix = yfix_of<R>(h, h.ty) ? 1 : 0;
+    d.zfix = zfix_of<R>(h, h.tz) ? 1 : 0;
     d.bx0 = bx0; d.by0 = by0; d.bz0 = bz0;
     d.nvox = h.nvox;
     d.inv_nvox = R(1.0 / (double)h.nvox);
@@ -543,7 +581,7 @@ static int upload_devs(cpf_solver *s)
     for (auto &h : s->rv) {
         t.push_back(make_dev<R>(s, h, bx, by, bz));
         bx += h.nbx;
-        by += h.nty * h.nz * 6;
+        by += h.nty * h.nz;
         bz += h.nbz;
     }
     HIPCHK(hipMemcpyAsync(s->ws + s->off_dev, t.data(), sizeof(RveDev<R>) * t.size(), hipMemcpyHostToDevice,
@@ -591,11 +629,11 @@ static void init_rve(RveHost &h, const cpf_problem &p, int green)
     // Nyquist one (kx < nx/2 for even nx, all nx/2 + 1 for odd nx): Gamma0
     // is zero on the Nyquist column and the residual leaves it out, so the
     // column is neither stored nor transformed along y and z.  The rotated
-    // operator acts on it, so it is kept.  Rows are padded to whole
-    // 128-byte lines.
+    // operator acts on it, so it is kept.  The spectrum is stored
+    // [z][y][kx][c]; rows of nhp columns (a multiple of 8: whole 128-byte
+    // lines of 6 components).
     h.nkx = (green == CPF_GREEN_ROTATED || (p.nx & 1)) ? p.nx / 2 + 1 : p.nx / 2;
-    const int line = (int)(128 / sizeof(C2<R>));
-    h.nhp = (h.nkx + line - 1) / line * line;
+    h.nhp = (h.nkx + 7) / 8 * 8;
     h.nvox = (long)p.nx * p.ny * p.nz;
     radix_plan(h.nx, h.px);
     radix_plan(h.ny, h.py);
@@ -952,7 +990,7 @@ static void launch_xiter_any(cpf_solver *s, const LawP<R> &P)
 // the autotuner pass a one-RVE table and an explicit spectrum
 template <typename R>
 static void launch_y(cpf_solver *s, bool inv, const RveDev<R> *table = nullptr, int nrve = 0, int grid = 0,
-                     size_t lds = 0, C2<R> *spec = nullptr, int elems = 0)
+                     size_t lds = 0, C2<R> *spec = nullptr, int elems = 0, int kinds = 0)
 {
     if (!table) {
         table = dptr<RveDev<R>>(s, s->off_dev);
@@ -960,13 +998,28 @@ static void launch_y(cpf_solver *s, bool inv, const RveDev<R> *table = nullptr, 
         grid = s->nby_tot;
         lds = s->lds_y;
         elems = s->y_elems;
+        kinds = s->y_kinds;
     }
-    // registers for 8 elements per thread when the tiles allow it
-    if (elems <= 8 * 256) {
+    if (kinds & 1) {
         if (inv)
-            hipLaunchKernelGGL((k_ypass<R, true, 8>), dim3(grid), dim3(256), lds, s->stream, table, nrve, spec);
+            hipLaunchKernelGGL((k_ypass_fx<R, true>), dim3(grid), dim3(FX_THREADS), lds, s->stream, table, nrve, spec);
         else
-            hipLaunchKernelGGL((k_ypass<R, false, 8>), dim3(grid), dim3(256), lds, s->stream, table, nrve, spec);
+            hipLaunchKernelGGL((k_ypass_fx<R, false>), dim3(grid), dim3(FX_THREADS), lds, s->stream, table, nrve,
+                               spec);
+    }
+    if (!(kinds & 2)) return;
+    // registers for fewer elements per thread when the tiles allow it
+    constexpr int EQ = EPT_Y / 4, EH = EPT_Y / 2;
+    if (elems <= EQ * 256) {
+        if (inv)
+            hipLaunchKernelGGL((k_ypass<R, true, EQ>), dim3(grid), dim3(256), lds, s->stream, table, nrve, spec);
+        else
+            hipLaunchKernelGGL((k_ypass<R, false, EQ>), dim3(grid), dim3(256), lds, s->stream, table, nrve, spec);
+    } else if (elems <= EH * 256) {
+        if (inv)
+            hipLaunchKernelGGL((k_ypass<R, true, EH>), dim3(grid), dim3(256), lds, s->stream, table, nrve, spec);
+        else
+            hipLaunchKernelGGL((k_ypass<R, false, EH>), dim3(grid), dim3(256), lds, s->stream, table, nrve, spec);
     } else {
         if (inv)
             hipLaunchKernelGGL((k_ypass<R, true, EPT_Y>), dim3(grid), dim3(256), lds, s->stream, table, nrve, spec);
@@ -977,7 +1030,7 @@ static void launch_y(cpf_solver *s, bool inv, const RveDev<R> *table = nullptr, 
 
 template <typename R>
 static void launch_z(cpf_solver *s, int mode, const RveDev<R> *table = nullptr, int nrve = 0, int grid = 0,
-                     size_t lds = 0, C2<R> *spec = nullptr, int elems = 0)
+                     size_t lds = 0, C2<R> *spec = nullptr, int elems = 0, int kinds = 0)
 {
     if (!table) {
         table = dptr<RveDev<R>>(s, s->off_dev);
@@ -985,17 +1038,25 @@ static void launch_z(cpf_solver *s, int mode, const RveDev<R> *table = nullptr, 
         grid = s->nbz_tot;
         lds = s->lds_z;
         elems = s->z_elems;
+        kinds = s->z_kinds;
     }
     const R inv_mu0 = R(1.0 / s->mu0);
     const R coef = R((s->lam0 + s->mu0) / (s->mu0 * (s->lam0 + 2.0 * s->mu0)));
     if ((mode & ZMODE_GREEN) && s->opt.green == CPF_GREEN_ROTATED) mode |= ZMODE_ROTATED;
-    constexpr int E = ept_z<R>(), EH = E / 2;
-    if (elems <= EH * 256)
-        hipLaunchKernelGGL((k_zpass_green<R, EH>), dim3(grid), dim3(256), lds, s->stream, table, nrve, inv_mu0, coef,
+    if (kinds & 1)
+        hipLaunchKernelGGL(k_zpass_fx<R>, dim3(grid), dim3(FX_THREADS), lds, s->stream, table, nrve, inv_mu0, coef,
                            mode, spec);
+    if (!(kinds & 2)) return;
+    constexpr int EQ = EPT_Z / 4, EH = EPT_Z / 2;
+    if (elems <= EQ * Z_THREADS)
+        hipLaunchKernelGGL((k_zpass_green<R, EQ>), dim3(grid), dim3(Z_THREADS), lds, s->stream, table, nrve, inv_mu0,
+                           coef, mode, spec);
+    else if (elems <= EH * Z_THREADS)
+        hipLaunchKernelGGL((k_zpass_green<R, EH>), dim3(grid), dim3(Z_THREADS), lds, s->stream, table, nrve, inv_mu0,
+                           coef, mode, spec);
     else
-        hipLaunchKernelGGL((k_zpass_green<R, E>), dim3(grid), dim3(256), lds, s->stream, table, nrve, inv_mu0, coef,
-                           mode, spec);
+        hipLaunchKernelGGL((k_zpass_green<R, EPT_Z>), dim3(grid), dim3(Z_THREADS), lds, s->stream, table, nrve,
+                           inv_mu0, coef, mode, spec);
 }
 
 template <typename R>
@@ -1327,9 +1388,10 @@ static int time_pass(cpf_solver *s, int r, int ty, int tz, bool zpass, int reps,
         if (it == 1) HIPCHK(hipEventRecord(a, s->stream));
         if (zpass)
             launch_z<R>(s, ZMODE_FWD | ZMODE_GREEN, tab, 1, h.ntz * h.ny, lds_z_bytes<R>(h, tz), d.spec,
-                        6 * h.nz * tz);
+                        6 * h.nz * tz, z_kinds<R>(h, tz));
         else
-            launch_y<R>(s, false, tab, 1, h.nty * h.nz * 6, lds_y_bytes<R>(h, ty), d.spec, h.ny * ty);
+            launch_y<R>(s, false, tab, 1, h.nty * h.nz, lds_y_bytes<R>(h, ty), d.spec, 6 * h.ny * ty,
+                        y_kinds<R>(h, ty));
     }
     HIPCHK(hipEventRecord(b, s->stream));
     HIPCHK(hipEventSynchronize(b));
@@ -1399,6 +1461,29 @@ extern "C" int cpf_solver_autotune(cpf_solver *s, int *n_timed)
     return CPF_OK;
 }
 
+template <typename R>
+static int set_tiles_impl(cpf_solver *s, int rve, int ty, int tz)
+{
+    RveHost &h = s->rv[rve];
+    if (!tiles_valid<R>(h, ty, tz))
+        return fail(CPF_E_INVALID_ARG, "tiles (%d, %d) not valid for a %dx%dx%d grid", ty, tz, h.nx, h.ny, h.nz);
+    set_tiles<R>(h, ty, tz);
+    pass_grids<R>(s);
+    return upload_devs<R>(s);
+}
+
+extern "C" int cpf_solver_set_tiles(cpf_solver *s, int rve, int ty, int tz)
+{
+    if (!s || !s->bound) return fail(CPF_E_BAD_STATE, "solver not bound");
+    if (rve < 0 || rve >= (int)s->rv.size()) return fail(CPF_E_INVALID_ARG, "RVE %d outside the batch", rve);
+    HIPCHK(hipStreamSynchronize(s->stream));
+    drop_graph(s);
+    int rc = s->prec == CPF_PREC_FP64 ? set_tiles_impl<double>(s, rve, ty, tz) : set_tiles_impl<float>(s, rve, ty, tz);
+    if (rc) return rc;
+    HIPCHK(hipStreamSynchronize(s->stream));
+    return CPF_OK;
+}
+
 extern "C" int cpf_solver_tiles(const cpf_solver *s, int rve, int *ty, int *tz)
 {
     if (!s || !ty || !tz) return fail(CPF_E_INVALID_ARG, "null argument");
@@ -1411,7 +1496,7 @@ extern "C" int cpf_solver_tiles(const cpf_solver *s, int rve, int *ty, int *tz)
 // ---------------------------------------------------------------------------
 // component operators (RVE 0)
 // ---------------------------------------------------------------------------
-// The component operators work on caller spectra [6][nz][ny][nx/2+1]: all
+// The component operators work on caller spectra [nz][ny][nx/2+1][6]: all
 // columns, unpadded rows.
 template <typename R>
 static RveHost op_host(const RveHost &solve)
@@ -1431,8 +1516,8 @@ static int op_fft_impl(cpf_solver *s, const void *field, void *spec)
     RveDev<R> *tab = dptr<RveDev<R>>(s, s->off_opdev);
     HIPCHK(hipMemcpyAsync(tab, &d, sizeof d, hipMemcpyHostToDevice, s->stream));
     hipLaunchKernelGGL(k_xpass_fwd<R>, dim3(h.nbx), dim3(256), s->lds_x, s->stream, (const R *)field, sp, d);
-    launch_y<R>(s, false, tab, 1, h.nty * h.nz * 6, lds_y_bytes<R>(h, h.ty), sp, h.ny * h.ty);
-    launch_z<R>(s, ZMODE_FWD, tab, 1, h.nbz, lds_z_bytes<R>(h, h.tz), sp, 6 * h.nz * h.tz);
+    launch_y<R>(s, false, tab, 1, h.nty * h.nz, lds_y_bytes<R>(h, h.ty), sp, 6 * h.ny * h.ty, y_kinds<R>(h, h.ty));
+    launch_z<R>(s, ZMODE_FWD, tab, 1, h.nbz, lds_z_bytes<R>(h, h.tz), sp, 6 * h.nz * h.tz, z_kinds<R>(h, h.tz));
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s->stream));
     return CPF_OK;
@@ -1454,8 +1539,8 @@ static int op_green_impl(cpf_solver *s, void *spec, void *outp, double *err2)
     const RveDev<R> d = make_dev<R>(s, h, 0, 0, 0);
     RveDev<R> *tab = dptr<RveDev<R>>(s, s->off_opdev);
     HIPCHK(hipMemcpyAsync(tab, &d, sizeof d, hipMemcpyHostToDevice, s->stream));
-    launch_z<R>(s, ZMODE_GREEN, tab, 1, h.nbz, lds_z_bytes<R>(h, h.tz), sp, 6 * h.nz * h.tz);
-    launch_y<R>(s, true, tab, 1, h.nty * h.nz * 6, lds_y_bytes<R>(h, h.ty), sp, h.ny * h.ty);
+    launch_z<R>(s, ZMODE_GREEN, tab, 1, h.nbz, lds_z_bytes<R>(h, h.tz), sp, 6 * h.nz * h.tz, z_kinds<R>(h, h.tz));
+    launch_y<R>(s, true, tab, 1, h.nty * h.nz, lds_y_bytes<R>(h, h.ty), sp, 6 * h.ny * h.ty, y_kinds<R>(h, h.ty));
     hipLaunchKernelGGL(k_xpass_inv<R>, dim3(h.nbx), dim3(256), s->lds_x, s->stream, sp, (R *)outp, d);
     HIPCHK(hipGetLastError());
     if (err2) {

@@ -105,13 +105,50 @@ __device__ __forceinline__ void dft8(C2<R> *v)
     v[7] = csub(e[3], o3);
 }
 
+// 16 points as 4 x 4: 4-point DFTs over the four stride-4 subsequences,
+// twiddles exp(-+2 pi i n2 k1 / 16), 4-point DFTs across them.
+template <typename R, bool INV>
+__device__ __forceinline__ void dft16(C2<R> *v)
+{
+    // cos and sin of 2 pi p / 16, p = 0..9
+    constexpr double C[10] = {1.0, 0.923879532511286756, 0.707106781186547524, 0.382683432365089772, 0.0,
+                              -0.382683432365089772, -0.707106781186547524, -0.923879532511286756, -1.0,
+                              -0.923879532511286756};
+    constexpr double S[10] = {0.0, 0.382683432365089772, 0.707106781186547524, 0.923879532511286756, 1.0,
+                              0.923879532511286756, 0.707106781186547524, 0.382683432365089772, 0.0,
+                              -0.382683432365089772};
+    C2<R> a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+        for (int n1 = 0; n1 < 4; ++n1) a[n2][n1] = v[4 * n1 + n2];
+        dft4<R, INV>(a[n2]);
+    }
+#pragma unroll
+    for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+        for (int k1 = 1; k1 < 4; ++k1) {
+            const int p = n2 * k1;
+            const C2<R> w = {R(C[p]), INV ? R(S[p]) : R(-S[p])};
+            a[n2][k1] = cmul(a[n2][k1], w);
+        }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+        C2<R> b[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+        dft4<R, INV>(b);
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = b[k2];
+    }
+}
+
 template <typename R, bool INV, int RAD>
 __device__ __forceinline__ void dft(C2<R> *v)
 {
     if constexpr (RAD == 2) dft2<R, INV>(v);
     else if constexpr (RAD == 3) dft3<R, INV>(v);
     else if constexpr (RAD == 4) dft4<R, INV>(v);
-    else dft8<R, INV>(v);
+    else if constexpr (RAD == 8) dft8<R, INV>(v);
+    else dft16<R, INV>(v);
 }
 
 // ---------------------------------------------------------------------------
@@ -184,6 +221,300 @@ __device__ void lds_fft(C2<R> *buf, int nlines, int ls, const FftPlan &P,
         else
             fft_pass<R, INV, 2, (EPT + 1) / 2>(buf, nlines, ls, P.n, Ns, mm, mn, tw, tid, nthr);
         Ns *= r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Transforms of nl lines of length N whose lines are adjacent and whose
+// elements are strided: LDS word buf[e * es + l] holds element e of line l.
+// Butterfly b of a pass takes line l = b mod nl and index j = b div nl, so
+// the lanes of a wave touch adjacent lines at the same element: adjacent
+// LDS words, and in global memory adjacent columns of one row (the y and z
+// passes' lines are the kx columns of a tile).  The first pass can read
+// its inputs straight from global memory and the last can write its
+// outputs there, so a tile is never staged through LDS on the way in or
+// out: LDS sees the middle passes only.  In global memory element e of
+// line l is gline(l)[e * gs] (gs uniform).
+// ---------------------------------------------------------------------------
+// Loads and stores of one complex value that the compiler may issue as
+// global-memory instructions (the pointers come from device tables, where
+// their address space is not known to it).
+template <typename R>
+__device__ __forceinline__ C2<R> gload(const C2<R> *p)
+{
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    const v2 t = *(const __attribute__((address_space(1))) v2 *)p;
+    return {t.x, t.y};
+}
+template <typename R>
+__device__ __forceinline__ void gstore(C2<R> *p, C2<R> v)
+{
+    typedef R v2 __attribute__((ext_vector_type(2)));
+    const v2 t = {v.x, v.y};
+    *(__attribute__((address_space(1))) v2 *)p = t;
+}
+
+// Twiddle and butterfly of one radix-RAD butterfly with index j.
+template <typename R, bool INV, int RAD>
+__device__ __forceinline__ void strided_bfly(C2<R> (&v)[RAD], int k, int tstride, const C2<R> *__restrict__ tw)
+{
+    if (k) {
+#pragma unroll
+        for (int q = 1; q < RAD; ++q) {
+            C2<R> w = tw[q * k * tstride];
+            if (INV) w.y = -w.y;
+            v[q] = cmul(v[q], w);
+        }
+    }
+    dft<R, INV, RAD>(v);
+}
+
+template <typename R, bool INV, int RAD, int MAXB, bool SRC_G, bool DST_G, class GL>
+__device__ __forceinline__ void strided_pass(C2<R> *buf, int es, int nl, unsigned mag_nl, int N, int Ns,
+                                             unsigned mag_ns, const C2<R> *__restrict__ tw, int tid, int nthr,
+                                             const GL &gline, long gs)
+{
+    const int m = N / RAD;
+    const int nb = nl * m;
+    const int tstride = N / (Ns * RAD);
+    if constexpr (SRC_G || DST_G) {
+        // reads and writes go to different memories: one butterfly at a
+        // time (its RAD loads in flight together)
+        const long gq = (long)m * gs;   // global step between the inputs of a butterfly
+        for (int i = tid; i < nb; i += nthr) {
+            const int j = (int)fdiv((unsigned)i, mag_nl), l = i - j * nl;
+            const int k = j - (int)fdiv((unsigned)j, mag_ns) * Ns;
+            C2<R> v[RAD];
+            if constexpr (SRC_G) {
+                const C2<R> *src = gline(l) + j * gs;
+#pragma unroll
+                for (int q = 0; q < RAD; ++q) v[q] = gload(src + q * gq);
+            } else {
+                const C2<R> *src = buf + j * es + l;
+#pragma unroll
+                for (int q = 0; q < RAD; ++q) v[q] = src[q * m * es];
+            }
+            strided_bfly<R, INV, RAD>(v, k, tstride, tw);
+            const int o = (j - k) * RAD + k;
+            if constexpr (DST_G) {
+                C2<R> *dst = gline(l) + o * gs;
+#pragma unroll
+                for (int q = 0; q < RAD; ++q) gstore(dst + (long)q * Ns * gs, v[q]);
+            } else {
+                C2<R> *dst = buf + o * es + l;
+#pragma unroll
+                for (int q = 0; q < RAD; ++q) dst[q * Ns * es] = v[q];
+            }
+        }
+        if constexpr (!DST_G) __syncthreads();
+    } else {
+        // in place in LDS: every read before any write
+        C2<R> v[MAXB][RAD];
+#pragma unroll
+        for (int b = 0; b < MAXB; ++b) {
+            const int i = tid + b * nthr;
+            if (i < nb) {
+                const int j = (int)fdiv((unsigned)i, mag_nl), l = i - j * nl;
+                const C2<R> *src = buf + j * es + l;
+#pragma unroll
+                for (int q = 0; q < RAD; ++q) v[b][q] = src[q * m * es];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int b = 0; b < MAXB; ++b) {
+            const int i = tid + b * nthr;
+            if (i < nb) {
+                const int j = (int)fdiv((unsigned)i, mag_nl), l = i - j * nl;
+                const int k = j - (int)fdiv((unsigned)j, mag_ns) * Ns;
+                strided_bfly<R, INV, RAD>(v[b], k, tstride, tw);
+                C2<R> *dst = buf + ((j - k) * RAD + k) * es + l;
+#pragma unroll
+                for (int q = 0; q < RAD; ++q) dst[q * Ns * es] = v[b][q];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+template <typename R, bool INV, int RAD, int MAXB, class GL>
+__device__ __forceinline__ void strided_pass_any(bool src_g, bool dst_g, C2<R> *buf, int es, int nl,
+                                                 unsigned mag_nl, int N, int Ns, unsigned mag_ns,
+                                                 const C2<R> *__restrict__ tw, int tid, int nthr, const GL &gline,
+                                                 long gs)
+{
+    if (src_g && dst_g)
+        strided_pass<R, INV, RAD, MAXB, true, true>(buf, es, nl, mag_nl, N, Ns, mag_ns, tw, tid, nthr, gline, gs);
+    else if (src_g)
+        strided_pass<R, INV, RAD, MAXB, true, false>(buf, es, nl, mag_nl, N, Ns, mag_ns, tw, tid, nthr, gline, gs);
+    else if (dst_g)
+        strided_pass<R, INV, RAD, MAXB, false, true>(buf, es, nl, mag_nl, N, Ns, mag_ns, tw, tid, nthr, gline, gs);
+    else
+        strided_pass<R, INV, RAD, MAXB, false, false>(buf, es, nl, mag_nl, N, Ns, mag_ns, tw, tid, nthr, gline,
+                                                      gs);
+}
+
+// Whole transforms of the nl lines.  FROM_G: the input is in global memory
+// (else in LDS); TO_G: the output goes to global memory (else stays in
+// LDS, with the block synchronized).  EPT bounds the elements per thread:
+// nl * N <= EPT * nthr.  Twiddles tw[k] = exp(-2 pi i k / N) must be
+// readable by the second pass (the first uses none).  Called by every
+// thread of the block.
+template <typename R, bool INV, int EPT, bool FROM_G, bool TO_G, class GL>
+__device__ void strided_fft(C2<R> *buf, int es, int nl, const FftPlan &P, const C2<R> *__restrict__ tw, int tid,
+                            int nthr, const GL &gline, long gs)
+{
+    const unsigned mag_nl = fdiv_magic((unsigned)nl);
+    int Ns = 1;
+    for (int p = 0; p < P.npass; ++p) {
+        const int r = P.radix[p];
+        const unsigned mn = P.mag_ns[p];
+        const bool sg = FROM_G && p == 0, dg = TO_G && p == P.npass - 1;
+        if (r == 8)
+            strided_pass_any<R, INV, 8, (EPT + 7) / 8>(sg, dg, buf, es, nl, mag_nl, P.n, Ns, mn, tw, tid, nthr,
+                                                       gline, gs);
+        else if (r == 4)
+            strided_pass_any<R, INV, 4, (EPT + 3) / 4>(sg, dg, buf, es, nl, mag_nl, P.n, Ns, mn, tw, tid, nthr,
+                                                       gline, gs);
+        else if (r == 3)
+            strided_pass_any<R, INV, 3, (EPT + 2) / 3>(sg, dg, buf, es, nl, mag_nl, P.n, Ns, mn, tw, tid, nthr,
+                                                       gline, gs);
+        else
+            strided_pass_any<R, INV, 2, (EPT + 1) / 2>(sg, dg, buf, es, nl, mag_nl, P.n, Ns, mn, tw, tid, nthr,
+                                                       gline, gs);
+        Ns *= r;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The same line transforms for lengths known at compile time (the common
+// grid sizes): a fixed radix plan of two or three passes, all index
+// arithmetic by constants, NL lines and NT threads fixed.  nlv <= NL lines
+// hold data (a narrower last tile); the others are never read from or
+// written to global memory.
+// ---------------------------------------------------------------------------
+template <int N> struct FixedPlan { static constexpr int np = 0, r0 = 1, r1 = 1, r2 = 1; };
+template <> struct FixedPlan<32> { static constexpr int np = 2, r0 = 8, r1 = 4, r2 = 1; };
+template <> struct FixedPlan<48> { static constexpr int np = 2, r0 = 16, r1 = 3, r2 = 1; };
+template <> struct FixedPlan<64> { static constexpr int np = 2, r0 = 8, r1 = 8, r2 = 1; };
+template <> struct FixedPlan<96> { static constexpr int np = 3, r0 = 8, r1 = 4, r2 = 3; };
+template <> struct FixedPlan<128> { static constexpr int np = 2, r0 = 8, r1 = 16, r2 = 1; };
+template <> struct FixedPlan<256> { static constexpr int np = 2, r0 = 16, r1 = 16, r2 = 1; };
+
+struct NoHook {
+    __device__ void operator()() const {}
+};
+
+// hook: run by every thread after its butterflies and before the closing
+// barrier of the pass (the first pass stages the twiddles there, so their
+// load overlaps the tile's)
+template <typename R, bool INV, int N, int NL, int NT, int RAD, int NS, bool SRC_G, bool DST_G, class GL,
+          class HK = NoHook>
+__device__ __forceinline__ void fixed_pass(C2<R> *buf, int nlv, const C2<R> *__restrict__ tw, const GL &gline,
+                                           long gs, const HK &hook = HK())
+{
+    constexpr int m = N / RAD, nb = NL * m, TS = N / (NS * RAD);
+    constexpr int ITER = (nb + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    if constexpr (SRC_G || DST_G) {
+#pragma unroll
+        for (int it = 0; it < ITER; ++it) {
+            const int i = tid + it * NT;
+            if (nb % NT == 0 || i < nb) {
+                const int j = i / NL, l = i - j * NL;
+                const int k = NS > 1 ? j % NS : 0;
+                C2<R> v[RAD];
+                if constexpr (SRC_G) {
+                    if (l < nlv) {
+                        const C2<R> *src = gline(l) + j * gs;
+#pragma unroll
+                        for (int q = 0; q < RAD; ++q) v[q] = gload(src + (long)q * m * gs);
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < RAD; ++q) v[q] = C2<R>{R(0), R(0)};
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < RAD; ++q) v[q] = buf[(j + q * m) * NL + l];
+                }
+                if constexpr (NS > 1) {
+                    if (k) {
+#pragma unroll
+                        for (int q = 1; q < RAD; ++q) {
+                            C2<R> w = tw[q * k * TS];
+                            if (INV) w.y = -w.y;
+                            v[q] = cmul(v[q], w);
+                        }
+                    }
+                }
+                dft<R, INV, RAD>(v);
+                const int o = (j - k) * RAD + k;
+                if constexpr (DST_G) {
+                    if (l < nlv) {
+                        C2<R> *dst = gline(l) + o * gs;
+#pragma unroll
+                        for (int q = 0; q < RAD; ++q) gstore(dst + (long)q * NS * gs, v[q]);
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < RAD; ++q) buf[(o + q * NS) * NL + l] = v[q];
+                }
+            }
+        }
+        hook();
+        if constexpr (!DST_G) __syncthreads();
+    } else {
+        C2<R> v[ITER][RAD];
+#pragma unroll
+        for (int it = 0; it < ITER; ++it) {
+            const int i = tid + it * NT;
+            if (nb % NT == 0 || i < nb) {
+                const int j = i / NL, l = i - j * NL;
+#pragma unroll
+                for (int q = 0; q < RAD; ++q) v[it][q] = buf[(j + q * m) * NL + l];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int it = 0; it < ITER; ++it) {
+            const int i = tid + it * NT;
+            if (nb % NT == 0 || i < nb) {
+                const int j = i / NL, l = i - j * NL;
+                const int k = j % NS;
+                if (k) {
+#pragma unroll
+                    for (int q = 1; q < RAD; ++q) {
+                        C2<R> w = tw[q * k * TS];
+                        if (INV) w.y = -w.y;
+                        v[it][q] = cmul(v[it][q], w);
+                    }
+                }
+                dft<R, INV, RAD>(v[it]);
+                const int o = (j - k) * RAD + k;
+#pragma unroll
+                for (int q = 0; q < RAD; ++q) buf[(o + q * NS) * NL + l] = v[it][q];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Whole transforms with the plan of N (FixedPlan<N>::np > 0); FROM_G, TO_G
+// and the twiddle table as for strided_fft; the LDS buffer is [N][NL].
+// hook: run inside the first pass before its barrier (staging the
+// twiddles that the later passes read).
+template <typename R, bool INV, int N, int NL, int NT, bool FROM_G, bool TO_G, class GL, class HK = NoHook>
+__device__ __forceinline__ void fixed_fft(C2<R> *buf, int nlv, const C2<R> *__restrict__ tw, const GL &gline,
+                                          long gs, const HK &hook = HK())
+{
+    using P = FixedPlan<N>;
+    static_assert(P::np >= 2, "no fixed plan for this length");
+    fixed_pass<R, INV, N, NL, NT, P::r0, 1, FROM_G, false>(buf, nlv, tw, gline, gs, hook);
+    if constexpr (P::np == 2) {
+        fixed_pass<R, INV, N, NL, NT, P::r1, P::r0, false, TO_G>(buf, nlv, tw, gline, gs);
+    } else {
+        fixed_pass<R, INV, N, NL, NT, P::r1, P::r0, false, false>(buf, nlv, tw, gline, gs);
+        fixed_pass<R, INV, N, NL, NT, P::r2, P::r0 * P::r1, false, TO_G>(buf, nlv, tw, gline, gs);
     }
 }
 

@@ -65,6 +65,7 @@ struct RveDev {
                                // out the Nyquist column, which it zeroes) and row pitch
     int L, tpbx, nlines;       // x pass: lines per block, threads used
     int ty, nty, tz, ntz;      // y / z pass tiles (kx columns) and tile counts
+    int yfix, zfix;            // 1: the fixed-length kernels do this RVE's y / z passes
     int bx0, by0, bz0;         // first block in the x, y and z pass grids
     long nvox;
     R inv_nvox;
@@ -75,7 +76,7 @@ struct RveDev {
     R *st[2];                  // state [6+2S][nvox]: committed = st[cur]
     int32_t *mv;               // [nvox] substep exponent j (count M 2^j) of the current
                                // load step, with error-controlled substeps
-    C2<R> *spec;               // [6][nz][ny][nhp], columns kx < nkx
+    C2<R> *spec;               // [nz][ny][nhp][6], columns kx < nkx
     const C2<R> *tw[3];        // twiddles exp(-2 pi i k / n) along x, y, z
     double *part_x;            // [x blocks][NPX]
     double *part_z;            // [z blocks]
@@ -122,18 +123,18 @@ __device__ __forceinline__ void load_halfspec_pairs(const C2<R> *__restrict__ sp
 {
     // Z_k = A_k + i B_k over the full x spectrum from the stored halves,
     // using A_{N-k} = conj(A_k); DC and Nyquist bins keep their real parts;
-    // bins not stored (k >= nkx) are zero.
-    const long plane = (long)nz * ny * nhp;
+    // bins not stored (k >= nkx) are zero.  Spectrum layout [z][y][kx][c].
     const long row = ((long)z * ny + y) * nhp;
     const bool mirror = x > nx / 2;
     const int k = mirror ? nx - x : x;
     const bool realbin = (k == 0) || ((nx & 1) == 0 && k == nx / 2);
+    const C2<R> *bin = spec + (row + k) * 6;
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
         C2<R> z2 = {R(0), R(0)};
         if (valid && k < nkx) {
-            C2<R> A = spec[(2 * p) * plane + row + k];
-            C2<R> B = spec[(2 * p + 1) * plane + row + k];
+            C2<R> A = bin[2 * p];
+            C2<R> B = bin[2 * p + 1];
             if (realbin) { A.y = R(0); B.y = R(0); }
             if (mirror) { A.y = -A.y; B.y = -B.y; }
             z2 = {A.x - B.y, A.y + B.x};
@@ -149,8 +150,8 @@ __device__ __forceinline__ void store_halfspec_pairs(C2<R> *__restrict__ spec, c
 {
     // Split Z = FFT(a + i b) into A = FFT(a), B = FFT(b) on k in [0, nkx).
     if (!valid || x >= nkx) return;
-    const long plane = (long)nz * ny * nhp;
     const long row = ((long)z * ny + y) * nhp;
+    C2<R> *bin = spec + (row + x) * 6;
     const int xm = x == 0 ? 0 : nx - x;
 #pragma unroll
     for (int p = 0; p < 3; ++p) {
@@ -158,8 +159,8 @@ __device__ __forceinline__ void store_halfspec_pairs(C2<R> *__restrict__ spec, c
         const C2<R> Zm = buf[(p * L + li) * nx + xm];
         const C2<R> A = {R(0.5) * (Zk.x + Zm.x), R(0.5) * (Zk.y - Zm.y)};
         const C2<R> B = {R(0.5) * (Zk.y + Zm.y), R(0.5) * (Zm.x - Zk.x)};
-        spec[(2 * p) * plane + row + x] = A;
-        spec[(2 * p + 1) * plane + row + x] = B;
+        bin[2 * p] = A;
+        bin[2 * p + 1] = B;
     }
 }
 
@@ -530,8 +531,12 @@ __global__ __launch_bounds__(256) void k_xpass_inv(const C2<R> *__restrict__ spe
 }
 
 // ---------------------------------------------------------------------------
-// y pass: C2C along y on the half spectrum.  Block = one component, one z,
-// a tile of ty consecutive kx columns; LDS holds ty lines of ny points.
+// y pass: C2C along y on the half spectrum, stored [z][y][kx][c] (the six
+// components of a frequency adjacent).  Block = one z, a tile of ty
+// consecutive kx columns: 6 ty lines (column-major, components adjacent),
+// each row of the tile one contiguous run of 6 ty values.  The first radix
+// pass reads its inputs straight from the rows and the last writes its
+// outputs straight back; the middle passes run in LDS laid out [y][line].
 // ---------------------------------------------------------------------------
 // spec_override (component operators): transform this array instead of the
 // RVE's own spectrum, and ignore the step flag.
@@ -541,32 +546,22 @@ __global__ __launch_bounds__(256) void k_ypass(const RveDev<R> *__restrict__ rv,
 {
     const int r = find_rve(rv, nrve, (int)blockIdx.x, 1);
     const RveDev<R> &d = rv[r];
-    if (!spec_override && d.sc->done) return;
+    if ((!spec_override && d.sc->done) || d.yfix) return;
     extern __shared__ unsigned char smem_raw[];
     C2<R> *buf = reinterpret_cast<C2<R> *>(smem_raw);
     const int local = blockIdx.x - d.by0;
-    const int tile = local % d.nty, zc = local / d.nty;
-    const int z = zc % d.nz, c = zc / d.nz;
+    const int tile = local % d.nty, z = local / d.nty;
     const int ny = d.ny, nhp = d.nhp;
     const int kx0 = tile * d.ty;
-    const int tw_ = min(d.ty, d.nkx - kx0);
-    const int ls = ny + 1;
-    C2<R> *g = (spec_override ? spec_override : d.spec) + ((long)c * d.nz + z) * ny * nhp + kx0;
+    const int nl = 6 * min(d.ty, d.nkx - kx0);
+    C2<R> *g = (spec_override ? spec_override : d.spec) + ((long)z * ny * nhp + kx0) * 6;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    // twiddles after the tile (the launch adds ny entries of LDS)
-    C2<R> *twl = buf + (size_t)d.ty * ls;
+    // twiddles after the tile (the launch adds ny entries of LDS); the
+    // first pass needs none and ends with a barrier
+    C2<R> *twl = buf + (size_t)6 * d.ty * ny;
     for (int i = tid; i < ny; i += nthr) twl[i] = d.tw[1][i];
-    const unsigned mt = fdiv_magic((unsigned)tw_);   // indices stay below 2^16
-    for (int i = tid; i < ny * tw_; i += nthr) {
-        const int y = (int)fdiv((unsigned)i, mt), col = i - y * tw_;
-        buf[col * ls + y] = g[(long)y * nhp + col];
-    }
-    __syncthreads();
-    lds_fft<R, INV, EPT>(buf, tw_, ls, d.py, twl, tid, nthr);
-    for (int i = tid; i < ny * tw_; i += nthr) {
-        const int y = (int)fdiv((unsigned)i, mt), col = i - y * tw_;
-        g[(long)y * nhp + col] = buf[col * ls + y];
-    }
+    const auto gline = [=](int l) { return g + l; };
+    strided_fft<R, INV, EPT, true, true>(buf, nl, nl, d.py, twl, tid, nthr, gline, 6L * nhp);
 }
 
 // ---------------------------------------------------------------------------
@@ -658,66 +653,198 @@ constexpr int ZMODE_FWD = 1;
 constexpr int ZMODE_GREEN = 2;
 constexpr int ZMODE_ROTATED = 4;   // with ZMODE_GREEN: the rotated-scheme operator
 
+// Block = one ky, a tile of tz kx columns, all kz, all 6 components: the
+// 6 tz lines (column-major, components adjacent) of nz points, each row of
+// the tile one contiguous run of 6 tz values, laid out [kz][line] in LDS.
+// The forward transform reads its first pass from the spectrum rows, the
+// Green operator works in LDS (a frequency's six components adjacent), and
+// the inverse writes its last pass back to the rows.
+constexpr int Z_THREADS = 256;
+
 template <typename R, int EPT>
-__global__ __launch_bounds__(256) void k_zpass_green(const RveDev<R> *__restrict__ rv, int nrve, R inv_mu0,
-                                                     R coef, int mode, C2<R> *spec_override)
+__global__ __launch_bounds__(Z_THREADS) void k_zpass_green(const RveDev<R> *__restrict__ rv, int nrve, R inv_mu0,
+                                                           R coef, int mode, C2<R> *spec_override)
 {
     const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
     const int r = find_rve(rv, nrve, blk, 2);
     const RveDev<R> &d = rv[r];
-    if (!spec_override && d.sc->done) return;
+    if ((!spec_override && d.sc->done) || d.zfix) return;
     extern __shared__ unsigned char smem_raw[];
     C2<R> *buf = reinterpret_cast<C2<R> *>(smem_raw);
     const int local = blk - d.bz0;
     const int tile = local % d.ntz, ky = local / d.ntz;
     const int kx0 = tile * d.tz;
     const int tw_ = min(d.tz, d.nkx - kx0);
-    const int nz = d.nz, ls = nz + 1;
-    C2<R> *spec = spec_override ? spec_override : d.spec;
-    const long plane = (long)d.nz * d.ny * d.nhp;
-    const long colbase = (long)ky * d.nhp + kx0;
-    const long zstride = (long)d.ny * d.nhp;
+    const int nz = d.nz, nl = 6 * tw_;
+    C2<R> *spec = (spec_override ? spec_override : d.spec) + ((long)ky * d.nhp + kx0) * 6;
+    const long zstride = 6L * d.ny * d.nhp;
     const int tid = threadIdx.x, nthr = blockDim.x;
-    const int nrow = 6 * nz;
     // twiddles after the tile (the launch adds nz entries of LDS)
-    C2<R> *twl = buf + (size_t)6 * d.tz * ls;
+    C2<R> *twl = buf + (size_t)6 * d.tz * nz;
     for (int i = tid; i < nz; i += nthr) twl[i] = d.tw[2][i];
-    // exact quotients by multiply-high (indices stay below 2^16)
-    const unsigned mt = fdiv_magic((unsigned)tw_), mz = fdiv_magic((unsigned)nz);
-    for (int i = tid; i < nrow * tw_; i += nthr) {
-        const int rr = (int)fdiv((unsigned)i, mt), col = i - rr * tw_;
-        const int c = (int)fdiv((unsigned)rr, mz), kz = rr - c * nz;
-        buf[(c * tw_ + col) * ls + kz] = spec[c * plane + kz * zstride + colbase + col];
-    }
-    __syncthreads();
-    if (mode & ZMODE_FWD) lds_fft<R, false, EPT>(buf, 6 * tw_, ls, d.pz, twl, tid, nthr);
+    const unsigned mt = fdiv_magic((unsigned)tw_);
+    const auto gline = [=](int l) { return spec + l; };
     if (!(mode & ZMODE_GREEN)) {
-        for (int i = tid; i < nrow * tw_; i += nthr) {
-            const int rr = (int)fdiv((unsigned)i, mt), col = i - rr * tw_;
-            const int c = (int)fdiv((unsigned)rr, mz), kz = rr - c * nz;
-            spec[c * plane + kz * zstride + colbase + col] = buf[(c * tw_ + col) * ls + kz];
-        }
+        // forward transform only (component operator)
+        strided_fft<R, false, EPT, true, true>(buf, nl, nl, d.pz, twl, tid, nthr, gline, zstride);
         return;
+    }
+    if (mode & ZMODE_FWD) {
+        strided_fft<R, false, EPT, true, false>(buf, nl, nl, d.pz, twl, tid, nthr, gline, zstride);
+    } else {
+        const unsigned ml = fdiv_magic((unsigned)nl);
+        for (int i = tid; i < nl * nz; i += nthr) {
+            const int e = (int)fdiv((unsigned)i, ml), l = i - e * nl;
+            buf[e * nl + l] = gline(l)[e * zstride];
+        }
+        __syncthreads();
     }
     const GreenArgs<R> g = {d.nx, d.ny, d.nz, inv_mu0, coef};
     double err2 = 0.0;
     for (int i = tid; i < tw_ * nz; i += nthr) {
-        const int col = (int)fdiv((unsigned)i, mz), kz = i - col * nz;
-        C2<R> s[6];
+        const int kz = (int)fdiv((unsigned)i, mt), col = i - kz * tw_;
+        C2<R> sv[6];
+        C2<R> *f = buf + kz * nl + col * 6;
 #pragma unroll
-        for (int c = 0; c < 6; ++c) s[c] = buf[(c * tw_ + col) * ls + kz];
-        green_point<R>(s, kx0 + col, ky, kz, g, (mode & ZMODE_ROTATED) != 0, err2);
+        for (int c = 0; c < 6; ++c) sv[c] = f[c];
+        green_point<R>(sv, kx0 + col, ky, kz, g, (mode & ZMODE_ROTATED) != 0, err2);
 #pragma unroll
-        for (int c = 0; c < 6; ++c) buf[(c * tw_ + col) * ls + kz] = s[c];
+        for (int c = 0; c < 6; ++c) f[c] = sv[c];
     }
     double e[1] = {err2};
-    block_sum<1>(e, d.part_z + local);
+    block_sum<1, Z_THREADS / 64>(e, d.part_z + local);
     __syncthreads();
-    lds_fft<R, true, EPT>(buf, 6 * tw_, ls, d.pz, twl, tid, nthr);
-    for (int i = tid; i < nrow * tw_; i += nthr) {
-        const int rr = (int)fdiv((unsigned)i, mt), col = i - rr * tw_;
-        const int c = (int)fdiv((unsigned)rr, mz), kz = rr - c * nz;
-        spec[c * plane + kz * zstride + colbase + col] = buf[(c * tw_ + col) * ls + kz];
+    strided_fft<R, true, EPT, false, true>(buf, nl, nl, d.pz, twl, tid, nthr, gline, zstride);
+}
+
+// ---------------------------------------------------------------------------
+// Fixed-length y and z passes: the common lengths (fixed_len) with their
+// radix plans and the tile width known at compile time (fixed_tile columns
+// of 6 components), 256 threads.  The same transforms as k_ypass and
+// k_zpass_green; an RVE is done by one kernel or the other (yfix, zfix).
+// ---------------------------------------------------------------------------
+constexpr int FX_THREADS = 256;   // threads of the fixed-length y and z blocks
+
+__host__ __device__ constexpr bool fixed_len(int n)
+{
+    return n == 32 || n == 48 || n == 64 || n == 96 || n == 128 || n == 256;
+}
+template <typename R, int N>
+__host__ __device__ constexpr int fixed_tile()
+{
+    return (sizeof(R) == 8 && N == 256) ? 2 : 4;
+}
+template <typename R>
+__host__ __device__ constexpr int fixed_tile_of(int n)
+{
+    return (sizeof(R) == 8 && n == 256) ? 2 : 4;
+}
+
+template <typename R, bool INV, int N>
+__device__ __forceinline__ void ypass_fixed(const RveDev<R> &d, C2<R> *g, C2<R> *buf, int nlv)
+{
+    constexpr int NL = 6 * fixed_tile<R, N>();
+    C2<R> *twl = buf + NL * N;
+    const C2<R> *twg = d.tw[1];
+    const auto stage = [=]() {
+        for (int i = threadIdx.x; i < N; i += FX_THREADS) twl[i] = twg[i];
+    };
+    const auto gline = [=](int l) { return g + l; };
+    fixed_fft<R, INV, N, NL, FX_THREADS, true, true>(buf, nlv, twl, gline, 6L * d.nhp, stage);
+}
+
+template <typename R, bool INV>
+__global__ __launch_bounds__(FX_THREADS) void k_ypass_fx(const RveDev<R> *__restrict__ rv, int nrve, C2<R> *spec_override)
+{
+    const int r = find_rve(rv, nrve, (int)blockIdx.x, 1);
+    const RveDev<R> &d = rv[r];
+    if ((!spec_override && d.sc->done) || !d.yfix) return;
+    extern __shared__ unsigned char smem_raw[];
+    C2<R> *buf = reinterpret_cast<C2<R> *>(smem_raw);
+    const int local = blockIdx.x - d.by0;
+    const int tile = local % d.nty, z = local / d.nty;
+    const int kx0 = tile * d.ty;
+    const int nlv = 6 * min(d.ty, d.nkx - kx0);
+    C2<R> *g = (spec_override ? spec_override : d.spec) + ((long)z * d.ny * d.nhp + kx0) * 6;
+    switch (d.ny) {
+    case 32: ypass_fixed<R, INV, 32>(d, g, buf, nlv); break;
+    case 48: ypass_fixed<R, INV, 48>(d, g, buf, nlv); break;
+    case 64: ypass_fixed<R, INV, 64>(d, g, buf, nlv); break;
+    case 96: ypass_fixed<R, INV, 96>(d, g, buf, nlv); break;
+    case 128: ypass_fixed<R, INV, 128>(d, g, buf, nlv); break;
+    default: ypass_fixed<R, INV, 256>(d, g, buf, nlv); break;
+    }
+}
+
+template <typename R, int N>
+__device__ __forceinline__ void zpass_fixed(const RveDev<R> &d, C2<R> *spec, C2<R> *buf, int tw_, int kx0, int ky,
+                                            int local, R inv_mu0, R coef, int mode)
+{
+    constexpr int TILE = fixed_tile<R, N>(), NL = 6 * TILE;
+    const int nlv = 6 * tw_;
+    const long zs = 6L * d.ny * d.nhp;
+    C2<R> *twl = buf + NL * N;
+    const C2<R> *twg = d.tw[2];
+    const auto stage = [=]() {
+        for (int i = threadIdx.x; i < N; i += FX_THREADS) twl[i] = twg[i];
+    };
+    const auto gline = [=](int l) { return spec + l; };
+    if (!(mode & ZMODE_GREEN)) {
+        fixed_fft<R, false, N, NL, FX_THREADS, true, true>(buf, nlv, twl, gline, zs, stage);
+        return;
+    }
+    if (mode & ZMODE_FWD) {
+        fixed_fft<R, false, N, NL, FX_THREADS, true, false>(buf, nlv, twl, gline, zs, stage);
+    } else {
+        for (int i = threadIdx.x; i < NL * N; i += FX_THREADS) {
+            const int e = i / NL, l = i - e * NL;
+            buf[i] = l < nlv ? gload(gline(l) + e * zs) : C2<R>{R(0), R(0)};
+        }
+        stage();
+        __syncthreads();
+    }
+    const GreenArgs<R> g = {d.nx, d.ny, d.nz, inv_mu0, coef};
+    double err2 = 0.0;
+    for (int i = threadIdx.x; i < TILE * N; i += FX_THREADS) {
+        const int kz = i / TILE, col = i - kz * TILE;
+        if (col < tw_) {
+            C2<R> sv[6];
+            C2<R> *f = buf + kz * NL + col * 6;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) sv[c] = f[c];
+            green_point<R>(sv, kx0 + col, ky, kz, g, (mode & ZMODE_ROTATED) != 0, err2);
+#pragma unroll
+            for (int c = 0; c < 6; ++c) f[c] = sv[c];
+        }
+    }
+    double e[1] = {err2};
+    block_sum<1, FX_THREADS / 64>(e, d.part_z + local);
+    __syncthreads();
+    fixed_fft<R, true, N, NL, FX_THREADS, false, true>(buf, nlv, twl, gline, zs);
+}
+
+template <typename R>
+__global__ __launch_bounds__(FX_THREADS) void k_zpass_fx(const RveDev<R> *__restrict__ rv, int nrve, R inv_mu0, R coef,
+                                                  int mode, C2<R> *spec_override)
+{
+    const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int r = find_rve(rv, nrve, blk, 2);
+    const RveDev<R> &d = rv[r];
+    if ((!spec_override && d.sc->done) || !d.zfix) return;
+    extern __shared__ unsigned char smem_raw[];
+    C2<R> *buf = reinterpret_cast<C2<R> *>(smem_raw);
+    const int local = blk - d.bz0;
+    const int tile = local % d.ntz, ky = local / d.ntz;
+    const int kx0 = tile * d.tz;
+    const int tw_ = min(d.tz, d.nkx - kx0);
+    C2<R> *spec = (spec_override ? spec_override : d.spec) + ((long)ky * d.nhp + kx0) * 6;
+    switch (d.nz) {
+    case 32: zpass_fixed<R, 32>(d, spec, buf, tw_, kx0, ky, local, inv_mu0, coef, mode); break;
+    case 48: zpass_fixed<R, 48>(d, spec, buf, tw_, kx0, ky, local, inv_mu0, coef, mode); break;
+    case 64: zpass_fixed<R, 64>(d, spec, buf, tw_, kx0, ky, local, inv_mu0, coef, mode); break;
+    case 96: zpass_fixed<R, 96>(d, spec, buf, tw_, kx0, ky, local, inv_mu0, coef, mode); break;
+    case 128: zpass_fixed<R, 128>(d, spec, buf, tw_, kx0, ky, local, inv_mu0, coef, mode); break;
+    default: zpass_fixed<R, 256>(d, spec, buf, tw_, kx0, ky, local, inv_mu0, coef, mode); break;
     }
 }
 

@@ -24,7 +24,8 @@ def _gpu():
 def _members():
     C, law = rvegen.config_law()
     S = rvegen.config_systems(with_twins=True)
-    shapes = [(8, 8, 8), (12, 12, 12), (6, 12, 18), (16, 16, 16)]
+    # generic and fixed-length y/z transforms in one batch (32: fixed)
+    shapes = [(8, 8, 8), (12, 12, 12), (6, 12, 18), (16, 16, 16), (32, 32, 32)]
     rves = [rvegen.make_rve(sh, 4 + i, 300 + i, twin_share=0.5 if i % 2 == 0 else 0.0)
             for i, sh in enumerate(shapes)]
     path = rvegen.uniaxial_path(0.004, 4)

@@ -182,6 +182,18 @@ def test_workload0_fp32_accuracy_against_fp64_oracle():
     _assert_fields(gs, ref, 1e-3)
 
 
+@pytest.mark.parametrize("shape", [(32, 32, 8), (48, 32, 8), (32, 96, 8), (256, 16, 4)])
+def test_fixed_length_passes_fp64_parity(shape):
+    """Whole solves on grids whose y and z lengths take the fixed-length
+    transform kernels (plans 8x4, 16x3, 8x4x3, 16x16), twinned, plastic."""
+    print("case shape", shape, flush=True)
+    w = _wl(shape, 6, 31, twins=True, steps=3, strain_per_step=5e-4)
+    gs, R, ref = _compare_solves(w)
+    _assert_effective(R, ref, 1e-10)
+    _assert_fields(gs, ref, 1e-10)
+    assert ref.mean_v[-1] > 0
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_twinned_noncubic_fp64_parity(mode):
     """Twins (Norton and paper twin-fraction laws) on a 6x12x18 grid
