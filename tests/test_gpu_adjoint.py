@@ -53,11 +53,11 @@ def test_adjoint_matches_oracle_fp64(twin_mode):
     L, g, sxx = s.gradient(w.path, tgt, checkpoint_every=2, adj_tol=1e-12)
     Lo, go, so = oracle.solver_for(w, oracle.Options(tol=1e-12)).gradient(w.path, tgt, adj_tol=1e-12)
     assert np.abs(sxx - so).max() <= 1e-10 * np.abs(so).max()
-    assert L == pytest.approx(Lo, rel=1e-7)
+    assert L == pytest.approx(Lo, rel=1e-9)
     for f in (0, 1):
         scale = np.abs(go[f]).max()
         assert scale > 0
-        assert np.abs(g[f] - go[f]).max() <= 1e-7 * scale, (f, g[f], go[f])
+        assert np.abs(g[f] - go[f]).max() <= 1e-9 * scale, (f, g[f], go[f])
 
 
 def test_adjoint_independent_of_checkpoint_interval():
@@ -153,7 +153,7 @@ def test_vjp_general_cotangent_matches_oracle():
     go, so = oracle.solver_for(w, oracle.Options(tol=1e-12)).vjp(w.path, sb, adj_tol=1e-12)
     assert np.abs(sig - so).max() <= 1e-10 * np.abs(so).max()
     for f in (0, 1):
-        assert np.abs(g[f] - go[f]).max() <= 1e-7 * np.abs(go[f]).max(), (f, g[f], go[f])
+        assert np.abs(g[f] - go[f]).max() <= 1e-9 * np.abs(go[f]).max(), (f, g[f], go[f])
     # the stress-curve loss is the cotangent 2 (Sigma_11 - target) e_11
     tgt = sig[:, 0] * 1.03
     L, g2, _ = s.gradient(w.path, tgt, checkpoint_every=2, adj_tol=1e-12)

@@ -195,6 +195,30 @@ def test_fixed_length_passes_fp64_parity(shape):
 
 
 @pytest.mark.parametrize("mode", [0, 1])
+def test_twinned_fp32_accuracy_against_fp64_oracle(mode):
+    """A reduced RVE shaped like the 64^3 workload (every grain split into a
+    twin pair, 12 slip + 4 twin systems, its 0.04 % load increments of 0.4 s,
+    8 RK4 substeps), both twin laws: FP32 against the FP64 oracle, 1e-4 on
+    the mean stress and 1e-3 relative L2 on every local field."""
+    print("case fp32 twinned, twin mode", mode, flush=True)
+    C, law = rvegen.config_law()
+    law.twin_mode = mode
+    if mode == 1:
+        law.K_c, law.f_m = 1.45, 0.8
+    S = rvegen.config_systems(with_twins=True)
+    rve = rvegen.make_rve(16, 12, 20240216, twin_share=1.0)
+    path = rvegen.uniaxial_path(0.0004 * 8, 8)
+    w = rvegen.Workload("fp32-twinned", rve, S, C, law, path)
+    gs = _gpu_solver(w, "fp32", tol=1e-6, stag_tol=1e-4)
+    R = gs.run(path)
+    ref = oracle.solver_for(w, oracle.Options(tol=1e-10)).run(path, keep_fields=True)
+    assert np.all(R["status"] == 0)
+    assert ref.mean_v[-1] > 0 and ref.mean_f[-1] > 0
+    assert np.abs(R["Sigma"] - ref.Sigma).max() / np.abs(ref.Sigma[:, 0]).max() < 1e-4
+    _assert_fields(gs, ref, 1e-3)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
 def test_twinned_noncubic_fp64_parity(mode):
     """Twins (Norton and paper twin-fraction laws) on a 6x12x18 grid
     (radix 2 and 3, ragged tiles)."""
