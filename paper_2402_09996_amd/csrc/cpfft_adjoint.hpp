@@ -215,7 +215,7 @@ constexpr int VJP_F = 1;    // final sweep with sigma_bar_L - W mu, parameter gr
 // with every stage input and Newton root written to the scratch).  Dynamic
 // LDS: law_lds_bytes<R, NS>().
 template <typename R, int NS, int SPEC>
-__global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_law_record(AdjArgs<R> a, LawP<R> P)
+__global__ __launch_bounds__(256, (xpass_min_blocks<R, SPEC>())) void k_law_record(AdjArgs<R> a, LawP<R> P)
 {
     const RveDev<R> &d = a.rv[0];
     const long N = d.nvox;
@@ -240,13 +240,11 @@ __global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_law_recor
     load_state<R, NS>(a.st0, N, vox, nsys, Q, ep, v, al);
     const int M = a.M;
     const R h = a.dt / R(M), invM = R(1) / R(M);
-    R de[6], yw[NS];
+    R de[6];
     uint32_t warm = 0;
     law_fam_store(P, W);
 #pragma unroll
     for (int i = 0; i < 6; ++i) de[i] = e1[i] - e0[i];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) yw[s] = R(0);
     int nact = 0, nnewt = 0;
 #pragma unroll 1
     for (int j = 0; j < M; ++j) {
@@ -275,19 +273,10 @@ __global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_law_recor
             R e[6];
 #pragma unroll
             for (int i = 0; i < 6; ++i) e[i] = e0[i] + sfrac * de[i];
-            if constexpr (law_compact<R>()) {
-                rk_stage_cmp<R, NS, SPEC>(P, e, tep, tv, tal, ep, v, al, aep, av, aal, warm, W, wacc, cnext,
-                                          st < 3, nact, nnewt);
+            rk_stage<R, NS, SPEC>(P, e, tep, tv, tal, ep, v, al, aep, av, aal, warm, W, wacc, cnext, nact, nnewt);
 #pragma unroll
-                for (int s = 0; s < NS; ++s)
-                    if (s < nsys) zs[(D + s) * N] = ((warm >> s) & 1u) ? W.y[s * W.ls] : R(0);
-            } else {
-                rk_stage<R, NS, SPEC>(P, e, tep, tv, tal, ep, v, al, aep, av, aal, yw, wacc, cnext, st < 3,
-                                      nact, nnewt);
-#pragma unroll
-                for (int s = 0; s < NS; ++s)
-                    if (s < nsys) zs[(D + s) * N] = yw[s];
-            }
+            for (int s = 0; s < NS; ++s)
+                if (s < nsys) zs[(D + s) * N] = ((warm >> s) & 1u) ? W.y[s * W.ls] : R(0);
         }
 #pragma unroll
         for (int i = 0; i < 6; ++i) ep[i] = aep[i];

@@ -789,12 +789,8 @@ extern "C" int cpf_solver_set_graph(cpf_solver *s, int iters_per_launch)
 // error left after that step is about (n - 1)/2 times the square of the
 // step (4.5 rtol^2 at n = 10): 1e-7 in FP32, the level at which rounding of
 // the overstress already perturbs the root, and 5e-14 in FP64.
-#ifndef CPF_NEWTON_RTOL_F32
-#define CPF_NEWTON_RTOL_F32 1.5e-4
-#endif
-#ifndef CPF_NEWTON_RTOL_F64
-#define CPF_NEWTON_RTOL_F64 1e-7
-#endif
+constexpr double NEWTON_RTOL_F32 = 1.5e-4;
+constexpr double NEWTON_RTOL_F64 = 1e-7;
 
 template <typename R>
 static LawP<R> make_law(const cpf_solver *s)
@@ -832,7 +828,7 @@ static LawP<R> make_law(const cpf_solver *s)
     }
     P.Kc_gT = R(p.Kc * p.gT); P.fm = R(p.fm); P.inv_gT = R(1.0 / p.gT);
     P.eta = R(p.eta); P.inv_eta = R(p.eta > 0 ? 1.0 / p.eta : 0.0);
-    P.newton_rtol = sizeof(R) == 4 ? R(CPF_NEWTON_RTOL_F32) : R(CPF_NEWTON_RTOL_F64);
+    P.newton_rtol = sizeof(R) == 4 ? R(NEWTON_RTOL_F32) : R(NEWTON_RTOL_F64);
     return P;
 }
 

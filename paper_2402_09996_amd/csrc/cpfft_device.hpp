@@ -737,9 +737,6 @@ __device__ __forceinline__ bool is_twin(const LawP<R> &P, int s)
 // (twin); the plastic strain rate collects signed sums of the rates per
 // pattern before one multiplication.  Only the rounding order differs
 // from the plain contraction.
-#ifndef CPF_T1_FACTOR
-#define CPF_T1_FACTOR 1
-#endif
 constexpr double T1_A = 0.40824829046386302;
 constexpr double T1_B = 0.23570226039551589;
 constexpr double T1_BA = T1_B / T1_A;   // 1/sqrt3
@@ -774,7 +771,7 @@ static_assert(t1_pattern_ok(), "Table 1 Schmid tensors do not have the factored 
 template <int SPEC>
 constexpr bool t1_factor()
 {
-    return SPEC == LAW_TABLE1 && CPF_T1_FACTOR != 0;
+    return SPEC == LAW_TABLE1;
 }
 
 // Diagonal pair of slip system s (p < q: 0 = (0,1), 1 = (0,2), 2 = (1,2))
@@ -888,152 +885,12 @@ __device__ __forceinline__ void hooke_c(const R (&C)[36], const R ee[6], R sig[6
     }
 }
 
-// Regularized Norton rate (equations 5/6 with the yield stress raised by
-// eta |g|): g = A y^n, where y > 0 is the root of phi(y) = K y + eta A y^n - o.
-// phi is increasing and convex, so Newton converges from any y > 0 and
-// stays above the root after the first step.  The iteration starts from
-// ywarm (the root found for the same system at the previous RK stage) when
-// there is one, capped by the upper bound o/K; otherwise from the smaller
-// of the two upper bounds o/K and (o/(eta A))^(1/n).  At the root,
-// A y^n = (o - K y) / eta, which gives g without another power.
-// ywarm is updated (0 when the system is below its threshold).
-template <typename R>
-__device__ __forceinline__ R newton_root(R o, R A, R inv_etaA, R etaA, R inv_eta, R K, R invK, R n, R inv_n,
-                                         R nm1, int nm1_int, R rtol, R &ywarm, int &nnewt)
-{
-    const R yk = o * invK;
-    R y;
-    if (ywarm > R(0)) {
-        y = ywarm < yk ? ywarm : yk;
-    } else {
-        y = ex2(lg2(o * inv_etaA) * inv_n);
-        y = yk < y ? yk : y;
-    }
-    R yn1 = R(0);
-    // not unrolled: an unrolled loop leaves a long chain of exec-mask
-    // restores at every exit, paid once per solve
-#pragma unroll 1
-    for (int it = 0; it < 40; ++it) {
-        yn1 = pow_nm1(y, nm1, nm1_int);
-        const R phi = K * y + etaA * yn1 * y - o;
-        const R dphi = K + etaA * n * yn1;
-        const R step = fdiv(phi, dphi);
-        y -= step;
-        ++nnewt;
-        if (fabs(step) <= rtol * y) break;
-    }
-    ywarm = y;
-    if (etaA > R(0)) return (o - K * y) * inv_eta;
-    return A * y * pow_nm1(y, nm1, nm1_int);
-}
+// Compiler fence between systems: keeps the per-system law parameters from
+// being hoisted (and held in registers) across the whole system loop.
+__device__ __forceinline__ void law_fence() { asm volatile("" ::: "memory"); }
 
-template <typename R>
-__device__ __forceinline__ R reg_rate(R o, R A, R inv_etaA, R etaA, R inv_eta, const FamP<R> &F,
-                                      R rtol, R &ywarm, int &nact, int &nnewt)
-{
-    if (!(o > R(0)) || !(A > R(0))) {
-        ywarm = R(0);
-        return R(0);
-    }
-    ++nact;
-    return newton_root<R>(o, A, inv_etaA, etaA, inv_eta, F.K, F.invK, F.n, F.inv_n, F.nm1, F.nm1_int, rtol,
-                          ywarm, nnewt);
-}
-
-// Optional compiler fence between systems: keeps the per-system law
-// parameters from being hoisted (and held in registers) across the whole
-// system loop.
-#ifndef CPF_LAW_FENCE
-#define CPF_LAW_FENCE 1
-#endif
-__device__ __forceinline__ void law_fence()
-{
-#if CPF_LAW_FENCE
-    asm volatile("" ::: "memory");
-#endif
-}
-
-// One RK4 stage of the internal variables in the crystal frame.  Inputs:
-// total strain e at the stage time and the stage state t* (overwritten with
-// the next stage state y + cnext*k when has_next); the stage slope k is
-// accumulated into a* with weight wacc.  yw holds the per-system Newton
-// warm starts.
-template <typename R, int NS, int SPEC>
-__device__ __forceinline__ void rk_stage(const LawP<R> &P, const R e[6], R (&tep)[6], R (&tv)[NS],
-                                         R (&tal)[NS], const R (&yep)[6], const R (&yv)[NS],
-                                         const R (&yal)[NS], R (&aep)[6], R (&av)[NS],
-                                         R (&aal)[NS], R (&yw)[NS], R wacc, R cnext, bool has_next,
-                                         int &nact, int &nnewt)
-{
-    R ee[6], sig[6];
-#pragma unroll
-    for (int i = 0; i < 6; ++i) ee[i] = e[i] - tep[i];
-    hooke_c<R, SPEC>(P.C, ee, sig);
-    // saturating hardening terms and family sums (equation 4)
-    R h[NS];
-    R Hs = R(0), Ht = R(0), sumf = R(0);
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        law_fence();
-        const bool tw = is_twin<SPEC>(P, s);
-        const R bl = tw ? P.ft.bl2e : P.fs.bl2e;
-        h[s] = R(1) - ex2(-bl * tv[s]);
-        if (tw) {
-            Ht += h[s];
-            sumf += tv[s] * P.inv_gT;
-        } else {
-            Hs += h[s];
-        }
-    }
-    const R wslip = R(1) - sumf;
-    // twin rate prefactor A (paper mode) and its regularization scale
-    const R Atw = P.twin_mode ? P.Kc_gT * (P.fm - sumf) : R(1);
-    const R etaAtw = P.eta * Atw;
-    const R inv_etaAtw = P.twin_mode ? fdiv(R(1), etaAtw) : P.inv_eta;
-    R dep[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
-#pragma unroll
-    for (int s = 0; s < NS; ++s) {
-        law_fence();
-        const bool tw = is_twin<SPEC>(P, s);
-        const FamP<R> &F = tw ? P.ft : P.fs;
-        const R r = P.tau0[s] + F.QL * (tw ? Ht : Hs) + F.QD * h[s];
-        R tau = R(0);
-#pragma unroll
-        for (int i = 0; i < 6; ++i)
-            if (schmid_nonzero<SPEC>(s, i))
-                tau += (i < 3 ? sig[i] : R(2) * sig[i]) * schmid<R, SPEC>(P.m, s, i);
-        const R tx = tau - F.c * tal[s];
-        R gd;
-        if (tw) {
-            gd = reg_rate<R>(tx - r, Atw, inv_etaAtw, etaAtw, P.inv_eta, F, P.newton_rtol, yw[s], nact,
-                             nnewt);
-        } else {
-            const R g = reg_rate<R>(fabs(tx) - r, R(1), P.inv_eta, P.eta, P.inv_eta, F, P.newton_rtol,
-                                    yw[s], nact, nnewt);
-            gd = tx >= R(0) ? g : -g;
-        }
-        const R ag = fabs(gd);
-        const R dal = gd - F.d * ag * tal[s];
-        av[s] += wacc * ag;
-        aal[s] += wacc * dal;
-        if (has_next) {
-            tv[s] = yv[s] + cnext * ag;
-            tal[s] = yal[s] + cnext * dal;
-        }
-        const R wg = tw ? gd : wslip * gd;
-#pragma unroll
-        for (int i = 0; i < 6; ++i)
-            if (schmid_nonzero<SPEC>(s, i)) dep[i] += wg * schmid<R, SPEC>(P.m, s, i);
-    }
-#pragma unroll
-    for (int i = 0; i < 6; ++i) {
-        aep[i] += wacc * dep[i];
-        if (has_next) tep[i] = yep[i] + cnext * dep[i];
-    }
-}
-
-// Per-thread LDS work area of the compacted stage: overstress / rate and
-// Newton root per system, column of the thread with stride ls.
+// Per-thread LDS work area of a stage: overstress / rate and Newton root
+// per system, column of the thread with stride ls.
 template <typename R>
 struct LawLds {
     R *o;       // [NS] overstress, then rate
@@ -1044,57 +901,29 @@ struct LawLds {
     int ls;
 };
 
-// The Newton passes of the compacted stage take the constants of each
-// lane's family from a small table in LDS instead of selecting every one
-// of them between two scalar registers (two instructions each: a scalar
-// source must be moved to a vector register first).  Per family: K, 1/K,
-// n, 1/n, n - 1, the integer exponent (as a value of R; FP64 only) and two
-// words of padding (16-byte aligned rows).  One table per block (64 bytes
-// in FP32): three FP32 law blocks per CU leave no room for a table per
-// wave in the 160 KB of LDS.
+// The Newton passes take the constants of each lane's family from a small
+// table in LDS instead of selecting every one of them between two scalar
+// registers (two instructions each: a scalar source must be moved to a
+// vector register first).  Per family: K, 1/K, n, 1/n, n - 1, the integer
+// exponent (as a value of R; FP64 only) and two words of padding (16-byte
+// aligned rows).  One table per block (64 bytes in FP32): three FP32 law
+// blocks per CU leave no room for a table per wave in the 160 KB of LDS.
 constexpr int LAW_FAM_WORDS = 8;
-#ifndef CPF_LAW_FAM_TABLE
-#define CPF_LAW_FAM_TABLE 1
-#endif
 
-// Whether the law kernels solve the active systems of a stage compacted per
-// lane (2 NS words of LDS per thread: 32 KB per 256-thread block in FP32 and
-// 64 KB in FP64 at NS = 16, within the 160 KB a block may use).
-#ifndef CPF_LAW_COMPACT
-#define CPF_LAW_COMPACT 1
-#endif
-template <typename R>
-constexpr bool law_compact()
-{
-    return CPF_LAW_COMPACT != 0;
-}
-
-// Register relief through the LDS work area: hardening terms within a
-// stage, and the strain path of the step.
-#ifndef CPF_PARK_H_F32
-#define CPF_PARK_H_F32 0
-#endif
-#ifndef CPF_PARK_H_F64
-#define CPF_PARK_H_F64 1
-#endif
-#ifndef CPF_PARK_E_F32
-#define CPF_PARK_E_F32 1
-#endif
-#ifndef CPF_PARK_E_F64
-#define CPF_PARK_E_F64 1
-#endif
+// Register relief through the LDS work area: the hardening terms within a
+// stage are parked there in FP64 (FP32 keeps them in registers), and the
+// strain path of the step in both precisions, except in FP64 beyond 16
+// systems, where the x pass's LDS (FFT lines, 2 NS columns, 12 strain
+// rows) would exceed the 160 KB a block may use.
 template <typename R>
 constexpr bool law_park_h()
 {
-    return law_compact<R>() && (sizeof(R) == 4 ? CPF_PARK_H_F32 : CPF_PARK_H_F64);
+    return sizeof(R) == 8;
 }
-// The strain path is not parked in FP64 beyond 16 systems: the x pass's
-// LDS (FFT lines, 2 NS columns, 12 strain rows) would exceed the 160 KB a
-// block may use.
 template <typename R>
 constexpr bool law_park_e_ns(int ns)
 {
-    return law_compact<R>() && (sizeof(R) == 4 ? CPF_PARK_E_F32 : CPF_PARK_E_F64) && !(sizeof(R) == 8 && ns > 16);
+    return !(sizeof(R) == 8 && ns > 16);
 }
 template <typename R, int NS>
 constexpr bool law_park_e()
@@ -1107,12 +936,12 @@ constexpr int law_e_rows(int ns)
     return law_park_e_ns<R>(ns) ? 12 : 0;
 }
 
-// Bytes of the law's LDS work area of a 256-thread block: the per-thread
-// columns, then the family table.
+// Bytes of the law's LDS work area of a 256-thread block (2 NS words and the
+// strain rows per thread: 44 KB in FP32 at NS = 16), then the family table.
 template <typename R>
 constexpr size_t law_lds_bytes_ns(int ns)
 {
-    return law_compact<R>() ? ((2 * (size_t)ns + law_e_rows<R>(ns)) * 256 + 2 * LAW_FAM_WORDS) * sizeof(R) : 0;
+    return ((2 * (size_t)ns + law_e_rows<R>(ns)) * 256 + 2 * LAW_FAM_WORDS) * sizeof(R);
 }
 template <typename R, int NS>
 constexpr size_t law_lds_bytes()
@@ -1126,34 +955,75 @@ constexpr size_t law_lds_bytes()
 template <typename R>
 __device__ __forceinline__ void law_fam_store(const LawP<R> &P, const LawLds<R> &W)
 {
-    if constexpr (law_compact<R>() && CPF_LAW_FAM_TABLE) {
-        const FamP<R> *F[2] = {&P.fs, &P.ft};
+    const FamP<R> *F[2] = {&P.fs, &P.ft};
 #pragma unroll
-        for (int f = 0; f < 2; ++f) {
-            R *t = W.fam + f * LAW_FAM_WORDS;
-            t[0] = F[f]->K;
-            t[1] = F[f]->invK;
-            t[2] = F[f]->n;
-            t[3] = F[f]->inv_n;
-            t[4] = F[f]->nm1;
-            if constexpr (sizeof(R) == 8) t[5] = R(F[f]->nm1_int);
-        }
+    for (int f = 0; f < 2; ++f) {
+        R *t = W.fam + f * LAW_FAM_WORDS;
+        t[0] = F[f]->K;
+        t[1] = F[f]->invK;
+        t[2] = F[f]->n;
+        t[3] = F[f]->inv_n;
+        t[4] = F[f]->nm1;
+        if constexpr (sizeof(R) == 8) t[5] = R(F[f]->nm1_int);
     }
 }
 
-// The same RK4 stage as rk_stage, with the Newton solves compacted: the
-// lanes of a wave rarely share their active systems (only a third of the
-// systems that some lane needs are active in a given lane), so instead of
-// one divergent solve per system, every lane takes its own next active
-// system in each pass of the solve loop.  Overstresses go to the thread's
-// LDS column, rates and roots come back through it; warm holds the systems
-// whose root from the previous stage is a valid warm start.
+// Regularized Norton rate (equations 5/6 with the yield stress raised by
+// eta |g|) of one active system: g = A y^n, where y > 0 is the root of
+// phi(y) = K y + eta A y^n - o, o > 0.  phi is increasing and convex, so
+// Newton converges from any y > 0 and stays above the root after the first
+// step.  The iteration starts from the warm start yw (the root found for
+// the same system at the previous RK stage, 0 if none), capped by the upper
+// bound o/K, or else from the smaller of the two upper bounds o/K and
+// (o/(eta A))^(1/n).  With eta > 0 (uniform), A y^n = (o - K y)/eta at the
+// root gives g without another power.  A lane stops at |step| <= rtol y or
+// after 40 iterations (the loop is not unrolled: an unrolled loop leaves a
+// long chain of exec-mask restores at every exit).  yw receives the root.
+template <typename R>
+__device__ __forceinline__ R newton_solve(R o, R A, R etaA, R inv_etaA, const R *fam, const LawP<R> &P, R &yw,
+                                          int &nnewt)
+{
+    const R K = fam[0], invK = fam[1], n = fam[2], inv_n = fam[3], nm1 = fam[4];
+    const int nm1_int = sizeof(R) == 8 ? (int)fam[5] : -1;
+    const R yk = o * invK;
+    R y = yw > R(0) ? (yw < yk ? yw : yk) : R(0);
+    if (!(yw > R(0))) {
+        const R yc = ex2(lg2(o * inv_etaA) * inv_n);
+        y = yk < yc ? yk : yc;
+    }
+    const R etaAn = etaA * n;
+#pragma unroll 1
+    for (int it = 0; it < 40; ++it) {
+        const R yn1 = pow_nm1(y, nm1, nm1_int);
+        const R phi = K * y + etaA * yn1 * y - o;
+        const R dphi = K + etaAn * yn1;
+        const R step = fdiv(phi, dphi);
+        y -= step;
+        ++nnewt;
+        if (fabs(step) <= P.newton_rtol * y) break;
+    }
+    yw = y;
+    if (P.eta > R(0)) return (o - K * y) * P.inv_eta;
+    return A * y * pow_nm1(y, nm1, nm1_int);
+}
+
+// One RK4 stage of the internal variables in the crystal frame.  Inputs:
+// total strain e at the stage time and the stage state t*, overwritten with
+// the next stage state y + cnext*k (at the last stage of a substep that
+// value is not used: the next substep starts from the accumulated state);
+// the stage slope k is accumulated into a* with weight wacc.
+// The Newton solves are compacted: the lanes of a wave rarely share their
+// active systems (only a third of the systems that some lane needs are
+// active in a given lane), so instead of one divergent solve per system,
+// every lane takes its own next active system in each pass of the solve
+// loop.  Overstresses go to the thread's LDS column, rates and roots come
+// back through it; warm holds the systems whose root from the previous
+// stage is a valid warm start.
 template <typename R, int NS, int SPEC>
-__device__ __forceinline__ void rk_stage_cmp(const LawP<R> &P, const R e[6], R (&tep)[6], R (&tv)[NS],
-                                             R (&tal)[NS], const R (&yep)[6], const R (&yv)[NS],
-                                             const R (&yal)[NS], R (&aep)[6], R (&av)[NS], R (&aal)[NS],
-                                             uint32_t &warm, const LawLds<R> &W, R wacc, R cnext,
-                                             bool has_next, int &nact, int &nnewt)
+__device__ __forceinline__ void rk_stage(const LawP<R> &P, const R e[6], R (&tep)[6], R (&tv)[NS], R (&tal)[NS],
+                                         const R (&yep)[6], const R (&yv)[NS], const R (&yal)[NS], R (&aep)[6],
+                                         R (&av)[NS], R (&aal)[NS], uint32_t &warm, const LawLds<R> &W, R wacc,
+                                         R cnext, int &nact, int &nnewt)
 {
     R ee[6], sig[6];
 #pragma unroll
@@ -1223,24 +1093,12 @@ __device__ __forceinline__ void rk_stage_cmp(const LawP<R> &P, const R e[6], R (
             const int s = __builtin_ctz(rem);
             rem &= rem - 1u;
             const bool tw = SPEC == LAW_TABLE1 ? s >= 12 : ((P.twin_mask >> s) & 1u) != 0u;
-            const FamP<R> &Fs = P.fs;
-            const FamP<R> &Ft = P.ft;
             const R os = W.o[s * W.ls];
-            const R o = fabs(os);
-            R yw = ((warm >> s) & 1u) ? W.y[s * W.ls] : R(0);
-            R g;
-            if constexpr (CPF_LAW_FAM_TABLE) {
-                const R *ft = W.fam + (tw ? LAW_FAM_WORDS : 0);
-                const int nm1_int = sizeof(R) == 8 ? (int)ft[5] : -1;
-                g = newton_root<R>(o, tw ? Atw : R(1), tw ? inv_etaAtw : P.inv_eta, tw ? etaAtw : P.eta,
-                                   P.inv_eta, ft[0], ft[1], ft[2], ft[3], ft[4], nm1_int, P.newton_rtol, yw,
-                                   nnewt);
-            } else {
-                g = newton_root<R>(o, tw ? Atw : R(1), tw ? inv_etaAtw : P.inv_eta, tw ? etaAtw : P.eta,
-                                   P.inv_eta, tw ? Ft.K : Fs.K, tw ? Ft.invK : Fs.invK, tw ? Ft.n : Fs.n,
-                                   tw ? Ft.inv_n : Fs.inv_n, tw ? Ft.nm1 : Fs.nm1,
-                                   tw ? Ft.nm1_int : Fs.nm1_int, P.newton_rtol, yw, nnewt);
-            }
+            const R yprev = W.y[s * W.ls];
+            R yw = ((warm >> s) & 1u) ? yprev : R(0);
+            const R g = newton_solve<R>(fabs(os), tw ? Atw : R(1), tw ? etaAtw : P.eta,
+                                        tw ? inv_etaAtw : P.inv_eta, W.fam + (tw ? LAW_FAM_WORDS : 0), P, yw,
+                                        nnewt);
             W.y[s * W.ls] = yw;
             W.o[s * W.ls] = os < R(0) ? -g : g;
         }
@@ -1260,10 +1118,8 @@ __device__ __forceinline__ void rk_stage_cmp(const LawP<R> &P, const R e[6], R (
         const R dal = gd - F.d * ag * tal[s];
         av[s] += wacc * ag;
         aal[s] += wacc * dal;
-        if (has_next) {
-            tv[s] = yv[s] + cnext * ag;
-            tal[s] = yal[s] + cnext * dal;
-        }
+        tv[s] = yv[s] + cnext * ag;
+        tal[s] = yal[s] + cnext * dal;
         if constexpr (t1_factor<SPEC>()) {
             t1_acc_add(acc, s, gd);
         } else {
@@ -1277,25 +1133,23 @@ __device__ __forceinline__ void rk_stage_cmp(const LawP<R> &P, const R e[6], R (
 #pragma unroll
     for (int i = 0; i < 6; ++i) {
         aep[i] += wacc * dep[i];
-        if (has_next) tep[i] = yep[i] + cnext * dep[i];
+        tep[i] = yep[i] + cnext * dep[i];
     }
 }
 
 // Integrate the internal variables over one load increment (crystal frame):
 // total strain linear in time from e0 to e1, M classical RK4 substeps.
-// W: LDS work area, used when law_compact<R>().
+// W: LDS work area.
 template <typename R, int NS, int SPEC>
 __device__ void integrate(const LawP<R> &P, const R e0[6], const R e1[6], R (&ep)[6], R (&v)[NS],
                           R (&al)[NS], R dt, int M, int &nact, int &nnewt, const LawLds<R> &W)
 {
     const R h = dt / R(M);
     const R invM = R(1) / R(M);
-    R de[6], yw[NS];
+    R de[6];
     uint32_t warm = 0;
 #pragma unroll
     for (int i = 0; i < 6; ++i) de[i] = e1[i] - e0[i];
-#pragma unroll
-    for (int s = 0; s < NS; ++s) yw[s] = R(0);
     law_fam_store(P, W);
     if constexpr (law_park_e<R, NS>()) {
         // the strain path lives in LDS through the integration
@@ -1331,12 +1185,7 @@ __device__ void integrate(const LawP<R> &P, const R e0[6], const R e1[6], R (&ep
 #pragma unroll
                 for (int i = 0; i < 6; ++i) e[i] = e0[i] + sfrac * de[i];
             }
-            if constexpr (law_compact<R>())
-                rk_stage_cmp<R, NS, SPEC>(P, e, tep, tv, tal, ep, v, al, aep, av, aal, warm, W, wacc, cnext,
-                                          st < 3, nact, nnewt);
-            else
-                rk_stage<R, NS, SPEC>(P, e, tep, tv, tal, ep, v, al, aep, av, aal, yw, wacc, cnext, st < 3,
-                                      nact, nnewt);
+            rk_stage<R, NS, SPEC>(P, e, tep, tv, tal, ep, v, al, aep, av, aal, warm, W, wacc, cnext, nact, nnewt);
         }
 #pragma unroll
         for (int i = 0; i < 6; ++i) ep[i] = aep[i];

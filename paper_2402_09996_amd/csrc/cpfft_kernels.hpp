@@ -197,9 +197,6 @@ __device__ __forceinline__ void store_state(R *__restrict__ st, long nvox, long 
     }
 }
 
-#ifndef CPF_RELOAD_Q
-#define CPF_RELOAD_Q 1
-#endif
 // Local law at one voxel: lab strains in, lab stress out; the committed
 // state is read from st_in and the new state written to *st_out.  The
 // rotation and the output address are read again after the integration
@@ -220,9 +217,7 @@ __device__ __forceinline__ void voxel_law(const LawP<R> &P, const R *Qrow, const
         load_state<R, NS>(st_in, nvox, vox, P.nsys, Q, ep, v, al);
     }
     integrate<R, NS, SPEC>(P, e0, e1, ep, v, al, dt, M, nact, nnewt, W);
-#if CPF_RELOAD_Q
     asm volatile("" ::: "memory");
-#endif
     R Q[9], sc[6];
 #pragma unroll
     for (int i = 0; i < 9; ++i) Q[i] = Qrow[i];
@@ -269,9 +264,7 @@ __device__ __forceinline__ void voxel_law_probe(const LawP<R> &P, const R *Qrow,
         for (int i = 0; i < 9; ++i) Q[i] = Qrow[i];
         load_state<R, NS>(st_in, nvox, vox, P.nsys, Q, ep, v, al);
         integrate<R, NS, SPEC>(P, e0, e1, ep, v, al, dt, M << a, nact, nnewt, W);
-#if CPF_RELOAD_Q
         asm volatile("" ::: "memory");
-#endif
 #pragma unroll
         for (int i = 0; i < 9; ++i) Q[i] = Qrow[i];
         if (a > 0) {
@@ -316,36 +309,13 @@ __device__ __forceinline__ void voxel_law_probe(const LawP<R> &P, const R *Qrow,
 // ---------------------------------------------------------------------------
 // Minimum resident blocks per CU for the law kernels (register budget):
 // three 256-thread blocks = 3 waves per SIMD = 168 registers per lane in
-// FP32 (a few spills, but the latency hiding of the third wave is worth
-// 20 %); one block in FP64.
-#ifndef CPF_XPASS_MINBLOCKS_F32
-#define CPF_XPASS_MINBLOCKS_F32 3
-#endif
-#ifndef CPF_XPASS_MINBLOCKS_F64
-#define CPF_XPASS_MINBLOCKS_F64 1
-#endif
-// The general law (runtime Schmid tensors and stiffness) needs more
-// registers; it keeps two blocks in FP32.
-#define CPF_XPASS_MINBLOCKS(R, SPEC)                                                                  \
-    (sizeof(R) == 4 ? (SPEC == LAW_TABLE1 ? CPF_XPASS_MINBLOCKS_F32 : 2) : CPF_XPASS_MINBLOCKS_F64)
-#ifndef CPF_LAW_IN_LDS
-#define CPF_LAW_IN_LDS 0
-#endif
-// The law parameters as the kernel reads them: straight from the argument
-// block, or from a copy in LDS made once per block.
-template <typename R>
-__device__ __forceinline__ const LawP<R> &law_params(const LawP<R> &arg)
+// the FP32 Table 1 law (a few spills, but the latency hiding of the third
+// wave is worth 20 %); two for the FP32 general law (runtime Schmid
+// tensors and stiffness need more registers); one block in FP64.
+template <typename R, int SPEC>
+constexpr int xpass_min_blocks()
 {
-#if CPF_LAW_IN_LDS
-    __shared__ LawP<R> lp;
-    const uint32_t *src = reinterpret_cast<const uint32_t *>(&arg);
-    uint32_t *dst = reinterpret_cast<uint32_t *>(&lp);
-    for (int i = threadIdx.x; i < (int)(sizeof(LawP<R>) / 4); i += blockDim.x) dst[i] = src[i];
-    __syncthreads();
-    return lp;
-#else
-    return arg;
-#endif
+    return sizeof(R) == 4 ? (SPEC == LAW_TABLE1 ? 3 : 2) : 1;
 }
 
 // The law's LDS work area of this thread inside a 256-thread block's
@@ -370,14 +340,14 @@ constexpr size_t xfft_lds_bytes()
 }
 
 template <typename R, int NS, int SPEC, bool ADAPT = false, bool AAM = false>
-__global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_xpass_iter(
+__global__ __launch_bounds__(256, (xpass_min_blocks<R, SPEC>())) void k_xpass_iter(
     const RveDev<R> *__restrict__ rv, int nrve, LawP<R> Parg, double rk_lim2, int rk_maxd)
 {
     const int r = find_rve(rv, nrve, (int)blockIdx.x, 0);
     const RveDev<R> &d = rv[r];
     Scalars *sc = d.sc;
     if (sc->done) return;
-    const LawP<R> &P = law_params(Parg);
+    const LawP<R> &P = Parg;
     extern __shared__ unsigned char smem_raw[];
     C2<R> *buf = reinterpret_cast<C2<R> *>(smem_raw);
     const int tid = threadIdx.x, nthr = blockDim.x;
@@ -1256,11 +1226,11 @@ __global__ __launch_bounds__(64) void k_bc_update(const RveDev<R> *__restrict__ 
 // Component operators and field outputs
 // ---------------------------------------------------------------------------
 template <typename R, int NS, int SPEC>
-__global__ __launch_bounds__(256, CPF_XPASS_MINBLOCKS(R, SPEC)) void k_constitutive(
+__global__ __launch_bounds__(256, (xpass_min_blocks<R, SPEC>())) void k_constitutive(
     const int32_t *labels, const R *Qtab, const R *eps0, const R *eps1, const R *st0, R *st1, R *sig,
     LawP<R> Parg, long nvox, R dt, int M)
 {
-    const LawP<R> &P = law_params(Parg);
+    const LawP<R> &P = Parg;
     extern __shared__ unsigned char smem_raw[];
     const long vox = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (vox >= nvox) return;
