@@ -213,7 +213,7 @@ constexpr int VJP_F = 1;    // final sweep with sigma_bar_L - W mu, parameter gr
 
 // Replay of the forward integration of the step (the solver's integrate()
 // with every stage input and Newton root written to the scratch).  Dynamic
-// LDS: law_lds_bytes<R, NS>().
+// LDS: law_lds_bytes<R, NS>() + law_items_bytes<R>().
 template <typename R, int NS, int SPEC>
 __global__ __launch_bounds__(256, (xpass_min_blocks<R, SPEC>())) void k_law_record(AdjArgs<R> a, LawP<R> P)
 {
@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256, (xpass_min_blocks<R, SPEC>())) void k_law_reco
     if (vox >= N) return;
     const int nsys = P.nsys, D = 6 + 2 * nsys, DY = D + nsys;
     extern __shared__ unsigned char smem_raw[];
-    const LawLds<R> W = law_lds<R, NS>(smem_raw, 0);
+    const LawLds<R> W = law_lds<R, NS>(smem_raw, 0, law_lds_bytes<R, NS>());
     const int lab = d.labels[vox];
     R Q[9];
 #pragma unroll

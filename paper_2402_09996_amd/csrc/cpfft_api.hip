@@ -1565,7 +1565,7 @@ static void launch_cp(cpf_solver *s, const void *e0, const void *e1, const void 
                       double dt, int M)
 {
     const RveHost &h = s->rv[0];
-    const size_t lds = law_lds_bytes<R, NS>();
+    const size_t lds = law_lds_bytes<R, NS>() + law_items_bytes<R>();
     hipLaunchKernelGGL((k_constitutive<R, NS, SPEC>), dim3((h.nvox + 255) / 256), dim3(256), lds, s->stream,
                        dptr<int32_t>(s, h.off_labels), dptr<R>(s, h.off_Q), (const R *)e0, (const R *)e1,
                        (const R *)s0, (R *)s1, (R *)sig, make_law<R>(s), h.nvox, R(dt), M);
@@ -1663,7 +1663,7 @@ static void launch_law_adj(cpf_solver *s, const AdjArgs<R> &a, int what)
     const RveHost &h = s->rv[0];
     const dim3 grid((h.nvox + 255) / 256), block(256);
     const LawP<R> P = make_law<R>(s);
-    const size_t lds = law_lds_bytes<R, NS>();
+    const size_t lds = law_lds_bytes<R, NS>() + law_items_bytes<R>();
     if (what == 0) hipLaunchKernelGGL((k_law_record<R, NS, SPEC>), grid, block, lds, s->stream, a, P);
     else if (what == 1) hipLaunchKernelGGL((k_law_vjp<R, NS, SPEC, VJP_GA>), grid, block, 0, s->stream, a, P);
     else hipLaunchKernelGGL((k_law_vjp<R, NS, SPEC, VJP_F>), grid, block, 0, s->stream, a, P);

@@ -899,7 +899,34 @@ struct LawLds {
     R *fam;     // [2][LAW_FAM_WORDS] Norton constants of the slip and twin
                 // families, one copy per block
     int ls;
+    uint16_t *items;   // this wave's Newton items (law_items_q per lane)
+    R *aw;             // this wave's twin rate prefactors, one per lane
 };
+
+// The Newton solves of a stage are balanced over the lanes of a wave: the
+// active systems of all lanes go to a list of 16-bit items (owner lane,
+// system, warm-start bit), and the wave's active lanes take the items in
+// turn, so a stage needs ceil(items / lanes) passes instead of the largest
+// count of one lane.  Up to law_items_q systems of a lane go to the list
+// (the rest, rare, are solved by their own lane afterwards).  Per wave:
+// the items, then the twin rate prefactor A of each lane (it depends on
+// the lane's twin fractions).
+template <typename R>
+constexpr int law_items_q()
+{
+    return sizeof(R) == 4 ? 10 : 16;
+}
+template <typename R>
+constexpr size_t law_items_wave_bytes()
+{
+    return 64 * law_items_q<R>() * 2 + 64 * sizeof(R);
+}
+// a 256-thread block's item area
+template <typename R>
+constexpr size_t law_items_bytes()
+{
+    return 4 * law_items_wave_bytes<R>();
+}
 
 // The Newton passes take the constants of each lane's family from a small
 // table in LDS instead of selecting every one of them between two scalar
@@ -1086,21 +1113,83 @@ __device__ __forceinline__ void rk_stage(const LawP<R> &P, const R e[6], R (&tep
         W.o[s * W.ls] = on ? os : R(0);
     }
     nact += __popc(act);
-    // Newton solves of the active systems, one system per lane per pass
-    uint32_t rem = act;
+    // Newton solves: the first law_items_q active systems of each lane go to
+    // the wave's item list, taken in turn by the wave's active lanes
+    constexpr int Q = law_items_q<R>();
+    const int lane = (int)(threadIdx.x & 63u);
+    uint32_t mine = act, rest = 0u;
+    int cnt = __popc(act);
+    if (cnt > Q) {
+        uint32_t m = act;
+        for (int k = 0; k < Q; ++k) m &= m - 1u;
+        rest = m;
+        mine = act & ~m;
+        cnt = Q;
+    }
+    // exclusive prefix sum of the counts over the active lanes (cnt < 32)
+    int excl = 0, total = 0;
+#pragma unroll
+    for (int b = 0; b < 5; ++b) {
+        const uint64_t bal = __ballot((cnt >> b) & 1);
+        excl += (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u))
+                << b;
+        total += __popcll(bal) << b;
+    }
+    {
+        uint32_t m = mine;
+        int k = excl;
+        while (m) {
+            const int sy = __builtin_ctz(m);
+            m &= m - 1u;
+            W.items[k++] = (uint16_t)((lane << 6) | (sy << 1) | ((warm >> sy) & 1u));
+        }
+    }
+    W.aw[lane] = Atw;
+    __builtin_amdgcn_wave_barrier();
+    const uint64_t ex = __ballot(1);
+    const int nlanes = __popcll(ex);
+    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(ex >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)ex, 0u));
+    R *const o_wave = W.o - lane;   // column of lane l: o_wave + l
+    R *const y_wave = W.y - lane;
+    for (int base = 0; base < total; base += nlanes) {
+        const int idx = base + rank;
+        if (idx < total) {
+            const uint32_t it = W.items[idx];
+            const int owner = (int)(it >> 6), sy = (int)((it >> 1) & 31u);
+            const bool tw = SPEC == LAW_TABLE1 ? sy >= 12 : ((P.twin_mask >> sy) & 1u) != 0u;
+            R *const po = o_wave + owner + sy * W.ls;
+            R *const py = y_wave + owner + sy * W.ls;
+            const R os = *po;
+            const R yprev = *py;
+            R yw = (it & 1u) ? yprev : R(0);
+            R A = R(1), etaA = P.eta, inv_etaA = P.inv_eta;
+            if (tw) {
+                A = W.aw[owner];
+                etaA = P.eta * A;
+                if (P.twin_mode) inv_etaA = fdiv(R(1), etaA);
+            }
+            const R g = newton_solve<R>(fabs(os), A, etaA, inv_etaA, W.fam + (tw ? LAW_FAM_WORDS : 0), P, yw,
+                                        nnewt);
+            *py = yw;
+            *po = os < R(0) ? -g : g;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    // systems beyond the list: solved by their own lane
+    uint32_t rem = rest;
     while (__any(rem != 0u)) {
         if (rem) {
-            const int s = __builtin_ctz(rem);
+            const int sy = __builtin_ctz(rem);
             rem &= rem - 1u;
-            const bool tw = SPEC == LAW_TABLE1 ? s >= 12 : ((P.twin_mask >> s) & 1u) != 0u;
-            const R os = W.o[s * W.ls];
-            const R yprev = W.y[s * W.ls];
-            R yw = ((warm >> s) & 1u) ? yprev : R(0);
+            const bool tw = SPEC == LAW_TABLE1 ? sy >= 12 : ((P.twin_mask >> sy) & 1u) != 0u;
+            const R os = W.o[sy * W.ls];
+            const R yprev = W.y[sy * W.ls];
+            R yw = ((warm >> sy) & 1u) ? yprev : R(0);
             const R g = newton_solve<R>(fabs(os), tw ? Atw : R(1), tw ? etaAtw : P.eta,
                                         tw ? inv_etaAtw : P.inv_eta, W.fam + (tw ? LAW_FAM_WORDS : 0), P, yw,
                                         nnewt);
-            W.y[s * W.ls] = yw;
-            W.o[s * W.ls] = os < R(0) ? -g : g;
+            W.y[sy * W.ls] = yw;
+            W.o[sy * W.ls] = os < R(0) ? -g : g;
         }
     }
     warm = act;

@@ -323,21 +323,27 @@ constexpr int xpass_min_blocks()
 // per thread (plus 12 when the strain path is parked), column-major
 // (compile-time stride: plain shifts), then the family table.
 template <typename R, int NS, int BD = 256>
-__device__ __forceinline__ LawLds<R> law_lds(unsigned char *smem, size_t offset)
+__device__ __forceinline__ LawLds<R> law_lds(unsigned char *smem, size_t offset, size_t items_offset)
 {
     R *base = reinterpret_cast<R *>(smem + offset);
     const int t = threadIdx.x;
     R *fam = base + (2 * NS + law_e_rows<R>(NS)) * BD;
-    return LawLds<R>{base + t, base + NS * BD + t, base + 2 * NS * BD + t, fam, BD};
+    unsigned char *iw = smem + items_offset + (t >> 6) * law_items_wave_bytes<R>();
+    uint16_t *items = reinterpret_cast<uint16_t *>(iw);
+    R *aw = reinterpret_cast<R *>(iw + 64 * law_items_q<R>() * 2);
+    return LawLds<R>{base + t, base + NS * BD + t, base + 2 * NS * BD + t, fam, BD, items, aw};
 }
 
 // Bytes of the x pass FFT area in dynamic LDS: 3 complex lines of up to
-// 256 points, then the twiddles of the line length.
+// 256 points, then the twiddles of the line length.  The lines are free
+// while the law runs, and hold its Newton item lists then.
 template <typename R>
 constexpr size_t xfft_lds_bytes()
 {
     return (3 * 256 + 256) * sizeof(C2<R>);
 }
+static_assert(law_items_bytes<float>() <= 3 * 256 * sizeof(C2<float>), "Newton items exceed the FFT lines");
+static_assert(law_items_bytes<double>() <= 3 * 256 * sizeof(C2<double>), "Newton items exceed the FFT lines");
 
 template <typename R, int NS, int SPEC, bool ADAPT = false, bool AAM = false>
 __global__ __launch_bounds__(256, (xpass_min_blocks<R, SPEC>())) void k_xpass_iter(
@@ -412,15 +418,15 @@ __global__ __launch_bounds__(256, (xpass_min_blocks<R, SPEC>())) void k_xpass_it
             if (first)
                 voxel_law_probe<R, NS, SPEC>(P, d.Qtab + lab * 9, e0, e1, d.st[cur], &d.st[1 - cur], d.nvox, vox,
                                              R(sc->dt), sc->M, rk_lim2, rk_maxd, d.mv + vox, sig, v, nact, nnewt,
-                                             law_lds<R, NS>(smem_raw, xfft_lds_bytes<R>()));
+                                             law_lds<R, NS>(smem_raw, xfft_lds_bytes<R>(), 0));
             else
                 voxel_law<R, NS, SPEC>(P, d.Qtab + lab * 9, e0, e1, d.st[cur], &d.st[1 - cur], d.nvox, vox,
                                        R(sc->dt), sc->M << d.mv[vox], sig, v, nact, nnewt,
-                                       law_lds<R, NS>(smem_raw, xfft_lds_bytes<R>()));
+                                       law_lds<R, NS>(smem_raw, xfft_lds_bytes<R>(), 0));
         } else {
             voxel_law<R, NS, SPEC>(P, d.Qtab + lab * 9, e0, e1, d.st[cur], &d.st[1 - cur], d.nvox, vox,
                                    R(sc->dt), sc->M, sig, v, nact, nnewt,
-                                   law_lds<R, NS>(smem_raw, xfft_lds_bytes<R>()));
+                                   law_lds<R, NS>(smem_raw, xfft_lds_bytes<R>(), 0));
         }
         part[9] = (double)nact;
         part[10] = (double)nnewt;
@@ -1244,7 +1250,7 @@ __global__ __launch_bounds__(256, (xpass_min_blocks<R, SPEC>())) void k_constitu
     R v[NS];
     int nact = 0, nnewt = 0;
     voxel_law<R, NS, SPEC>(P, Qtab + lab * 9, e0, e1, st0, &st1, nvox, vox, dt, M, s, v, nact, nnewt,
-                           law_lds<R, NS>(smem_raw, 0));
+                           law_lds<R, NS>(smem_raw, 0, law_lds_bytes<R, NS>()));
 #pragma unroll
     for (int c = 0; c < 6; ++c) sig[c * nvox + vox] = s[c];
 }
