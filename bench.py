@@ -109,20 +109,48 @@ def cpu_baseline(w, s32, K, budget_s):
     o.Sigma = f["stress"].reshape(6, -1).mean(axis=1)
     o.E = f["strain"].reshape(6, -1).mean(axis=1)
     n = min(K, w.path.n_steps - 1)
-    its, t_used = 0, 0.0
-    while t_used < budget_s and its < 20:
-        t0 = time.perf_counter()
-        try:
-            o.step(w.path.t[n], w.path.t[n + 1], w.path.strain_ctrl[n], w.path.target[n])
-        except oracle.NotConverged:
-            pass
-        t_used += time.perf_counter() - t0
-        its += 1
-        print("[bench] oracle iteration %d: %.2f s" % (its, t_used), file=sys.stderr, flush=True)
+    state = (o.eps.copy(), o.y.copy(), o.sig.copy(), o.Sigma.copy(), o.E.copy())
+
+    def sample(limit_s, max_its):
+        o.eps, o.y, o.sig, o.Sigma, o.E = (a.copy() for a in state)
+        its, t_used = 0, 0.0
+        while its < max_its and (its == 0 or t_used < limit_s):
+            t0 = time.perf_counter()
+            try:
+                o.step(w.path.t[n], w.path.t[n + 1], w.path.strain_ctrl[n], w.path.target[n])
+            except oracle.NotConverged:
+                pass
+            t_used += time.perf_counter() - t0
+            its += 1
+            print("[bench] oracle iteration %d (%d threads): %.2f s" % (its, oracle.threads(), t_used),
+                  file=sys.stderr, flush=True)
+        return its, t_used
+
+    cores = oracle.threads()
+    its, t_used = sample(budget_s, 20)
+    oracle.set_threads(1)
+    its1, t1 = sample(0.0, 1)
+    oracle.set_threads(cores)
     return {"value": its * nx * ny * nz / t_used, "unit": "voxel-iterations/s",
-            "cores": oracle.threads(), "kind": "oracle",
+            "cores": cores, "kind": "oracle", "cpu_model": cpu_model(),
             "sample": "%d fixed-point iteration(s) of load step %d of the same 128^3 workload "
-                      "(FP64 oracle, from the GPU's committed state), %.1f s" % (its, n, t_used)}
+                      "(FP64 oracle, from the GPU's committed state), %.1f s" % (its, n, t_used),
+            "single_thread": {"value": its1 * nx * ny * nz / t1, "unit": "voxel-iterations/s",
+                              "cores": 1, "sample": "1 fixed-point iteration from the same state "
+                              "(the oracle's C law on one thread; numpy's FFTs are single-threaded "
+                              "in both figures), %.1f s" % t1}}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
 
 
 def batch_leg(cp, steps, ref_tol=1e-10):

@@ -109,6 +109,7 @@ typedef struct cpf_options {
     int green;         /* CPF_GREEN_*: which Green operator (Section 3)      */
     double rk_tol;     /* > 0: frozen error-controlled substep counts, below */
     int aa_depth;      /* > 0: Anderson-accelerated fixed point, below       */
+    int nyquist_mode;  /* CPF_NYQUIST_*: Nyquist frequencies, below          */
 } cpf_options;
 
 /* Anderson acceleration of the fixed point (an option; the paper's scheme
@@ -153,6 +154,24 @@ typedef struct cpf_options {
  *   directions. */
 #define CPF_GREEN_CONTINUOUS 0
 #define CPF_GREEN_ROTATED 1
+
+/* Nyquist frequencies of the continuous operator (even grid sizes; the
+ * paper does not say how they are treated).
+ * CPF_NYQUIST_ZERO (default): Gamma0 = 0 at every frequency with a
+ *   component m_j = N_j/2, and those frequencies are left out of the
+ *   residual; the kx = nx/2 column is then neither stored nor transformed.
+ * CPF_NYQUIST_FORMULA: the formula at every nonzero frequency, with
+ *   m_j = +N_j/2 at Nyquist, and the real part of the inverse transform
+ *   (the formula there is not Hermitian-symmetric: the partner index -k has
+ *   the same +N_j/2, so the applied operator is the average of the formula
+ *   at m and at m with its Nyquist components negated); the residual sums
+ *   |sigma_hat . xi_hat|^2 over every nonzero frequency of the full
+ *   spectrum.  The averaged operator is not a projector where a Nyquist
+ *   component meets another nonzero one, and the fixed point contracts
+ *   far more slowly there (5-20 times the iterations of CPF_NYQUIST_ZERO on
+ *   small even grids).  Needs CPF_GREEN_CONTINUOUS. */
+#define CPF_NYQUIST_ZERO 0
+#define CPF_NYQUIST_FORMULA 1
 
 /* Loading path: n_steps increments; t has n_steps+1 times (s).  For step
  * n, strain_ctrl[n][i] = 1 prescribes the mean strain component i to
@@ -281,9 +300,14 @@ int cpf_op_constitutive(cpf_solver *s, const void *dev_eps0, const void *dev_eps
                         const void *dev_state0, void *dev_state1, void *dev_sig1,
                         double dt, int M);
 
-/* Discrete adjoint of the load-stepped solve (gradient-based parameter
- * identification, Sec. 5 of the paper, which fits the law parameters of
- * Sec. 2 to effective stress curves).  Loss
+/* Discrete adjoint of the load-stepped solve.  The paper identifies the
+ * plastic parameters of its law (Section 3, the paragraph on their values)
+ * from effective stress responses; this is the gradient such an
+ * identification, or any training through the solver, needs: the exact
+ * derivative of a loss of the effective stress history with respect to
+ * the law parameters of equations 2-6 (the paper itself prints no
+ * gradient; the computation follows from differentiating the discrete
+ * scheme of Sections 3-4 step by step).  Loss
  *   L = sum_n (Sigma_11(t_n+1) - target_xx[n])^2
  * over the path's steps, and its exact gradient with respect to the 14
  * parameters theta[f][k], f = 0 slip / 1 twin family, k = r0 (initial

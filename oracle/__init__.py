@@ -18,7 +18,10 @@ the design notes of the repository):
 * Green operator: the continuous isotropic Gamma0 of a reference medium
   (lam0, mu0); frequencies xi_j = m_j / N_j with m_j in (-N_j/2, N_j/2];
   Gamma0 = 0 at xi = 0 and at every frequency with a Nyquist component
-  (m_j = N_j/2, N_j even), which keeps the real field real.
+  (m_j = N_j/2, N_j even), which keeps the real field real.  Option
+  nyquist='formula': the formula at every nonzero frequency (Nyquist
+  components taken as +N_j/2) and the real part of the inverse transform,
+  with those frequencies in the residual.
 * Discrete variant (option): the Green operator of the rotated
   finite-difference scheme, the continuous formula at the unit vector of
   s_j = sin(q_j/2) prod_{l != j} cos(q_l/2); zero where s = 0.
@@ -76,7 +79,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        path = os.path.join(_HERE, "_cp_law.so")
+        path = os.environ.get("CP_ORACLE_LIB") or os.path.join(_HERE, "_cp_law.so")
+        if os.environ.get("CP_ORACLE_LIB") and not os.path.exists(path):
+            raise FileNotFoundError("CP_ORACLE_LIB names a missing library: " + path)
         if not os.path.exists(path):
             from . import build as _b
             _b.build()
@@ -98,6 +103,8 @@ def lib():
                                     ctypes.POINTER(ctypes.c_int), dp, dp, dp, dp, dp,
                                     ctypes.c_double, ctypes.c_int]
         L.orc_max_threads.restype = ctypes.c_int
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_rate_vjp_point.restype = None
         L.orc_rate_vjp_point.argtypes = [ctypes.POINTER(_Material), ctypes.c_int, dp, dp, dp, dp, dp, dp]
         L.orc_vjp_grid.restype = ctypes.c_int
@@ -114,6 +121,11 @@ def _dp(a: np.ndarray):
 
 def threads() -> int:
     return lib().orc_max_threads()
+
+
+def set_threads(n: int) -> None:
+    """Thread count of the C law loops (the FFTs are numpy's, one thread)."""
+    lib().orc_set_threads(int(n))
 
 
 # ---------------------------------------------------------------------------
@@ -434,9 +446,14 @@ def von_mises_histogram(stress_fields, nbins: int, lo: float, hi: float) -> np.n
     return counts
 
 
-def frequency_directions(shape):
-    """Unit frequency directions xi_hat [3,nz,ny,nx] (x,y,z order) and the
-    mask of controlled frequencies (not zero, no Nyquist component)."""
+def frequency_directions(shape, nyquist: str = "zero"):
+    """Unit frequency directions xi_hat [3,nz,ny,nx] (x,y,z order) of the
+    frequencies m_j in (-N_j/2, N_j/2] and the mask of controlled
+    frequencies: not zero and, with nyquist='zero', no Nyquist component
+    (m_j = N_j/2); with nyquist='formula' every nonzero frequency (the
+    Nyquist components taken as +N_j/2)."""
+    if nyquist not in ("zero", "formula"):
+        raise ValueError("nyquist must be 'zero' or 'formula'")
     nz, ny, nx = shape
     ms, nyq = [], []
     for N in (nx, ny, nz):
@@ -448,7 +465,7 @@ def frequency_directions(shape):
     NZ, NY, NX = np.meshgrid(nyq[2], nyq[1], nyq[0], indexing="ij")
     xi = np.stack([MX, MY, MZ])
     nrm = np.sqrt(np.sum(xi * xi, axis=0))
-    ctrl = (nrm > 0) & ~(NX | NY | NZ)
+    ctrl = (nrm > 0) & ~(NX | NY | NZ) if nyquist == "zero" else nrm > 0
     xi_hat = np.where(ctrl, xi / np.where(nrm > 0, nrm, 1.0), 0.0)
     return xi_hat, ctrl
 
@@ -485,12 +502,15 @@ def frequency_directions_rotated(shape):
     return np.where(ctrl, s / np.where(ctrl, nrm, 1.0), 0.0), ctrl
 
 
-def green_directions(shape, green: str = "continuous"):
+def green_directions(shape, green: str = "continuous", nyquist: str = "zero"):
     """Unit directions and controlled-frequency mask of the chosen Green
-    operator: 'continuous' (the default) or 'rotated'."""
+    operator: 'continuous' (the default; nyquist as in
+    frequency_directions) or 'rotated'."""
     if green == "continuous":
-        return frequency_directions(shape)
+        return frequency_directions(shape, nyquist)
     if green == "rotated":
+        if nyquist != "zero":
+            raise ValueError("nyquist='formula' applies to the continuous operator only")
         return frequency_directions_rotated(shape)
     raise ValueError("green must be 'continuous' or 'rotated'")
 
@@ -552,6 +572,7 @@ class Options:
     rk_tol: float = 0.0               # > 0: frozen error-controlled substep counts per load step
     rk_max_doublings: int = 4
     aa_depth: int = 0                 # > 0: Anderson-accelerated fixed point of that depth
+    nyquist: str = "zero"             # continuous operator at Nyquist frequencies: 'zero' or 'formula'
 
 
 class NotConverged(RuntimeError):
@@ -588,7 +609,7 @@ class Solver:
             lam0, mu0 = self.opts.lam0, self.opts.mu0
         self.lam0, self.mu0 = lam0, mu0
         self.K0 = iso_stiffness(lam0, mu0)
-        self.xi_hat, self.ctrl = green_directions(self.shape, self.opts.green)
+        self.xi_hat, self.ctrl = green_directions(self.shape, self.opts.green, self.opts.nyquist)
         self.slip = self.mat.family == 0
         self.twin = self.mat.family == 1
         self.reset()

@@ -22,5 +22,20 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_sanitized(out: str, verbose: bool = False) -> str:
+    """The same source under AddressSanitizer and UndefinedBehaviorSanitizer
+    (every report fatal), for the host-side memory and UB checks of the
+    tests; loaded by pointing ``CP_ORACLE_LIB`` at ``out`` in a process that
+    preloads the sanitizer runtimes."""
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-fPIC", "-shared", "-fopenmp",
+           "-ffp-contract=off", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+           "-o", out, SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd), file=sys.stderr)
+    subprocess.run(cmd, check=True)
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

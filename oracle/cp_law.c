@@ -292,6 +292,18 @@ int orc_max_threads(void)
 #endif
 }
 
+/* Thread count of the parallel loops above (timing only: every voxel's
+ * result is independent of it). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    extern void omp_set_num_threads(int);
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------
  * Reverse mode (adjoint) of the local law, for gradients with respect to
  * the per-family parameters theta[f] = (r0, Q, b, c, d, K, n), f = slip,

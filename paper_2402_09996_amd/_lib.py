@@ -63,6 +63,7 @@ class CpfOptions(ctypes.Structure):
         ("precision", _i), ("tol", _d), ("max_iter", _i), ("h_max", _d),
         ("rk4_M", _i), ("lam0", _d), ("mu0", _d), ("stag_tol", _d),
         ("check_every", _i), ("green", _i), ("rk_tol", _d), ("aa_depth", _i),
+        ("nyquist_mode", _i),
     ]
 
 
@@ -155,8 +156,8 @@ def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
-            raise ImportError("libcpfft.so is not built: run __graft_entry__.build() "
-                              "or python paper_2402_09996_amd/build.py")
+            raise ImportError("%s is not built: run __graft_entry__.build() "
+                              "or python paper_2402_09996_amd/build.py" % LIB_PATH)
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             f = getattr(L, name)

@@ -89,6 +89,7 @@ extern "C" void cpf_options_default(cpf_options *o)
     o->green = CPF_GREEN_CONTINUOUS;
     o->rk_tol = 0.0;
     o->aa_depth = 0;
+    o->nyquist_mode = CPF_NYQUIST_ZERO;
 }
 
 // ---------------------------------------------------------------------------
@@ -620,7 +621,7 @@ static bool same_material(const cpf_problem &a, const cpf_problem &b)
 }
 
 template <typename R>
-static void init_rve(RveHost &h, const cpf_problem &p, int green)
+static void init_rve(RveHost &h, const cpf_problem &p, int green, int nyquist)
 {
     h.pb = p;
     h.nx = p.nx; h.ny = p.ny; h.nz = p.nz;
@@ -629,10 +630,12 @@ static void init_rve(RveHost &h, const cpf_problem &p, int green)
     // Nyquist one (kx < nx/2 for even nx, all nx/2 + 1 for odd nx): Gamma0
     // is zero on the Nyquist column and the residual leaves it out, so the
     // column is neither stored nor transformed along y and z.  The rotated
-    // operator acts on it, so it is kept.  The spectrum is stored
+    // operator, and the continuous one applied at Nyquist frequencies too,
+    // act on it, so it is kept.  The spectrum is stored
     // [z][y][kx][c]; rows of nhp columns (a multiple of 8: whole 128-byte
     // lines of 6 components).
-    h.nkx = (green == CPF_GREEN_ROTATED || (p.nx & 1)) ? p.nx / 2 + 1 : p.nx / 2;
+    h.nkx = (green == CPF_GREEN_ROTATED || nyquist == CPF_NYQUIST_FORMULA || (p.nx & 1)) ? p.nx / 2 + 1
+                                                                                          : p.nx / 2;
     h.nhp = (h.nkx + 7) / 8 * 8;
     h.nvox = (long)p.nx * p.ny * p.nz;
     radix_plan(h.nx, h.px);
@@ -663,6 +666,10 @@ extern "C" int cpf_batch_create(int n, const cpf_problem *const *probs, const cp
         return fail(CPF_E_INVALID_ARG, "need tol > 0, max_iter >= 1 and rk4_M > 0 or h_max > 0");
     if (o.green != CPF_GREEN_CONTINUOUS && o.green != CPF_GREEN_ROTATED)
         return fail(CPF_E_INVALID_ARG, "unknown Green operator %d", o.green);
+    if (o.nyquist_mode != CPF_NYQUIST_ZERO && o.nyquist_mode != CPF_NYQUIST_FORMULA)
+        return fail(CPF_E_INVALID_ARG, "unknown nyquist_mode %d", o.nyquist_mode);
+    if (o.nyquist_mode == CPF_NYQUIST_FORMULA && o.green != CPF_GREEN_CONTINUOUS)
+        return fail(CPF_E_INVALID_ARG, "nyquist_mode applies to the continuous Green operator only");
     if (!(o.rk_tol >= 0.0) || !std::isfinite(o.rk_tol))
         return fail(CPF_E_INVALID_ARG, "rk_tol must be finite and >= 0");
     if (o.aa_depth < 0 || o.aa_depth > AA_MAX)
@@ -681,8 +688,8 @@ extern "C" int cpf_batch_create(int n, const cpf_problem *const *probs, const cp
     s->n_twin = p0.n_twin;
     s->rv.resize(n);
     for (int i = 0; i < n; ++i) {
-        if (s->prec == CPF_PREC_FP64) init_rve<double>(s->rv[i], *probs[i], o.green);
-        else init_rve<float>(s->rv[i], *probs[i], o.green);
+        if (s->prec == CPF_PREC_FP64) init_rve<double>(s->rv[i], *probs[i], o.green, o.nyquist_mode);
+        else init_rve<float>(s->rv[i], *probs[i], o.green, o.nyquist_mode);
     }
     if (s->prec == CPF_PREC_FP64) { layout<double>(s); pass_grids<double>(s); }
     else { layout<float>(s); pass_grids<float>(s); }
@@ -1039,6 +1046,7 @@ static void launch_z(cpf_solver *s, int mode, const RveDev<R> *table = nullptr, 
     const R inv_mu0 = R(1.0 / s->mu0);
     const R coef = R((s->lam0 + s->mu0) / (s->mu0 * (s->lam0 + 2.0 * s->mu0)));
     if ((mode & ZMODE_GREEN) && s->opt.green == CPF_GREEN_ROTATED) mode |= ZMODE_ROTATED;
+    if ((mode & ZMODE_GREEN) && s->opt.nyquist_mode == CPF_NYQUIST_FORMULA) mode |= ZMODE_NYQUIST;
     if (kinds & 1)
         hipLaunchKernelGGL(k_zpass_fx<R>, dim3(grid), dim3(FX_THREADS), lds, s->stream, table, nrve, inv_mu0, coef,
                            mode, spec);

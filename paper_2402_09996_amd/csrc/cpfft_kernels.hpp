@@ -520,12 +520,13 @@ template <typename R, bool INV, int EPT>
 __global__ __launch_bounds__(256) void k_ypass(const RveDev<R> *__restrict__ rv, int nrve,
                                                C2<R> *spec_override)
 {
-    const int r = find_rve(rv, nrve, (int)blockIdx.x, 1);
+    const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int r = find_rve(rv, nrve, blk, 1);
     const RveDev<R> &d = rv[r];
     if ((!spec_override && d.sc->done) || d.yfix) return;
     extern __shared__ unsigned char smem_raw[];
     C2<R> *buf = reinterpret_cast<C2<R> *>(smem_raw);
-    const int local = blockIdx.x - d.by0;
+    const int local = blk - d.by0;
     const int tile = local % d.nty, z = local / d.nty;
     const int ny = d.ny, nhp = d.nhp;
     const int kx0 = tile * d.ty;
@@ -564,37 +565,16 @@ __device__ __forceinline__ void half_angle(int m, int n, double &sn, double &cs)
     sincospi((double)m / (double)n, &sn, &cs);
 }
 
+// operator of green_point
+constexpr int GREEN_CONT = 0;       // continuous, zero at every frequency with a Nyquist component
+constexpr int GREEN_ROT = 1;        // rotated finite-difference scheme
+constexpr int GREEN_CONT_NYQ = 2;   // continuous, the formula also at Nyquist frequencies
+
+// Gamma0(x) : s for the unit direction x, into o; returns |s . x|^2.
 template <typename R>
-__device__ __forceinline__ void green_point(C2<R> (&s)[6], int kx, int ky, int kz, const GreenArgs<R> &g,
-                                            bool rotated, double &err2)
+__device__ __forceinline__ double green_dir(const C2<R> (&s)[6], R x1, R x2, R x3, const GreenArgs<R> &g,
+                                            C2<R> (&o)[6])
 {
-    // frequency m_j in (-N_j/2, N_j/2]
-    const int my = ky <= g.ny / 2 ? ky : ky - g.ny;
-    const int mz = kz <= g.nz / 2 ? kz : kz - g.nz;
-    const int qx = (g.nx & 1) == 0 && 2 * kx == g.nx, qy = (g.ny & 1) == 0 && 2 * ky == g.ny,
-              qz = (g.nz & 1) == 0 && 2 * kz == g.nz;
-    // continuous operator: zero at any Nyquist component; rotated: zero
-    // where two or more components are at Nyquist (s = 0 there)
-    const bool zero = rotated ? qx + qy + qz >= 2 : (qx | qy | qz) != 0;
-    if (zero || (kx == 0 && my == 0 && mz == 0)) {
-#pragma unroll
-        for (int c = 0; c < 6; ++c) s[c] = C2<R>{R(0), R(0)};
-        return;
-    }
-    R x1, x2, x3;
-    if (rotated) {
-        // rotated scheme: s_j = sin(q_j/2) prod_{l != j} cos(q_l/2)
-        R sx, cx, sy, cy, sz, cz;
-        half_angle(kx, g.nx, sx, cx);
-        half_angle(my, g.ny, sy, cy);
-        half_angle(mz, g.nz, sz, cz);
-        x1 = sx * cy * cz; x2 = sy * cx * cz; x3 = sz * cx * cy;
-    } else {
-        // direction of (m_x/N_x, m_y/N_y, m_z/N_z)
-        x1 = R(kx) / R(g.nx); x2 = R(my) / R(g.ny); x3 = R(mz) / R(g.nz);
-    }
-    const R inr = R(1) / sqrt(x1 * x1 + x2 * x2 + x3 * x3);
-    x1 *= inr; x2 *= inr; x3 *= inr;
     // a = tau . xi, b = xi . a
     C2<R> a1, a2, a3;
     a1.x = s[0].x * x1 + s[5].x * x2 + s[4].x * x3;
@@ -603,11 +583,8 @@ __device__ __forceinline__ void green_point(C2<R> (&s)[6], int kx, int ky, int k
     a2.y = s[5].y * x1 + s[1].y * x2 + s[3].y * x3;
     a3.x = s[4].x * x1 + s[3].x * x2 + s[2].x * x3;
     a3.y = s[4].y * x1 + s[3].y * x2 + s[2].y * x3;
-    // Hermitian partner in the half spectrum (the kx = 0 and Nyquist columns
-    // hold their own)
-    const double w = (kx == 0 || qx) ? 1.0 : 2.0;
-    err2 += w * ((double)a1.x * a1.x + (double)a1.y * a1.y + (double)a2.x * a2.x +
-                 (double)a2.y * a2.y + (double)a3.x * a3.x + (double)a3.y * a3.y);
+    const double t = (double)a1.x * a1.x + (double)a1.y * a1.y + (double)a2.x * a2.x +
+                     (double)a2.y * a2.y + (double)a3.x * a3.x + (double)a3.y * a3.y;
     const C2<R> b = {a1.x * x1 + a2.x * x2 + a3.x * x3, a1.y * x1 + a2.y * x2 + a3.y * x3};
     const R hm = R(0.5) * g.inv_mu0;
     const R xs[3] = {x1, x2, x3};
@@ -617,9 +594,66 @@ __device__ __forceinline__ void green_point(C2<R> (&s)[6], int kx, int ky, int k
     for (int c = 0; c < 6; ++c) {
         const R xi = xs[I[c]], xj = xs[J[c]];
         const R q = g.coef * xi * xj;
-        s[c].x = hm * (xi * as[J[c]].x + xj * as[I[c]].x) - q * b.x;
-        s[c].y = hm * (xi * as[J[c]].y + xj * as[I[c]].y) - q * b.y;
+        o[c].x = hm * (xi * as[J[c]].x + xj * as[I[c]].x) - q * b.x;
+        o[c].y = hm * (xi * as[J[c]].y + xj * as[I[c]].y) - q * b.y;
     }
+    return t;
+}
+
+template <typename R>
+__device__ __forceinline__ void green_point(C2<R> (&s)[6], int kx, int ky, int kz, const GreenArgs<R> &g,
+                                            int op, double &err2)
+{
+    // frequency m_j in (-N_j/2, N_j/2]
+    const int my = ky <= g.ny / 2 ? ky : ky - g.ny;
+    const int mz = kz <= g.nz / 2 ? kz : kz - g.nz;
+    const int qx = (g.nx & 1) == 0 && 2 * kx == g.nx, qy = (g.ny & 1) == 0 && 2 * ky == g.ny,
+              qz = (g.nz & 1) == 0 && 2 * kz == g.nz;
+    // continuous operator: zero at any Nyquist component; rotated: zero
+    // where two or more components are at Nyquist (s = 0 there); continuous
+    // with Nyquist frequencies: zero only at the zero frequency
+    const bool zero = op == GREEN_ROT ? qx + qy + qz >= 2 : (op == GREEN_CONT && (qx | qy | qz) != 0);
+    if (zero || (kx == 0 && my == 0 && mz == 0)) {
+#pragma unroll
+        for (int c = 0; c < 6; ++c) s[c] = C2<R>{R(0), R(0)};
+        return;
+    }
+    R x1, x2, x3;
+    if (op == GREEN_ROT) {
+        // rotated scheme: s_j = sin(q_j/2) prod_{l != j} cos(q_l/2)
+        R sx, cx, sy, cy, sz, cz;
+        half_angle(kx, g.nx, sx, cx);
+        half_angle(my, g.ny, sy, cy);
+        half_angle(mz, g.nz, sz, cz);
+        x1 = sx * cy * cz; x2 = sy * cx * cz; x3 = sz * cx * cy;
+    } else {
+        // direction of (m_x/N_x, m_y/N_y, m_z/N_z), m_j = +N_j/2 at Nyquist
+        x1 = R(kx) / R(g.nx); x2 = R(my) / R(g.ny); x3 = R(mz) / R(g.nz);
+    }
+    const R inr = R(1) / sqrt(x1 * x1 + x2 * x2 + x3 * x3);
+    x1 *= inr; x2 *= inr; x3 *= inr;
+    // Hermitian partner in the half spectrum (the kx = 0 and Nyquist columns
+    // hold their own)
+    const bool own = kx == 0 || qx;
+    C2<R> o[6];
+    const double t = green_dir<R>(s, x1, x2, x3, g, o);
+    if (op == GREEN_CONT_NYQ && (qx | qy | qz)) {
+        // The partner index -k has the same +N/2 at its Nyquist components,
+        // i.e. the direction m' = m with those components negated (Gamma0 is
+        // even).  The real part of the inverse transform of the formula
+        // applied at every frequency is the transform of the Hermitian part
+        // 1/2 (Gamma0(m) + Gamma0(m')) : s, stored here; the residual counts
+        // the partner with its own direction.
+        C2<R> o2[6];
+        const double t2 = green_dir<R>(s, qx ? -x1 : x1, qy ? -x2 : x2, qz ? -x3 : x3, g, o2);
+        err2 += own ? t : t + t2;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) s[c] = C2<R>{R(0.5) * (o[c].x + o2[c].x), R(0.5) * (o[c].y + o2[c].y)};
+        return;
+    }
+    err2 += (own ? 1.0 : 2.0) * t;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) s[c] = o[c];
 }
 
 // mode bits: ZMODE_FWD forward z transform; ZMODE_GREEN Gamma0, residual and
@@ -628,6 +662,12 @@ __device__ __forceinline__ void green_point(C2<R> (&s)[6], int kx, int ky, int k
 constexpr int ZMODE_FWD = 1;
 constexpr int ZMODE_GREEN = 2;
 constexpr int ZMODE_ROTATED = 4;   // with ZMODE_GREEN: the rotated-scheme operator
+constexpr int ZMODE_NYQUIST = 8;   // with ZMODE_GREEN: the continuous operator also at Nyquist frequencies
+
+__device__ __forceinline__ int green_op(int mode)
+{
+    return (mode & ZMODE_ROTATED) ? GREEN_ROT : (mode & ZMODE_NYQUIST) ? GREEN_CONT_NYQ : GREEN_CONT;
+}
 
 // Block = one ky, a tile of tz kx columns, all kz, all 6 components: the
 // 6 tz lines (column-major, components adjacent) of nz points, each row of
@@ -683,7 +723,7 @@ __global__ __launch_bounds__(Z_THREADS) void k_zpass_green(const RveDev<R> *__re
         C2<R> *f = buf + kz * nl + col * 6;
 #pragma unroll
         for (int c = 0; c < 6; ++c) sv[c] = f[c];
-        green_point<R>(sv, kx0 + col, ky, kz, g, (mode & ZMODE_ROTATED) != 0, err2);
+        green_point<R>(sv, kx0 + col, ky, kz, g, green_op(mode), err2);
 #pragma unroll
         for (int c = 0; c < 6; ++c) f[c] = sv[c];
     }
@@ -732,12 +772,13 @@ __device__ __forceinline__ void ypass_fixed(const RveDev<R> &d, C2<R> *g, C2<R> 
 template <typename R, bool INV>
 __global__ __launch_bounds__(FX_THREADS) void k_ypass_fx(const RveDev<R> *__restrict__ rv, int nrve, C2<R> *spec_override)
 {
-    const int r = find_rve(rv, nrve, (int)blockIdx.x, 1);
+    const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int r = find_rve(rv, nrve, blk, 1);
     const RveDev<R> &d = rv[r];
     if ((!spec_override && d.sc->done) || !d.yfix) return;
     extern __shared__ unsigned char smem_raw[];
     C2<R> *buf = reinterpret_cast<C2<R> *>(smem_raw);
-    const int local = blockIdx.x - d.by0;
+    const int local = blk - d.by0;
     const int tile = local % d.nty, z = local / d.nty;
     const int kx0 = tile * d.ty;
     const int nlv = 6 * min(d.ty, d.nkx - kx0);
@@ -788,7 +829,7 @@ __device__ __forceinline__ void zpass_fixed(const RveDev<R> &d, C2<R> *spec, C2<
             C2<R> *f = buf + kz * NL + col * 6;
 #pragma unroll
             for (int c = 0; c < 6; ++c) sv[c] = f[c];
-            green_point<R>(sv, kx0 + col, ky, kz, g, (mode & ZMODE_ROTATED) != 0, err2);
+            green_point<R>(sv, kx0 + col, ky, kz, g, green_op(mode), err2);
 #pragma unroll
             for (int c = 0; c < 6; ++c) f[c] = sv[c];
         }

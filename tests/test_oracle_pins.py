@@ -363,6 +363,41 @@ def test_twinning_is_unidirectional_and_saturates():
 # ---------------------------------------------------------------------------
 # Fixed-point solver
 # ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shape", [(4, 4, 6), (2, 6, 4), (3, 4, 4)])
+def test_nyquist_formula_is_the_real_part_of_the_full_inverse(shape):
+    """With nyquist='formula', Gamma0 * tau is the real part of the inverse
+    DFT, summed here by brute force, of the formula applied at every nonzero
+    frequency with Nyquist components at +N/2 (directions built here from
+    the indices); on an odd grid there is nothing to differ from 'zero'."""
+    lam0, mu0 = 57583.3, 79625.0
+    rng = np.random.default_rng(11)
+    tau = rng.standard_normal((6,) + shape)
+    nz, ny, nx = shape
+    th = oracle.fft3(tau)
+    ref = np.zeros((6,) + shape, dtype=complex)
+    grid = np.stack(np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij"))
+    for kz in range(nz):
+        for ky in range(ny):
+            for kx in range(nx):
+                m = np.array([kx if 2 * kx <= nx else kx - nx, ky if 2 * ky <= ny else ky - ny,
+                              kz if 2 * kz <= nz else kz - nz], float) / np.array([nx, ny, nz])
+                if not m.any():
+                    continue
+                G = _gamma_matrix(m / np.linalg.norm(m), lam0, mu0)
+                e = (G @ (th[:, kz, ky, kx] * oracle.MANDEL_W)) / oracle.MANDEL_W
+                ph = np.exp(2j * np.pi * (kz * grid[0] / nz + ky * grid[1] / ny + kx * grid[2] / nx))
+                ref += e[:, None, None, None] * ph[None] / tau[0].size
+    xi, ctrl = oracle.frequency_directions(shape, "formula")
+    out = oracle.ifft3_real(oracle.gamma0_apply(th, lam0, mu0, xi, ctrl))
+    assert np.allclose(out, ref.real, rtol=0, atol=1e-13 * np.abs(ref).max())
+    assert np.abs(ref.imag).max() > 1e-6 * np.abs(ref.real).max()   # the formula is not Hermitian there
+    xz, cz = oracle.frequency_directions(shape, "zero")
+    assert not np.allclose(oracle.ifft3_real(oracle.gamma0_apply(th, lam0, mu0, xz, cz)), out)
+    xo, co = oracle.frequency_directions((3, 5, 7), "formula")
+    xe, ce = oracle.frequency_directions((3, 5, 7), "zero")
+    assert np.array_equal(co, ce) and np.array_equal(xo, xe)
+
+
 def _solver(labels, euler, C, law, systems=None, **kw):
     S = systems or rvegen.config_systems(False)
     return oracle.Solver(labels, euler, C, S.n_miller, S.l_miller, S.family,
@@ -382,23 +417,25 @@ def test_homogeneous_reference_medium_converges_in_one_iteration():
     assert R.iters[0] <= 2
 
 
-@pytest.mark.parametrize("green,lo,hi", [("continuous", 4, 10), ("rotated", 4, 10), ("rotated", 3, 10)])
-def test_two_phase_laminate_closed_form(green, lo, hi):
+@pytest.mark.parametrize("green,nyquist,lo,hi", [("continuous", "zero", 4, 10), ("rotated", "zero", 4, 10),
+                                                ("rotated", "zero", 3, 10), ("continuous", "formula", 3, 10),
+                                                ("continuous", "formula", 4, 10)])
+def test_two_phase_laminate_closed_form(green, nyquist, lo, hi):
     """Layers normal to x of two orientations of a cubic crystal, elastic.
     Exact solution: piecewise constant fields with continuous traction
     sigma.e_x and continuous in-plane strain; solved here as an 11x11
     linear system independent of the oracle's operator.  Layer widths 6
-    and 10 have no Nyquist content; 7 and 9 do, which only the rotated
-    operator controls (its direction at (q_x, 0, 0) is e_x for every
-    q_x != 0, Nyquist included), so the exact solution is its fixed point
-    too."""
+    and 10 have no Nyquist content; 7 and 9 do, which the rotated operator
+    and the continuous one applied at Nyquist frequencies control (the
+    direction at (m_x, 0, 0) is e_x for every m_x != 0, Nyquist included),
+    so the exact solution is their fixed point too."""
     n = 16
     C = rvegen.cubic_stiffness(183000.0, 74500.0, 105000.0)
     eul = np.array([[0.3, 0.9, 0.2], [1.7, 2.1, 0.5]])
     labels = np.zeros((4, 4, n), np.int32)
     labels[..., lo:hi] = 1
     f2 = (hi - lo) / n
-    s = _solver(labels, eul, C, _law(), tau0=np.full(12, 1e9), tol=1e-13, green=green)
+    s = _solver(labels, eul, C, _law(), tau0=np.full(12, 1e9), tol=1e-13, green=green, nyquist=nyquist)
     path = rvegen.uniaxial_path(1e-3, 1)
     R = s.run(path, keep_fields=True)
     Cm = [oracle.lab_stiffness(C, oracle.euler_to_rotation(eul[i:i + 1]))[0] for i in range(2)]
