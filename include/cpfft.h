@@ -110,6 +110,10 @@ typedef struct cpf_options {
     double rk_tol;     /* > 0: frozen error-controlled substep counts, below */
     int aa_depth;      /* > 0: Anderson-accelerated fixed point, below       */
     int nyquist_mode;  /* CPF_NYQUIST_*: Nyquist frequencies, below          */
+    int cutback;       /* > 0: a load step that ends CPF_E_NOT_CONVERGED or
+                          CPF_E_NAN is retried as two half steps (times and
+                          targets halved from the committed state of the
+                          first RVE), recursively up to this many halvings */
 } cpf_options;
 
 /* Anderson acceleration of the fixed point (an option; the paper's scheme
@@ -198,6 +202,15 @@ typedef struct cpf_step_out {
                          (stag_tol), with err above tol                    */
     int host_syncs;   /* host waits on the device during the step (polls of
                          the step status; the same for every member)       */
+    long long n_symptom; /* voxels whose stress moved by more than E0 |dE|:
+                         |sigma_{n+1} - sigma_n|_F > E0 |E_{n+1} - E_n|_F
+                         (Frobenius norms of tensor components, E0 the
+                         Young's modulus of the reference medium), the
+                         local condition under which Section 4 reports
+                         that equilibrium stops being enforced; summed
+                         over the sub-steps of a cut-back step             */
+    int cutbacks;     /* failed attempts of the step that were retried as
+                         two half steps (options.cutback)                  */
 } cpf_step_out;
 
 typedef struct cpf_problem cpf_problem;

@@ -573,6 +573,7 @@ class Options:
     rk_max_doublings: int = 4
     aa_depth: int = 0                 # > 0: Anderson-accelerated fixed point of that depth
     nyquist: str = "zero"             # continuous operator at Nyquist frequencies: 'zero' or 'formula'
+    cutback: int = 0                  # > 0: a failed load step is retried as two half steps, recursively
 
 
 class NotConverged(RuntimeError):
@@ -592,6 +593,8 @@ class Result:
     err_bc: np.ndarray
     wall: float = 0.0
     fields: Optional[dict] = None
+    n_symptom: Optional[np.ndarray] = None   # local-stress test count per step (Solver.symptom_count)
+    cutbacks: Optional[np.ndarray] = None    # failed attempts retried as half steps
 
 
 class Solver:
@@ -723,9 +726,44 @@ class Solver:
                 eps = eps - to_mandel(corr) + to_mandel(dE)
         else:
             raise NotConverged("no convergence in %d iterations" % o.max_iter)
+        self.last_symptom = self.symptom_count(sig, E)
+        self.last_errors = (err_eq, err_bc)
         self.eps, self.y, self.sig = eps, y1, sig
         self.Sigma, self.E = Sigma, E
         return k + 1, err_eq, err_bc
+
+    def symptom_count(self, sig_new: np.ndarray, E_new: np.ndarray) -> int:
+        """Voxels whose stress moved by more than E0 |dE| over the load step
+        (Section 4's condition under which the basic scheme stops enforcing
+        equilibrium locally): |sigma_{n+1} - sigma_n|_F > E0 |E_{n+1} - E_n|_F,
+        Frobenius norms (Mandel vectors carry them as Euclidean norms), E0
+        the Young's modulus of the reference medium; squares compared."""
+        lam0, mu0 = self.lam0, self.mu0
+        E0 = mu0 * (3.0 * lam0 + 2.0 * mu0) / (lam0 + mu0)
+        dE = np.asarray(E_new) - self.E
+        thr2 = E0 * E0 * float(np.sum(FROB_W * dE * dE))
+        d = sig_new - self.sig
+        return int(np.count_nonzero(np.sum(d * d, axis=1) > thr2))
+
+    def step_cut(self, t0: float, t1: float, ctrl_row, target_row, depth: int):
+        """One load step, retried as two half steps when it does not converge
+        (or its residual is not finite) and halvings are left; the half
+        step's targets are the midpoints between the committed mean strain
+        (strain-controlled components) or mean stress (stress-controlled ones)
+        and the step's targets.  Returns (iterations of the completed
+        sub-steps, failed attempts, local-stress counts summed)."""
+        try:
+            its, _, _ = self.step(t0, t1, ctrl_row, target_row)
+            return its, 0, self.last_symptom
+        except (NotConverged, FloatingPointError):
+            if depth <= 0:
+                raise
+        ctrl = np.asarray(ctrl_row, dtype=bool)
+        target = np.asarray(target_row, dtype=np.float64)
+        mid = 0.5 * (np.where(ctrl, self.E, self.Sigma) + target)
+        i0, c0, s0 = self.step_cut(t0, 0.5 * (t0 + t1), ctrl_row, mid, depth - 1)
+        i1, c1, s1 = self.step_cut(0.5 * (t0 + t1), t1, ctrl_row, target, depth - 1)
+        return i0 + i1, c0 + c1 + 1, s0 + s1
 
     def outputs(self):
         S = self.mat.n_sys
@@ -740,10 +778,18 @@ class Solver:
         R = Result(*(np.zeros((ns, 6)) for _ in range(2)),
                    *(np.zeros(ns) for _ in range(4)),
                    np.zeros(ns, dtype=np.int64), np.zeros(ns), np.zeros(ns))
+        R.n_symptom = np.zeros(ns, dtype=np.int64)
+        R.cutbacks = np.zeros(ns, dtype=np.int64)
         t_start = time.perf_counter()
         for n in range(ns):
-            its, ee, eb = self.step(path.t[n], path.t[n + 1], path.strain_ctrl[n],
-                                    path.target[n])
+            if self.opts.cutback > 0:
+                its, R.cutbacks[n], R.n_symptom[n] = self.step_cut(
+                    path.t[n], path.t[n + 1], path.strain_ctrl[n], path.target[n], self.opts.cutback)
+                ee, eb = self.last_errors
+            else:
+                its, ee, eb = self.step(path.t[n], path.t[n + 1], path.strain_ctrl[n],
+                                        path.target[n])
+                R.n_symptom[n] = self.last_symptom
             R.Sigma[n], R.E[n] = self.Sigma, self.E
             (R.sig_eq_of_mean[n], R.mean_sig_eq[n], R.mean_v[n],
              R.mean_f[n]) = self.outputs()

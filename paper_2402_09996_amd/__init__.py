@@ -135,7 +135,9 @@ def _outs_to_dict(outs, n):
          "iters": np.array([outs[i].iters for i in range(n)], dtype=np.int64),
          "status": np.array([outs[i].status for i in range(n)], dtype=np.int64),
          "stagnated": np.array([outs[i].stagnated for i in range(n)], dtype=np.int64),
-         "host_syncs": np.array([outs[i].host_syncs for i in range(n)], dtype=np.int64)}
+         "host_syncs": np.array([outs[i].host_syncs for i in range(n)], dtype=np.int64),
+         "n_symptom": np.array([outs[i].n_symptom for i in range(n)], dtype=np.int64),
+         "cutbacks": np.array([outs[i].cutbacks for i in range(n)], dtype=np.int64)}
     for k in keys:
         r[k] = np.array([getattr(outs[i], k) for i in range(n)])
     return r
@@ -146,7 +148,7 @@ NYQUIST = {"zero": 0, "formula": 1}
 
 
 def _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_every, green="continuous",
-             rk_tol=0.0, aa_depth=0, nyquist="zero"):
+             rk_tol=0.0, aa_depth=0, nyquist="zero", cutback=0):
     o = _lib.CpfOptions()
     _lib.lib().cpf_options_default(ctypes.byref(o))
     o.precision = CPF_PREC_FP64 if precision == "fp64" else CPF_PREC_FP32
@@ -162,6 +164,7 @@ def _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_
     if nyquist not in NYQUIST:
         raise ValueError("nyquist must be one of %s" % sorted(NYQUIST))
     o.nyquist_mode = NYQUIST[nyquist]
+    o.cutback = int(cutback)
     return o
 
 
@@ -177,7 +180,7 @@ class Solver:
                  stag_tol: float = 0.0, check_every: int = 0, device: str = "cuda:0",
                  stream=None, graph_iters: int = 0, autotune: bool = False,
                  green: str = "continuous", rk_tol: float = 0.0, aa_depth: int = 0,
-                 nyquist: str = "zero"):
+                 nyquist: str = "zero", cutback: int = 0):
         import torch
         L = _lib.lib()
         probs = list(problem) if isinstance(problem, (list, tuple)) else [problem]
@@ -187,7 +190,7 @@ class Solver:
         self.precision = precision
         self.dtype = {"fp64": torch.float64, "fp32": torch.float32}[precision]
         o = _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_every, green, rk_tol,
-                     aa_depth, nyquist)
+                     aa_depth, nyquist, cutback)
         self.green_operator = green
         self.nyquist = nyquist
         h = ctypes.c_void_p()

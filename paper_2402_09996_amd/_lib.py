@@ -63,7 +63,7 @@ class CpfOptions(ctypes.Structure):
         ("precision", _i), ("tol", _d), ("max_iter", _i), ("h_max", _d),
         ("rk4_M", _i), ("lam0", _d), ("mu0", _d), ("stag_tol", _d),
         ("check_every", _i), ("green", _i), ("rk_tol", _d), ("aa_depth", _i),
-        ("nyquist_mode", _i),
+        ("nyquist_mode", _i), ("cutback", _i),
     ]
 
 
@@ -77,6 +77,7 @@ class CpfStepOut(ctypes.Structure):
         ("sig_eq_of_mean", _d), ("mean_sig_eq", _d), ("mean_v", _d), ("mean_f", _d),
         ("err_eq", _d), ("err_bc", _d), ("n_active", _d), ("n_newton", _d),
         ("iters", _i), ("status", _i), ("stagnated", _i), ("host_syncs", _i),
+        ("n_symptom", ctypes.c_longlong), ("cutbacks", _i),
     ]
 
 

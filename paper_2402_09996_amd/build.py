@@ -19,6 +19,8 @@ FLAGS = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-result",
 ]
+# roctx ranges (load step, iteration chunk, pass; adjoint step) for profiler runs
+LIBS = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
 
 
 # Host code under AddressSanitizer and UndefinedBehaviorSanitizer (every
@@ -35,7 +37,7 @@ SAN_FLAGS = [
 
 
 def _command(flags, extra, tmp):
-    return [HIPCC, *flags, *extra, "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
+    return [HIPCC, *flags, *extra, "-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES] + LIBS
 
 
 def _build_with(flags, extra, out, verbose):

@@ -6,8 +6,10 @@
 // and every kernel returns at once when the device flag says the step has
 // ended, so the host only polls the step status between chunks.
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <algorithm>
+#include <cstddef>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -47,6 +49,16 @@ static int fail(int code, const char *fmt, ...)
             return fail(CPF_E_HIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),  \
                         __FILE__, __LINE__);                                               \
     } while (0)
+
+// roctx range over a scope (host side: the enqueue of a load step, an
+// iteration chunk or a pass; a profiler run with marker tracing shows them
+// beside the kernels)
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 extern "C" int cpf_version(void) { return CPF_VERSION; }
 
@@ -90,6 +102,7 @@ extern "C" void cpf_options_default(cpf_options *o)
     o->rk_tol = 0.0;
     o->aa_depth = 0;
     o->nyquist_mode = CPF_NYQUIST_ZERO;
+    o->cutback = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -670,6 +683,8 @@ extern "C" int cpf_batch_create(int n, const cpf_problem *const *probs, const cp
         return fail(CPF_E_INVALID_ARG, "unknown nyquist_mode %d", o.nyquist_mode);
     if (o.nyquist_mode == CPF_NYQUIST_FORMULA && o.green != CPF_GREEN_CONTINUOUS)
         return fail(CPF_E_INVALID_ARG, "nyquist_mode applies to the continuous Green operator only");
+    if (o.cutback < 0 || o.cutback > 20)
+        return fail(CPF_E_INVALID_ARG, "cutback must be in [0, 20]");
     if (!(o.rk_tol >= 0.0) || !std::isfinite(o.rk_tol))
         return fail(CPF_E_INVALID_ARG, "rk_tol must be finite and >= 0");
     if (o.aa_depth < 0 || o.aa_depth > AA_MAX)
@@ -1093,11 +1108,11 @@ static int launch_iteration(cpf_solver *s, const LawP<R> &P)
         hipLaunchKernelGGL(k_aa_solve<R>, dim3(nrve), dim3(64), 0, s->stream, tab);
         hipLaunchKernelGGL(k_aa_update<R>, dim3(s->nbx_tot), dim3(256), 0, s->stream, tab, nrve);
     }
-    TIMED(s, 0, launch_xiter_any<R>(s, P));
-    TIMED(s, 1, launch_y<R>(s, false));
-    TIMED(s, 2, launch_z<R>(s, ZMODE_FWD | ZMODE_GREEN));
-    TIMED(s, 3, launch_y<R>(s, true));
-    TIMED(s, 4, launch_bc<R>(s));
+    { TraceRange t("cpf x pass (law, x transforms)"); TIMED(s, 0, launch_xiter_any<R>(s, P)); }
+    { TraceRange t("cpf y pass"); TIMED(s, 1, launch_y<R>(s, false)); }
+    { TraceRange t("cpf z pass (Green operator)"); TIMED(s, 2, launch_z<R>(s, ZMODE_FWD | ZMODE_GREEN)); }
+    { TraceRange t("cpf y pass (inverse)"); TIMED(s, 3, launch_y<R>(s, true)); }
+    { TraceRange t("cpf boundary update"); TIMED(s, 4, launch_bc<R>(s)); }
     return CPF_OK;
 }
 
@@ -1167,6 +1182,7 @@ static int check_path(const cpf_path *p)
 template <typename R>
 static int step_impl(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *outs)
 {
+    TraceRange trace("cpf load step");
     const double dt = path->t[n + 1] - path->t[n];
     const int M = s->opt.rk4_M > 0 ? s->opt.rk4_M : substeps(dt, s->opt.h_max);
     const size_t nr = s->rv.size();
@@ -1207,6 +1223,7 @@ static int step_impl(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *o
     for (const auto &h : s->rv) prev = std::max(prev, h.prev_iters);
     int chunk = s->opt.check_every > 0 ? s->opt.check_every : std::max(2, prev);
     for (;;) {
+        TraceRange chunk_trace("cpf iterations until the next poll");
         if (s->graph_iters != 0) {
             const int len = s->graph_iters > 0 ? s->graph_iters : adaptive_len(prev, queued, s->opt.max_iter);
             hipGraphExec_t x = nullptr;
@@ -1237,6 +1254,31 @@ static int step_impl(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *o
             return fail(CPF_E_BAD_STATE, "device did not end the step after %d iterations", queued);
         chunk = s->opt.check_every > 0 ? s->opt.check_every : 4;
     }
+    bool all_ok = true;
+    for (size_t r = 0; r < nr; ++r) all_ok = all_ok && s->hsc[r].status == 0;
+    if (all_ok) {
+        // local-stress test of the converged step (k_symptom)
+        const double E0 = s->mu0 * (3.0 * s->lam0 + 2.0 * s->mu0) / (s->lam0 + s->mu0);
+        for (size_t r = 0; r < nr; ++r) {
+            const RveHost &h = s->rv[r];
+            double d2 = 0.0;
+            for (int i = 0; i < 6; ++i) {
+                const double d = s->hsc[r].E[i] - h.E_n[i];
+                d2 += (i < 3 ? 1.0 : 2.0) * d * d;
+            }
+            const int a = h.cur, b = 1 - h.cur;
+            unsigned long long *cnt =
+                (unsigned long long *)(s->ws + h.off_sc + offsetof(Scalars, n_symptom));
+            hipLaunchKernelGGL(k_symptom<R>, dim3((h.nvox + 255) / 256), dim3(256), 0, s->stream,
+                               dptr<int32_t>(s, h.off_labels), dptr<R>(s, h.off_Q), dptr<R>(s, h.off_eps[b]),
+                               dptr<R>(s, h.off_st[b]), dptr<R>(s, h.off_eps[a]), dptr<R>(s, h.off_st[a]), P,
+                               h.nvox, E0 * E0 * d2, cnt);
+            HIPCHK(hipGetLastError());
+            HIPCHK(hipMemcpyAsync(&s->hsc[r].n_symptom, cnt, sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                  s->stream));
+        }
+        HIPCHK(hipStreamSynchronize(s->stream));
+    }
     int worst = CPF_OK, worst_r = -1;
     for (size_t r = 0; r < nr; ++r) {
         const Scalars &h = s->hsc[r];
@@ -1259,6 +1301,8 @@ static int step_impl(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *o
             out->status = h.status;
             out->stagnated = h.stagnated;
             out->host_syncs = syncs;
+            out->n_symptom = all_ok ? (long long)h.n_symptom : 0;
+            out->cutbacks = 0;
         }
         if (h.status != 0 && worst == CPF_OK) {
             worst = h.status;
@@ -1281,13 +1325,54 @@ static int step_impl(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *o
     return CPF_OK;
 }
 
+// A load step, retried as two half steps when it ends NOT_CONVERGED or NAN
+// and halvings are left.  Nothing is committed by a failed attempt, so the
+// retry starts from the same committed state.  The half step's targets are
+// the midpoints between the committed mean strain (strain-controlled
+// components) or mean stress (stress-controlled ones) of the first RVE and
+// the step's targets.  Outputs: the last sub-step's, with the iterations
+// and local-stress counts of all completed sub-steps summed and the failed
+// attempts counted.
+static int step_cut(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *outs, int depth)
+{
+    int rc = s->prec == CPF_PREC_FP64 ? step_impl<double>(s, path, n, outs) : step_impl<float>(s, path, n, outs);
+    if ((rc != CPF_E_NOT_CONVERGED && rc != CPF_E_NAN) || depth <= 0) return rc;
+    const size_t nr = s->rv.size();
+    const RveHost &h0 = s->rv[0];
+    double t[3] = {path->t[n], 0.5 * (path->t[n] + path->t[n + 1]), path->t[n + 1]};
+    uint8_t ctrl[12];
+    double tg[12];
+    for (int i = 0; i < 6; ++i) {
+        ctrl[i] = ctrl[6 + i] = path->strain_ctrl[6 * n + i];
+        const double from = ctrl[i] ? h0.E_n[i] : h0.Sigma_n[i];
+        tg[i] = 0.5 * (from + path->target[6 * n + i]);
+        tg[6 + i] = path->target[6 * n + i];
+    }
+    const cpf_path half = {2, t, ctrl, tg};
+    std::vector<cpf_step_out> first(nr);
+    rc = step_cut(s, &half, 0, outs ? first.data() : nullptr, depth - 1);
+    if (rc) return rc;
+    rc = step_cut(s, &half, 1, outs, depth - 1);
+    if (rc) return rc;
+    if (outs)
+        for (size_t r = 0; r < nr; ++r) {
+            outs[r].iters += first[r].iters;
+            outs[r].n_symptom += first[r].n_symptom;
+            outs[r].n_active += first[r].n_active;
+            outs[r].n_newton += first[r].n_newton;
+            outs[r].host_syncs += first[r].host_syncs;
+            outs[r].cutbacks += first[r].cutbacks + 1;
+        }
+    return CPF_OK;
+}
+
 extern "C" int cpf_batch_step(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *outs)
 {
     if (!s || !s->bound) return fail(CPF_E_BAD_STATE, "solver not bound");
     int rc = check_path(path);
     if (rc) return rc;
     if (n < 0 || n >= path->n_steps) return fail(CPF_E_INVALID_ARG, "step %d outside the path", n);
-    return s->prec == CPF_PREC_FP64 ? step_impl<double>(s, path, n, outs) : step_impl<float>(s, path, n, outs);
+    return step_cut(s, path, n, outs, s->opt.cutback);
 }
 
 extern "C" int cpf_solver_step(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *out)
@@ -1751,6 +1836,7 @@ template <typename R>
 static int adjoint_impl(cpf_solver *s, const cpf_path *path, const double *target, const double *sbar, int C,
                         double adj_tol, unsigned char *aws, double *loss, double *grad, double *sig_out)
 {
+    TraceRange trace("cpf adjoint (forward with checkpoints, then reverse)");
     const AdjLayout L = adj_layout<R>(s, path, C);
     RveHost &h = s->rv[0];
     const long N = h.nvox;
@@ -1841,6 +1927,7 @@ static int adjoint_impl(cpf_solver *s, const cpf_path *path, const double *targe
                                          : P(L.seg) + (size_t)(n - n0 - 1) * slot;
         };
         for (int n = n1 - 1; n >= n0; --n) {
+            TraceRange step_trace("cpf adjoint load step");
             const unsigned char *sl = start_of(n);
             a.e0 = (const R *)sl;
             a.st0 = (const R *)(sl + fe);

@@ -1080,7 +1080,15 @@ __device__ __forceinline__ void rk_stage(const LawP<R> &P, const R e[6], R (&tep
     const R etaAtw = P.eta * Atw;
     const R inv_etaAtw = P.twin_mode ? fdiv(R(1), etaAtw) : P.inv_eta;
     // latent hardening per family (one product per family, not per system)
-    const R QLHs = P.fs.QL * Hs, QLHt = P.ft.QL * Ht;
+    // (kept as products: fused into every system's resistance they would
+    // cost a move of the scalar resistance and an FMA per system instead of
+    // one addition)
+    R QLHs, QLHt;
+    {
+#pragma clang fp contract(off)
+        QLHs = P.fs.QL * Hs;
+        QLHt = P.ft.QL * Ht;
+    }
     // overstress of every system, stored with the sign of the slip rate
     // (zero for inactive systems)
     uint32_t act = 0;

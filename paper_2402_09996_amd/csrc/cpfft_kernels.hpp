@@ -36,6 +36,7 @@ struct Scalars {
     double Sigma[6];    // mean stress of the last evaluated iterate
     double err_eq, err_bc, mean_sig_eq, mean_v, mean_f;
     double work_active, work_newton;   // law work counters summed over the step
+    unsigned long long n_symptom;      // voxels of the load step's local-stress test (k_symptom)
 };
 
 // Anderson acceleration of the fixed point (an option): the last AA_MAX
@@ -901,6 +902,7 @@ __global__ void k_begin_step(const RveDev<R> *__restrict__ rv, const StepInit *_
     sc->err_eq = sc->err_bc = 0.0;
     sc->mean_sig_eq = sc->mean_v = sc->mean_f = 0.0;
     sc->work_active = sc->work_newton = 0.0;
+    sc->n_symptom = 0ull;
     AaState *aa = rv[blockIdx.x].aa;
     if (aa) {
         aa->count = 0;
@@ -1328,6 +1330,49 @@ __global__ __launch_bounds__(256) void k_stress_field(const int32_t *labels, con
     voxel_stress<R>(labels, Qtab, eps, st, P, nvox, vox, sl);
 #pragma unroll
     for (int c = 0; c < 6; ++c) sig[c * nvox + vox] = sl[c];
+}
+
+// Voxels whose stress moved by more than E0 |dE| over the load step, the
+// situation in which the paper observes that the basic scheme stops
+// enforcing equilibrium locally (Section 4): |sigma_{n+1} - sigma_n|_F >
+// E0 |E_{n+1} - E_n|_F, Frobenius norms of tensor components, E0 the
+// Young's modulus of the reference medium, thr2 = (E0 |dE|_F)^2.  The
+// stress difference is Hooke's law of the difference of the elastic
+// strains, taken in the crystal frame (the norm does not depend on the
+// frame); the norm is summed in FP64.  Block counts are added with one
+// integer atomic per block (the total does not depend on the order).
+template <typename R>
+__global__ __launch_bounds__(256) void k_symptom(const int32_t *labels, const R *Qtab, const R *e1, const R *s1,
+                                                 const R *e0, const R *s0, LawP<R> P, long nvox, double thr2,
+                                                 unsigned long long *count)
+{
+    const long vox = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    int hit = 0;
+    if (vox < nvox) {
+        const int lab = labels[vox];
+        R Q[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) Q[i] = Qtab[lab * 9 + i];
+        R dl[6], dc[6], zero[6], sc[6];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) {
+            dl[c] = (e1[c * nvox + vox] - s1[c * nvox + vox]) - (e0[c * nvox + vox] - s0[c * nvox + vox]);
+            zero[c] = R(0);
+        }
+        rot_to_crystal(Q, dl, dc);
+        hooke(P, dc, zero, sc);
+        double n2 = 0.0;
+#pragma unroll
+        for (int c = 0; c < 6; ++c) n2 += (c < 3 ? 1.0 : 2.0) * (double)sc[c] * (double)sc[c];
+        hit = n2 > thr2;
+    }
+    __shared__ unsigned int block_count;
+    if (threadIdx.x == 0) block_count = 0u;
+    __syncthreads();
+    const int wc = __popcll(__ballot(hit));
+    if ((threadIdx.x & 63u) == 0u && wc) atomicAdd(&block_count, (unsigned int)wc);
+    __syncthreads();
+    if (threadIdx.x == 0 && block_count) atomicAdd(count, (unsigned long long)block_count);
 }
 
 // Square of the von Mises stress in FP64 by a fixed order of single,

@@ -1,0 +1,69 @@
+"""Failure handling on the device, through the C-ABI, against the oracle:
+the per-step count of Section 4's local-stress condition (FP64, count for
+count), a diverging load step reported as CPF_E_NAN, and the same step
+completed by cut-back into the oracle's half steps (FP64 to 1e-10 with the
+same iterations and retries)."""
+import numpy as np
+import pytest
+
+import oracle
+import rvegen
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+cp = pytest.importorskip("paper_2402_09996_amd")
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    cp._lib.lib()
+    yield
+
+
+def _relerr(a, b):
+    a, b = np.asarray(a, float), np.asarray(b, float)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.mark.parametrize("shape,steps,per_step", [((6, 8, 9), 4, 1e-3), ((8, 8, 8), 4, 1e-3), ((8, 8, 8), 3, 2e-3)])
+def test_symptom_counts_match_oracle(shape, steps, per_step):
+    print("case symptom", shape, steps, per_step, flush=True)
+    C, law = rvegen.config_law()
+    rve = rvegen.make_rve(shape, 5, 21, twin_share=0.5)
+    S = rvegen.config_systems(with_twins=True)
+    w = rvegen.Workload("s", rve, S, C, law, rvegen.uniaxial_path(per_step * steps, steps))
+    R = cp.Solver(cp.Problem.from_workload(w), precision="fp64", tol=1e-12).run(w.path)
+    ref = oracle.solver_for(w, oracle.Options(tol=1e-12)).run(w.path)
+    print("counts", R["n_symptom"], "oracle", ref.n_symptom, flush=True)
+    assert np.array_equal(R["n_symptom"], ref.n_symptom)
+    assert np.array_equal(R["cutbacks"], np.zeros(steps, np.int64))
+
+
+def _stiff_step_workload(strain=2e-3):
+    C, law = rvegen.config_law()
+    rve = rvegen.make_rve((4, 4, 4), 3, 4)
+    S = rvegen.config_systems(with_twins=False)
+    return rvegen.Workload("cb", rve, S, C, law, rvegen.uniaxial_path(strain, 1))
+
+
+def test_diverging_step_reported_then_cut_back_like_the_oracle():
+    w = _stiff_step_workload()
+    print("case cut-back 4^3", flush=True)
+    with pytest.raises(cp.CpfError) as e:
+        cp.Solver(cp.Problem.from_workload(w), precision="fp64", tol=1e-10, rk4_M=1).run(w.path)
+    assert e.value.code in (cp._lib.CPF_E_NAN, cp._lib.CPF_E_NOT_CONVERGED)
+    gs = cp.Solver(cp.Problem.from_workload(w), precision="fp64", tol=1e-10, rk4_M=1, cutback=6)
+    R = gs.run(w.path)
+    ref = oracle.solver_for(w, oracle.Options(tol=1e-10, M=1, cutback=6)).run(w.path, keep_fields=True)
+    print("cutbacks", R["cutbacks"], ref.cutbacks, "iters", R["iters"], ref.iters, flush=True)
+    assert R["cutbacks"][0] >= 1
+    assert np.array_equal(R["cutbacks"], ref.cutbacks)
+    assert np.array_equal(R["iters"], ref.iters)
+    assert np.array_equal(R["n_symptom"], ref.n_symptom)
+    assert _relerr(R["Sigma"], ref.Sigma) < 1e-10
+    for name in ("stress", "strain", "plastic_strain", "acc_slip"):
+        assert _relerr(gs.field(name).cpu().numpy(), ref.fields[name]) < 1e-10, name
+    with pytest.raises(cp.CpfError):
+        cp.Solver(cp.Problem.from_workload(w), precision="fp64", tol=1e-10, rk4_M=1, cutback=21)
