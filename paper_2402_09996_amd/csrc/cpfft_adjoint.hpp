@@ -242,7 +242,7 @@ __global__ __launch_bounds__(256, (xpass_min_blocks<R, SPEC>())) void k_law_reco
     const R h = a.dt / R(M), invM = R(1) / R(M);
     R de[6];
     uint32_t warm = 0;
-    law_fam_store(P, W);
+    law_fam_store<R, NS>(P, W);
 #pragma unroll
     for (int i = 0; i < 6; ++i) de[i] = e1[i] - e0[i];
     int nact = 0, nnewt = 0;

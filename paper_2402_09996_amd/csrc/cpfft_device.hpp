@@ -646,6 +646,19 @@ __device__ __forceinline__ float ex2(float x) { return __builtin_amdgcn_exp2f(x)
 __device__ __forceinline__ double ex2(double x) { return exp2(x); }
 __device__ __forceinline__ float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
 __device__ __forceinline__ double fdiv(double a, double b) { return a / b; }
+// Reciprocal for the Newton step, where the last ulp does not matter: the
+// hardware estimate refined by two Newton-Raphson steps in FP64 (error
+// below an ulp or two) instead of the correctly rounded division sequence;
+// in FP32 the hardware reciprocal as in fdiv.
+__device__ __forceinline__ float rcp_nr(float b) { return __builtin_amdgcn_rcpf(b); }
+__device__ __forceinline__ double rcp_nr(double b)
+{
+    double r = __builtin_amdgcn_rcp(b);
+    double e = fma(-b, r, 1.0);
+    r = fma(r, e, r);
+    e = fma(-b, r, 1.0);
+    return fma(r, e, r);
+}
 
 // y^p for an integer 0 <= p < 64 that is uniform across the wave: six
 // squarings with the multiplications selected by scalar branches.
@@ -901,6 +914,7 @@ struct LawLds {
     int ls;
     uint16_t *items;   // this wave's Newton items (law_items_q per lane)
     R *aw;             // this wave's twin rate prefactors, one per lane
+    R *tau0;           // [NS] initial resistances, one copy per block (FP64)
 };
 
 // The Newton solves of a stage are balanced over the lanes of a wave: the
@@ -968,7 +982,7 @@ constexpr int law_e_rows(int ns)
 template <typename R>
 constexpr size_t law_lds_bytes_ns(int ns)
 {
-    return ((2 * (size_t)ns + law_e_rows<R>(ns)) * 256 + 2 * LAW_FAM_WORDS) * sizeof(R);
+    return ((2 * (size_t)ns + law_e_rows<R>(ns)) * 256 + 2 * LAW_FAM_WORDS + ns) * sizeof(R);
 }
 template <typename R, int NS>
 constexpr size_t law_lds_bytes()
@@ -976,12 +990,26 @@ constexpr size_t law_lds_bytes()
     return law_lds_bytes_ns<R>(NS);
 }
 
-// Fill the block's family table.  Every lane of every wave writes the
-// same values before its own first read, so no barrier is needed: a read
-// sees either its own wave's write or an identical one.
+// Fill the block's family table and, in FP64, its table of initial
+// resistances (read from LDS by every system of every stage: held in scalar
+// registers next to the FP64 parameters, which take two each, they crowd
+// out the rest, which the compiler then parks in vector lanes and reads
+// back each stage; 1.7 % of the FP64 x pass, while the FP32 one is 4 %
+// faster with the resistances in scalar registers).  Every lane of every
+// wave writes the same values before its own first read, so no barrier is
+// needed: a read sees either its own wave's write or an identical one.
 template <typename R>
+constexpr bool law_tau0_lds()
+{
+    return sizeof(R) == 8;
+}
+template <typename R, int NS>
 __device__ __forceinline__ void law_fam_store(const LawP<R> &P, const LawLds<R> &W)
 {
+    if constexpr (law_tau0_lds<R>()) {
+#pragma unroll
+        for (int s = 0; s < NS; ++s) W.tau0[s] = P.tau0[s];
+    }
     const FamP<R> *F[2] = {&P.fs, &P.ft};
 #pragma unroll
     for (int f = 0; f < 2; ++f) {
@@ -1015,7 +1043,18 @@ __device__ __forceinline__ R newton_solve(R o, R A, R etaA, R inv_etaA, const R 
     const R yk = o * invK;
     R y = yw > R(0) ? (yw < yk ? yw : yk) : R(0);
     if (!(yw > R(0))) {
-        const R yc = ex2(lg2(o * inv_etaA) * inv_n);
+        R yc;
+        if constexpr (sizeof(R) == 8) {
+            // The start only has to lie above the root: the bound in FP32
+            // (hardware log2/exp2, relative error below 1e-6), raised by
+            // 1e-5, instead of the FP64 library sequences.  An FP32 overflow
+            // gives +inf (start at o/K), an underflow 0 (the first step goes
+            // to o/K); both are upper bounds.
+            const float q = (float)(o * inv_etaA);
+            yc = (double)ex2(lg2(q) * (float)inv_n) * (1.0 + 1e-5);
+        } else {
+            yc = ex2(lg2(o * inv_etaA) * inv_n);
+        }
         y = yk < yc ? yk : yc;
     }
     const R etaAn = etaA * n;
@@ -1024,7 +1063,7 @@ __device__ __forceinline__ R newton_solve(R o, R A, R etaA, R inv_etaA, const R 
         const R yn1 = pow_nm1(y, nm1, nm1_int);
         const R phi = K * y + etaA * yn1 * y - o;
         const R dphi = K + etaAn * yn1;
-        const R step = fdiv(phi, dphi);
+        const R step = phi * rcp_nr(dphi);
         y -= step;
         ++nnewt;
         if (fabs(step) <= P.newton_rtol * y) break;
@@ -1100,7 +1139,8 @@ __device__ __forceinline__ void rk_stage(const LawP<R> &P, const R e[6], R (&tep
         const bool tw = is_twin<SPEC>(P, s);
         const FamP<R> &F = tw ? P.ft : P.fs;
         const R hs = law_park_h<R>() ? W.o[s * W.ls] : h[s];
-        const R r = (P.tau0[s] + (tw ? QLHt : QLHs)) + F.QD * hs;
+        const R t0 = law_tau0_lds<R>() ? W.tau0[s] : P.tau0[s];
+        const R r = (t0 + (tw ? QLHt : QLHs)) + F.QD * hs;
         R tau = R(0);
         if constexpr (t1_factor<SPEC>()) {
             tau = t1_tau(s, t1);
@@ -1247,7 +1287,7 @@ __device__ void integrate(const LawP<R> &P, const R e0[6], const R e1[6], R (&ep
     uint32_t warm = 0;
 #pragma unroll
     for (int i = 0; i < 6; ++i) de[i] = e1[i] - e0[i];
-    law_fam_store(P, W);
+    law_fam_store<R, NS>(P, W);
     if constexpr (law_park_e<R, NS>()) {
         // the strain path lives in LDS through the integration
 #pragma unroll

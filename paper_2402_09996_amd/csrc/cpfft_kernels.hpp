@@ -332,7 +332,8 @@ __device__ __forceinline__ LawLds<R> law_lds(unsigned char *smem, size_t offset,
     unsigned char *iw = smem + items_offset + (t >> 6) * law_items_wave_bytes<R>();
     uint16_t *items = reinterpret_cast<uint16_t *>(iw);
     R *aw = reinterpret_cast<R *>(iw + 64 * law_items_q<R>() * 2);
-    return LawLds<R>{base + t, base + NS * BD + t, base + 2 * NS * BD + t, fam, BD, items, aw};
+    return LawLds<R>{base + t, base + NS * BD + t, base + 2 * NS * BD + t, fam, BD, items, aw,
+                     fam + 2 * LAW_FAM_WORDS};
 }
 
 // Bytes of the x pass FFT area in dynamic LDS: 3 complex lines of up to
@@ -551,6 +552,7 @@ struct GreenArgs {
     int nx, ny, nz;
     R inv_mu0;      // 1 / mu0
     R coef;         // (lam0 + mu0) / (mu0 (lam0 + 2 mu0))
+    R inv_nx, inv_ny, inv_nz;
 };
 
 // sin and cos of the half angle pi m / N of frequency m (exact 1 and 0 at
@@ -571,7 +573,9 @@ constexpr int GREEN_CONT = 0;       // continuous, zero at every frequency with 
 constexpr int GREEN_ROT = 1;        // rotated finite-difference scheme
 constexpr int GREEN_CONT_NYQ = 2;   // continuous, the formula also at Nyquist frequencies
 
-// Gamma0(x) : s for the unit direction x, into o; returns |s . x|^2.
+// Gamma0(x) : s for the unit direction x, into o; returns |s . x|^2 (summed
+// in R: in FP32 a frequency's six squares need no FP64, the block sums of
+// the residual are FP64 all the same).
 template <typename R>
 __device__ __forceinline__ double green_dir(const C2<R> (&s)[6], R x1, R x2, R x3, const GreenArgs<R> &g,
                                             C2<R> (&o)[6])
@@ -584,8 +588,11 @@ __device__ __forceinline__ double green_dir(const C2<R> (&s)[6], R x1, R x2, R x
     a2.y = s[5].y * x1 + s[1].y * x2 + s[3].y * x3;
     a3.x = s[4].x * x1 + s[3].x * x2 + s[2].x * x3;
     a3.y = s[4].y * x1 + s[3].y * x2 + s[2].y * x3;
-    const double t = (double)a1.x * a1.x + (double)a1.y * a1.y + (double)a2.x * a2.x +
-                     (double)a2.y * a2.y + (double)a3.x * a3.x + (double)a3.y * a3.y;
+    double t;
+    if constexpr (sizeof(R) == 4)
+        t = (double)(a1.x * a1.x + a1.y * a1.y + a2.x * a2.x + a2.y * a2.y + a3.x * a3.x + a3.y * a3.y);
+    else
+        t = a1.x * a1.x + a1.y * a1.y + a2.x * a2.x + a2.y * a2.y + a3.x * a3.x + a3.y * a3.y;
     const C2<R> b = {a1.x * x1 + a2.x * x2 + a3.x * x3, a1.y * x1 + a2.y * x2 + a3.y * x3};
     const R hm = R(0.5) * g.inv_mu0;
     const R xs[3] = {x1, x2, x3};
@@ -627,11 +634,17 @@ __device__ __forceinline__ void green_point(C2<R> (&s)[6], int kx, int ky, int k
         half_angle(my, g.ny, sy, cy);
         half_angle(mz, g.nz, sz, cz);
         x1 = sx * cy * cz; x2 = sy * cx * cz; x3 = sz * cx * cy;
-    } else {
+    } else if constexpr (sizeof(R) == 4) {
         // direction of (m_x/N_x, m_y/N_y, m_z/N_z), m_j = +N_j/2 at Nyquist
+        // (FP32: by the reciprocal sizes, normalized with the hardware
+        // reciprocal square root; the direction is good to a few ulps)
+        x1 = R(kx) * g.inv_nx; x2 = R(my) * g.inv_ny; x3 = R(mz) * g.inv_nz;
+    } else {
         x1 = R(kx) / R(g.nx); x2 = R(my) / R(g.ny); x3 = R(mz) / R(g.nz);
     }
-    const R inr = R(1) / sqrt(x1 * x1 + x2 * x2 + x3 * x3);
+    R inr;
+    if constexpr (sizeof(R) == 4) inr = __builtin_amdgcn_rsqf(x1 * x1 + x2 * x2 + x3 * x3);
+    else inr = R(1) / sqrt(x1 * x1 + x2 * x2 + x3 * x3);
     x1 *= inr; x2 *= inr; x3 *= inr;
     // Hermitian partner in the half spectrum (the kx = 0 and Nyquist columns
     // hold their own)
@@ -716,7 +729,7 @@ __global__ __launch_bounds__(Z_THREADS) void k_zpass_green(const RveDev<R> *__re
         }
         __syncthreads();
     }
-    const GreenArgs<R> g = {d.nx, d.ny, d.nz, inv_mu0, coef};
+    const GreenArgs<R> g = {d.nx, d.ny, d.nz, inv_mu0, coef, R(1) / R(d.nx), R(1) / R(d.ny), R(1) / R(d.nz)};
     double err2 = 0.0;
     for (int i = tid; i < tw_ * nz; i += nthr) {
         const int kz = (int)fdiv((unsigned)i, mt), col = i - kz * tw_;
@@ -821,7 +834,7 @@ __device__ __forceinline__ void zpass_fixed(const RveDev<R> &d, C2<R> *spec, C2<
         stage();
         __syncthreads();
     }
-    const GreenArgs<R> g = {d.nx, d.ny, d.nz, inv_mu0, coef};
+    const GreenArgs<R> g = {d.nx, d.ny, d.nz, inv_mu0, coef, R(1) / R(d.nx), R(1) / R(d.ny), R(1) / R(d.nz)};
     double err2 = 0.0;
     for (int i = threadIdx.x; i < TILE * N; i += FX_THREADS) {
         const int kz = i / TILE, col = i - kz * TILE;
