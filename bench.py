@@ -451,6 +451,26 @@ def eta_leg(cp, etas=(1e2, 1e3, 2e3, 5e3, 1e4, 3e4, 1e5, 3e5, 1e6)):
         k = int(np.argmax(ep >= 2e-4))
         a = (2e-4 - ep[k - 1]) / (ep[k] - ep[k - 1])
         out["yield_MPa"]["%g" % eta] = float(S11[k - 1] + a * (S11[k] - S11[k - 1]))
+    # the semi-quantitative check: ordinary system 3 at Schmid factor 1/2
+    # (every other system a larger tau0 / m) should start to slip at 2 tau0
+    # = 260 MPa; 100 steps of 0.005 % resolve the onset to 9 MPa
+    S = rvegen.table1_systems(True)
+    e = rvegen.schmid_half_orientation(S, 2)
+    half = {"bunge": [float(x) for x in e], "steps": 100, "onset_bracket_MPa": {}, "yield_MPa": {}}
+    for eta in (1e4, 1e5, 1e6):
+        C, law = rvegen.paper_law()
+        law.eta = eta
+        prob = cp.Problem(np.zeros((2, 2, 2), np.int32), np.array([e]), C, S.n_miller, S.l_miller, S.family,
+                          S.tau0, law)
+        R = cp.Solver(prob, precision="fp64", tol=1e-12, rk4_M=1).run(rvegen.uniaxial_path(0.005, 100))
+        E11, S11 = R["E"][:, 0], R["Sigma"][:, 0]
+        k = int(np.argmax(R["mean_v"] > 0))
+        half["onset_bracket_MPa"]["%g" % eta] = [float(S11[k - 1]), float(S11[k])]
+        ep = E11 - S11 / (S11[0] / E11[0])
+        j = int(np.argmax(ep >= 2e-4))
+        a = (2e-4 - ep[j - 1]) / (ep[j] - ep[j - 1])
+        half["yield_MPa"]["%g" % eta] = float(S11[j - 1] + a * (S11[j] - S11[j - 1]))
+    out["schmid_half"] = half
     return out
 
 

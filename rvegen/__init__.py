@@ -72,6 +72,22 @@ class SystemSet:
     tau0: np.ndarray       # [S] float64, MPa
 
 
+def schmid_half_orientation(systems: "SystemSet", index: int = 0) -> np.ndarray:
+    """Bunge angles of a crystal whose lab x-axis is the crystal direction
+    (n + l)/|n + l| of system `index` (plane normal n, direction l, unit
+    pseudo-cubic vectors): under uniaxial stress along x that system has
+    the largest possible Schmid factor, 1/2.  The lab y-axis is
+    (l - n)/|l - n|."""
+    n = np.asarray(systems.n_miller[index], dtype=np.float64)
+    l = np.asarray(systems.l_miller[index], dtype=np.float64)
+    n = n / np.linalg.norm(n)
+    l = l / np.linalg.norm(l)
+    a = (n + l) / np.linalg.norm(n + l)
+    b = (l - n) / np.linalg.norm(l - n)
+    Q = np.stack([a, b, np.cross(a, b)])      # rows: lab axes in the crystal frame
+    return matrix_to_bunge(Q)
+
+
 def table1_systems(with_twins: bool = True, tau0_o: float = 130.0,
                    tau0_s: float = 200.0, tau0_t: float = 130.0) -> SystemSet:
     """Systems of Table 1 with per-kind initial resistances (MPa).

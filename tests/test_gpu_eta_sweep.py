@@ -37,13 +37,30 @@ def yield_offset(E11, S11, offset=2e-4):
     return S11[k - 1] + a * (S11[k] - S11[k - 1])
 
 
-def _workload(eta):
+def _workload(eta, euler=(0.3, 0.7, 1.1), steps=20):
     C, law = rvegen.paper_law()
     law.eta = eta
     S = rvegen.table1_systems(True)
-    rve = rvegen.Microstructure(labels=np.zeros((2, 2, 2), np.int32), euler=np.array([[0.3, 0.7, 1.1]]),
+    rve = rvegen.Microstructure(labels=np.zeros((2, 2, 2), np.int32), euler=np.array([euler]),
                                 n_grains=1, twinned=np.zeros(0, np.int64), twin_fraction=np.zeros(0))
-    return rvegen.Workload("point", rve, S, C, law, rvegen.uniaxial_path(0.005, 20))
+    return rvegen.Workload("point", rve, S, C, law, rvegen.uniaxial_path(0.005, steps))
+
+
+@pytest.mark.parametrize("eta", [1e4, 1e5])
+def test_schmid_half_crystal_first_yields_at_twice_tau0(eta):
+    """The semi-quantitative check of Section 4's yield stresses: a crystal
+    whose ordinary system 3 has the Schmid factor 1/2 along the load (all
+    other systems lower ratios tau0/m) stays elastic up to 2 tau0 = 260 MPa
+    and is plastic right after, whatever eta; device against the oracle."""
+    S = rvegen.table1_systems(True)
+    w = _workload(eta, tuple(rvegen.schmid_half_orientation(S, 2)), steps=100)
+    R = cp.Solver(cp.Problem.from_workload(w), precision="fp64", tol=1e-12, rk4_M=1).run(w.path)
+    ref = oracle.solver_for(w, oracle.Options(tol=1e-12, M=1)).run(w.path)
+    assert np.abs(R["Sigma"] - ref.Sigma).max() <= 1e-9 * np.abs(ref.Sigma).max()
+    k = int(np.argmax(R["mean_v"] > 0))
+    print("eta", eta, "onset between", R["Sigma"][k - 1, 0], R["Sigma"][k, 0], flush=True)
+    assert k > 0 and R["Sigma"][k - 1, 0] <= 260.0 < R["Sigma"][k, 0]
+    assert k == int(np.argmax(ref.mean_v > 0))
 
 
 @pytest.mark.parametrize("eta", [5e3, 1e4, 1e5])

@@ -177,3 +177,30 @@ def test_section5_averages_from_a_hand_set_state():
     s2 = _tiny_solver(0.5)
     s2.y[:] = s.y
     assert s2.outputs()[3] == pytest.approx(0.04, rel=1e-14)        # 0.02 / 0.5
+
+
+def test_schmid_half_crystal_first_yields_at_twice_tau0():
+    """A single crystal oriented so that ordinary system 3 of Table 1 has the
+    Schmid factor 1/2 along the load axis (the largest possible) and every
+    other system a larger ratio tau0 / m: under uniaxial tension it is
+    elastic while sigma_xx <= 2 tau0 = 260 MPa and slips once above (the
+    resolved shear of equation 3 reaches the initial resistance), for any
+    eta.  The step that first shows slip brackets 260 MPa."""
+    C, law = rvegen.paper_law()
+    S = rvegen.table1_systems(True)
+    e = rvegen.schmid_half_orientation(S, 2)
+    Q = oracle.euler_to_rotation(e)[0]
+    mxx = oracle.lab_schmid(oracle.schmid_tensors(S.n_miller, S.l_miller), Q[None]).reshape(-1, 6)[:, 0]
+    assert mxx[2] == pytest.approx(0.5, abs=1e-14)
+    lim = [S.tau0[i] / abs(mxx[i]) if S.family[i] == 0 else (S.tau0[i] / mxx[i] if mxx[i] > 0 else np.inf)
+           for i in range(16) if mxx[i] != 0]
+    assert min(lim) == pytest.approx(260.0, rel=1e-14)
+    rve = rvegen.Microstructure(labels=np.zeros((2, 2, 2), np.int32), euler=np.array([e]), n_grains=1,
+                                twinned=np.zeros(0, np.int64), twin_fraction=np.zeros(0))
+    for eta in (1e4, 1e5):
+        law.eta = eta
+        w = rvegen.Workload("point", rve, S, C, law, rvegen.uniaxial_path(0.005, 100))
+        R = oracle.solver_for(w, oracle.Options(tol=1e-12, M=1)).run(w.path)
+        k = int(np.argmax(R.mean_v > 0))
+        assert k > 0 and R.Sigma[k - 1, 0] <= 260.0 < R.Sigma[k, 0], (eta, R.Sigma[k - 1:k + 1, 0])
+        assert np.all(R.mean_v[:k] == 0.0)
