@@ -43,7 +43,9 @@ extern "C" {
 #define CPF_E_WORKSPACE (-2)
 #define CPF_E_HIP (-3)
 #define CPF_E_NOT_CONVERGED (-4)
-#define CPF_E_NAN (-5)
+#define CPF_E_NAN (-5)          /* a non-finite stress or residual during the
+                                   step, or a non-finite component of the
+                                   converged strain or state (not committed) */
 #define CPF_E_UNSUPPORTED_SIZE (-6)
 #define CPF_E_BAD_STATE (-7)
 

@@ -1270,15 +1270,23 @@ static int step_impl(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *o
             const int a = h.cur, b = 1 - h.cur;
             unsigned long long *cnt =
                 (unsigned long long *)(s->ws + h.off_sc + offsetof(Scalars, n_symptom));
+            int *bad = (int *)(s->ws + h.off_sc + offsetof(Scalars, bad_state));
             hipLaunchKernelGGL(k_symptom<R>, dim3((h.nvox + 255) / 256), dim3(256), 0, s->stream,
                                dptr<int32_t>(s, h.off_labels), dptr<R>(s, h.off_Q), dptr<R>(s, h.off_eps[b]),
                                dptr<R>(s, h.off_st[b]), dptr<R>(s, h.off_eps[a]), dptr<R>(s, h.off_st[a]), P,
-                               h.nvox, E0 * E0 * d2, cnt);
+                               h.nvox, E0 * E0 * d2, s->D, cnt, bad);
             HIPCHK(hipGetLastError());
-            HIPCHK(hipMemcpyAsync(&s->hsc[r].n_symptom, cnt, sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                                  s->stream));
+            static_assert(offsetof(Scalars, bad_state) == offsetof(Scalars, n_symptom) + sizeof(unsigned long long),
+                          "the count and the flag are copied back together");
+            HIPCHK(hipMemcpyAsync(&s->hsc[r].n_symptom, cnt, sizeof(unsigned long long) + sizeof(int),
+                                  hipMemcpyDeviceToHost, s->stream));
         }
         HIPCHK(hipStreamSynchronize(s->stream));
+        for (size_t r = 0; r < nr; ++r)
+            if (s->hsc[r].bad_state) {
+                s->hsc[r].status = CPF_E_NAN;
+                all_ok = false;
+            }
     }
     int worst = CPF_OK, worst_r = -1;
     for (size_t r = 0; r < nr; ++r) {
@@ -1311,7 +1319,7 @@ static int step_impl(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *o
         }
     }
     if (worst == CPF_E_NAN)
-        return fail(CPF_E_NAN, "non-finite stress or residual in load step %d (RVE %d)", n, worst_r);
+        return fail(CPF_E_NAN, "non-finite stress, residual or state in load step %d (RVE %d)", n, worst_r);
     if (worst == CPF_E_NOT_CONVERGED)
         return fail(CPF_E_NOT_CONVERGED, "load step %d (RVE %d): no convergence in %d iterations (err %.3g)", n,
                     worst_r, s->hsc[worst_r].iter,

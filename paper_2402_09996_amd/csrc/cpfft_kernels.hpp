@@ -37,6 +37,7 @@ struct Scalars {
     double err_eq, err_bc, mean_sig_eq, mean_v, mean_f;
     double work_active, work_newton;   // law work counters summed over the step
     unsigned long long n_symptom;      // voxels of the load step's local-stress test (k_symptom)
+    int bad_state;                     // 1: a non-finite value in the converged strain or state
 };
 
 // Anderson acceleration of the fixed point (an option): the last AA_MAX
@@ -916,6 +917,7 @@ __global__ void k_begin_step(const RveDev<R> *__restrict__ rv, const StepInit *_
     sc->mean_sig_eq = sc->mean_v = sc->mean_f = 0.0;
     sc->work_active = sc->work_newton = 0.0;
     sc->n_symptom = 0ull;
+    sc->bad_state = 0;
     AaState *aa = rv[blockIdx.x].aa;
     if (aa) {
         aa->count = 0;
@@ -1353,14 +1355,24 @@ __global__ __launch_bounds__(256) void k_stress_field(const int32_t *labels, con
 // stress difference is Hooke's law of the difference of the elastic
 // strains, taken in the crystal frame (the norm does not depend on the
 // frame); the norm is summed in FP64.  Block counts are added with one
-// integer atomic per block (the total does not depend on the order).
+// integer atomic per block (the total does not depend on the order).  The
+// same pass checks every component of the converged strain and state for
+// non-finite values (a state variable of an inactive system never reaches
+// the stress, so the residual would not show it) and raises *bad.
 template <typename R>
 __global__ __launch_bounds__(256) void k_symptom(const int32_t *labels, const R *Qtab, const R *e1, const R *s1,
                                                  const R *e0, const R *s0, LawP<R> P, long nvox, double thr2,
-                                                 unsigned long long *count)
+                                                 int D, unsigned long long *count, int *bad)
 {
     const long vox = (long)blockIdx.x * blockDim.x + threadIdx.x;
     int hit = 0;
+    bool finite = true;
+    if (vox < nvox) {
+        for (int c = 0; c < D; ++c) finite = finite && isfinite(s1[c * nvox + vox]);
+#pragma unroll
+        for (int c = 0; c < 6; ++c) finite = finite && isfinite(e1[c * nvox + vox]);
+    }
+    if (__ballot(!finite) && (threadIdx.x & 63u) == 0u) atomicOr(bad, 1);
     if (vox < nvox) {
         const int lab = labels[vox];
         R Q[9];

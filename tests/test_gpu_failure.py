@@ -67,3 +67,30 @@ def test_diverging_step_reported_then_cut_back_like_the_oracle():
         assert _relerr(gs.field(name).cpu().numpy(), ref.fields[name]) < 1e-10, name
     with pytest.raises(cp.CpfError):
         cp.Solver(cp.Problem.from_workload(w), precision="fp64", tol=1e-10, rk4_M=1, cutback=21)
+
+
+def test_nan_injected_into_the_committed_state_is_reported():
+    """A non-finite value restored into the committed state makes the next
+    load step end with CPF_E_NAN, also where it never reaches the stress:
+    the end of the last state component (the back strain of the last twin
+    system, inactive in these voxels) and, separately, the start of the
+    plastic strain; the state saved before continues normally."""
+    C, law = rvegen.config_law()
+    rve = rvegen.make_rve((8, 8, 8), 4, 9, twin_share=0.5)
+    S = rvegen.config_systems(with_twins=True)
+    w = rvegen.Workload("nan", rve, S, C, law, rvegen.uniaxial_path(3e-3, 3))
+    s = cp.Solver(cp.Problem.from_workload(w), precision="fp64", tol=1e-10)
+    s.step(w.path, 0)
+    good = s.save_state().clone()
+    nv, D = 512, 6 + 2 * 16
+    start = good.numel() // 8 - D * nv           # the state section ends the buffer (no padding here)
+    for sl in (slice(-32, None), slice(start, start + 32)):
+        bad = good.clone()
+        bad.view(torch.float64)[sl] = float("nan")
+        s.restore_state(bad)
+        with pytest.raises(cp.CpfError) as e:
+            s.step(w.path, 1)
+        assert e.value.code == cp._lib.CPF_E_NAN
+    s.restore_state(good)
+    o = s.step(w.path, 1)
+    assert o["status"] == 0 and np.all(np.isfinite(o["Sigma"]))
