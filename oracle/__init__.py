@@ -98,6 +98,10 @@ def lib():
         L.orc_cp_update_j.restype = ctypes.c_int
         L.orc_cp_update_j.argtypes = [ctypes.POINTER(_Material), ctypes.c_long, ip, dp, dp, dp, dp, dp,
                                       ctypes.c_double, ctypes.c_int, ip]
+        L.orc_cp_update_lagged.restype = ctypes.c_int
+        L.orc_cp_update_lagged.argtypes = [ctypes.POINTER(_Material), ctypes.c_long,
+                                           ctypes.POINTER(ctypes.c_int), dp, dp, dp, dp, dp, dp,
+                                           ctypes.c_double, ctypes.c_int]
         L.orc_cp_update.restype = ctypes.c_int
         L.orc_cp_update.argtypes = [ctypes.POINTER(_Material), ctypes.c_long,
                                     ctypes.POINTER(ctypes.c_int), dp, dp, dp, dp, dp,
@@ -326,6 +330,26 @@ class Material:
             raise ValueError("orc_cp_update rejected its input")
         return y1, sig
 
+
+    def update_lagged(self, labels, eps0, eps1, y0, dr, dt, M):
+        """update() with the lagged regularization: dr [n][S] = eta |gdot| of
+        the previous load step raises each system's resistance, and the
+        rate is the plain Norton law."""
+        labels = np.ascontiguousarray(np.asarray(labels, dtype=np.int32).ravel())
+        n = labels.shape[0]
+        eps0 = np.ascontiguousarray(np.broadcast_to(eps0, (n, 6)), dtype=np.float64)
+        eps1 = np.ascontiguousarray(np.broadcast_to(eps1, (n, 6)), dtype=np.float64)
+        y0 = np.ascontiguousarray(y0, dtype=np.float64)
+        dr = np.ascontiguousarray(np.broadcast_to(dr, (n, self.n_sys)), dtype=np.float64)
+        y1 = np.empty_like(y0)
+        sig = np.empty((n, 6))
+        rc = lib().orc_cp_update_lagged(ctypes.byref(self._s), n,
+                                        labels.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
+                                        _dp(eps0), _dp(eps1), _dp(y0), _dp(dr), _dp(y1), _dp(sig),
+                                        float(dt), int(M))
+        if rc != 0:
+            raise ValueError("orc_cp_update_lagged rejected its input")
+        return y1, sig
 
     def _prep(self, labels, eps0, eps1, y0):
         labels = np.ascontiguousarray(np.asarray(labels, dtype=np.int32).ravel())
@@ -574,6 +598,7 @@ class Options:
     aa_depth: int = 0                 # > 0: Anderson-accelerated fixed point of that depth
     nyquist: str = "zero"             # continuous operator at Nyquist frequencies: 'zero' or 'formula'
     cutback: int = 0                  # > 0: a failed load step is retried as two half steps, recursively
+    reg: str = "implicit"             # 'implicit' (equation "regu" with the rate itself) or 'lagged'
 
 
 class NotConverged(RuntimeError):
@@ -613,6 +638,10 @@ class Solver:
         self.lam0, self.mu0 = lam0, mu0
         self.K0 = iso_stiffness(lam0, mu0)
         self.xi_hat, self.ctrl = green_directions(self.shape, self.opts.green, self.opts.nyquist)
+        if self.opts.reg not in ("implicit", "lagged"):
+            raise ValueError("reg must be 'implicit' or 'lagged'")
+        if self.opts.reg == "lagged" and (self.opts.rk_tol > 0 or self.opts.aa_depth > 0):
+            raise ValueError("the lagged regularization runs the basic fixed point with fixed substeps")
         self.slip = self.mat.family == 0
         self.twin = self.mat.family == 1
         self.reset()
@@ -624,6 +653,9 @@ class Solver:
         self.Sigma = np.zeros(6)             # committed mean stress (tensor)
         self.E = np.zeros(6)                 # committed mean strain (tensor)
         self.sig = np.zeros((n, 6))          # committed stress (Mandel)
+        # lagged regularization: eta |gdot| of the previous load step per
+        # point and system (zero before the first step)
+        self.dr = np.zeros((n, self.mat.n_sys))
 
     # -- pieces ------------------------------------------------------------
     def errors(self, sig_t: np.ndarray, Sigma: np.ndarray, sidx, target):
@@ -708,6 +740,8 @@ class Solver:
                                                          o.rk_tol, o.rk_max_doublings)
             elif o.rk_tol > 0:
                 y1, sig = self.mat.update_j(self.labels, self.eps, eps, self.y, dt, M, self.substep_j)
+            elif o.reg == "lagged":
+                y1, sig = self.mat.update_lagged(self.labels, self.eps, eps, self.y, self.dr, dt, M)
             else:
                 y1, sig = self.mat.update(self.labels, self.eps, eps, self.y, dt, M)
             sig_t = from_mandel(sig)
@@ -728,6 +762,10 @@ class Solver:
             raise NotConverged("no convergence in %d iterations" % o.max_iter)
         self.last_symptom = self.symptom_count(sig, E)
         self.last_errors = (err_eq, err_bc)
+        if o.reg == "lagged":
+            # the step's mean slip rates |gdot| = (v_{n+1} - v_n) / dt
+            S = self.mat.n_sys
+            self.dr = self.mat.law.eta * (y1[:, 6:6 + S] - self.y[:, 6:6 + S]) / dt
         self.eps, self.y, self.sig = eps, y1, sig
         self.Sigma, self.E = Sigma, E
         return k + 1, err_eq, err_bc
@@ -842,6 +880,8 @@ class Solver:
           then one reverse sweep of the local law with cotangents
           (sigma_bar_L - mu, S_bar) gives S_bar_n, eps_bar_n and theta_bar.
         """
+        if self.opts.reg != "implicit":
+            raise ValueError("the discrete adjoint differentiates the implicit regularization only")
         ns = path.target.shape[0] if n_steps is None else n_steps
         self.reset()
         rec = []

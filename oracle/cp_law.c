@@ -74,9 +74,13 @@ double orc_reg_rate(double o, double A, double K, double n, double eta)
     return A * pow(y, n);
 }
 
-/* Rate of the internal variables, dy/dt = F(eps, y), at total strain eps. */
-void orc_rate(const orc_material *mt, int lab, const double eps[6],
-              const double *y, double *dy)
+/* Rate of the internal variables, dy/dt = F(eps, y), at total strain eps.
+ * dr: NULL for the implicit regularization (the rate solves equation
+ * "regu" with the rate itself); otherwise the lagged reading: dr[s] =
+ * eta |gdot_s| of the previous load step raises the resistance of system s
+ * and the rate is the plain Norton law (eta = 0 in it). */
+static void rate_dr(const orc_material *mt, int lab, const double eps[6],
+                    const double *y, const double *dr, double *dy)
 {
     const int S = mt->n_sys;
     const double *C = mt->C_lab + 36 * (long)lab;
@@ -118,10 +122,13 @@ void orc_rate(const orc_material *mt, int lab, const double eps[6],
         for (int i = 0; i < 6; ++i)
             tau += sig[i] * m[6 * s + i];
         double x = mt->c[f] * al[s];
+        const double eta = dr ? 0.0 : mt->eta;
+        if (dr)
+            r += dr[s];
         if (f == ORC_FAM_SLIP) {
             /* equation 5, two-sided */
             double o = fabs(tau - x) - r;
-            double g = orc_reg_rate(o, 1.0, mt->K[f], mt->n[f], mt->eta);
+            double g = orc_reg_rate(o, 1.0, mt->K[f], mt->n[f], eta);
             gd[s] = (tau - x >= 0.0) ? g : -g;
         } else {
             /* equation 6, one-sided (twinning is unidirectional) */
@@ -129,7 +136,7 @@ void orc_rate(const orc_material *mt, int lab, const double eps[6],
             if (mt->twin_mode == ORC_TWIN_PAPER)
                 A = mt->gamma_T * mt->K_c * (mt->f_m - sum_f);
             double o = (tau - x) - r;
-            gd[s] = orc_reg_rate(o, A, mt->K[f], mt->n[f], mt->eta);
+            gd[s] = orc_reg_rate(o, A, mt->K[f], mt->n[f], eta);
         }
     }
 
@@ -149,14 +156,31 @@ void orc_rate(const orc_material *mt, int lab, const double eps[6],
     }
 }
 
+void orc_rate(const orc_material *mt, int lab, const double eps[6],
+              const double *y, double *dy)
+{
+    rate_dr(mt, lab, eps, y, NULL, dy);
+}
+
 /*
  * One load increment at one point: total strain moves linearly in time
  * from eps0 (start of the increment) to eps1 (end); the internal variables
  * are integrated with classical RK4 over M equal substeps of dt/M.
  * Returns the end state y1 and the end stress sig1 = C:(eps1 - eps_p).
  */
+static void integrate_dr(const orc_material *mt, int lab, const double eps0[6],
+                         const double eps1[6], const double *y0, const double *dr, double *y1,
+                         double sig1[6], double dt, int M);
+
 void orc_integrate_point(const orc_material *mt, int lab, const double eps0[6],
                          const double eps1[6], const double *y0, double *y1,
+                         double sig1[6], double dt, int M)
+{
+    integrate_dr(mt, lab, eps0, eps1, y0, NULL, y1, sig1, dt, M);
+}
+
+static void integrate_dr(const orc_material *mt, int lab, const double eps0[6],
+                         const double eps1[6], const double *y0, const double *dr, double *y1,
                          double sig1[6], double dt, int M)
 {
     const int S = mt->n_sys, D = 6 + 2 * S;
@@ -169,15 +193,15 @@ void orc_integrate_point(const orc_material *mt, int lab, const double eps0[6],
     for (int j = 0; j < M; ++j) {
         const double s0 = (double)j / M, sh = (j + 0.5) / M, s1 = (double)(j + 1) / M;
         for (int i = 0; i < 6; ++i) e[i] = eps0[i] + s0 * (eps1[i] - eps0[i]);
-        orc_rate(mt, lab, e, y, k1);
+        rate_dr(mt, lab, e, y, dr, k1);
         for (int i = 0; i < 6; ++i) e[i] = eps0[i] + sh * (eps1[i] - eps0[i]);
         for (int q = 0; q < D; ++q) tmp[q] = y[q] + 0.5 * h * k1[q];
-        orc_rate(mt, lab, e, tmp, k2);
+        rate_dr(mt, lab, e, tmp, dr, k2);
         for (int q = 0; q < D; ++q) tmp[q] = y[q] + 0.5 * h * k2[q];
-        orc_rate(mt, lab, e, tmp, k3);
+        rate_dr(mt, lab, e, tmp, dr, k3);
         for (int i = 0; i < 6; ++i) e[i] = eps0[i] + s1 * (eps1[i] - eps0[i]);
         for (int q = 0; q < D; ++q) tmp[q] = y[q] + h * k3[q];
-        orc_rate(mt, lab, e, tmp, k4);
+        rate_dr(mt, lab, e, tmp, dr, k4);
         for (int q = 0; q < D; ++q)
             y[q] += h / 6.0 * (k1[q] + 2.0 * k2[q] + 2.0 * k3[q] + k4[q]);
     }
@@ -279,6 +303,24 @@ int orc_cp_update(const orc_material *mt, long n_pts, const int *labels,
     for (long p = 0; p < n_pts; ++p)
         orc_integrate_point(mt, labels[p], eps0 + 6 * p, eps1 + 6 * p,
                             y0 + D * p, y1 + D * p, sig1 + 6 * p, dt, M);
+    return 0;
+}
+
+/* orc_cp_update with the lagged regularization: dr [n][S] per point. */
+int orc_cp_update_lagged(const orc_material *mt, long n_pts, const int *labels,
+                         const double *eps0, const double *eps1, const double *y0,
+                         const double *dr, double *y1, double *sig1, double dt, int M)
+{
+    if (mt->n_sys < 0 || mt->n_sys > ORC_MAXS || M < 1 || !dr)
+        return -1;
+    const int S = mt->n_sys, D = 6 + 2 * S;
+    for (long p = 0; p < n_pts; ++p)
+        if (labels[p] < 0 || labels[p] >= mt->n_labels)
+            return -1;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (long p = 0; p < n_pts; ++p)
+        integrate_dr(mt, labels[p], eps0 + 6 * p, eps1 + 6 * p, y0 + D * p, dr + (long)S * p,
+                     y1 + D * p, sig1 + 6 * p, dt, M);
     return 0;
 }
 
