@@ -116,7 +116,27 @@ typedef struct cpf_options {
                           CPF_E_NAN is retried as two half steps (times and
                           targets halved from the committed state of the
                           first RVE), recursively up to this many halvings */
+    int reg_mode;      /* CPF_REG_*: when eta |gdot| enters the resistance,
+                          below                                           */
 } cpf_options;
+
+/* Regularization of the yield stress (Section 4, equation "regu": the
+ * resistance is raised by eta |gdot|, instantaneously; Section 4 also
+ * remarks that without regularization elastoplastic and purely elastic
+ * steps alternate).
+ * CPF_REG_IMPLICIT (default): the rate solves gdot = A <(|tau - x| -
+ *   r - eta |gdot|)/K>^n for itself at every rate evaluation (a scalar
+ *   Newton solve per active system).
+ * CPF_REG_LAGGED: eta times each system's mean slip rate over the previous
+ *   load step, (v_n - v_{n-1}) eta / dt (zero in the first step after
+ *   creation or reset), raises the resistance for the whole step, and the
+ *   rate is the plain Norton law A <(|tau - x| - r - raise)/K>^n.  With
+ *   eta much larger than K the steps then alternate between no slip and
+ *   slip.  The raise [S][N] per RVE is part of the saved state and takes
+ *   S N words of workspace.  Needs rk_tol = 0 and aa_depth = 0; the adjoint
+ *   entry points and cpf_op_constitutive reject it. */
+#define CPF_REG_IMPLICIT 0
+#define CPF_REG_LAGGED 1
 
 /* Anderson acceleration of the fixed point (an option; the paper's scheme
  * is the basic one; Walker and Ni, 2011).  With aa_depth = m in 1..8, the
@@ -418,7 +438,8 @@ int cpf_seq_histogram_field(const void *dev_sig, int precision, long long nvox, 
                             unsigned long long *counts, void *hip_stream);
 
 /* Committed state of every RVE (strain, plastic strain, accumulated slip,
- * back strain, and the step's mean stress and strain), for checkpoints
+ * back strain, the step's mean stress and strain, and with CPF_REG_LAGGED
+ * the resistance raises of the next step), for checkpoints
  * and restarts along a path.  dev_buf: device memory of at least
  * cpf_state_size() bytes, 256-byte aligned, caller-owned.  Save copies the
  * committed state into it; restore makes it the committed state again (the

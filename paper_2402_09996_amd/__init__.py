@@ -145,10 +145,11 @@ def _outs_to_dict(outs, n):
 
 GREEN = {"continuous": 0, "rotated": 1}
 NYQUIST = {"zero": 0, "formula": 1}
+REG = {"implicit": 0, "lagged": 1}
 
 
 def _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_every, green="continuous",
-             rk_tol=0.0, aa_depth=0, nyquist="zero", cutback=0):
+             rk_tol=0.0, aa_depth=0, nyquist="zero", cutback=0, reg="implicit"):
     o = _lib.CpfOptions()
     _lib.lib().cpf_options_default(ctypes.byref(o))
     o.precision = CPF_PREC_FP64 if precision == "fp64" else CPF_PREC_FP32
@@ -165,6 +166,9 @@ def _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_
         raise ValueError("nyquist must be one of %s" % sorted(NYQUIST))
     o.nyquist_mode = NYQUIST[nyquist]
     o.cutback = int(cutback)
+    if reg not in REG:
+        raise ValueError("reg must be one of %s" % sorted(REG))
+    o.reg_mode = REG[reg]
     return o
 
 
@@ -180,7 +184,7 @@ class Solver:
                  stag_tol: float = 0.0, check_every: int = 0, device: str = "cuda:0",
                  stream=None, graph_iters: int = 0, autotune: bool = False,
                  green: str = "continuous", rk_tol: float = 0.0, aa_depth: int = 0,
-                 nyquist: str = "zero", cutback: int = 0):
+                 nyquist: str = "zero", cutback: int = 0, reg: str = "implicit"):
         import torch
         L = _lib.lib()
         probs = list(problem) if isinstance(problem, (list, tuple)) else [problem]
@@ -190,9 +194,10 @@ class Solver:
         self.precision = precision
         self.dtype = {"fp64": torch.float64, "fp32": torch.float32}[precision]
         o = _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_every, green, rk_tol,
-                     aa_depth, nyquist, cutback)
+                     aa_depth, nyquist, cutback, reg)
         self.green_operator = green
         self.nyquist = nyquist
+        self.reg = reg
         h = ctypes.c_void_p()
         arr = (ctypes.c_void_p * self.n_rve)(*[p._h.value for p in probs])
         check(L.cpf_batch_create(self.n_rve, arr, ctypes.byref(o), ctypes.byref(h)))

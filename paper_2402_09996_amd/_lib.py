@@ -32,6 +32,9 @@ CPF_FIELD_ACC_SLIP = 3
 CPF_FIELD_BACK_STRAIN = 4
 CPF_FIELD_SUBSTEPS = 5
 
+CPF_REG_IMPLICIT = 0
+CPF_REG_LAGGED = 1
+
 CPF_MAX_SYSTEMS = 32
 CPF_GRAPH_ADAPTIVE = -1
 
@@ -63,7 +66,7 @@ class CpfOptions(ctypes.Structure):
         ("precision", _i), ("tol", _d), ("max_iter", _i), ("h_max", _d),
         ("rk4_M", _i), ("lam0", _d), ("mu0", _d), ("stag_tol", _d),
         ("check_every", _i), ("green", _i), ("rk_tol", _d), ("aa_depth", _i),
-        ("nyquist_mode", _i), ("cutback", _i),
+        ("nyquist_mode", _i), ("cutback", _i), ("reg_mode", _i),
     ]
 
 

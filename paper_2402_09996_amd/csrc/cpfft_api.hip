@@ -103,6 +103,7 @@ extern "C" void cpf_options_default(cpf_options *o)
     o->aa_depth = 0;
     o->nyquist_mode = CPF_NYQUIST_ZERO;
     o->cutback = 0;
+    o->reg_mode = CPF_REG_IMPLICIT;
 }
 
 // ---------------------------------------------------------------------------
@@ -305,6 +306,7 @@ struct RveHost {
     bool tiles_fixed = false;   // set explicitly or by the autotuner
     size_t off_labels, off_Q, off_eps[2], off_st[2], off_spec, off_tw[3], off_px, off_pz, off_sc, off_mv;
     size_t off_pb;
+    size_t off_lag = 0;         // lagged regularization: raises [S][N]
     size_t off_aa = 0, off_aax = 0, off_aaf = 0, off_aadx = 0, off_aadf = 0, off_aap = 0, off_aac = 0;
     int cur = 0;
     double Sigma_n[6], E_n[6];
@@ -524,6 +526,7 @@ static void layout(cpf_solver *s)
         h.off_sc = take(sizeof(Scalars));
         h.off_mv = take(sizeof(int32_t) * h.nvox);
         h.off_pb = take(sizeof(double) * (NPX + 1) * BC_CHUNKS);
+        if (s->opt.reg_mode == CPF_REG_LAGGED) h.off_lag = take(sizeof(R) * (size_t)(s->D - 6) / 2 * h.nvox);
         if (s->opt.aa_depth > 0) {
             const size_t f6 = sizeof(R) * 6 * h.nvox;
             h.off_aa = take(sizeof(AaState));
@@ -582,6 +585,7 @@ static RveDev<R> make_dev(cpf_solver *s, const RveHost &h, int bx0, int by0, int
     d.aa_part = s->opt.aa_depth > 0 ? dptr<double>(s, h.off_aap) : nullptr;
     d.aa_chunk = s->opt.aa_depth > 0 ? dptr<double>(s, h.off_aac) : nullptr;
     d.sc = dptr<Scalars>(s, h.off_sc);
+    d.lag = s->opt.reg_mode == CPF_REG_LAGGED ? dptr<R>(s, h.off_lag) : nullptr;
     return d;
 }
 
@@ -691,6 +695,10 @@ extern "C" int cpf_batch_create(int n, const cpf_problem *const *probs, const cp
         return fail(CPF_E_INVALID_ARG, "aa_depth must be in [0, %d]", AA_MAX);
     if (o.aa_depth > 0 && o.rk_tol > 0.0)
         return fail(CPF_E_INVALID_ARG, "Anderson acceleration and error-controlled substeps are exclusive");
+    if (o.reg_mode != CPF_REG_IMPLICIT && o.reg_mode != CPF_REG_LAGGED)
+        return fail(CPF_E_INVALID_ARG, "unknown reg_mode %d", o.reg_mode);
+    if (o.reg_mode == CPF_REG_LAGGED && (o.rk_tol > 0.0 || o.aa_depth > 0))
+        return fail(CPF_E_INVALID_ARG, "the lagged regularization runs the basic fixed point with fixed substeps");
     cpf_solver *s = new (std::nothrow) cpf_solver();
     if (!s) return fail(CPF_E_INVALID_ARG, "out of host memory");
     const cpf_problem &p0 = *probs[0];
@@ -864,6 +872,9 @@ static int zero_state(cpf_solver *s)
             hipLaunchKernelGGL(k_fill<R>, dim3(512), dim3(256), 0, s->stream, dptr<R>(s, h.off_eps[b]), n6, R(0));
             hipLaunchKernelGGL(k_fill<R>, dim3(512), dim3(256), 0, s->stream, dptr<R>(s, h.off_st[b]), nD, R(0));
         }
+        if (s->opt.reg_mode == CPF_REG_LAGGED)
+            hipLaunchKernelGGL(k_fill<R>, dim3(512), dim3(256), 0, s->stream, dptr<R>(s, h.off_lag),
+                               (long)(s->D - 6) / 2 * h.nvox, R(0));
         h.cur = 0;
         for (int i = 0; i < 6; ++i) h.Sigma_n[i] = h.E_n[i] = 0.0;
         h.prev_iters = 8;
@@ -983,6 +994,9 @@ static void launch_xiter(cpf_solver *s, const LawP<R> &P)
     } else if (s->opt.aa_depth > 0) {
         hipLaunchKernelGGL((k_xpass_iter<R, NS, SPEC, false, true>), dim3(s->nbx_tot), dim3(256), s->lds_x,
                            s->stream, dptr<RveDev<R>>(s, s->off_dev), (int)s->rv.size(), P, 0.0, 0);
+    } else if (s->opt.reg_mode == CPF_REG_LAGGED) {
+        hipLaunchKernelGGL((k_xpass_iter<R, NS, SPEC, false, false, true>), dim3(s->nbx_tot), dim3(256),
+                           s->lds_x, s->stream, dptr<RveDev<R>>(s, s->off_dev), (int)s->rv.size(), P, 0.0, 0);
     } else {
         hipLaunchKernelGGL((k_xpass_iter<R, NS, SPEC, false>), dim3(s->nbx_tot), dim3(256), s->lds_x, s->stream,
                            dptr<RveDev<R>>(s, s->off_dev), (int)s->rv.size(), P, 0.0, 0);
@@ -1325,8 +1339,19 @@ static int step_impl(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *o
                     worst_r, s->hsc[worst_r].iter,
                     std::max(s->hsc[worst_r].err_eq, s->hsc[worst_r].err_bc));
     // commit: the iterate and the trial state become the committed ones
+    // (the lagged regularization first takes the raises of the next step
+    // from the slip of this one)
     for (size_t r = 0; r < nr; ++r) {
         RveHost &h = s->rv[r];
+        if (s->opt.reg_mode == CPF_REG_LAGGED) {
+            const int S = (s->D - 6) / 2;
+            const long n = (long)S * h.nvox;
+            const int nb = (int)std::min<long>(4096, std::max<long>(1, (n + 255) / 256));
+            hipLaunchKernelGGL(k_lag_update<R>, dim3(nb), dim3(256), 0, s->stream, dptr<R>(s, h.off_lag),
+                               dptr<R>(s, h.off_st[1 - h.cur]), dptr<R>(s, h.off_st[h.cur]), h.nvox, S,
+                               R(s->rv[r].pb.eta / dt));
+            HIPCHK(hipGetLastError());
+        }
         h.cur = 1 - h.cur;
         for (int i = 0; i < 6; ++i) { h.Sigma_n[i] = s->hsc[r].Sigma[i]; h.E_n[i] = s->hsc[r].E[i]; }
         h.prev_iters = s->hsc[r].iter;
@@ -1699,6 +1724,8 @@ extern "C" int cpf_op_constitutive(cpf_solver *s, const void *e0, const void *e1
     if (!s || !s->bound) return fail(CPF_E_BAD_STATE, "solver not bound");
     if (!e0 || !e1 || !s0 || !s1 || !sig) return fail(CPF_E_INVALID_ARG, "null device pointer");
     if (!(dt > 0) || M < 1) return fail(CPF_E_INVALID_ARG, "need dt > 0 and M >= 1");
+    if (s->opt.reg_mode != CPF_REG_IMPLICIT)
+        return fail(CPF_E_INVALID_ARG, "the component operator evaluates the implicit regularization only");
     return s->prec == CPF_PREC_FP64 ? op_cp_impl<double>(s, e0, e1, s0, s1, sig, dt, M)
                                     : op_cp_impl<float>(s, e0, e1, s0, s1, sig, dt, M);
 }
@@ -1751,6 +1778,8 @@ extern "C" int cpf_adjoint_workspace_size(const cpf_solver *s, const cpf_path *p
         return fail(CPF_E_INVALID_ARG, "the adjoint replays fixed substep counts: rk_tol must be 0");
     if (s->opt.aa_depth > 0)
         return fail(CPF_E_INVALID_ARG, "the adjoint runs the basic fixed point: aa_depth must be 0");
+    if (s->opt.reg_mode != CPF_REG_IMPLICIT)
+        return fail(CPF_E_INVALID_ARG, "the adjoint differentiates the implicit regularization only");
     int rc = check_path(path);
     if (rc) return rc;
     if (checkpoint_every < 1) return fail(CPF_E_INVALID_ARG, "checkpoint_every must be >= 1");
@@ -2173,7 +2202,13 @@ struct SavedHead {
 };
 
 // Buffer layout: one SavedHead per RVE, then per RVE the committed strain
-// [6][N] and state [D][N] in the solver's precision, 256-byte sections.
+// [6][N], state [D][N] and, with the lagged regularization, the raises
+// [S][N] of the next step, in the solver's precision, 256-byte sections.
+static size_t lag_words(const cpf_solver *s, const RveHost &h)
+{
+    return s->opt.reg_mode == CPF_REG_LAGGED ? (size_t)(s->D - 6) / 2 * h.nvox : 0;
+}
+
 static size_t state_layout(const cpf_solver *s, std::vector<size_t> *off)
 {
     const size_t rb = s->prec == CPF_PREC_FP64 ? 8 : 4;
@@ -2183,6 +2218,8 @@ static size_t state_layout(const cpf_solver *s, std::vector<size_t> *off)
         o = align256(o + rb * 6 * (size_t)h.nvox);
         if (off) off->push_back(o);
         o = align256(o + rb * (size_t)s->D * h.nvox);
+        if (off) off->push_back(o);
+        o = align256(o + rb * lag_words(s, h));
     }
     return o;
 }
@@ -2217,10 +2254,13 @@ extern "C" int cpf_state_save(cpf_solver *s, void *dev_buf)
         memcpy(head[r].E, h.E_n, sizeof h.E_n);
         head[r].prev_iters = h.prev_iters;
         head[r].pad = 0;
-        HIPCHK(hipMemcpyAsync(b + off[2 * r], s->ws + h.off_eps[h.cur], rb * 6 * h.nvox, hipMemcpyDeviceToDevice,
+        HIPCHK(hipMemcpyAsync(b + off[3 * r], s->ws + h.off_eps[h.cur], rb * 6 * h.nvox, hipMemcpyDeviceToDevice,
                               s->stream));
-        HIPCHK(hipMemcpyAsync(b + off[2 * r + 1], s->ws + h.off_st[h.cur], rb * s->D * h.nvox,
+        HIPCHK(hipMemcpyAsync(b + off[3 * r + 1], s->ws + h.off_st[h.cur], rb * s->D * h.nvox,
                               hipMemcpyDeviceToDevice, s->stream));
+        if (lag_words(s, h))
+            HIPCHK(hipMemcpyAsync(b + off[3 * r + 2], s->ws + h.off_lag, rb * lag_words(s, h),
+                                  hipMemcpyDeviceToDevice, s->stream));
     }
     HIPCHK(hipMemcpyAsync(b, head.data(), sizeof(SavedHead) * head.size(), hipMemcpyHostToDevice, s->stream));
     HIPCHK(hipStreamSynchronize(s->stream));
@@ -2247,10 +2287,13 @@ extern "C" int cpf_state_restore(cpf_solver *s, const void *dev_buf)
         memcpy(h.Sigma_n, head[r].Sigma, sizeof h.Sigma_n);
         memcpy(h.E_n, head[r].E, sizeof h.E_n);
         h.prev_iters = std::max(1, head[r].prev_iters);
-        HIPCHK(hipMemcpyAsync(s->ws + h.off_eps[h.cur], b + off[2 * r], rb * 6 * h.nvox, hipMemcpyDeviceToDevice,
+        HIPCHK(hipMemcpyAsync(s->ws + h.off_eps[h.cur], b + off[3 * r], rb * 6 * h.nvox, hipMemcpyDeviceToDevice,
                               s->stream));
-        HIPCHK(hipMemcpyAsync(s->ws + h.off_st[h.cur], b + off[2 * r + 1], rb * s->D * h.nvox,
+        HIPCHK(hipMemcpyAsync(s->ws + h.off_st[h.cur], b + off[3 * r + 1], rb * s->D * h.nvox,
                               hipMemcpyDeviceToDevice, s->stream));
+        if (lag_words(s, h))
+            HIPCHK(hipMemcpyAsync(s->ws + h.off_lag, b + off[3 * r + 2], rb * lag_words(s, h),
+                                  hipMemcpyDeviceToDevice, s->stream));
     }
     HIPCHK(hipStreamSynchronize(s->stream));
     return CPF_OK;

@@ -1085,11 +1085,23 @@ __device__ __forceinline__ R newton_solve(R o, R A, R etaA, R inv_etaA, const R 
 // loop.  Overstresses go to the thread's LDS column, rates and roots come
 // back through it; warm holds the systems whose root from the previous
 // stage is a valid warm start.
-template <typename R, int NS, int SPEC>
+//
+// Lagged regularization (LAG): instead of raising the resistance by eta
+// times the rate being solved for, each system's resistance is raised by
+// a fixed amount for the whole load step, lag.p[s lag.stride] for s <
+// n_sys (eta times the system's mean slip rate over the previous step),
+// and the rate is the plain Norton law A (o/K)^n: no Newton solve.
+template <typename R>
+struct LagRef {
+    const R *p;      // this voxel's raise of system 0
+    long stride;     // between systems
+};
+
+template <typename R, int NS, int SPEC, bool LAG = false>
 __device__ __forceinline__ void rk_stage(const LawP<R> &P, const R e[6], R (&tep)[6], R (&tv)[NS], R (&tal)[NS],
                                          const R (&yep)[6], const R (&yv)[NS], const R (&yal)[NS], R (&aep)[6],
                                          R (&av)[NS], R (&aal)[NS], uint32_t &warm, const LawLds<R> &W, R wacc,
-                                         R cnext, int &nact, int &nnewt)
+                                         R cnext, int &nact, int &nnewt, LagRef<R> lag = {nullptr, 0})
 {
     R ee[6], sig[6];
 #pragma unroll
@@ -1140,7 +1152,11 @@ __device__ __forceinline__ void rk_stage(const LawP<R> &P, const R e[6], R (&tep
         const FamP<R> &F = tw ? P.ft : P.fs;
         const R hs = law_park_h<R>() ? W.o[s * W.ls] : h[s];
         const R t0 = law_tau0_lds<R>() ? W.tau0[s] : P.tau0[s];
-        const R r = (t0 + (tw ? QLHt : QLHs)) + F.QD * hs;
+        R r = (t0 + (tw ? QLHt : QLHs)) + F.QD * hs;
+        if constexpr (LAG) {
+            // the raises cover the problem's systems only (NS rounds n_sys up)
+            if (s < P.nsys) r += lag.p[s * lag.stride];
+        }
         R tau = R(0);
         if constexpr (t1_factor<SPEC>()) {
             tau = t1_tau(s, t1);
@@ -1158,9 +1174,19 @@ __device__ __forceinline__ void rk_stage(const LawP<R> &P, const R e[6], R (&tep
         // an active slip system has |tx| > r >= 0, so the sign bit of tx is
         // the sign of the rate
         const R os = tw ? o : copysign(o, tx);
-        W.o[s * W.ls] = on ? os : R(0);
+        if constexpr (LAG) {
+            R g = R(0);
+            if (on) {
+                const R yk = o * F.invK;
+                g = A * yk * pow_nm1(yk, F.nm1, sizeof(R) == 8 ? F.nm1_int : -1);
+            }
+            W.o[s * W.ls] = tw ? g : copysign(g, tx);
+        } else {
+            W.o[s * W.ls] = on ? os : R(0);
+        }
     }
     nact += __popc(act);
+    if constexpr (!LAG) {
     // Newton solves: the first law_items_q active systems of each lane go to
     // the wave's item list, taken in turn by the wave's active lanes
     constexpr int Q = law_items_q<R>();
@@ -1241,6 +1267,7 @@ __device__ __forceinline__ void rk_stage(const LawP<R> &P, const R e[6], R (&tep
         }
     }
     warm = act;
+    }
     // rates of the internal variables (signed rates from the LDS column)
     R dep[6] = {R(0), R(0), R(0), R(0), R(0), R(0)};
     T1Acc<R> acc;
@@ -1277,9 +1304,10 @@ __device__ __forceinline__ void rk_stage(const LawP<R> &P, const R e[6], R (&tep
 // Integrate the internal variables over one load increment (crystal frame):
 // total strain linear in time from e0 to e1, M classical RK4 substeps.
 // W: LDS work area.
-template <typename R, int NS, int SPEC>
+template <typename R, int NS, int SPEC, bool LAG = false>
 __device__ void integrate(const LawP<R> &P, const R e0[6], const R e1[6], R (&ep)[6], R (&v)[NS],
-                          R (&al)[NS], R dt, int M, int &nact, int &nnewt, const LawLds<R> &W)
+                          R (&al)[NS], R dt, int M, int &nact, int &nnewt, const LawLds<R> &W,
+                          LagRef<R> lag = {nullptr, 0})
 {
     const R h = dt / R(M);
     const R invM = R(1) / R(M);
@@ -1322,7 +1350,8 @@ __device__ void integrate(const LawP<R> &P, const R e0[6], const R e1[6], R (&ep
 #pragma unroll
                 for (int i = 0; i < 6; ++i) e[i] = e0[i] + sfrac * de[i];
             }
-            rk_stage<R, NS, SPEC>(P, e, tep, tv, tal, ep, v, al, aep, av, aal, warm, W, wacc, cnext, nact, nnewt);
+            rk_stage<R, NS, SPEC, LAG>(P, e, tep, tv, tal, ep, v, al, aep, av, aal, warm, W, wacc, cnext, nact,
+                                       nnewt, lag);
         }
 #pragma unroll
         for (int i = 0; i < 6; ++i) ep[i] = aep[i];

@@ -90,6 +90,8 @@ struct RveDev {
     double *aa_part;           // [x blocks][2 AA_MAX] block dot products
     double *aa_chunk;          // [BC_CHUNKS][2 AA_MAX]
     Scalars *sc;
+    R *lag;                    // lagged regularization: [S][nvox] raise of each system's
+                               // resistance in the current load step (null: off)
 };
 
 // XCD-aware block order.  Consecutive workgroups of a launch are dealt
@@ -204,10 +206,11 @@ __device__ __forceinline__ void store_state(R *__restrict__ st, long nvox, long 
 // rotation and the output address are read again after the integration
 // (behind a compiler memory fence) instead of being held in registers
 // through it.
-template <typename R, int NS, int SPEC>
+template <typename R, int NS, int SPEC, bool LAG = false>
 __device__ __forceinline__ void voxel_law(const LawP<R> &P, const R *Qrow, const R e0l[6], const R e1l[6],
                                           const R *st_in, R *const *st_out, long nvox, long vox, R dt, int M,
-                                          R sigl[6], R (&v)[NS], int &nact, int &nnewt, const LawLds<R> &W)
+                                          R sigl[6], R (&v)[NS], int &nact, int &nnewt, const LawLds<R> &W,
+                                          LagRef<R> lag = {nullptr, 0})
 {
     R e0[6], e1[6], ep[6], al[NS];
     {
@@ -218,7 +221,7 @@ __device__ __forceinline__ void voxel_law(const LawP<R> &P, const R *Qrow, const
         rot_to_crystal(Q, e1l, e1);
         load_state<R, NS>(st_in, nvox, vox, P.nsys, Q, ep, v, al);
     }
-    integrate<R, NS, SPEC>(P, e0, e1, ep, v, al, dt, M, nact, nnewt, W);
+    integrate<R, NS, SPEC, LAG>(P, e0, e1, ep, v, al, dt, M, nact, nnewt, W, lag);
     asm volatile("" ::: "memory");
     R Q[9], sc[6];
 #pragma unroll
@@ -348,7 +351,8 @@ constexpr size_t xfft_lds_bytes()
 static_assert(law_items_bytes<float>() <= 3 * 256 * sizeof(C2<float>), "Newton items exceed the FFT lines");
 static_assert(law_items_bytes<double>() <= 3 * 256 * sizeof(C2<double>), "Newton items exceed the FFT lines");
 
-template <typename R, int NS, int SPEC, bool ADAPT = false, bool AAM = false>
+// LAG: the lagged regularization (d.lag holds the raises of the step).
+template <typename R, int NS, int SPEC, bool ADAPT = false, bool AAM = false, bool LAG = false>
 __global__ __launch_bounds__(256, (xpass_min_blocks<R, SPEC>())) void k_xpass_iter(
     const RveDev<R> *__restrict__ rv, int nrve, LawP<R> Parg, double rk_lim2, int rk_maxd)
 {
@@ -426,6 +430,11 @@ __global__ __launch_bounds__(256, (xpass_min_blocks<R, SPEC>())) void k_xpass_it
                 voxel_law<R, NS, SPEC>(P, d.Qtab + lab * 9, e0, e1, d.st[cur], &d.st[1 - cur], d.nvox, vox,
                                        R(sc->dt), sc->M << d.mv[vox], sig, v, nact, nnewt,
                                        law_lds<R, NS>(smem_raw, xfft_lds_bytes<R>(), 0));
+        } else if constexpr (LAG) {
+            voxel_law<R, NS, SPEC, true>(P, d.Qtab + lab * 9, e0, e1, d.st[cur], &d.st[1 - cur], d.nvox, vox,
+                                         R(sc->dt), sc->M, sig, v, nact, nnewt,
+                                         law_lds<R, NS>(smem_raw, xfft_lds_bytes<R>(), 0),
+                                         LagRef<R>{d.lag + vox, d.nvox});
         } else {
             voxel_law<R, NS, SPEC>(P, d.Qtab + lab * 9, e0, e1, d.st[cur], &d.st[1 - cur], d.nvox, vox,
                                    R(sc->dt), sc->M, sig, v, nact, nnewt,
@@ -1311,6 +1320,21 @@ __global__ __launch_bounds__(256, (xpass_min_blocks<R, SPEC>())) void k_constitu
                            law_lds<R, NS>(smem_raw, 0, law_lds_bytes<R, NS>()));
 #pragma unroll
     for (int c = 0; c < 6; ++c) sig[c * nvox + vox] = s[c];
+}
+
+// Lagged regularization, at the commit of a load step: the raise of each
+// system's resistance in the next step is eta times the system's mean slip
+// rate over this one, (v_{n+1} - v_n) eta / dt, with f = eta / dt.  The
+// slip rows of the state are contiguous ([6 + s][nvox]), so element i of
+// the raise array [S][nvox] pairs with element 6 nvox + i of the state.
+template <typename R>
+__global__ void k_lag_update(R *__restrict__ lag, const R *__restrict__ st_new, const R *__restrict__ st_old,
+                             long nvox, int nsys, R f)
+{
+    const long n = (long)nsys * nvox;
+    const R *vn = st_new + 6 * nvox, *vo = st_old + 6 * nvox;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        lag[i] = f * (vn[i] - vo[i]);
 }
 
 // sigma = C_lab : (eps - eps_p) at one voxel from a committed strain and

@@ -122,6 +122,45 @@ def test_solver_lifecycle_errors_before_binding():
     L.cpf_problem_destroy(p)
 
 
+def test_reg_mode_is_checked_and_sizes_its_raises():
+    """The lagged regularization: unknown modes and the combinations it does
+    not run with are rejected at creation; its raises [S][N] add S N words
+    of workspace and of saved state."""
+    L = _lib.lib()
+    d, keep = _desc()
+    rc, p = _create(d)
+    assert rc == 0
+    S, N = d.n_sys, 512
+
+    def make(**kw):
+        o = _lib.CpfOptions()
+        L.cpf_options_default(ctypes.byref(o))
+        assert o.reg_mode == _lib.CPF_REG_IMPLICIT
+        for k, v in kw.items():
+            setattr(o, k, v)
+        s = ctypes.c_void_p()
+        return L.cpf_solver_create(p, ctypes.byref(o), ctypes.byref(s)), s
+
+    E = _lib.CPF_E_INVALID_ARG
+    assert make(reg_mode=2)[0] == E
+    assert make(reg_mode=-1)[0] == E
+    assert make(reg_mode=_lib.CPF_REG_LAGGED, rk_tol=1e-6)[0] == E
+    assert make(reg_mode=_lib.CPF_REG_LAGGED, aa_depth=2)[0] == E
+    sizes = {}
+    for mode in (_lib.CPF_REG_IMPLICIT, _lib.CPF_REG_LAGGED):
+        rc, s = make(reg_mode=mode)
+        assert rc == 0
+        ws, st = ctypes.c_size_t(), ctypes.c_size_t()
+        assert L.cpf_solver_workspace_size(s, ctypes.byref(ws)) == 0
+        assert L.cpf_state_size(s, ctypes.byref(st)) == 0
+        sizes[mode] = (ws.value, st.value)
+        L.cpf_solver_destroy(s)
+    words = -(-S * N * 8 // 256) * 256          # FP64, one 256-byte aligned section
+    assert sizes[1][0] - sizes[0][0] == words
+    assert sizes[1][1] - sizes[0][1] == words
+    L.cpf_problem_destroy(p)
+
+
 def test_histogram_field_rejects_bad_arguments_on_the_host():
     """The allocation-free histogram checks its arguments before any device
     call (a fake device pointer is never touched)."""
