@@ -116,7 +116,7 @@ __device__ __forceinline__ void rate_vjp(const LawP<R> &P, const R e[6], const R
         // g = A y^n with K y + eta A y^n = o: partials of g in o, A, K, n
         R g = R(0), Go = R(0), GA = R(0), GK = R(0), Gn = R(0);
         if (y > R(0)) {
-            const R yn1 = pow_nm1(y, F.nm1, F.nm1_int), yn = yn1 * y;
+            const R yn1 = pow_nm1(y, F.nm1, F.nm1_int, -1), yn = yn1 * y;
             const R inv_D = R(1) / (F.K + P.eta * A * F.n * yn1);
             g = A * yn;
             Go = A * F.n * yn1 * inv_D;

@@ -860,6 +860,17 @@ static LawP<R> make_law(const cpf_solver *s)
     P.Kc_gT = R(p.Kc * p.gT); P.fm = R(p.fm); P.inv_gT = R(1.0 / p.gT);
     P.eta = R(p.eta); P.inv_eta = R(p.eta > 0 ? 1.0 / p.eta : 0.0);
     P.newton_rtol = sizeof(R) == 4 ? R(NEWTON_RTOL_F32) : R(NEWTON_RTOL_F64);
+    // one integer exponent n - 1 for every family that has systems (the
+    // Newton passes mix the families of different lanes)
+    bool has[2] = {false, false};
+    for (int sy = 0; sy < p.nsys; ++sy) has[p.fam[sy] ? 1 : 0] = true;
+    P.nm1_uni = -1;
+    for (int f = 0; f < 2; ++f) {
+        if (!has[f]) continue;
+        const int e = (f ? P.ft : P.fs).nm1_int;
+        if (e < 0 || (P.nm1_uni >= 0 && e != P.nm1_uni)) { P.nm1_uni = -1; break; }
+        P.nm1_uni = e;
+    }
     return P;
 }
 
