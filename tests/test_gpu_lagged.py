@@ -153,6 +153,19 @@ def test_lagged_state_restore_carries_the_raises_and_reset_clears_them():
     assert np.array_equal(a.field("acc_slip").cpu().numpy(), b.field("acc_slip").cpu().numpy())
 
 
+@pytest.mark.parametrize("graph_iters", [3, "adaptive"])
+def test_lagged_graph_replays_equal_direct_launches(graph_iters):
+    """The raises are written at commit, outside the captured iterations:
+    graph replays give the direct launches' results bit for bit."""
+    print("case lagged graphs", graph_iters, flush=True)
+    w = _wl(steps=5)
+    Rd = _solver(w, "fp32", tol=1e-6, stag_tol=1e-4).run(w.path)
+    Rg = _solver(w, "fp32", tol=1e-6, stag_tol=1e-4, graph_iters=graph_iters).run(w.path)
+    assert np.array_equal(Rd["iters"], Rg["iters"])
+    assert np.array_equal(Rd["Sigma"], Rg["Sigma"])
+    assert np.array_equal(Rd["mean_v"], Rg["mean_v"])
+
+
 def test_lagged_fp32_against_fp64_oracle():
     print("case lagged fp32", flush=True)
     w = _wl(steps=6)
