@@ -34,7 +34,7 @@ def _relerr(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def _wl(shape=(8, 8, 8), steps=6, eta=2e4, K=2000.0, n=2.0, mode=0, seed=21):
+def _wl(shape=(8, 8, 8), steps=6, eta=2e4, K=2000.0, n=2.0, mode=0, seed=21, per_step=1e-3):
     C, law = rvegen.config_law()
     law = dataclasses.replace(law, slip=dataclasses.replace(law.slip, K=K, n=n),
                               twin=dataclasses.replace(law.twin, K=K, n=n), eta=eta, twin_mode=mode)
@@ -42,7 +42,7 @@ def _wl(shape=(8, 8, 8), steps=6, eta=2e4, K=2000.0, n=2.0, mode=0, seed=21):
         law.K_c, law.f_m = 1.45, 0.8
     rve = rvegen.make_rve(shape, 5, seed, twin_share=0.5)
     S = rvegen.config_systems(with_twins=True)
-    return rvegen.Workload("lagged", rve, S, C, law, rvegen.uniaxial_path(1e-3 * steps, steps))
+    return rvegen.Workload("lagged", rve, S, C, law, rvegen.uniaxial_path(per_step * steps, steps))
 
 
 def _solver(w, precision="fp64", **kw):
@@ -164,6 +164,26 @@ def test_lagged_graph_replays_equal_direct_launches(graph_iters):
     assert np.array_equal(Rd["iters"], Rg["iters"])
     assert np.array_equal(Rd["Sigma"], Rg["Sigma"])
     assert np.array_equal(Rd["mean_v"], Rg["mean_v"])
+
+
+def test_lagged_cut_back_like_the_oracle():
+    """Load steps of 2e-3 with at most 40 iterations: every step is cut
+    back (2-3 failed attempts), and each committed half step sets the raises
+    of the next from its own slip and duration; retries, iterations and
+    fields as the oracle's."""
+    print("case lagged cut-back", flush=True)
+    w = _wl(steps=4, per_step=2e-3)
+    gs = _solver(w, tol=1e-10, max_iter=40, cutback=5)
+    R = gs.run(w.path)
+    ref = oracle.solver_for(w, oracle.Options(tol=1e-10, reg="lagged", max_iter=40, cutback=5)).run(
+        w.path, keep_fields=True)
+    print("cutbacks", R["cutbacks"], ref.cutbacks, "iters", R["iters"], ref.iters, flush=True)
+    assert np.all(ref.cutbacks >= 1)
+    assert np.array_equal(R["cutbacks"], ref.cutbacks)
+    assert np.array_equal(R["iters"], ref.iters)
+    assert _relerr(R["Sigma"], ref.Sigma) < 1e-10
+    for name in FIELDS:
+        assert _relerr(gs.field(name).cpu().numpy(), ref.fields[name]) < 1e-10, name
 
 
 def test_lagged_fp32_against_fp64_oracle():
