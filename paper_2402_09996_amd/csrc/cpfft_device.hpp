@@ -1070,7 +1070,12 @@ __device__ __forceinline__ R newton_solve(R o, R A, R etaA, R inv_etaA, const R 
     const int nm1_int = sizeof(R) == 8 ? (int)fam[5] : -1;
     const R yk = o * invK;
     R y = yw > R(0) ? (yw < yk ? yw : yk) : R(0);
-    if (!(yw > R(0))) {
+    // the cold start only when some lane of the pass has no warm start (a
+    // wave vote: most passes are warm after the first stage of a step; the
+    // empty asm keeps the block a branch instead of selects after an
+    // unconditional log2 and exp2)
+    if (__any(!(yw > R(0)))) {
+        asm volatile("");
         R yc;
         if constexpr (sizeof(R) == 8) {
             // The start only has to lie above the root: the bound in FP32
@@ -1083,7 +1088,7 @@ __device__ __forceinline__ R newton_solve(R o, R A, R etaA, R inv_etaA, const R 
         } else {
             yc = ex2(lg2(o * inv_etaA) * inv_n);
         }
-        y = yk < yc ? yk : yc;
+        if (!(yw > R(0))) y = yk < yc ? yk : yc;
     }
     const R etaAn = etaA * n;
 #pragma unroll 1
