@@ -446,7 +446,8 @@ int cpf_seq_histogram_field(const void *dev_sig, int precision, long long nvox, 
  * same solver, or one created from the same problems and options).  Both
  * synchronize the bound stream.  Errors: CPF_E_BAD_STATE if not bound,
  * CPF_E_WORKSPACE for a misaligned buffer, CPF_E_INVALID_ARG if restore
- * finds no saved state in the buffer. */
+ * finds no saved state in the buffer, or one saved under the other
+ * reg_mode (whose buffer has another size); it then copies nothing. */
 int cpf_state_size(const cpf_solver *s, size_t *bytes);
 int cpf_state_save(cpf_solver *s, void *dev_buf);
 int cpf_state_restore(cpf_solver *s, const void *dev_buf);

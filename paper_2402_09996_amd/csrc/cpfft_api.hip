@@ -2209,7 +2209,9 @@ extern "C" int cpf_seq_histogram_field(const void *dev_sig, int precision, long 
 // ---------------------------------------------------------------------------
 struct SavedHead {
     double Sigma[6], E[6];
-    int prev_iters, pad;
+    int prev_iters;
+    int reg_mode;   // the saving solver's regularization reading (the layout
+                    // of the sections that follow depends on it)
 };
 
 // Buffer layout: one SavedHead per RVE, then per RVE the committed strain
@@ -2264,7 +2266,7 @@ extern "C" int cpf_state_save(cpf_solver *s, void *dev_buf)
         memcpy(head[r].Sigma, h.Sigma_n, sizeof h.Sigma_n);
         memcpy(head[r].E, h.E_n, sizeof h.E_n);
         head[r].prev_iters = h.prev_iters;
-        head[r].pad = 0;
+        head[r].reg_mode = s->opt.reg_mode;
         HIPCHK(hipMemcpyAsync(b + off[3 * r], s->ws + h.off_eps[h.cur], rb * 6 * h.nvox, hipMemcpyDeviceToDevice,
                               s->stream));
         HIPCHK(hipMemcpyAsync(b + off[3 * r + 1], s->ws + h.off_st[h.cur], rb * s->D * h.nvox,
@@ -2291,8 +2293,10 @@ extern "C" int cpf_state_restore(cpf_solver *s, const void *dev_buf)
     HIPCHK(hipStreamSynchronize(s->stream));
     for (size_t r = 0; r < s->rv.size(); ++r)
         for (int i = 0; i < 6; ++i)
-            if (!std::isfinite(head[r].Sigma[i]) || !std::isfinite(head[r].E[i]) || head[r].pad != 0)
-                return fail(CPF_E_INVALID_ARG, "state buffer does not hold a saved state of this solver");
+            if (!std::isfinite(head[r].Sigma[i]) || !std::isfinite(head[r].E[i]) ||
+                head[r].reg_mode != s->opt.reg_mode)
+                return fail(CPF_E_INVALID_ARG, "state buffer does not hold a saved state of this solver "
+                                               "(or holds one of the other regularization reading)");
     for (size_t r = 0; r < s->rv.size(); ++r) {
         RveHost &h = s->rv[r];
         memcpy(h.Sigma_n, head[r].Sigma, sizeof h.Sigma_n);

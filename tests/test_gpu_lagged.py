@@ -186,6 +186,24 @@ def test_lagged_cut_back_like_the_oracle():
         assert _relerr(gs.field(name).cpu().numpy(), ref.fields[name]) < 1e-10, name
 
 
+def test_state_of_the_other_reading_is_rejected():
+    """A state saved under one regularization reading is rejected by a
+    solver of the other before anything is copied (the lagged state holds
+    one more section, so the buffers differ in size)."""
+    w = _wl(steps=2)
+    imp = cp.Solver(cp.Problem.from_workload(w), precision="fp64", tol=1e-12)
+    lag = _solver(w)
+    imp.step(w.path, 0)
+    lag.step(w.path, 0)
+    s_imp, s_lag = imp.save_state(), lag.save_state()
+    assert s_lag.numel() > s_imp.numel()
+    with pytest.raises(cp.CpfError):
+        lag.restore_state(s_imp)
+    with pytest.raises(cp.CpfError):
+        imp.restore_state(s_lag)
+    lag.restore_state(s_lag)          # its own state is accepted
+
+
 def test_lagged_fp32_against_fp64_oracle():
     print("case lagged fp32", flush=True)
     w = _wl(steps=6)
