@@ -33,6 +33,11 @@ the design notes of the repository):
   over controlled frequencies, err_bc = |P_S(Sigma - Sigma*)| / |Sigma|.
 * Local integration: total strain linear in time within a load step;
   RK4 with M = ceil(dt / h_max) equal substeps.
+* Regularization (equation "regu", Section 4): by default the resistance
+  is raised by eta times the rate being solved for.  Option reg='lagged':
+  by eta times each system's mean slip rate over the previous load step,
+  (v_n - v_{n-1}) / dt, with the plain Norton rate in the step (the reading
+  under which elastoplastic and purely elastic steps alternate).
 """
 from __future__ import annotations
 
