@@ -4,6 +4,7 @@ FP64 mode must match the FP64 oracle to 1e-10 relative (effective and
 local responses); FP32 mode to 1e-4 on effective stress and 1e-3 relative
 L2 on local fields.  Component operators are compared on identical inputs.
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -161,6 +162,22 @@ def _assert_fields(gs, ref, tol):
             assert np.abs(g).max() == 0
             continue
         assert _relerr(g, r) < tol, name
+
+
+@pytest.mark.parametrize("n_twin", [6.0, 7.5])
+def test_family_exponents_that_differ_fp64_parity(n_twin):
+    """Slip n = 10 with twin n = 6 (both integers) or 7.5: the Newton passes
+    mix the families across lanes, so y^(n-1) takes each lane's own
+    exponent (per-lane products, or exp2/log2 for the non-integer one)
+    instead of the wave-uniform products of a shared integer n."""
+    print("case n_twin", n_twin, flush=True)
+    C, law = rvegen.config_law()
+    law = dataclasses.replace(law, twin=dataclasses.replace(law.twin, n=n_twin))
+    w = _wl((8, 8, 8), 4, 33, twins=True, steps=5, law=law)
+    gs, R, ref = _compare_solves(w)
+    assert ref.mean_v[-1] > 0 and ref.mean_f[-1] > 0
+    _assert_effective(R, ref, 1e-10)
+    _assert_fields(gs, ref, 1e-10)
 
 
 def test_workload0_fp64_parity():
