@@ -1031,10 +1031,12 @@ static void launch_xiter_any(cpf_solver *s, const LawP<R> &P)
 }
 
 // table/nrve/grid default to the whole batch; the component operators and
-// the autotuner pass a one-RVE table and an explicit spectrum
+// the autotuner pass a one-RVE table and an explicit spectrum.  nbc > 0:
+// the fixed-length kernel's launch also runs the first stage of the scalar
+// reduction in nbc leading blocks (the caller then skips k_bc_partials).
 template <typename R>
 static void launch_y(cpf_solver *s, bool inv, const RveDev<R> *table = nullptr, int nrve = 0, int grid = 0,
-                     size_t lds = 0, C2<R> *spec = nullptr, int elems = 0, int kinds = 0)
+                     size_t lds = 0, C2<R> *spec = nullptr, int elems = 0, int kinds = 0, int nbc = 0)
 {
     if (!table) {
         table = dptr<RveDev<R>>(s, s->off_dev);
@@ -1046,10 +1048,11 @@ static void launch_y(cpf_solver *s, bool inv, const RveDev<R> *table = nullptr, 
     }
     if (kinds & 1) {
         if (inv)
-            hipLaunchKernelGGL((k_ypass_fx<R, true>), dim3(grid), dim3(FX_THREADS), lds, s->stream, table, nrve, spec);
+            hipLaunchKernelGGL((k_ypass_fx<R, true>), dim3(grid + nbc), dim3(FX_THREADS), lds, s->stream, table, nrve,
+                               spec, nbc);
         else
-            hipLaunchKernelGGL((k_ypass_fx<R, false>), dim3(grid), dim3(FX_THREADS), lds, s->stream, table, nrve,
-                               spec);
+            hipLaunchKernelGGL((k_ypass_fx<R, false>), dim3(grid + nbc), dim3(FX_THREADS), lds, s->stream, table, nrve,
+                               spec, nbc);
     }
     if (!(kinds & 2)) return;
     // registers for fewer elements per thread when the tiles allow it
@@ -1105,7 +1108,7 @@ static void launch_z(cpf_solver *s, int mode, const RveDev<R> *table = nullptr, 
 }
 
 template <typename R>
-static void launch_bc(cpf_solver *s)
+static void launch_bc(cpf_solver *s, bool partials_done = false)
 {
     BcArgs b;
     b.n_slip = s->n_slip;
@@ -1116,8 +1119,9 @@ static void launch_bc(cpf_solver *s)
     // two stages: BC_CHUNKS blocks per RVE sum fixed chunks of the block
     // partials (a 128^3 x pass leaves 8192 x 11 doubles), one wave per RVE
     // sums the chunks and updates the scalars
-    hipLaunchKernelGGL(k_bc_partials<R>, dim3(s->rv.size() * BC_CHUNKS), dim3(256), 0, s->stream,
-                       dptr<RveDev<R>>(s, s->off_dev));
+    if (!partials_done)
+        hipLaunchKernelGGL(k_bc_partials<R>, dim3(s->rv.size() * BC_CHUNKS), dim3(256), 0, s->stream,
+                           dptr<RveDev<R>>(s, s->off_dev));
     hipLaunchKernelGGL(k_bc_update<R>, dim3(s->rv.size()), dim3(64), 0, s->stream,
                        dptr<RveDev<R>>(s, s->off_dev), b);
 }
@@ -1137,8 +1141,12 @@ static int launch_iteration(cpf_solver *s, const LawP<R> &P)
     { TraceRange t("cpf x pass (law, x transforms)"); TIMED(s, 0, launch_xiter_any<R>(s, P)); }
     { TraceRange t("cpf y pass"); TIMED(s, 1, launch_y<R>(s, false)); }
     { TraceRange t("cpf z pass (Green operator)"); TIMED(s, 2, launch_z<R>(s, ZMODE_FWD | ZMODE_GREEN)); }
-    { TraceRange t("cpf y pass (inverse)"); TIMED(s, 3, launch_y<R>(s, true)); }
-    { TraceRange t("cpf boundary update"); TIMED(s, 4, launch_bc<R>(s)); }
+    // the first stage of the scalar reduction rides in the inverse y pass's
+    // launch when the fixed-length kernel runs it (one launch less per
+    // iteration)
+    const int nbc = (s->y_kinds & 1) ? (int)s->rv.size() * BC_CHUNKS : 0;
+    { TraceRange t("cpf y pass (inverse)"); TIMED(s, 3, launch_y<R>(s, true, nullptr, 0, 0, 0, nullptr, 0, 0, nbc)); }
+    { TraceRange t("cpf boundary update"); TIMED(s, 4, launch_bc<R>(s, nbc > 0)); }
     return CPF_OK;
 }
 

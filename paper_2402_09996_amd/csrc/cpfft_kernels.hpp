@@ -758,6 +758,33 @@ __global__ __launch_bounds__(Z_THREADS) void k_zpass_green(const RveDev<R> *__re
 }
 
 // ---------------------------------------------------------------------------
+// First stage of the scalar reduction: BC_CHUNKS blocks per RVE each sum a
+// fixed contiguous chunk of the x-pass block sums (NPX values each) and of
+// the z-pass residual sums, in a fixed order; b = RVE * BC_CHUNKS + chunk.
+// 256 threads.
+// ---------------------------------------------------------------------------
+constexpr int BC_CHUNKS = 32;
+
+template <typename R>
+__device__ __forceinline__ void bc_partials_block(const RveDev<R> *__restrict__ rv, int b)
+{
+    const RveDev<R> &d = rv[b / BC_CHUNKS];
+    const int c = b % BC_CHUNKS;
+    if (d.sc->done) return;
+    const int nbx = (d.nlines + d.L - 1) / d.L, nbz = d.ntz * d.ny;
+    const int x0 = (int)((long)nbx * c / BC_CHUNKS), x1 = (int)((long)nbx * (c + 1) / BC_CHUNKS);
+    const int z0 = (int)((long)nbz * c / BC_CHUNKS), z1 = (int)((long)nbz * (c + 1) / BC_CHUNKS);
+    double acc[NPX + 1];
+#pragma unroll
+    for (int i = 0; i < NPX + 1; ++i) acc[i] = 0.0;
+    for (int j = x0 + threadIdx.x; j < x1; j += blockDim.x)
+#pragma unroll
+        for (int i = 0; i < NPX; ++i) acc[i] += d.part_x[(long)j * NPX + i];
+    for (int j = z0 + threadIdx.x; j < z1; j += blockDim.x) acc[NPX] += d.part_z[j];
+    block_sum<NPX + 1, 4>(acc, d.part_b + (long)c * (NPX + 1));
+}
+
+// ---------------------------------------------------------------------------
 // Fixed-length y and z passes: the common lengths (fixed_len) with their
 // radix plans and the tile width known at compile time (fixed_tile columns
 // of 6 components), 256 threads.  The same transforms as k_ypass and
@@ -793,10 +820,19 @@ __device__ __forceinline__ void ypass_fixed(const RveDev<R> &d, C2<R> *g, C2<R> 
     fixed_fft<R, INV, N, NL, FX_THREADS, true, true>(buf, nlv, twl, gline, 6L * d.nhp, stage);
 }
 
+// nbc > 0 (a multiple of 8, so that the XCD of each transform block is
+// unchanged): the first nbc blocks of the launch are the first stage of the
+// scalar reduction (bc_partials_block) instead of a launch of their own;
+// the x and z passes that wrote its inputs ran before.
 template <typename R, bool INV>
-__global__ __launch_bounds__(FX_THREADS) void k_ypass_fx(const RveDev<R> *__restrict__ rv, int nrve, C2<R> *spec_override)
+__global__ __launch_bounds__(FX_THREADS) void k_ypass_fx(const RveDev<R> *__restrict__ rv, int nrve, C2<R> *spec_override,
+                                                  int nbc)
 {
-    const int blk = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    if ((int)blockIdx.x < nbc) {
+        bc_partials_block<R>(rv, (int)blockIdx.x);
+        return;
+    }
+    const int blk = xcd_block((int)blockIdx.x - nbc, (int)gridDim.x - nbc);
     const int r = find_rve(rv, nrve, blk, 1);
     const RveDev<R> &d = rv[r];
     if ((!spec_override && d.sc->done) || !d.yfix) return;
@@ -1196,28 +1232,13 @@ __global__ __launch_bounds__(256) void k_aa_update(const RveDev<R> *__restrict__
     for (int c = 0; c < 6; ++c) eps_k[c * d.nvox + vox] = e[c];
 }
 
-// First stage of the scalar reduction: BC_CHUNKS blocks per RVE each sum a
-// fixed contiguous chunk of the x-pass block sums (NPX values each) and of
-// the z-pass residual sums, in a fixed order.
-constexpr int BC_CHUNKS = 32;
-
+// First stage of the scalar reduction as its own launch (the iteration runs
+// it inside the inverse y pass's launch where that pass is the fixed-length
+// kernel).
 template <typename R>
 __global__ __launch_bounds__(256) void k_bc_partials(const RveDev<R> *__restrict__ rv)
 {
-    const RveDev<R> &d = rv[blockIdx.x / BC_CHUNKS];
-    const int c = blockIdx.x % BC_CHUNKS;
-    if (d.sc->done) return;
-    const int nbx = (d.nlines + d.L - 1) / d.L, nbz = d.ntz * d.ny;
-    const int x0 = (int)((long)nbx * c / BC_CHUNKS), x1 = (int)((long)nbx * (c + 1) / BC_CHUNKS);
-    const int z0 = (int)((long)nbz * c / BC_CHUNKS), z1 = (int)((long)nbz * (c + 1) / BC_CHUNKS);
-    double acc[NPX + 1];
-#pragma unroll
-    for (int i = 0; i < NPX + 1; ++i) acc[i] = 0.0;
-    for (int j = x0 + threadIdx.x; j < x1; j += blockDim.x)
-#pragma unroll
-        for (int i = 0; i < NPX; ++i) acc[i] += d.part_x[(long)j * NPX + i];
-    for (int j = z0 + threadIdx.x; j < z1; j += blockDim.x) acc[NPX] += d.part_z[j];
-    block_sum<NPX + 1, 4>(acc, d.part_b + (long)c * (NPX + 1));
+    bc_partials_block<R>(rv, (int)blockIdx.x);
 }
 
 // One block per RVE: sum the chunk sums (fixed order), evaluate the
