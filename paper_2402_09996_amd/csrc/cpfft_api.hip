@@ -618,6 +618,9 @@ static bool table1_specializable(const cpf_problem &p)
         if (p.fam[s] != (s < 12 ? 0 : 1)) return false;
         for (int i = 0; i < 6; ++i)
             if (fabs(p.m[6 * s + i] - T1_M[s][i]) > 1e-12) return false;
+        // one initial resistance per kind (the first system of each kind)
+        for (int q = 0; q < s; ++q)
+            if (T1_KIND[q] == T1_KIND[s] && p.tau0[q] != p.tau0[s]) return false;
     }
     for (int i = 0; i < 6; ++i)
         for (int j = 0; j < 6; ++j) {
@@ -859,6 +862,11 @@ static LawP<R> make_law(const cpf_solver *s)
     }
     P.Kc_gT = R(p.Kc * p.gT); P.fm = R(p.fm); P.inv_gT = R(1.0 / p.gT);
     P.eta = R(p.eta); P.inv_eta = R(p.eta > 0 ? 1.0 / p.eta : 0.0);
+    // per-kind resistances of the Table 1 specialization (kinds absent from
+    // the problem never activate)
+    for (int k = 0; k < 3; ++k) P.tau0k[k] = R(1e30);
+    if (s->law_spec == LAW_TABLE1)
+        for (int sy = p.nsys - 1; sy >= 0; --sy) P.tau0k[T1_KIND[sy]] = R(p.tau0[sy]);
     P.newton_rtol = sizeof(R) == 4 ? R(NEWTON_RTOL_F32) : R(NEWTON_RTOL_F64);
     // one integer exponent n - 1 for every family that has systems (the
     // Newton passes mix the families of different lanes)

@@ -637,6 +637,8 @@ struct LawP {
     R newton_rtol;
     int nm1_uni;          // n - 1 when every family present has the same integer
                           // n in [1, 64] (a wave-uniform exponent), else -1
+    R tau0k[3];           // FP32 LAW_TABLE1: initial resistance per kind of
+                          // Table 1 system (ordinary, superdislocation, twin)
 };
 
 // Math in the working precision.  FP32 uses the hardware transcendental
@@ -738,11 +740,19 @@ constexpr double T1_M[16][6] = {
      -0.11785113019775795, 0.23570226039551589},
 };
 
+// Kind of each Table 1 system: 0 ordinary dislocation, 1 superdislocation,
+// 2 twin (the table's last column).  The FP32 Table 1 specialization takes
+// one initial resistance per kind (LawP::tau0k): three scalar registers in
+// place of sixteen, which otherwise are spilled to vector lanes and read
+// back at every RK stage (FP64 reads its resistances from LDS).
+constexpr int T1_KIND[16] = {1, 1, 0, 1, 1, 0, 1, 1, 0, 1, 1, 0, 2, 2, 2, 2};
+
 // Kernel specializations of the law:
 //   LAW_GENERAL : any systems (Schmid tensors and stiffness from the arguments)
 //   LAW_TABLE1  : the Table 1 systems in order (12 slip, optionally + 4 twin)
-//                 and a crystal stiffness with orthotropic zero pattern
-//                 (cubic, tetragonal): compile-time Schmid tensors, 12-term Hooke
+//                 with one initial resistance per kind of system, and a
+//                 crystal stiffness with orthotropic zero pattern (cubic,
+//                 tetragonal): compile-time Schmid tensors, 12-term Hooke
 constexpr int LAW_GENERAL = 0;
 constexpr int LAW_TABLE1 = 1;
 
@@ -1184,7 +1194,10 @@ __device__ __forceinline__ void rk_stage(const LawP<R> &P, const R e[6], R (&tep
         const bool tw = is_twin<SPEC>(P, s);
         const FamP<R> &F = tw ? P.ft : P.fs;
         const R hs = law_park_h<R>() ? W.o[s * W.ls] : h[s];
-        const R t0 = law_tau0_lds<R>() ? W.tau0[s] : P.tau0[s];
+        R t0;
+        if constexpr (law_tau0_lds<R>()) t0 = W.tau0[s];
+        else if constexpr (SPEC == LAW_TABLE1) t0 = P.tau0k[T1_KIND[s]];
+        else t0 = P.tau0[s];
         R r = (t0 + (tw ? QLHt : QLHs)) + F.QD * hs;
         if constexpr (LAG) {
             // the raises cover the problem's systems only (NS rounds n_sys up)

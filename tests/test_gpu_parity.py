@@ -180,6 +180,25 @@ def test_family_exponents_that_differ_fp64_parity(n_twin):
     _assert_fields(gs, ref, 1e-10)
 
 
+def test_table1_systems_with_resistances_that_vary_within_a_kind():
+    """The Table 1 systems with one resistance per kind (ordinary,
+    superdislocation, twin) run the Table 1 specialization; with two
+    superdislocation systems of different resistance they run the general
+    law.  Both match the oracle to 1e-10."""
+    C, law = rvegen.config_law()
+    for t0 in (None, 185.0):
+        S = rvegen.table1_systems(True, tau0_o=90.0, tau0_s=140.0, tau0_t=110.0)
+        if t0 is not None:
+            S.tau0 = S.tau0.copy()
+            S.tau0[0] = t0
+        print("case table1 tau0", S.tau0, flush=True)
+        w = _wl((8, 8, 8), 4, 35, twins=True, steps=4, law=law, systems=S)
+        gs, R, ref = _compare_solves(w)
+        assert ref.mean_v[-1] > 0
+        _assert_effective(R, ref, 1e-10)
+        _assert_fields(gs, ref, 1e-10)
+
+
 def test_workload0_fp64_parity():
     """16^3, 8 grains, 12 slip systems, 0.5% in 10 steps (full workload)."""
     w = rvegen.workload(0)
