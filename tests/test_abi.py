@@ -197,3 +197,18 @@ def test_theta_round_trip_keeps_per_system_offsets():
     assert np.array_equal(q.tau0 - p.tau0, np.where(S.family == 0, 5.0, 0.0))
     assert q.law.twin.b == 7.0 and p.law.twin.b != 7.0
     assert np.array_equal(cp.theta_of(q), th2)
+
+
+def test_table1_kind_map_matches_the_table():
+    """The device's compile-time kind of each Table 1 system (which of the
+    three per-kind initial resistances the Table 1 law reads) is Table 1's
+    kind column as printed (o = 0, s = 1, t = 2).  A wrong map would not
+    change results (such problems would run the general law) but would
+    keep the paper's resistances off the specialized path."""
+    src = open(os.path.join(ROOT, "paper_2402_09996_amd", "csrc", "cpfft_device.hpp")).read()
+    m = re.search(r"constexpr int T1_KIND\[16\]\s*=\s*\{([^}]*)\}", src)
+    assert m, "T1_KIND not found"
+    device = [int(v) for v in m.group(1).split(",")]
+    rows = [l.split() for l in open(os.path.join(ROOT, "tests", "golden", "table1_systems.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert device == [{"o": 0, "s": 1, "t": 2}[r[1]] for r in rows]
