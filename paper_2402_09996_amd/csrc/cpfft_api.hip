@@ -356,7 +356,10 @@ static int timed_begin(cpf_solver *s, hipEvent_t *a, hipEvent_t *b)
     if (!s->timing) return CPF_OK;
     for (hipEvent_t *e : {a, b}) {
         if (s->ev_pool.empty()) {
-            HIPCHK(hipEventCreate(e));
+            // timing markers only (the polls copy the scalars back and
+            // synchronize the stream): no system-scope release, which would
+            // write the L2 back between every two kernels of an iteration
+            HIPCHK(hipEventCreateWithFlags(e, hipEventDisableSystemFence));
         } else {
             *e = s->ev_pool.back();
             s->ev_pool.pop_back();
@@ -374,10 +377,14 @@ static int timed_end(cpf_solver *s, int k, hipEvent_t a, hipEvent_t b)
     return CPF_OK;
 }
 
-// After a stream synchronization: fold the pending event pairs into the counters.
-static int timed_collect(cpf_solver *s)
+// Fold the first `count` pending event pairs (all by default) into the
+// counters; they must have completed (recorded before a stream
+// synchronization).
+static int timed_collect(cpf_solver *s, size_t count = (size_t)-1)
 {
-    for (auto &p : s->ev_pending) {
+    const size_t n = std::min(count, s->ev_pending.size());
+    for (size_t i = 0; i < n; ++i) {
+        auto &p = s->ev_pending[i];
         float ms = 0;
         HIPCHK(hipEventElapsedTime(&ms, p.second.first, p.second.second));
         s->t_ms[p.first] += ms;
@@ -385,7 +392,7 @@ static int timed_collect(cpf_solver *s)
         s->ev_pool.push_back(p.second.first);
         s->ev_pool.push_back(p.second.second);
     }
-    s->ev_pending.clear();
+    s->ev_pending.erase(s->ev_pending.begin(), s->ev_pending.begin() + n);
     return CPF_OK;
 }
 
@@ -1264,6 +1271,10 @@ static int step_impl(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *o
     int queued = 0, prev = 0, syncs = 0;
     for (const auto &h : s->rv) prev = std::max(prev, h.prev_iters);
     int chunk = s->opt.check_every > 0 ? s->opt.check_every : std::max(2, prev);
+    // timing events known to have completed (recorded before the last poll's
+    // synchronization): read after the next launches are queued, while the
+    // device works, not between the poll and those launches
+    size_t ev_done = 0;
     for (;;) {
         TraceRange chunk_trace("cpf iterations until the next poll");
         if (s->graph_iters != 0) {
@@ -1283,12 +1294,13 @@ static int step_impl(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *o
         for (size_t r = 0; r < nr; ++r)
             HIPCHK(hipMemcpyAsync(s->hsc + r, s->ws + s->rv[r].off_sc, sizeof(Scalars), hipMemcpyDeviceToHost,
                                   s->stream));
-        HIPCHK(hipStreamSynchronize(s->stream));
-        ++syncs;
         {
-            int rc = timed_collect(s);
+            int rc = timed_collect(s, ev_done);
             if (rc) return rc;
         }
+        HIPCHK(hipStreamSynchronize(s->stream));
+        ++syncs;
+        ev_done = s->ev_pending.size();
         bool all = true;
         for (size_t r = 0; r < nr; ++r) all = all && s->hsc[r].done;
         if (all) break;
@@ -1322,12 +1334,20 @@ static int step_impl(cpf_solver *s, const cpf_path *path, int n, cpf_step_out *o
             HIPCHK(hipMemcpyAsync(&s->hsc[r].n_symptom, cnt, sizeof(unsigned long long) + sizeof(int),
                                   hipMemcpyDeviceToHost, s->stream));
         }
+        {
+            int rc = timed_collect(s);   // no timed launch since the last poll
+            if (rc) return rc;
+        }
         HIPCHK(hipStreamSynchronize(s->stream));
         for (size_t r = 0; r < nr; ++r)
             if (s->hsc[r].bad_state) {
                 s->hsc[r].status = CPF_E_NAN;
                 all_ok = false;
             }
+    }
+    {
+        int rc = timed_collect(s);   // the last chunk's events when the check did not run
+        if (rc) return rc;
     }
     int worst = CPF_OK, worst_r = -1;
     for (size_t r = 0; r < nr; ++r) {
