@@ -33,7 +33,7 @@ FP64_PEAK_TFLOPS = 78.6
 # HBM bytes per launch of the x pass (the dominant kernel) at 128^3 FP32,
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy (factors
 # 0.5 and 1.0); valid only for the library sources they were taken on.
-XPASS_TRAFFIC = {"src": "d7499bc16a957599", "read_bytes": 479.4e6, "write_bytes": 420.4e6}
+XPASS_TRAFFIC = {"src": "5dde7f71e6166ed7", "read_bytes": 479.4e6, "write_bytes": 420.4e6}
 
 
 def library_source_hash() -> str:
