@@ -33,7 +33,7 @@ FP64_PEAK_TFLOPS = 78.6
 # HBM bytes per launch of the x pass (the dominant kernel) at 128^3 FP32,
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a 1 GiB copy (factors
 # 0.5 and 1.0); valid only for the library sources they were taken on.
-XPASS_TRAFFIC = {"src": "5dde7f71e6166ed7", "read_bytes": 479.4e6, "write_bytes": 420.4e6}
+XPASS_TRAFFIC = {"src": "feb78cbf0f56681f", "read_bytes": 479.4e6, "write_bytes": 420.4e6}
 
 
 def library_source_hash() -> str:
@@ -65,14 +65,17 @@ def fft_pass_bytes(nx: int, ny: int, nz: int, rbytes: int) -> float:
     return 2.0 * 6 * nz * ny * (nx // 2) * 2 * rbytes
 
 
-def run_mode(cp, w, precision, K, W, tol, stag, green="continuous"):
+def run_mode(cp, w, precision, K, W, tol, stag, green="continuous", timing=True):
+    """K timed load steps after W warm-up steps.  timing: True (HIP events
+    around every kernel) or "xpass" (around the x pass only: two events per
+    iteration instead of ten, the least disturbance of a timed run)."""
     import torch
     prob = cp.Problem.from_workload(w)
     s = cp.Solver(prob, precision=precision, tol=tol, stag_tol=stag, green=green)
     for n in range(W):
         s.step(w.path, n)
     s.reset()
-    s.set_timing(True)
+    s.set_timing(timing)
     torch.cuda.synchronize()
     iters, act, newt, outs = 0, 0.0, 0.0, []
     t0 = time.perf_counter()
@@ -312,7 +315,7 @@ def green_leg(cp, w, KG, W, r32, K, nvox):
     """The same FP32 workload with the rotated-scheme Green operator:
     iterations, throughput and time per load step against the continuous
     operator's run (which stores 64 of the 65 kx columns of a 128^3 grid;
-    the rotated operator needs all 65)."""
+    the rotated operator needs all 65).  Both runs time every kernel."""
     import numpy as np
     s, r = run_mode(cp, w, "fp32", KG, W, 1e-6, 1e-4, green="rotated")
     kern = r["kernels"]
@@ -581,6 +584,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--fp64-steps", type=int, default=None)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-breakdown", action="store_true",
+                    help="skip the second FP32 run that times every kernel")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--batch-steps", type=int, default=10)
     ap.add_argument("--adjoint-steps", type=int, default=50)
@@ -641,19 +646,27 @@ def main():
     dt = w.path.t[1] - w.path.t[0]
     M = max(1, math.ceil(dt / 0.05 * (1 - 1e-12)))
 
-    s32, r32 = run_mode(cp, w, "fp32", K, W, 1e-6, 1e-4)
+    # headline: HIP events around the x pass only
+    s32, r32 = run_mode(cp, w, "fp32", K, W, 1e-6, 1e-4, timing="xpass")
     value = r32["iters"] * nvox / r32["wall"]
+    # the same steps again with every kernel timed: the per-kernel breakdown
+    # (y and z pass rates) and the base of the rotated operator's comparison
+    rk = None
+    if not args.no_breakdown:
+        sk, rk = run_mode(cp, w, "fp32", K, W, 1e-6, 1e-4, timing=True)
+        del sk
     s64, r64 = (None, None)
     if K64 > 0:
-        s64, r64 = run_mode(cp, w, "fp64", K64, min(W, 1), 1e-8, 0.0)
+        s64, r64 = run_mode(cp, w, "fp64", K64, min(W, 1), 1e-8, 0.0, timing="xpass")
 
-    # dominant kernel of the headline run
-    kern = r32["kernels"]
+    # dominant kernel (by the breakdown run when there is one)
+    kern = rk["kernels"] if rk is not None else r32["kernels"]
     dom = max(kern, key=lambda k: kern[k][0])
     it = max(1, r32["iters"])
     if dom == "xpass_law":
         flops = law_flops(S, n_twin, M, nvox, r32["n_active"] / it, r32["n_newton"] / it)
-        avg_s = kern[dom][0] / 1e3 / it
+        # the headline run's own events
+        avg_s = r32["kernels"]["xpass_law"][0] / 1e3 / it
         ach = flops / avg_s / 1e12
         same = library_source_hash() == XPASS_TRAFFIC["src"] and (nz, ny, nx) == (128, 128, 128)
         traffic = XPASS_TRAFFIC["read_bytes"] + XPASS_TRAFFIC["write_bytes"] if same else None
@@ -664,14 +677,16 @@ def main():
                 "flops_per_launch": flops}
     else:
         b = fft_pass_bytes(nx, ny, nz, 4)
-        avg_s = kern[dom][0] / 1e3 / it
+        avg_s = kern[dom][0] / 1e3 / max(1, (rk or r32)["iters"])
         ach = b / avg_s / 1e9
         roof = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
                 "avg_launch_ms": avg_s * 1e3}
     fft_gbs = {}
     for k in ("ypass_fwd", "zpass_green", "ypass_inv"):
-        t = kern[k][0] / 1e3 / it
+        if kern[k][1] == 0:
+            continue
+        t = kern[k][0] / 1e3 / max(1, (rk or r32)["iters"])
         fft_gbs[k] = {"avg_ms": t * 1e3, "GB/s": fft_pass_bytes(nx, ny, nz, 4) / t / 1e9,
                       "frac_hbm": fft_pass_bytes(nx, ny, nz, 4) / t / 1e9 / HBM_PEAK_GBS}
 
@@ -684,7 +699,10 @@ def main():
                    "labels": int(w.rve.n_labels), "systems": S, "load_steps_timed": K,
                    "rk4_substeps": M, "tol": 1e-6, "global_batch": 1},
         "iterations": r32["iters"],
-        "kernel_ms": {k: v[0] for k, v in kern.items()},
+        "kernel_ms": {k: v[0] for k, v in kern.items() if v[1] > 0},
+        "kernel_timing": ("x pass: HIP events of the timed run (x pass only); all kernels: a second run of "
+                          "the same steps with every kernel timed" if rk is not None else
+                          "HIP events of the timed run (x pass only)"),
         "fft_passes": fft_gbs,
         "roofline": roof,
     }
@@ -692,7 +710,7 @@ def main():
         v64 = r64["iters"] * nvox / r64["wall"]
         line["fp64"] = {"value": v64, "unit": "voxel-iterations/s", "steps": K64,
                         "iterations": r64["iters"], "ms_per_step": r64["wall"] / K64 * 1e3,
-                        "tol": 1e-8, "kernel_ms": {k: v[0] for k, v in r64["kernels"].items()},
+                        "tol": 1e-8, "kernel_ms": {k: v[0] for k, v in r64["kernels"].items() if v[1] > 0},
                         "fp32_over_fp64_wall": (r64["wall"] / K64) / (r32["wall"] / K)}
         if K64 == K:
             import numpy as np
@@ -701,7 +719,7 @@ def main():
             line["fp64"]["fp32_max_rel_err_Sigma_xx"] = float(np.abs(a - b).max() / np.abs(b).max())
     KG = args.green_steps if args.green_steps is not None else K
     if KG > 0:
-        line["rotated_green"] = green_leg(cp, w, KG, min(W, 1), r32, K, nvox)
+        line["rotated_green"] = green_leg(cp, w, KG, min(W, 1), rk if rk is not None else r32, K, nvox)
         line["error_controlled_substeps"] = substeps_leg(cp, w, KG, r32, K, nvox)
         line["anderson"] = anderson_leg(cp, w, KG, r32, K, nvox)
     line["seq_histogram"] = histogram_leg(s32, nvox)

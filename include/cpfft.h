@@ -309,8 +309,17 @@ int cpf_solver_set_tiles(cpf_solver *s, int rve, int ty, int tz);
  * time is accumulated per kernel class: 0 x pass (local law and x
  * transforms), 1 forward y pass, 2 z pass with the Green operator, 3
  * inverse y pass, 4 boundary update.  Enabling clears the counters.
- * Launches that return at once after the step has ended are included. */
+ * Launches that return at once after the step has ended are included.
+ * `enable`: CPF_TIMING_OFF, CPF_TIMING_ALL (every kernel class) or
+ * CPF_TIMING_XPASS (class 0 only: two events per iteration instead of
+ * ten, for timing the dominant kernel with the least disturbance of the
+ * rest; the other classes then stay at zero).  Other values:
+ * CPF_E_INVALID_ARG.  The events are timing markers only (no system-scope
+ * release).  Synchronizes the bound stream. */
 #define CPF_NKERNELS 5
+#define CPF_TIMING_OFF 0
+#define CPF_TIMING_ALL 1
+#define CPF_TIMING_XPASS 2
 int cpf_solver_set_timing(cpf_solver *s, int enable);
 int cpf_solver_get_timing(const cpf_solver *s, double *ms /*[5]*/, long long *launches /*[5]*/);
 

@@ -146,6 +146,7 @@ def _outs_to_dict(outs, n):
 GREEN = {"continuous": 0, "rotated": 1}
 NYQUIST = {"zero": 0, "formula": 1}
 REG = {"implicit": 0, "lagged": 1}
+TIMING_OFF, TIMING_ALL, TIMING_XPASS = _lib.CPF_TIMING_OFF, _lib.CPF_TIMING_ALL, _lib.CPF_TIMING_XPASS
 
 
 def _options(precision, tol, max_iter, h_max, rk4_M, lam0, mu0, stag_tol, check_every, green="continuous",
@@ -392,8 +393,11 @@ class Solver:
     # -- kernel timing -------------------------------------------------------
     KERNELS = ("xpass_law", "ypass_fwd", "zpass_green", "ypass_inv", "bc_update")
 
-    def set_timing(self, on: bool = True):
-        check(_lib.lib().cpf_solver_set_timing(self._h, int(bool(on))))
+    def set_timing(self, on=True):
+        """Per-kernel HIP-event timing: True (every kernel class), False, or
+        "xpass" (the x pass only: two events per iteration instead of ten)."""
+        mode = TIMING_XPASS if on == "xpass" else (TIMING_ALL if on else TIMING_OFF)
+        check(_lib.lib().cpf_solver_set_timing(self._h, mode))
 
     def timing(self) -> dict:
         ms = (ctypes.c_double * 5)()

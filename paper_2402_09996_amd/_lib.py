@@ -35,6 +35,10 @@ CPF_FIELD_SUBSTEPS = 5
 CPF_REG_IMPLICIT = 0
 CPF_REG_LAGGED = 1
 
+CPF_TIMING_OFF = 0
+CPF_TIMING_ALL = 1
+CPF_TIMING_XPASS = 2
+
 CPF_MAX_SYSTEMS = 32
 CPF_GRAPH_ADAPTIVE = -1
 

@@ -343,17 +343,20 @@ struct cpf_solver {
     // by length
     int graph_iters = 0;
     std::map<int, std::pair<hipGraph_t, hipGraphExec_t>> graphs;
-    // kernel timing
+    // kernel timing (timing_xpass: the x pass only)
     bool timing = false;
+    bool timing_xpass = false;
     double t_ms[CPF_NKERNELS] = {0};
     long long t_n[CPF_NKERNELS] = {0};
     std::vector<hipEvent_t> ev_pool;
     std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_pending;
 };
 
-static int timed_begin(cpf_solver *s, hipEvent_t *a, hipEvent_t *b)
+static bool timed_on(const cpf_solver *s, int k) { return s->timing && (!s->timing_xpass || k == 0); }
+
+static int timed_begin(cpf_solver *s, int k, hipEvent_t *a, hipEvent_t *b)
 {
-    if (!s->timing) return CPF_OK;
+    if (!timed_on(s, k)) return CPF_OK;
     for (hipEvent_t *e : {a, b}) {
         if (s->ev_pool.empty()) {
             // timing markers only (the polls copy the scalars back and
@@ -371,7 +374,7 @@ static int timed_begin(cpf_solver *s, hipEvent_t *a, hipEvent_t *b)
 
 static int timed_end(cpf_solver *s, int k, hipEvent_t a, hipEvent_t b)
 {
-    if (!s->timing) return CPF_OK;
+    if (!timed_on(s, k)) return CPF_OK;
     HIPCHK(hipEventRecord(b, s->stream));
     s->ev_pending.push_back({k, {a, b}});
     return CPF_OK;
@@ -399,7 +402,7 @@ static int timed_collect(cpf_solver *s, size_t count = (size_t)-1)
 #define TIMED(s, k, launch)                                   \
     do {                                                      \
         hipEvent_t ea_ = nullptr, eb_ = nullptr;              \
-        int rc_ = timed_begin(s, &ea_, &eb_);                 \
+        int rc_ = timed_begin(s, k, &ea_, &eb_);              \
         if (rc_) return rc_;                                  \
         launch;                                               \
         rc_ = timed_end(s, k, ea_, eb_);                      \
@@ -792,10 +795,13 @@ extern "C" void cpf_solver_destroy(cpf_solver *s)
 extern "C" int cpf_solver_set_timing(cpf_solver *s, int enable)
 {
     if (!s) return fail(CPF_E_INVALID_ARG, "null solver");
+    if (enable != CPF_TIMING_OFF && enable != CPF_TIMING_ALL && enable != CPF_TIMING_XPASS)
+        return fail(CPF_E_INVALID_ARG, "timing mode must be CPF_TIMING_OFF, CPF_TIMING_ALL or CPF_TIMING_XPASS");
     if (s->bound) HIPCHK(hipStreamSynchronize(s->stream));
     int rc = timed_collect(s);
     if (rc) return rc;
-    s->timing = enable != 0;
+    s->timing = enable != CPF_TIMING_OFF;
+    s->timing_xpass = enable == CPF_TIMING_XPASS;
     for (int k = 0; k < CPF_NKERNELS; ++k) {
         s->t_ms[k] = 0.0;
         s->t_n[k] = 0;

@@ -31,6 +31,17 @@ def test_every_declared_symbol_is_exported_and_bound():
     assert L.cpf_error_string(-4) == b"fixed point did not converge"
 
 
+def test_binding_constants_equal_the_header_defines():
+    src = "".join(open(os.path.join(ROOT, "include", h)).read()
+                  for h in sorted(os.listdir(os.path.join(ROOT, "include"))) if h.endswith(".h"))
+    defs = {k: int(v) for k, v in re.findall(r"#define\s+(CPF_[A-Z0-9_]+)\s+\(?(-?\d+)\)?\s", src)}
+    bound = {k: getattr(_lib, k) for k in dir(_lib) if k.startswith("CPF_") and isinstance(getattr(_lib, k), int)}
+    assert len(bound) >= 20
+    for k, v in bound.items():
+        assert defs.get(k) == v, k
+    assert {defs["CPF_TIMING_OFF"], defs["CPF_TIMING_ALL"], defs["CPF_TIMING_XPASS"]} == {0, 1, 2}
+
+
 def _desc(n=(8, 8, 8), **over):
     w = rvegen.workload(0, n_override=8)
     keep = {}

@@ -2,7 +2,8 @@
 divides by): the solve is bit for bit the same with timing on or off, every
 timed launch of a load step has been read when the step returns (the
 events of a finished chunk are read while the next chunk runs, the last
-chunk's at the end of the step), and enabling timing resets the counts."""
+chunk's at the end of the step), enabling timing resets the counts, and
+the x-pass-only mode times that kernel alone."""
 import numpy as np
 import pytest
 
@@ -62,3 +63,25 @@ def test_timing_reads_every_launch_and_leaves_the_solve_unchanged(precision, che
     assert all(v == (0.0, 0) for v in timed.timing().values())
     timed.step(path, 0)
     assert timed.timing()["xpass_law"][1] >= 1
+
+
+def test_xpass_only_timing_counts_the_x_pass_alone():
+    w, path = _workload()
+    kw = dict(tol=1e-6, stag_tol=1e-4)
+    full = cp.Solver(cp.Problem.from_workload(w), precision="fp32", **kw)
+    xonly = cp.Solver(cp.Problem.from_workload(w), precision="fp32", **kw)
+    full.set_timing(True)
+    xonly.set_timing("xpass")
+    its = 0
+    for n in range(3):
+        a = full.step(path, n)
+        b = xonly.step(path, n)
+        assert np.array_equal(a["Sigma"], b["Sigma"]) and a["iters"] == b["iters"]
+        its += int(b["iters"])
+    tx, tf = xonly.timing(), full.timing()
+    assert tx["xpass_law"][1] == tf["xpass_law"][1] >= its and tx["xpass_law"][0] > 0.0
+    assert all(tx[k] == (0.0, 0) for k in cp.Solver.KERNELS if k != "xpass_law")
+    # x-pass figures of the two modes agree (same launches; fewer markers)
+    assert tx["xpass_law"][0] == pytest.approx(tf["xpass_law"][0], rel=0.25)
+    for bad in (3, -1):
+        assert cp._lib.lib().cpf_solver_set_timing(xonly._h, bad) == cp._lib.CPF_E_INVALID_ARG
